@@ -1,0 +1,182 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+The paper fits Kodak (24 images, 768x512) and DIV2K (x2-downscaled, 408-1020 px sides) with
+70 000 Gaussians (Sec. 4.1, Table 1).  Neither dataset is available here, so these generators
+stand in for them with images and Gaussian sets of the same shapes and sizes.
+
+This module holds no part of the rendering method: it only draws random numbers.  It is the one
+module that both the FP64 oracle tests and the GPU path tests import, so that both sides see the
+same inputs.  Every array is produced on the CPU as float32 with ``numpy.random.default_rng``.
+
+Gaussian records follow the 8-parameter layout of the merged-colour Gaussian (Sec. 3.2,
+Eq. rasterization4): ``(mu_x, mu_y, l1, l2, l3, c0, c1, c2)`` in pixel units, where
+``L = [[l1, 0], [l2, l3]]`` is the Cholesky factor of the covariance (Sec. 3.1, Eq. cholesky).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+PARAMS_PER_GAUSSIAN = 8
+
+
+def gaussians(n: int, height: int, width: int, seed: int, l_lo: float = 1.0,
+              l_hi: float = 8.0, l2_sd: float = 0.5) -> np.ndarray:
+    """Random Gaussian records, float32 ``[n, 8]``.
+
+    Means are uniform over ``[0, W) x [0, H)``; the Cholesky diagonals ``l1, l3`` are
+    ``exp(U(log l_lo, log l_hi))`` pixels; the off-diagonal ``l2`` is ``N(0, l2_sd^2)``; the
+    weighted colours are ``U[0, 1]^3``.
+    """
+    rng = np.random.default_rng(seed)
+    out = np.empty((n, PARAMS_PER_GAUSSIAN), dtype=np.float32)
+    out[:, 0] = rng.uniform(0.0, width, n)
+    out[:, 1] = rng.uniform(0.0, height, n)
+    out[:, 2] = np.exp(rng.uniform(math.log(l_lo), math.log(l_hi), n))
+    out[:, 3] = rng.normal(0.0, l2_sd, n)
+    out[:, 4] = np.exp(rng.uniform(math.log(l_lo), math.log(l_hi), n))
+    out[:, 5:8] = rng.uniform(0.0, 1.0, (n, 3))
+    # uniform(0, W) can round up to W in float32; keep means inside the half-open frame
+    np.minimum(out[:, 0], np.nextafter(np.float32(width), np.float32(0)), out=out[:, 0])
+    np.minimum(out[:, 1], np.nextafter(np.float32(height), np.float32(0)), out=out[:, 1])
+    return out
+
+
+def target_sinusoids(height: int, width: int, seed: int) -> np.ndarray:
+    """Smooth target: per channel, 1/2 plus 1/16 times a sum of 8 random plane sinusoids.
+
+    Frequencies are U(0.5, 4) cycles per image along each axis and phases U[0, 2pi); the result
+    lies in [0, 1].  Float32 ``[H, W, 3]``.
+    """
+    rng = np.random.default_rng(seed)
+    y, x = np.meshgrid(np.arange(height, dtype=np.float64), np.arange(width, dtype=np.float64),
+                       indexing="ij")
+    img = np.empty((height, width, 3), dtype=np.float64)
+    for ch in range(3):
+        fx = rng.uniform(0.5, 4.0, 8)
+        fy = rng.uniform(0.5, 4.0, 8)
+        ph = rng.uniform(0.0, 2.0 * math.pi, 8)
+        acc = np.zeros((height, width))
+        for j in range(8):
+            acc += np.sin(2.0 * math.pi * (fx[j] * x / width + fy[j] * y / height) + ph[j])
+        img[:, :, ch] = 0.5 + acc / 16.0
+    return img.astype(np.float32)
+
+
+def _value_noise(height: int, width: int, rng: np.random.Generator) -> np.ndarray:
+    acc = np.zeros((height, width))
+    total = 0.0
+    for octave in range(6):
+        spacing = 64 >> octave
+        amp = 0.5 ** octave
+        gh = height // spacing + 2
+        gw = width // spacing + 2
+        lattice = rng.uniform(0.0, 1.0, (gh, gw))
+        ys = np.arange(height) / spacing
+        xs = np.arange(width) / spacing
+        y0 = np.floor(ys).astype(np.int64)
+        x0 = np.floor(xs).astype(np.int64)
+        ty = ys - y0
+        tx = xs - x0
+        ty = ty * ty * (3.0 - 2.0 * ty)
+        tx = tx * tx * (3.0 - 2.0 * tx)
+        v00 = lattice[np.ix_(y0, x0)]
+        v01 = lattice[np.ix_(y0, x0 + 1)]
+        v10 = lattice[np.ix_(y0 + 1, x0)]
+        v11 = lattice[np.ix_(y0 + 1, x0 + 1)]
+        top = v00 + (v01 - v00) * tx[None, :]
+        bot = v10 + (v11 - v10) * tx[None, :]
+        acc += amp * (top + (bot - top) * ty[:, None])
+        total += amp
+    return acc / total
+
+
+def target_noise_rects(height: int, width: int, seed: int, n_rects: int = 32) -> np.ndarray:
+    """Textured target: 6-octave value noise per channel plus sharp-edged rectangles.
+
+    Lattice spacings 64, 32, ..., 2 px with amplitudes 0.5^octave and smoothstep bilinear
+    interpolation, normalised to [0, 1]; then ``n_rects`` opaque axis-aligned rectangles with
+    sides U(2%, 25%) of the image side and colours U[0, 1]^3, painted in order; clipped to
+    [0, 1].  Float32 ``[H, W, 3]``.
+    """
+    rng = np.random.default_rng(seed)
+    img = np.stack([_value_noise(height, width, rng) for _ in range(3)], axis=-1)
+    for _ in range(n_rects):
+        rw = max(1, int(round(rng.uniform(0.02, 0.25) * width)))
+        rh = max(1, int(round(rng.uniform(0.02, 0.25) * height)))
+        x0 = int(rng.integers(0, max(1, width - rw + 1)))
+        y0 = int(rng.integers(0, max(1, height - rh + 1)))
+        img[y0:y0 + rh, x0:x0 + rw, :] = rng.uniform(0.0, 1.0, 3)
+    return np.clip(img, 0.0, 1.0).astype(np.float32)
+
+
+def upstream_gradient(height: int, width: int, seed: int) -> np.ndarray:
+    """A seeded dL/dimage of unit-order signed values, float32 ``[H, W, 3]``."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, (height, width, 3)).astype(np.float32)
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One image of a workload: its size, Gaussian count and the seeds of its inputs."""
+    name: str
+    height: int
+    width: int
+    n: int
+    param_seed: int
+    target_seed: int
+    l_lo: float = 1.0
+    l_hi: float = 8.0
+    smooth_target: bool = False
+
+    def params(self) -> np.ndarray:
+        return gaussians(self.n, self.height, self.width, self.param_seed, self.l_lo, self.l_hi)
+
+    def target(self) -> np.ndarray:
+        if self.smooth_target:
+            return target_sinusoids(self.height, self.width, self.target_seed)
+        return target_noise_rects(self.height, self.width, self.target_seed)
+
+
+def plain_256(n: int = 2000) -> Workload:
+    """One 256x256 image with 2 000 Gaussians and a smooth sinusoid target."""
+    return Workload("plain-256x256", 256, 256, n, param_seed=0, target_seed=1,
+                    smooth_target=True)
+
+
+def kodak_like(n: int = 70_000) -> Workload:
+    """One 768x512 image (Kodak's size) with 10k, 30k or 70k Gaussians."""
+    return Workload(f"kodak-768x512-{n // 1000}k", 512, 768, n, param_seed=2000 + n // 1000,
+                    target_seed=200)
+
+
+def div2k_full(n: int = 100_000) -> Workload:
+    """One 2040x1356 image (DIV2K full resolution) with 100k or 300k Gaussians, l in 0.5-32 px."""
+    return Workload(f"div2k-2040x1356-{n // 1000}k", 1356, 2040, n, param_seed=3000 + n // 1000,
+                    target_seed=300, l_lo=0.5, l_hi=32.0)
+
+
+def batch_small(count: int = 64) -> list[Workload]:
+    """64 images with sides U{128..1024} and N_i = clamp(round(HW * 50000 / 1024^2), 1e3, 5e4)."""
+    rng = np.random.default_rng(4)
+    out = []
+    for i in range(count):
+        h = int(rng.integers(128, 1025))
+        w = int(rng.integers(128, 1025))
+        n = int(min(50_000, max(1_000, round(h * w * 50_000 / 1024 ** 2))))
+        out.append(Workload(f"batch64-{i}", h, w, n, param_seed=4000 + i, target_seed=400 + i))
+    return out
+
+
+def batch_large(count: int = 256) -> list[Workload]:
+    """256 images with sides U{512..2048} and N_i = clamp(round(HW * 2e5 / 2048^2), 2e4, 2e5)."""
+    rng = np.random.default_rng(5)
+    out = []
+    for i in range(count):
+        h = int(rng.integers(512, 2049))
+        w = int(rng.integers(512, 2049))
+        n = int(min(200_000, max(20_000, round(h * w * 200_000 / 2048 ** 2))))
+        out.append(Workload(f"batch256-{i}", h, w, n, param_seed=5000 + i, target_seed=500 + i))
+    return out
