@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Throughput of the accumulated-summation 2-D Gaussian rasteriser on one MI355X.
+
+Workload: one 768x512 RGB image (Kodak's size) with 70 000 Gaussians (Table 1 of the paper uses
+560K parameters = 70 000 x 8), synthetic seeded inputs (synth.kodak_like).  A step is one fit
+step of the whole path: projection and culling, scan, key duplication, radix sort, tile ranges
+and gather, fused forward + L2 loss gradient + adjoint, per-Gaussian gradient reduction with the
+Adam update.  Steps are replayed from a captured HIP graph with the inputs resident in HBM.
+
+Prints one JSON line: value = fit iterations per second; also render FPS, the roofline of the
+dominant kernel (the fused raster kernel, VALU bound) timed with HIP events on its stream, and
+the FP64 CPU oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peak VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one FP32 operation per lane per
+# cycle (packed FP32 is not used), in lane-operations per second.
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
+# Algorithmic work per pixel-Gaussian pair (the unit), in FP32 operations: forward 10 VALU
+# operations + 1 exp2, adjoint 26 VALU operations + 1 exp2 (plain per-pair forms, before any
+# sharing of per-column terms); each exp2 is counted as one operation.
+OPS_PER_PAIR_FIT = 10 + 26 + 2
+OPS_PER_PAIR_FWD = 10 + 1
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=70_000, help="Gaussians (10k, 30k or 70k)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle fit steps (0: auto ~15 s)")
+    return ap.parse_args()
+
+
+def pairs_from_ranges(ranges, height, width):
+    """Exact pixel-Gaussian pair count: tile list lengths times in-image pixels of each tile."""
+    import numpy as np
+    tw = (width + 15) // 16
+    t = np.arange(ranges.shape[0])
+    tx, ty = t % tw, t // tw
+    pw = np.minimum(16, width - tx * 16)
+    ph = np.minimum(16, height - ty * 16)
+    return int(((ranges[:, 1] - ranges[:, 0]).astype(np.int64) * pw * ph).sum())
+
+
+def cpu_baseline(w, steps):
+    import numpy as np
+    from oracle import cref, ref
+    p = w.params()
+    T = w.target()
+    n = p.shape[0]
+    zeros = np.zeros((n, 8))
+    hp = dict(ref.DEFAULT_ADAM)
+    t0 = time.perf_counter()
+    cref.fit_step(p, zeros, zeros, T, 1, hp)  # one step to size the sample
+    one = time.perf_counter() - t0
+    k = steps if steps > 0 else max(1, min(20, int(15.0 / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    for i in range(k):
+        cref.fit_step(p, zeros, zeros, T, i + 1, hp)
+    dt = time.perf_counter() - t0
+    return {"value": k / dt, "unit": "it/s", "cores": cref.num_threads(), "kind": "oracle",
+            "sample": f"{k} FP64 fit steps (culled render, L2 loss, gradients, Adam) of the "
+                      f"same {w.width}x{w.height} / {n} Gaussian workload, after one untimed step"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (one image or one "
+              "batch per GPU; sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2403_08551_amd as P
+    import synth
+
+    w = synth.kodak_like(args.n)
+    H, W = w.height, w.width
+    dev = torch.device("cuda", 0)
+    params0 = torch.tensor(w.params(), device=dev)
+    target = torch.tensor(w.target(), device=dev)
+    ctx = P.Context(0)
+
+    # exact work of this workload
+    b = ctx.binning(params0, H, W)
+    ranges = b["ranges"].cpu().numpy()
+    P_pairs = pairs_from_ranges(ranges, H, W)
+    K = b["keys"]
+
+    # ---- fit steps, captured once and replayed
+    params = params0.clone()
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    step = torch.ones(1, dtype=torch.int32, device=dev)
+    loss = torch.empty(1, device=dev)
+    graph = ctx.fit_graph(params, m, v, target, step, loss_out=loss)
+    graph.launch(args.warmup)
+    torch.cuda.synchronize()
+    loss_start = float(loss.item())
+    t0 = time.perf_counter()
+    graph.launch(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    its = args.steps / dt
+    loss_end = float(loss.item())
+    keys_now, flags = ctx.query(clear=True)
+    if flags & P._lib.GI_FLAG_KEY_OVERFLOW:
+        raise RuntimeError("key capacity overflowed during the timed steps")
+    graph.close()
+
+    # ---- dominant kernel: the fused raster kernel, timed with events on its stream (eager
+    # steps without host waits, same parameters as the timed region's end state)
+    ctx.set_option(P._lib.GI_OPT_SYNC, 0)
+    ctx.set_option(P._lib.GI_OPT_TIMING, 1)
+    n_prof = min(args.steps, 100)
+    for _ in range(5):
+        ctx.fit_step(params, m, v, target, step)
+    torch.cuda.synchronize()
+    ctx.timing(0, reset=True)
+    for _ in range(n_prof):
+        ctx.fit_step(params, m, v, target, step)
+    torch.cuda.synchronize()
+    fit_ms, fit_n = ctx.timing(P._lib.GI_STAGE_RASTER_FIT)
+    bin_ms, bin_n = ctx.timing(P._lib.GI_STAGE_BINNING)
+    upd_ms, upd_n = ctx.timing(P._lib.GI_STAGE_UPDATE, reset=True)
+    b2 = ctx.binning(params, H, W)  # pairs of the state that was profiled
+    P_prof = pairs_from_ranges(b2["ranges"].cpu().numpy(), H, W)
+    ctx.set_option(P._lib.GI_OPT_SYNC, 0)
+    fit_avg_s = fit_ms / fit_n / 1e3
+    achieved = OPS_PER_PAIR_FIT * P_prof / fit_avg_s
+
+    # ---- render FPS: eager non-waiting renders of the initial parameters
+    img = torch.empty(H, W, 3, device=dev)
+    for _ in range(10):
+        ctx.render(params0, H, W, out=img)
+    torch.cuda.synchronize()
+    n_render = max(args.steps, 100)
+    t0 = time.perf_counter()
+    for _ in range(n_render):
+        ctx.render(params0, H, W, out=img)
+    torch.cuda.synchronize()
+    fps = n_render / (time.perf_counter() - t0)
+    ctx.set_option(P._lib.GI_OPT_TIMING, 0)
+    ctx.close()
+
+    out = {
+        "metric": "fit iters/s (fwd+bwd) + render FPS, 768x512 @70k Gaussians; batched vs plain",
+        "value": its,
+        "unit": "it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded value noise + rectangles target, random Gaussians)",
+        "config": {"workload": w.name, "height": H, "width": W, "gaussians": args.n,
+                   "keys": K, "pairs": P_pairs, "fit_steps": "hip graph replay"},
+        "render_fps": fps,
+        "stage_ms": {"binning": bin_ms / max(bin_n, 1), "raster_fit": fit_ms / max(fit_n, 1),
+                     "update": upd_ms / max(upd_n, 1)},
+        "loss": {"after_warmup": loss_start, "after_timed": loss_end},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "T FP32 op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                     "kernel": "k_raster_fit<2>", "ops_per_pair": OPS_PER_PAIR_FIT,
+                     "pairs_per_launch": P_prof, "avg_launch_ms": fit_ms / fit_n},
+        "paper_context": {"render_fps_v100_kodak_70k": 2092.17,
+                          "fit_its_v100_kodak_70k_derived": 50000 / 106.59},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,225 @@
+/*
+ * gi.h -- C ABI of an MI355X (gfx950) differentiable renderer of N anisotropic 2-D Gaussians by
+ * accumulated summation, the image representation of GaussianImage (arXiv 2403.08551).
+ *
+ * What is computed (paper Sec. 3.1, Eq. cholesky; Sec. 3.2, Eq. rasterization2 and
+ * rasterization4; App. A):
+ *   Each Gaussian n is a record of 8 floats (mu_x, mu_y, l1, l2, l3, c0, c1, c2) in pixel units:
+ *   mean mu, Cholesky factor L = [[l1, 0], [l2, l3]] of Sigma = L L^T, and weighted colour c'
+ *   (unbounded; Sec. 3.2 after Eq. rasterization4).  Pixel (x, y) of an H x W image has centre
+ *   p = (x + 0.5, y + 0.5) and value
+ *       C(p) = sum_n c'_n exp(-sigma_n(p)),   sigma_n(p) = 1/2 d^T Sigma_n^{-1} d,  d = p - mu_n,
+ *   with no depth order and no alpha blending (Sec. 3.2).  The sum runs over the Gaussians whose
+ *   3-sigma box touches the 16x16 tile of p: the box half-width is r = ceil(3 sqrt(lambda_max))
+ *   pixels, decided exactly in float64, and Gaussian n covers tiles
+ *   [floor((mu - r) / 16), floor((mu + r) / 16)] clipped to the image.  A Gaussian with a
+ *   non-finite number, |l1| or |l3| < 2^-24, or |l2|, |mu_x|, |mu_y| > 2^24 takes no part.
+ *   Gradients follow App. A (with dC/dsigma = -c' exp(-sigma) and dL/dl2 = 2 g2 l1 + 2 g3 l2).
+ *
+ * Conventions for every call:
+ *   - Pointers named *_dev are device pointers owned by the caller (for example torch tensor
+ *     storage); the library never frees them.  Pointers named *_host are host memory.
+ *   - Images are row-major [H][W][3] float32; batches concatenate images in order.
+ *   - Parameters are [N][8] float32 rows in the record order above; outputs are overwritten,
+ *     never accumulated into.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Work is enqueued
+ *     on it and the call returns without waiting, except where a call says it synchronises.
+ *   - Every argument is checked before anything is enqueued; a bad argument returns
+ *     GI_ERR_INVALID_ARG and enqueues nothing.
+ *   - A context is used from one host thread at a time; contexts are independent.
+ *   - Forward results are bitwise deterministic: the per-tile lists are in ascending Gaussian
+ *     order and each tile sums in that order.  Gradients are deterministic too: per (tile,
+ *     Gaussian) partial sums are reduced in a fixed order, with no floating-point atomics.
+ */
+#ifndef GI_H
+#define GI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes returned by every int-valued call. */
+enum {
+    GI_OK = 0,
+    GI_ERR_INVALID_ARG = -1,  /* a bad pointer, size or option; nothing was enqueued */
+    GI_ERR_CAPACITY = -2,     /* keys exceed the reserved capacity in a non-growing call */
+    GI_ERR_HIP = -3,          /* a HIP runtime call failed (gi_last_error has the text) */
+    GI_ERR_NONFINITE = -4,    /* a parameter was not finite (reported by gi_query) */
+    GI_ERR_UNSUPPORTED = -5,  /* valid request this build does not handle */
+    GI_ERR_NO_DEVICE = -6     /* no usable gfx950 device */
+};
+
+/* Sticky device flags read by gi_query. */
+#define GI_FLAG_KEY_OVERFLOW 1u /* more (tile, Gaussian) keys than capacity: outputs undefined */
+#define GI_FLAG_NONFINITE 2u    /* some parameter was NaN or Inf (that Gaussian took no part) */
+
+typedef struct gi_ctx gi_ctx;
+typedef struct gi_graph gi_graph;
+
+/* Adam hyper-parameters of the fused update (fit calls).  lr_* are per group: position (mu),
+ * Cholesky vector (l1, l2, l3) and colour (c').  After each update |l1| and |l3| are raised to
+ * at least l_min (0 disables), keeping Sigma away from singular (the paper adds 0.5 to the
+ * diagonal for the same reason, App. C).  Bias correction uses the step number t >= 1. */
+typedef struct gi_adam {
+    float lr_mu, lr_l, lr_c;
+    float beta1, beta2, eps;
+    float l_min;
+} gi_adam;
+
+/* A batch of B independent images fitted or rendered together (host arrays).  Image b is
+ * height[b] x width[b] and owns Gaussians [gauss_off[b], gauss_off[b+1]) of the concatenated
+ * parameter array; gauss_off[0] = 0.  Pixels of image b start at pixel sum_{b'<b} H W. */
+typedef struct gi_batch {
+    int32_t count;
+    const int32_t *height_host;
+    const int32_t *width_host;
+    const int64_t *gauss_off_host;
+} gi_batch;
+
+/* Options for gi_set_option. */
+enum {
+    GI_OPT_SYNC = 1,          /* 1 (default): calls read back the key count (4 bytes, waits on
+                                 the stream) and grow the key buffers; 0: use the reserved
+                                 capacity, never wait, report overflow through flags */
+    GI_OPT_SORT_BITS = 2,     /* radix digit width 1..11, 0 = automatic */
+    GI_OPT_FWD_PIXELS = 3,    /* pixels per lane in the forward kernels: 1, 2 or 4; 0 = auto */
+    GI_OPT_BINNING = 4,       /* 0 = auto, 1 = generic radix sort, 2 = one-pass counting sort */
+    GI_OPT_TIMING = 5         /* 1: bracket each stage of non-captured calls with HIP events on
+                                 the call's stream (read with gi_timing); 0 (default): off */
+};
+
+/* Stages timed when GI_OPT_TIMING is on. */
+enum {
+    GI_STAGE_BINNING = 0,     /* projection through the gather into tile order */
+    GI_STAGE_RASTER_FWD = 1,  /* forward kernel of gi_render */
+    GI_STAGE_RASTER_BWD = 2,  /* adjoint kernel of gi_grad */
+    GI_STAGE_RASTER_FIT = 3,  /* fused forward + loss gradient + adjoint of the fit calls */
+    GI_STAGE_UPDATE = 4,      /* per-Gaussian gradient reduction (and Adam) */
+    GI_STAGE_COUNT = 5
+};
+
+/* ---- context ------------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  Allocates a small fixed workspace.  Returns
+ * GI_ERR_NO_DEVICE when the device is missing or not gfx950. */
+int gi_create(gi_ctx **out, int device);
+/* Release the context and its workspace (waits for its work to finish).  NULL is accepted. */
+int gi_destroy(gi_ctx *ctx);
+/* Set an option (GI_OPT_*).  Host only. */
+int gi_set_option(gi_ctx *ctx, int option, int64_t value);
+/* Grow the workspace to hold n_gauss Gaussians, n_tiles tiles and key_capacity (tile,
+ * Gaussian) keys.  Host call that allocates; never call it while a graph is being captured. */
+int gi_reserve(gi_ctx *ctx, int64_t n_gauss, int64_t n_tiles, int64_t key_capacity);
+/* Wait for the context's work, then report the key count of the last binning and the sticky
+ * flags (GI_FLAG_*); clear = 1 resets the flags. */
+int gi_query(gi_ctx *ctx, int64_t *last_keys, uint32_t *flags, int clear);
+/* Read an option (GI_OPT_*); for the tunable options 0 means "automatic". */
+int gi_get_option(gi_ctx *ctx, int option, int64_t *value);
+
+/* Autotuner: time fit steps of this workload (batch == NULL: the single image n x height x
+ * width; else the batch) for each setting of the tunable knobs -- forward pixels per lane
+ * (1, 2, 4) and radix digit width (automatic, 4, 6, 8, 11) -- on scratch copies of the
+ * parameters (the caller's buffers are read, never written), `reps` timed steps per setting.
+ * The fastest setting is kept in the context for the workload's size class (Gaussian count and
+ * pixel count, each rounded to a power of sqrt(2)) and used by later calls whose options are
+ * automatic.  Allocates scratch memory and synchronises; never call it during graph capture.
+ * Writes the chosen settings to *fwd_pixels and *sort_bits (either may be NULL). */
+int gi_autotune(gi_ctx *ctx, const float *params_dev, const float *target_dev, int64_t n,
+                int32_t height, int32_t width, const gi_batch *batch, int32_t reps,
+                void *stream, int32_t *fwd_pixels, int32_t *sort_bits);
+
+/* Wait for the timed events, then report the summed milliseconds and the number of timed
+ * launches of `stage` (GI_STAGE_*) since the last reset; reset = 1 clears the totals. */
+int gi_timing(gi_ctx *ctx, int stage, double *total_ms, int64_t *launches, int reset);
+/* Static text for a status code. */
+const char *gi_status_string(int status);
+/* Text of the last HIP error seen by this context ("" if none). */
+const char *gi_last_error(gi_ctx *ctx);
+
+/* ---- single image (Sec. 3.2 forward, App. A backward) -------------------------------------- */
+
+/* render(params, H, W) -> image: Eq. rasterization4 over the tile support.
+ * params_dev [N][8], image_dev [H][W][3].  N >= 0 (N = 0 gives a zero image), 1 <= H, W <= 32768. */
+int gi_render(gi_ctx *ctx, const float *params_dev, int64_t n, int32_t height, int32_t width,
+              float *image_dev, void *stream);
+
+/* grad(params, dL/dimage) -> dparams (App. A): dparams_dev [N][8] in record order,
+ * dl_dimage_dev [H][W][3]. */
+int gi_grad(gi_ctx *ctx, const float *params_dev, int64_t n, int32_t height, int32_t width,
+            const float *dl_dimage_dev, float *dparams_dev, void *stream);
+
+/* One fit step (Sec. 3.4, L2 loss): render, loss = mean over H*W*3 of (C - target)^2,
+ * dL/dC = 2 (C - target) / (3 H W), gradients, then the Adam update of params_dev in place with
+ * moments m_dev, v_dev ([N][8], caller-initialised, usually zeros).  step_dev points to one
+ * int32 on the device holding the step number t >= 1, used for bias correction and then
+ * incremented, so that replays of a captured step advance it.  image_out_dev ([H][W][3]) and
+ * loss_out_dev (one float) receive the render and loss before the update; either may be NULL.
+ * If the key overflow flag is set the update is skipped (parameters unchanged). */
+int gi_fit_step(gi_ctx *ctx, float *params_dev, float *m_dev, float *v_dev,
+                const float *target_dev, int64_t n, int32_t height, int32_t width,
+                const gi_adam *hp, int32_t *step_dev, float *image_out_dev, float *loss_out_dev,
+                void *stream);
+
+/* ---- batched: B images, one launch per stage ---------------------------------------------- */
+
+/* Same as gi_render for every image of the batch; images_dev is the concatenation. */
+int gi_render_batched(gi_ctx *ctx, const float *params_dev, const gi_batch *batch,
+                      float *images_dev, void *stream);
+/* Same as gi_grad for every image; dl_dimages_dev and dparams_dev are concatenations. */
+int gi_grad_batched(gi_ctx *ctx, const float *params_dev, const gi_batch *batch,
+                    const float *dl_dimages_dev, float *dparams_dev, void *stream);
+/* Same as gi_fit_step for every image (each image's loss is its own mean);
+ * loss_out_dev receives B floats (may be NULL). */
+int gi_fit_step_batched(gi_ctx *ctx, float *params_dev, float *m_dev, float *v_dev,
+                        const float *targets_dev, const gi_batch *batch, const gi_adam *hp,
+                        int32_t *step_dev, float *images_out_dev, float *loss_out_dev,
+                        void *stream);
+
+/* ---- captured fit steps ------------------------------------------------------------------- */
+
+/* Capture one fit step (batch == NULL: the single image n x height x width; else the batch)
+ * into a HIP graph.  The context switches to non-waiting mode for the graph's kernels and uses
+ * key_capacity (at least the current key count is reserved first, with a 1.25x margin, by one
+ * synchronous binning pass).  All pointers are baked into the graph and must stay valid. */
+int gi_fit_graph_create(gi_ctx *ctx, float *params_dev, float *m_dev, float *v_dev,
+                        const float *target_dev, int64_t n, int32_t height, int32_t width,
+                        const gi_batch *batch, const gi_adam *hp, int32_t *step_dev,
+                        float *image_out_dev, float *loss_out_dev, void *stream,
+                        gi_graph **out);
+/* Replay the captured step `steps` times on `stream`. */
+int gi_fit_graph_launch(gi_graph *graph, int32_t steps, void *stream);
+int gi_fit_graph_destroy(gi_graph *graph);
+
+/* ---- the binning stages, for inspection and testing ---------------------------------------- */
+
+/* Run projection, key duplication, the stable radix sort and tile-range extraction (north star
+ * stages a-b; Sec. 3.2 drops the depth key, so the sort key is the tile id alone), then copy out:
+ * rects_dev [N][4] int32 (tx0, ty0, tx1, ty1; (0, 0, -1, -1) when the Gaussian covers nothing),
+ * counts_dev [N] uint32, offsets_dev [N] uint32 (exclusive prefix sum of counts),
+ * ranges_dev [T][2] uint32 ([start, end) into the sorted list, T = ceil(H/16) ceil(W/16)),
+ * ids_dev [ids_capacity] uint32 (Gaussian ids, tile-major, ascending within a tile).
+ * *keys_host receives the key count K (synchronises).  Any output pointer may be NULL; if
+ * ids_capacity < K the ids are not copied and GI_ERR_CAPACITY is returned. */
+int gi_binning(gi_ctx *ctx, const float *params_dev, int64_t n, int32_t height, int32_t width,
+               int32_t *rects_dev, uint32_t *counts_dev, uint32_t *offsets_dev,
+               uint32_t *ranges_dev, uint32_t *ids_dev, int64_t ids_capacity,
+               int64_t *keys_host, void *stream);
+
+/* Exclusive prefix sum of n uint32 values (out may alias in); total_dev (one uint64, may be
+ * NULL) receives the sum. */
+int gi_scan_u32(gi_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, int64_t n,
+                uint64_t *total_dev, void *stream);
+
+/* Stable LSD radix sort of n (key, value) uint32 pairs by the low key_bits (1..32) bits of the
+ * key.  Outputs must not alias inputs. */
+int gi_sort_pairs(gi_ctx *ctx, const uint32_t *keys_in_dev, const uint32_t *vals_in_dev,
+                  uint32_t *keys_out_dev, uint32_t *vals_out_dev, int64_t n, int32_t key_bits,
+                  void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GI_H */

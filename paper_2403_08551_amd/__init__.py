@@ -1,0 +1,383 @@
+"""MI355X (gfx950) differentiable renderer of 2-D Gaussians by accumulated summation.
+
+The image representation of GaussianImage (arXiv 2403.08551): N Gaussians, each with mean mu,
+Cholesky factor L (Sigma = L L^T, Sec. 3.1) and weighted colour c', render an image as
+C(p) = sum_n c'_n exp(-1/2 d^T Sigma_n^{-1} d) with no depth order and no alpha blending
+(Sec. 3.2, Eq. rasterization4); the gradients follow App. A.  Parameters are float32 tensors of
+shape [N, 8] = (mu_x, mu_y, l1, l2, l3, c0, c1, c2) in pixel units; images are [H, W, 3].
+
+Every computation runs in the HIP kernels of libgi.so behind the C ABI of include/gi.h; this
+module only passes device pointers, sizes and the current torch stream.  There is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import GiError
+
+__all__ = ["Context", "Batch", "AdamConfig", "GaussianRender", "render", "default_context",
+           "GiError"]
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclass
+class AdamConfig:
+    """Fused Adam hyper-parameters: learning rates per group (position, Cholesky vector,
+    colour), moment decay rates, epsilon, and the floor l_min on |l1|, |l3|."""
+    lr_mu: float = 0.05
+    lr_l: float = 0.01
+    lr_c: float = 0.005
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    l_min: float = 0.5
+
+    def c(self) -> _lib.gi_adam:
+        return _lib.gi_adam(self.lr_mu, self.lr_l, self.lr_c, self.beta1, self.beta2, self.eps,
+                            self.l_min)
+
+
+class Batch:
+    """Layout of B images rendered or fitted together: heights, widths and the Gaussian
+    offsets (image b owns rows gauss_off[b]:gauss_off[b+1] of the parameter array)."""
+
+    def __init__(self, heights, widths, gauss_off):
+        self.heights = [int(h) for h in heights]
+        self.widths = [int(w) for w in widths]
+        self.gauss_off = [int(g) for g in gauss_off]
+        b = len(self.heights)
+        if len(self.widths) != b or len(self.gauss_off) != b + 1:
+            raise ValueError("heights, widths need B entries and gauss_off B + 1")
+        self._h = (ctypes.c_int32 * b)(*self.heights)
+        self._w = (ctypes.c_int32 * b)(*self.widths)
+        self._g = (ctypes.c_int64 * (b + 1))(*self.gauss_off)
+        self.c = _lib.gi_batch(b, self._h, self._w, self._g)
+        self.pix_off = [0]
+        for h, w in zip(self.heights, self.widths):
+            self.pix_off.append(self.pix_off[-1] + h * w)
+
+    @property
+    def count(self) -> int:
+        return len(self.heights)
+
+    @property
+    def n_gauss(self) -> int:
+        return self.gauss_off[-1]
+
+    @property
+    def n_pix(self) -> int:
+        return self.pix_off[-1]
+
+    def image(self, flat: torch.Tensor, b: int) -> torch.Tensor:
+        """View of image b inside a concatenated [sum H W, 3] buffer."""
+        return flat.view(-1, 3)[self.pix_off[b]:self.pix_off[b + 1]].view(
+            self.heights[b], self.widths[b], 3)
+
+
+def _check(t: torch.Tensor, name: str, device, shape=None, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Context:
+    """One gi_ctx: owns the device workspace.  Use from one thread at a time."""
+
+    def __init__(self, device: int | torch.device = 0):
+        dev = torch.device(device) if not isinstance(device, int) else torch.device("cuda", device)
+        if dev.type != "cuda":
+            raise ValueError("the renderer runs on a GPU device only")
+        self.device = torch.device("cuda", dev.index if dev.index is not None else 0)
+        handle = ctypes.c_void_p()
+        self._raise(_lib.lib().gi_create(ctypes.byref(handle), self.device.index), "gi_create")
+        self._h = handle
+
+    # -- plumbing
+    def _raise(self, status: int, what: str):
+        if status != _lib.GI_OK:
+            detail = ""
+            h = getattr(self, "_h", None)
+            if h is not None and h.value:
+                detail = _lib.lib().gi_last_error(h).decode()
+            raise GiError(status, what, detail)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().gi_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, option: int, value: int):
+        self._raise(_lib.lib().gi_set_option(self._h, option, int(value)), "gi_set_option")
+
+    def reserve(self, n_gauss: int, n_tiles: int, key_capacity: int):
+        self._raise(_lib.lib().gi_reserve(self._h, n_gauss, n_tiles, key_capacity), "gi_reserve")
+
+    def query(self, clear: bool = False):
+        k = ctypes.c_int64()
+        f = ctypes.c_uint32()
+        self._raise(_lib.lib().gi_query(self._h, ctypes.byref(k), ctypes.byref(f), int(clear)),
+                    "gi_query")
+        return k.value, f.value
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int64()
+        self._raise(_lib.lib().gi_get_option(self._h, option, ctypes.byref(v)), "gi_get_option")
+        return v.value
+
+    def autotune(self, params, target, batch: Batch | None = None, reps: int = 5):
+        """Time the tunable settings on fit steps of this workload (scratch copies) and keep the
+        fastest for its size class; returns (pixels per lane, radix digit width, 0 = auto)."""
+        if batch is None:
+            h, w = target.shape[0], target.shape[1]
+            n = params.shape[0]
+        else:
+            h = w = 0
+            n = batch.n_gauss
+        _check(params, "params", self.device, (n, 8))
+        _check(target, "target", self.device)
+        px = ctypes.c_int32()
+        bits = ctypes.c_int32()
+        self._raise(_lib.lib().gi_autotune(
+            self._h, _ptr(params), _ptr(target), n, h, w,
+            ctypes.byref(batch.c) if batch is not None else None, reps, _stream(self.device),
+            ctypes.byref(px), ctypes.byref(bits)), "gi_autotune")
+        return px.value, bits.value
+
+    def timing(self, stage: int, reset: bool = False):
+        """(total milliseconds, launches) of a stage timed with GI_OPT_TIMING."""
+        ms = ctypes.c_double()
+        k = ctypes.c_int64()
+        self._raise(_lib.lib().gi_timing(self._h, stage, ctypes.byref(ms), ctypes.byref(k),
+                                         int(reset)), "gi_timing")
+        return ms.value, k.value
+
+    # -- single image
+    def render(self, params: torch.Tensor, height: int, width: int, out=None) -> torch.Tensor:
+        _check(params, "params", self.device, (params.shape[0], 8))
+        if out is None:
+            out = torch.empty(height, width, 3, device=self.device, dtype=torch.float32)
+        _check(out, "out", self.device, (height, width, 3))
+        self._raise(_lib.lib().gi_render(self._h, _ptr(params), params.shape[0], height, width,
+                                         _ptr(out), _stream(self.device)), "gi_render")
+        return out
+
+    def grad(self, params, height, width, dl_dimage, out=None) -> torch.Tensor:
+        _check(params, "params", self.device, (params.shape[0], 8))
+        _check(dl_dimage, "dl_dimage", self.device, (height, width, 3))
+        if out is None:
+            out = torch.empty_like(params)
+        _check(out, "out", self.device, tuple(params.shape))
+        self._raise(_lib.lib().gi_grad(self._h, _ptr(params), params.shape[0], height, width,
+                                       _ptr(dl_dimage), _ptr(out), _stream(self.device)),
+                    "gi_grad")
+        return out
+
+    def fit_step(self, params, m, v, target, step, hp: AdamConfig | None = None,
+                 image_out=None, loss_out=None):
+        """One fused fit step in place on params, m, v; step is an int32 device tensor [1]."""
+        n = params.shape[0]
+        h, w = target.shape[0], target.shape[1]
+        for t, name in ((params, "params"), (m, "m"), (v, "v")):
+            _check(t, name, self.device, (n, 8))
+        _check(target, "target", self.device, (h, w, 3))
+        _check(step, "step", self.device, (1,), torch.int32)
+        if image_out is not None:
+            _check(image_out, "image_out", self.device, (h, w, 3))
+        if loss_out is not None:
+            _check(loss_out, "loss_out", self.device, (1,))
+        hpc = (hp or AdamConfig()).c()
+        self._raise(_lib.lib().gi_fit_step(self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(target),
+                                           n, h, w, ctypes.byref(hpc), _ptr(step),
+                                           _ptr(image_out), _ptr(loss_out),
+                                           _stream(self.device)), "gi_fit_step")
+
+    # -- batched
+    def render_batched(self, params, batch: Batch, out=None) -> torch.Tensor:
+        _check(params, "params", self.device, (batch.n_gauss, 8))
+        if out is None:
+            out = torch.empty(batch.n_pix, 3, device=self.device, dtype=torch.float32)
+        _check(out, "out", self.device)
+        if out.numel() != batch.n_pix * 3:
+            raise ValueError("out must hold sum(H W) * 3 floats")
+        self._raise(_lib.lib().gi_render_batched(self._h, _ptr(params), ctypes.byref(batch.c),
+                                                 _ptr(out), _stream(self.device)),
+                    "gi_render_batched")
+        return out
+
+    def grad_batched(self, params, batch: Batch, dl_dimages, out=None) -> torch.Tensor:
+        _check(params, "params", self.device, (batch.n_gauss, 8))
+        _check(dl_dimages, "dl_dimages", self.device)
+        if dl_dimages.numel() != batch.n_pix * 3:
+            raise ValueError("dl_dimages must hold sum(H W) * 3 floats")
+        if out is None:
+            out = torch.empty_like(params)
+        _check(out, "out", self.device, tuple(params.shape))
+        self._raise(_lib.lib().gi_grad_batched(self._h, _ptr(params), ctypes.byref(batch.c),
+                                               _ptr(dl_dimages), _ptr(out),
+                                               _stream(self.device)), "gi_grad_batched")
+        return out
+
+    def fit_step_batched(self, params, m, v, targets, batch: Batch, step,
+                         hp: AdamConfig | None = None, images_out=None, loss_out=None):
+        n = batch.n_gauss
+        for t, name in ((params, "params"), (m, "m"), (v, "v")):
+            _check(t, name, self.device, (n, 8))
+        _check(targets, "targets", self.device)
+        if targets.numel() != batch.n_pix * 3:
+            raise ValueError("targets must hold sum(H W) * 3 floats")
+        _check(step, "step", self.device, (1,), torch.int32)
+        if images_out is not None:
+            _check(images_out, "images_out", self.device)
+        if loss_out is not None:
+            _check(loss_out, "loss_out", self.device, (batch.count,))
+        hpc = (hp or AdamConfig()).c()
+        self._raise(_lib.lib().gi_fit_step_batched(
+            self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(targets), ctypes.byref(batch.c),
+            ctypes.byref(hpc), _ptr(step), _ptr(images_out), _ptr(loss_out),
+            _stream(self.device)), "gi_fit_step_batched")
+
+    def fit_graph(self, params, m, v, target, step, hp: AdamConfig | None = None,
+                  batch: Batch | None = None, image_out=None, loss_out=None) -> "FitGraph":
+        """Capture one fit step into a HIP graph (see gi_fit_graph_create)."""
+        if batch is None:
+            h, w = target.shape[0], target.shape[1]
+            n = params.shape[0]
+        else:
+            h = w = 0
+            n = batch.n_gauss
+        hpc = (hp or AdamConfig()).c()
+        g = ctypes.c_void_p()
+        self._raise(_lib.lib().gi_fit_graph_create(
+            self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(target), n, h, w,
+            ctypes.byref(batch.c) if batch is not None else None, ctypes.byref(hpc), _ptr(step),
+            _ptr(image_out), _ptr(loss_out), _stream(self.device), ctypes.byref(g)),
+            "gi_fit_graph_create")
+        return FitGraph(self, g, (params, m, v, target, step, image_out, loss_out))
+
+    # -- inspection of the binning stages
+    def binning(self, params, height: int, width: int):
+        """Run the binning stages and return rects, counts, offsets, ranges and sorted ids."""
+        _check(params, "params", self.device, (params.shape[0], 8))
+        n = params.shape[0]
+        t = ((height + 15) // 16) * ((width + 15) // 16)
+        dev = self.device
+        rects = torch.empty(n, 4, dtype=torch.int32, device=dev)
+        counts = torch.empty(n, dtype=torch.int32, device=dev)
+        offs = torch.empty(n, dtype=torch.int32, device=dev)
+        ranges = torch.empty(t, 2, dtype=torch.int32, device=dev)
+        k = ctypes.c_int64()
+        st = _stream(dev)
+        self._raise(_lib.lib().gi_binning(self._h, _ptr(params), n, height, width, _ptr(rects),
+                                          _ptr(counts), _ptr(offs), _ptr(ranges), None, 0,
+                                          ctypes.byref(k), st), "gi_binning")
+        ids = torch.empty(max(k.value, 1), dtype=torch.int32, device=dev)
+        self._raise(_lib.lib().gi_binning(self._h, _ptr(params), n, height, width, None, None,
+                                          None, None, _ptr(ids), ids.numel(), ctypes.byref(k),
+                                          st), "gi_binning")
+        return dict(rects=rects, counts=counts, offsets=offs, ranges=ranges,
+                    ids=ids[:k.value], keys=k.value)
+
+    def scan_u32(self, x: torch.Tensor):
+        _check(x, "x", self.device, dtype=torch.int32)
+        out = torch.empty_like(x)
+        total = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self._raise(_lib.lib().gi_scan_u32(self._h, _ptr(x), _ptr(out), x.numel(), _ptr(total),
+                                           _stream(self.device)), "gi_scan_u32")
+        return out, total
+
+    def sort_pairs(self, keys: torch.Tensor, vals: torch.Tensor, key_bits: int):
+        _check(keys, "keys", self.device, dtype=torch.int32)
+        _check(vals, "vals", self.device, tuple(keys.shape), dtype=torch.int32)
+        ko = torch.empty_like(keys)
+        vo = torch.empty_like(vals)
+        self._raise(_lib.lib().gi_sort_pairs(self._h, _ptr(keys), _ptr(vals), _ptr(ko), _ptr(vo),
+                                             keys.numel(), key_bits, _stream(self.device)),
+                    "gi_sort_pairs")
+        return ko, vo
+
+
+class FitGraph:
+    """A captured fit step; launch(k) replays it k times on the current stream."""
+
+    def __init__(self, ctx: Context, handle, keep):
+        self.ctx = ctx
+        self._g = handle
+        self._keep = keep  # the graph holds raw pointers into these tensors
+
+    def launch(self, steps: int = 1):
+        self.ctx._raise(_lib.lib().gi_fit_graph_launch(self._g, int(steps),
+                                                       _stream(self.ctx.device)),
+                        "gi_fit_graph_launch")
+
+    def close(self):
+        if self._g is not None and self._g.value:
+            _lib.lib().gi_fit_graph_destroy(self._g)
+            self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default: dict[int, Context] = {}
+_default_lock = threading.Lock()
+
+
+def default_context(device=None) -> Context:
+    idx = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    with _default_lock:
+        if idx not in _default:
+            _default[idx] = Context(idx)
+        return _default[idx]
+
+
+class GaussianRender(torch.autograd.Function):
+    """image = render(params, H, W); backward gives dL/dparams through gi_grad (App. A)."""
+
+    @staticmethod
+    def forward(ctx, params, height, width, context=None):
+        c = context or default_context(params.device)
+        p = params.detach().contiguous()
+        img = c.render(p, height, width)
+        ctx.save_for_backward(p)
+        ctx.gi = (c, height, width)
+        return img
+
+    @staticmethod
+    def backward(ctx, dimage):
+        (p,) = ctx.saved_tensors
+        c, h, w = ctx.gi
+        d = c.grad(p, h, w, dimage.contiguous())
+        return d, None, None, None
+
+
+def render(params: torch.Tensor, height: int, width: int, context: Context | None = None):
+    """Differentiable render of [N, 8] Gaussians to an [H, W, 3] image."""
+    return GaussianRender.apply(params, height, width, context)

@@ -1,0 +1,127 @@
+"""ctypes declarations of the C ABI in include/gi.h (libgi.so, built in place).
+
+There is no fallback: if the library is missing or does not load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgi.so")
+
+GI_OK = 0
+GI_ERR_INVALID_ARG = -1
+GI_ERR_CAPACITY = -2
+GI_ERR_HIP = -3
+GI_ERR_NONFINITE = -4
+GI_ERR_UNSUPPORTED = -5
+GI_ERR_NO_DEVICE = -6
+
+GI_FLAG_KEY_OVERFLOW = 1
+GI_FLAG_NONFINITE = 2
+
+GI_OPT_SYNC = 1
+GI_OPT_SORT_BITS = 2
+GI_OPT_FWD_PIXELS = 3
+GI_OPT_BINNING = 4
+GI_OPT_TIMING = 5
+
+GI_STAGE_BINNING = 0
+GI_STAGE_RASTER_FWD = 1
+GI_STAGE_RASTER_BWD = 2
+GI_STAGE_RASTER_FIT = 3
+GI_STAGE_UPDATE = 4
+
+# every symbol that include/gi.h declares
+EXPORTS = (
+    "gi_create", "gi_destroy", "gi_set_option", "gi_reserve", "gi_query", "gi_status_string",
+    "gi_last_error", "gi_render", "gi_grad", "gi_fit_step", "gi_render_batched",
+    "gi_grad_batched", "gi_fit_step_batched", "gi_fit_graph_create", "gi_fit_graph_launch",
+    "gi_fit_graph_destroy", "gi_binning", "gi_scan_u32", "gi_sort_pairs", "gi_timing",
+    "gi_get_option", "gi_autotune",
+)
+
+
+class gi_adam(ctypes.Structure):
+    _fields_ = [("lr_mu", ctypes.c_float), ("lr_l", ctypes.c_float), ("lr_c", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("l_min", ctypes.c_float)]
+
+
+class gi_batch(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32),
+                ("height_host", ctypes.POINTER(ctypes.c_int32)),
+                ("width_host", ctypes.POINTER(ctypes.c_int32)),
+                ("gauss_off_host", ctypes.POINTER(ctypes.c_int64))]
+
+
+class GiError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str = ""):
+        self.status = status
+        msg = f"{what}: {status_string(status)} ({status})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+_lib = None
+
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+I32 = ctypes.c_int32
+
+
+def lib():
+    """Load libgi.so; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_2403_08551_amd/build.py` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "gi_create": ([ctypes.POINTER(P), ctypes.c_int], ctypes.c_int),
+            "gi_destroy": ([P], ctypes.c_int),
+            "gi_set_option": ([P, ctypes.c_int, I64], ctypes.c_int),
+            "gi_reserve": ([P, I64, I64, I64], ctypes.c_int),
+            "gi_query": ([P, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_uint32), ctypes.c_int],
+                         ctypes.c_int),
+            "gi_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "gi_last_error": ([P], ctypes.c_char_p),
+            "gi_render": ([P, P, I64, I32, I32, P, P], ctypes.c_int),
+            "gi_grad": ([P, P, I64, I32, I32, P, P, P], ctypes.c_int),
+            "gi_fit_step": ([P, P, P, P, P, I64, I32, I32, ctypes.POINTER(gi_adam), P, P, P, P],
+                            ctypes.c_int),
+            "gi_render_batched": ([P, P, ctypes.POINTER(gi_batch), P, P], ctypes.c_int),
+            "gi_grad_batched": ([P, P, ctypes.POINTER(gi_batch), P, P, P], ctypes.c_int),
+            "gi_fit_step_batched": ([P, P, P, P, P, ctypes.POINTER(gi_batch),
+                                     ctypes.POINTER(gi_adam), P, P, P, P], ctypes.c_int),
+            "gi_fit_graph_create": ([P, P, P, P, P, I64, I32, I32, ctypes.POINTER(gi_batch),
+                                     ctypes.POINTER(gi_adam), P, P, P, P, ctypes.POINTER(P)],
+                                    ctypes.c_int),
+            "gi_fit_graph_launch": ([P, I32, P], ctypes.c_int),
+            "gi_fit_graph_destroy": ([P], ctypes.c_int),
+            "gi_binning": ([P, P, I64, I32, I32, P, P, P, P, P, I64, ctypes.POINTER(I64), P],
+                           ctypes.c_int),
+            "gi_scan_u32": ([P, P, P, I64, P, P], ctypes.c_int),
+            "gi_sort_pairs": ([P, P, P, P, P, I64, I32, P], ctypes.c_int),
+            "gi_get_option": ([P, ctypes.c_int, ctypes.POINTER(I64)], ctypes.c_int),
+            "gi_autotune": ([P, P, P, I64, I32, I32, ctypes.POINTER(gi_batch), I32, P,
+                             ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
+            "gi_timing": ([P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64),
+                           ctypes.c_int], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return lib().gi_status_string(status).decode()
+    except Exception:  # library missing: plain text
+        return str(status)

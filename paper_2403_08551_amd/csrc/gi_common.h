@@ -1,0 +1,168 @@
+// Internal declarations shared by the gfx950 kernels and the host runtime.
+//
+// Data layout in device memory (one context):
+//   params  [N][8]  f32   (mu_x, mu_y, l1, l2, l3, c0, c1, c2), caller owned
+//   proj    [N][8]  f32   (mu_x, mu_y, a, b, k, c0, c1, c2) with a = s/l1, b = s/l3,
+//                          k = s*l2/(l1*l3), s = sqrt(log2(e)/2): then u1 = a*dx and
+//                          u2 = b*dy - k*dx satisfy u1^2 + u2^2 = log2(e)*sigma, so that
+//                          exp(-sigma) = exp2(-(u1^2 + u2^2)) (Eq. rasterization2 through the
+//                          Cholesky factor: sigma = |L^{-1} d|^2 / 2)
+//   rect    [N]     int4  inclusive tile rectangle (tx0, ty0, tx1, ty1); (0, 0, -1, -1) if none
+//   tinfo   [N]     uint2 (first global tile id of the Gaussian's image, tiles across)
+//   count   [N]     u32   tiles covered;  off [N] u32 exclusive prefix sum of count
+//   keys/vals [cap] u32   (global tile id, Gaussian id), two ping-pong pairs for the sort
+//   rec     [cap][8] f32  proj records gathered into tile-sorted order
+//   slot    [cap]   u32   position of each sorted key in the unsorted (Gaussian-major) order
+//   part    [cap][8] f32  per (tile, Gaussian) partial gradient sums, indexed by slot
+//   ranges  [T]     uint2 [start, end) of each tile in the sorted order
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gi {
+
+constexpr int TILE = 16;
+constexpr int TILE_PX = TILE * TILE;
+constexpr uint32_t FLAG_KEY_OVERFLOW = 1u;
+constexpr uint32_t FLAG_NONFINITE = 2u;
+
+// sqrt(log2(e) / 2): scales L^{-1} d so that exp(-sigma) = exp2(-|u|^2)
+constexpr double U_SCALE = 0.84932180028801904272;
+
+// Device-resident scalars of one context.
+struct DevState {
+    unsigned long long keys_total;  // keys of the last binning (may exceed capacity)
+    uint32_t flags;                 // sticky FLAG_*
+    uint32_t pad;
+};
+
+// Image geometry, passed by value.  B == 1 uses the scalar fields; B > 1 reads the tables.
+struct ImgTable {
+    int32_t B;
+    int32_t H, W, TW;                 // single image
+    const int4 *dims;                 // [B] (H, W, TW, TH)
+    const uint32_t *tile_base;        // [B+1] first global tile id of each image
+    const uint32_t *gauss_off;        // [B+1]
+    const unsigned long long *pix_off;  // [B+1] first pixel of each image
+};
+
+struct TileInfo {
+    int32_t img, tx, ty, H, W;
+    unsigned long long pix_base;
+};
+
+__device__ inline int32_t upper_index(const uint32_t *arr, int32_t n, uint32_t v) {
+    // largest i in [0, n) with arr[i] <= v (arr ascending, arr[0] = 0)
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (arr[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline TileInfo tile_info(const ImgTable &t, uint32_t tile) {
+    TileInfo ti;
+    if (t.B == 1) {
+        ti.img = 0; ti.H = t.H; ti.W = t.W;
+        ti.tx = (int32_t)(tile % (uint32_t)t.TW);
+        ti.ty = (int32_t)(tile / (uint32_t)t.TW);
+        ti.pix_base = 0;
+    } else {
+        int32_t b = upper_index(t.tile_base, t.B, tile);
+        int4 d = t.dims[b];
+        uint32_t lt = tile - t.tile_base[b];
+        ti.img = b; ti.H = d.x; ti.W = d.y;
+        ti.tx = (int32_t)(lt % (uint32_t)d.z);
+        ti.ty = (int32_t)(lt / (uint32_t)d.z);
+        ti.pix_base = t.pix_off[b];
+    }
+    return ti;
+}
+
+// ---- host-side launchers (defined next to their kernels) ------------------------------------
+
+struct BinBuffers {
+    const float *params;
+    int64_t n;
+    float *proj;
+    int4 *rect;
+    uint2 *tinfo;
+    uint32_t *count;
+    uint32_t *off;
+    unsigned long long *blocksum;  // [ceil(n/256)]
+    uint32_t *keys[2];
+    uint32_t *vals[2];
+    float *rec;
+    uint32_t *slot;
+    uint2 *ranges;
+    int64_t n_tiles;
+    int64_t cap;
+    DevState *state;
+    // sort scratch
+    uint32_t *hist;                 // [2^bits * max_sort_blocks]
+    unsigned long long *scan_blocksum;  // generic scan scratch
+    int64_t hist_cap;               // entries available in hist
+    int64_t scan_cap;               // entries available in scan_blocksum
+};
+
+hipError_t launch_project(const BinBuffers &b, const ImgTable &tab, hipStream_t s);
+hipError_t launch_count_scan(const BinBuffers &b, hipStream_t s);
+hipError_t launch_duplicate(const BinBuffers &b, hipStream_t s);
+// Sort keys[0]/vals[0] -> result in keys[r]/vals[r]; returns r through *which.  n_max bounds
+// the key count (the device total is read by the kernels); key_bits > 0.
+hipError_t launch_sort(const BinBuffers &b, int key_bits, int digit_bits, int64_t n_max,
+                       int *which, hipStream_t s);
+hipError_t launch_ranges_gather(const BinBuffers &b, int which, const ImgTable &tab,
+                                int64_t n_max, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+// generic pieces, also exported for testing
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n,
+                           unsigned long long *blocksum, unsigned long long *total,
+                           hipStream_t s);
+int64_t scan_scratch_entries(int64_t n);
+hipError_t launch_sort_pairs(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                             uint32_t *vout, uint32_t *ktmp, uint32_t *vtmp, int64_t n,
+                             const unsigned long long *n_dev, int key_bits, int digit_bits,
+                             uint32_t *hist, unsigned long long *scan_bs, int *which_out,
+                             hipStream_t s);
+int64_t sort_hist_entries(int64_t n, int digit_bits);
+int auto_digit_bits(int key_bits, int64_t n);
+
+struct RasterArgs {
+    const float *rec;
+    const uint32_t *slot;
+    const uint2 *ranges;
+    int64_t n_tiles;
+    ImgTable tab;
+};
+
+hipError_t launch_raster_fwd(const RasterArgs &a, float *image, int px_per_lane, hipStream_t s);
+hipError_t launch_raster_bwd(const RasterArgs &a, const float *dl_dimage, float *part,
+                             hipStream_t s);
+hipError_t launch_raster_fit(const RasterArgs &a, const float *target, float *part,
+                             float *image_out, float *loss_part, int px_per_lane, hipStream_t s);
+
+struct UpdateArgs {
+    const float *params_in;  // read (l1, l2, l3) and, for Adam, updated in place
+    float *params_out;
+    int64_t n;
+    const uint32_t *count;
+    const uint32_t *off;
+    const float *part;
+    const DevState *state;
+    int64_t cap;
+};
+hipError_t launch_grad_out(const UpdateArgs &u, float *dparams, hipStream_t s);
+struct AdamArgs {
+    float lr_mu, lr_l, lr_c, beta1, beta2, eps, l_min;
+};
+hipError_t launch_adam(const UpdateArgs &u, float *params, float *m, float *v,
+                       int32_t *step, const AdamArgs &hp, hipStream_t s);
+// Per-image loss from the per-tile sums (when loss_out != nullptr) and step += 1 (when
+// step != nullptr).
+hipError_t launch_finish(const float *loss_part, const ImgTable &tab, int64_t n_tiles,
+                         float *loss_out, int32_t *step, hipStream_t s);
+
+}  // namespace gi

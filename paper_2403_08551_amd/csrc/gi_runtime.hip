@@ -1,0 +1,960 @@
+// Host runtime behind include/gi.h: argument checks, the context workspace, the order of the
+// stages for render / grad / fit (single image and batched), captured fit steps, and the
+// inspection entry points for the binning stages.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gi.h"
+#include "gi_common.h"
+
+using namespace gi;
+
+struct gi_ctx {
+    int device = 0;
+    int sync = 1;
+    int sort_bits = 0;
+    int fwd_px = 0;
+    int binning = 0;
+    int64_t cap_n = 0, cap_t = 0, cap_k = 0;
+    int64_t last_keys = 0;
+    // per Gaussian
+    float *proj = nullptr;
+    int4 *rect = nullptr;
+    uint2 *tinfo = nullptr;
+    uint32_t *count = nullptr;
+    uint32_t *off = nullptr;
+    unsigned long long *blocksum = nullptr;
+    // per key
+    uint32_t *keys[2] = {nullptr, nullptr};
+    uint32_t *vals[2] = {nullptr, nullptr};
+    float *rec = nullptr;
+    uint32_t *slot = nullptr;
+    float *part = nullptr;
+    uint32_t *hist = nullptr;
+    int64_t hist_cap = 0;
+    unsigned long long *scan_bs = nullptr;
+    int64_t scan_cap = 0;
+    // per tile
+    uint2 *ranges = nullptr;
+    float *loss_part = nullptr;
+    // scalars
+    DevState *state = nullptr;
+    unsigned long long *pinned = nullptr;
+    // batch tables
+    int32_t batch_cap = 0;
+    int4 *dims = nullptr;
+    uint32_t *tile_base = nullptr;
+    uint32_t *gauss_off = nullptr;
+    unsigned long long *pix_off = nullptr;
+    std::vector<int64_t> batch_sig;  // host copy of the uploaded layout
+    // scratch for gi_sort_pairs / gi_scan_u32
+    uint32_t *tmp_k = nullptr, *tmp_v = nullptr;
+    int64_t tmp_cap = 0;
+    hipStream_t capture_stream = nullptr;
+    std::string err;
+    // stage timing (GI_OPT_TIMING)
+    int timing = 0;
+    struct Pending {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    double stage_ms[GI_STAGE_COUNT] = {0, 0, 0, 0, 0};
+    int64_t stage_n[GI_STAGE_COUNT] = {0, 0, 0, 0, 0};
+    // autotuned settings per size class: (Gaussian class, pixel class) -> (pixels/lane, digit)
+    std::map<std::pair<int, int>, std::pair<int, int>> tuned;
+};
+
+struct gi_graph {
+    gi_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr int32_t MAX_SIDE = 32768;
+constexpr int64_t MAX_KEYS = (int64_t)1 << 31;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int hip_fail(gi_ctx *c, hipError_t e, const char *what) {
+    if (c) {
+        c->err = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return GI_ERR_HIP;
+}
+
+#define CK(expr)                                                  \
+    do {                                                          \
+        hipError_t e_ = (expr);                                   \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr);    \
+    } while (0)
+
+template <typename T>
+hipError_t grow(T **p, int64_t count) {
+    if (*p) {
+        hipError_t e = hipFree(*p);
+        *p = nullptr;
+        if (e != hipSuccess) return e;
+    }
+    if (count <= 0) count = 1;
+    return hipMalloc((void **)p, sizeof(T) * (size_t)count);
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int key_bits_for(int64_t n_tiles) {
+    int b = 1;
+    while (((int64_t)1 << b) < n_tiles) ++b;
+    return b;
+}
+
+// Events bracketing one stage of a non-captured call (GI_OPT_TIMING).
+struct StageTimer {
+    gi_ctx *ctx;
+    hipStream_t s;
+    int stage;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(gi_ctx *c, hipStream_t st, int stg) : ctx(c), s(st), stage(stg) {
+        if (!ctx->timing) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+        a = take();
+        b = take();
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    hipEvent_t take() {
+        if (!ctx->event_pool.empty()) {
+            hipEvent_t e = ctx->event_pool.back();
+            ctx->event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void stop() {
+        if (a && b) {
+            (void)hipEventRecord(b, s);
+            ctx->pending.push_back({stage, a, b});
+            a = b = nullptr;
+        }
+    }
+    ~StageTimer() {
+        if (a) ctx->event_pool.push_back(a);
+        if (b) ctx->event_pool.push_back(b);
+    }
+};
+
+int ensure_gauss(gi_ctx *ctx, int64_t n) {
+    if (n <= ctx->cap_n) return GI_OK;
+    const int64_t c = std::max<int64_t>(n, 1024);
+    CK(hipDeviceSynchronize());
+    CK(grow(&ctx->proj, 8 * c));
+    CK(grow(&ctx->rect, c));
+    CK(grow(&ctx->tinfo, c));
+    CK(grow(&ctx->count, c));
+    CK(grow(&ctx->off, c));
+    CK(grow(&ctx->blocksum, (c + 255) / 256 + 1));
+    ctx->cap_n = c;
+    return GI_OK;
+}
+
+int ensure_tiles(gi_ctx *ctx, int64_t t) {
+    if (t <= ctx->cap_t) return GI_OK;
+    const int64_t c = std::max<int64_t>(t, 256);
+    CK(hipDeviceSynchronize());
+    CK(grow(&ctx->ranges, c));
+    CK(grow(&ctx->loss_part, c));
+    ctx->cap_t = c;
+    return GI_OK;
+}
+
+int ensure_keys(gi_ctx *ctx, int64_t k) {
+    if (k <= ctx->cap_k) return GI_OK;
+    if (k > MAX_KEYS) return GI_ERR_CAPACITY;
+    const int64_t c = std::min<int64_t>(std::max<int64_t>(k, 4096), MAX_KEYS);
+    CK(hipDeviceSynchronize());
+    for (int i = 0; i < 2; ++i) {
+        CK(grow(&ctx->keys[i], c));
+        CK(grow(&ctx->vals[i], c));
+    }
+    CK(grow(&ctx->rec, 8 * c));
+    CK(grow(&ctx->slot, c));
+    CK(grow(&ctx->part, 8 * c));
+    const int64_t hc = sort_hist_entries(c, 11);
+    CK(grow(&ctx->hist, hc));
+    ctx->hist_cap = hc;
+    const int64_t sc = scan_scratch_entries(hc) + 1;
+    CK(grow(&ctx->scan_bs, sc));
+    ctx->scan_cap = sc;
+    ctx->cap_k = c;
+    return GI_OK;
+}
+
+// Upload the batch tables when the layout differs from the last one uploaded.
+int upload_batch(gi_ctx *ctx, const gi_batch *b, ImgTable *tab, int64_t *n_tiles,
+                 int64_t *n_gauss, int64_t *n_pix) {
+    const int32_t B = b->count;
+    std::vector<int4> dims(B);
+    std::vector<uint32_t> tb(B + 1), go(B + 1);
+    std::vector<unsigned long long> po(B + 1);
+    int64_t t = 0, p = 0;
+    for (int32_t i = 0; i < B; ++i) {
+        const int32_t H = b->height_host[i], W = b->width_host[i];
+        const int32_t TW = (W + TILE - 1) / TILE, TH = (H + TILE - 1) / TILE;
+        dims[i] = make_int4(H, W, TW, TH);
+        tb[i] = (uint32_t)t;
+        po[i] = (unsigned long long)p;
+        go[i] = (uint32_t)b->gauss_off_host[i];
+        t += (int64_t)TW * TH;
+        p += (int64_t)H * W;
+    }
+    tb[B] = (uint32_t)t;
+    po[B] = (unsigned long long)p;
+    go[B] = (uint32_t)b->gauss_off_host[B];
+    std::vector<int64_t> sig;
+    sig.reserve(3 * B + 2);
+    sig.push_back(B);
+    for (int32_t i = 0; i < B; ++i) {
+        sig.push_back(b->height_host[i]);
+        sig.push_back(b->width_host[i]);
+    }
+    for (int32_t i = 0; i <= B; ++i) sig.push_back(b->gauss_off_host[i]);
+    if (sig != ctx->batch_sig) {
+        if (B > ctx->batch_cap) {
+            CK(hipDeviceSynchronize());
+            CK(grow(&ctx->dims, B));
+            CK(grow(&ctx->tile_base, B + 1));
+            CK(grow(&ctx->gauss_off, B + 1));
+            CK(grow(&ctx->pix_off, B + 1));
+            ctx->batch_cap = B;
+        }
+        CK(hipDeviceSynchronize());
+        CK(hipMemcpy(ctx->dims, dims.data(), sizeof(int4) * B, hipMemcpyHostToDevice));
+        CK(hipMemcpy(ctx->tile_base, tb.data(), sizeof(uint32_t) * (B + 1), hipMemcpyHostToDevice));
+        CK(hipMemcpy(ctx->gauss_off, go.data(), sizeof(uint32_t) * (B + 1), hipMemcpyHostToDevice));
+        CK(hipMemcpy(ctx->pix_off, po.data(), sizeof(unsigned long long) * (B + 1),
+                     hipMemcpyHostToDevice));
+        ctx->batch_sig = sig;
+    }
+    tab->B = B;
+    tab->H = B == 1 ? b->height_host[0] : 0;
+    tab->W = B == 1 ? b->width_host[0] : 0;
+    tab->TW = B == 1 ? (tab->W + TILE - 1) / TILE : 0;
+    tab->dims = ctx->dims;
+    tab->tile_base = ctx->tile_base;
+    tab->gauss_off = ctx->gauss_off;
+    tab->pix_off = ctx->pix_off;
+    if (B == 1) {
+        // single images read the scalar fields; the tables stay valid for B == 1 as well
+    }
+    *n_tiles = t;
+    *n_gauss = b->gauss_off_host[B];
+    *n_pix = p;
+    return GI_OK;
+}
+
+int check_batch(const gi_batch *b) {
+    if (!b || b->count < 1 || !b->height_host || !b->width_host || !b->gauss_off_host)
+        return GI_ERR_INVALID_ARG;
+    if (b->gauss_off_host[0] != 0) return GI_ERR_INVALID_ARG;
+    int64_t t = 0;
+    for (int32_t i = 0; i < b->count; ++i) {
+        const int32_t H = b->height_host[i], W = b->width_host[i];
+        if (H < 1 || W < 1 || H > MAX_SIDE || W > MAX_SIDE) return GI_ERR_INVALID_ARG;
+        if (b->gauss_off_host[i + 1] < b->gauss_off_host[i]) return GI_ERR_INVALID_ARG;
+        t += (int64_t)((W + TILE - 1) / TILE) * ((H + TILE - 1) / TILE);
+    }
+    if (b->gauss_off_host[b->count] >= ((int64_t)1 << 31)) return GI_ERR_INVALID_ARG;
+    if (t >= ((int64_t)1 << 31)) return GI_ERR_INVALID_ARG;
+    return GI_OK;
+}
+
+int check_single(int64_t n, int32_t H, int32_t W) {
+    if (n < 0 || n >= ((int64_t)1 << 31)) return GI_ERR_INVALID_ARG;
+    if (H < 1 || W < 1 || H > MAX_SIDE || W > MAX_SIDE) return GI_ERR_INVALID_ARG;
+    return GI_OK;
+}
+
+ImgTable single_table(int32_t H, int32_t W) {
+    ImgTable t;
+    memset(&t, 0, sizeof(t));
+    t.B = 1;
+    t.H = H;
+    t.W = W;
+    t.TW = (W + TILE - 1) / TILE;
+    return t;
+}
+
+std::pair<int, int> size_class(int64_t n, int64_t n_pix) {
+    auto cls = [](int64_t v) { return (int)std::lround(2.0 * std::log2((double)std::max<int64_t>(v, 1))); };
+    return {cls(n), cls(n_pix)};
+}
+
+int pick_px(gi_ctx *ctx, int64_t n, int64_t n_pix) {
+    if (ctx->fwd_px) return ctx->fwd_px;
+    auto it = ctx->tuned.find(size_class(n, n_pix));
+    return it != ctx->tuned.end() ? it->second.first : 2;
+}
+
+int pick_digit(gi_ctx *ctx, int64_t n, int64_t n_pix, int key_bits, int64_t keys) {
+    if (ctx->sort_bits) return ctx->sort_bits;
+    auto it = ctx->tuned.find(size_class(n, n_pix));
+    if (it != ctx->tuned.end() && it->second.second) return it->second.second;
+    return auto_digit_bits(key_bits, keys);
+}
+
+int64_t table_pixels(const ImgTable &tab, int64_t n_tiles) {
+    // pixel count used only for the size class: exact for one image, tile area for batches
+    return tab.B == 1 ? (int64_t)tab.H * tab.W : n_tiles * TILE_PX;
+}
+
+BinBuffers bin_buffers(gi_ctx *ctx, const float *params, int64_t n, int64_t n_tiles) {
+    BinBuffers b;
+    b.params = params;
+    b.n = n;
+    b.proj = ctx->proj;
+    b.rect = ctx->rect;
+    b.tinfo = ctx->tinfo;
+    b.count = ctx->count;
+    b.off = ctx->off;
+    b.blocksum = ctx->blocksum;
+    b.keys[0] = ctx->keys[0];
+    b.keys[1] = ctx->keys[1];
+    b.vals[0] = ctx->vals[0];
+    b.vals[1] = ctx->vals[1];
+    b.rec = ctx->rec;
+    b.slot = ctx->slot;
+    b.ranges = ctx->ranges;
+    b.n_tiles = n_tiles;
+    b.cap = ctx->cap_k;
+    b.state = ctx->state;
+    b.hist = ctx->hist;
+    b.scan_blocksum = ctx->scan_bs;
+    b.hist_cap = ctx->hist_cap;
+    b.scan_cap = ctx->scan_cap;
+    return b;
+}
+
+// Projection, scan, duplication, sort, ranges and gather.  *bound receives the key bound the
+// later kernels are sized for; *which the ping-pong buffer holding the sorted pairs.
+int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab,
+                int64_t n_tiles, hipStream_t s, int64_t *bound, int *which) {
+    int rc;
+    if ((rc = ensure_gauss(ctx, n)) != GI_OK) return rc;
+    if ((rc = ensure_tiles(ctx, n_tiles)) != GI_OK) return rc;
+    if (ctx->cap_k == 0 && (rc = ensure_keys(ctx, 4096)) != GI_OK) return rc;
+    BinBuffers b = bin_buffers(ctx, params, n, n_tiles);
+    StageTimer tm(ctx, s, GI_STAGE_BINNING);
+    CK(launch_project(b, tab, s));
+    CK(launch_count_scan(b, s));
+    int64_t K = ctx->cap_k;
+    if (ctx->sync) {
+        CK(hipMemcpyAsync(ctx->pinned, &ctx->state->keys_total, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        K = (int64_t)*ctx->pinned;
+        ctx->last_keys = K;
+        if (K > MAX_KEYS) return GI_ERR_CAPACITY;
+        if (K > ctx->cap_k) {
+            if ((rc = ensure_keys(ctx, K + K / 4)) != GI_OK) return rc;
+            b = bin_buffers(ctx, params, n, n_tiles);
+        }
+    }
+    CK(launch_duplicate(b, s));
+    const int kb = key_bits_for(n_tiles);
+    const int digit = pick_digit(ctx, n, table_pixels(tab, n_tiles), kb, K);
+    CK(launch_sort(b, kb, digit, K, which, s));
+    CK(launch_ranges_gather(b, *which, tab, K, s));
+    tm.stop();
+    *bound = K;
+    return GI_OK;
+}
+
+
+int do_render(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab, int64_t n_tiles,
+              float *image, hipStream_t s) {
+    int64_t bound;
+    int which;
+    int rc = run_binning(ctx, params, n, tab, n_tiles, s, &bound, &which);
+    if (rc != GI_OK) return rc;
+    RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
+    StageTimer tm(ctx, s, GI_STAGE_RASTER_FWD);
+    CK(launch_raster_fwd(a, image, pick_px(ctx, n, table_pixels(tab, n_tiles)), s));
+    tm.stop();
+    return GI_OK;
+}
+
+int do_grad(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab, int64_t n_tiles,
+            const float *dl, float *dparams, hipStream_t s) {
+    int64_t bound;
+    int which;
+    int rc = run_binning(ctx, params, n, tab, n_tiles, s, &bound, &which);
+    if (rc != GI_OK) return rc;
+    RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
+    StageTimer tm(ctx, s, GI_STAGE_RASTER_BWD);
+    CK(launch_raster_bwd(a, dl, ctx->part, s));
+    tm.stop();
+    UpdateArgs u{params, nullptr, n, ctx->count, ctx->off, ctx->part, ctx->state, ctx->cap_k};
+    StageTimer tu(ctx, s, GI_STAGE_UPDATE);
+    CK(launch_grad_out(u, dparams, s));
+    tu.stop();
+    return GI_OK;
+}
+
+int do_fit(gi_ctx *ctx, float *params, float *m, float *v, const float *target, int64_t n,
+           const ImgTable &tab, int64_t n_tiles, const gi_adam *hp, int32_t *step,
+           float *image_out, float *loss_out, hipStream_t s) {
+    int64_t bound;
+    int which;
+    int rc = run_binning(ctx, params, n, tab, n_tiles, s, &bound, &which);
+    if (rc != GI_OK) return rc;
+    RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
+    StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
+    CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
+                         pick_px(ctx, n, table_pixels(tab, n_tiles)), s));
+    tm.stop();
+    UpdateArgs u{params, params, n, ctx->count, ctx->off, ctx->part, ctx->state, ctx->cap_k};
+    AdamArgs h{hp->lr_mu, hp->lr_l, hp->lr_c, hp->beta1, hp->beta2, hp->eps, hp->l_min};
+    StageTimer tu(ctx, s, GI_STAGE_UPDATE);
+    CK(launch_adam(u, params, m, v, step, h, s));
+    tu.stop();
+    CK(launch_finish(ctx->loss_part, tab, n_tiles, loss_out, step, s));
+    return GI_OK;
+}
+
+int check_adam(const gi_adam *hp) {
+    if (!hp) return GI_ERR_INVALID_ARG;
+    if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f && hp->beta2 >= 0.f && hp->beta2 < 1.f))
+        return GI_ERR_INVALID_ARG;
+    if (!(hp->eps >= 0.f) || !(hp->l_min >= 0.f)) return GI_ERR_INVALID_ARG;
+    return GI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gi_status_string(int status) {
+    switch (status) {
+        case GI_OK: return "ok";
+        case GI_ERR_INVALID_ARG: return "invalid argument";
+        case GI_ERR_CAPACITY: return "key capacity exceeded";
+        case GI_ERR_HIP: return "HIP runtime error";
+        case GI_ERR_NONFINITE: return "non-finite parameter";
+        case GI_ERR_UNSUPPORTED: return "unsupported request";
+        case GI_ERR_NO_DEVICE: return "no usable gfx950 device";
+        default: return "unknown status";
+    }
+}
+
+const char *gi_last_error(gi_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int gi_create(gi_ctx **out, int device) {
+    if (!out) return GI_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return GI_ERR_NO_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return GI_ERR_NO_DEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return GI_ERR_NO_DEVICE;
+    DeviceGuard g(device);
+    gi_ctx *ctx = new gi_ctx();
+    ctx->device = device;
+    hipError_t e = hipMalloc((void **)&ctx->state, sizeof(DevState));
+    if (e == hipSuccess) e = hipMemset(ctx->state, 0, sizeof(DevState));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->pinned, sizeof(unsigned long long) * 2);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        gi_destroy(ctx);
+        return GI_ERR_HIP;
+    }
+    *out = ctx;
+    return GI_OK;
+}
+
+int gi_destroy(gi_ctx *ctx) {
+    if (!ctx) return GI_OK;
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    void *bufs[] = {ctx->proj, ctx->rect, ctx->tinfo, ctx->count, ctx->off, ctx->blocksum,
+                    ctx->keys[0], ctx->keys[1], ctx->vals[0], ctx->vals[1], ctx->rec, ctx->slot,
+                    ctx->part, ctx->hist, ctx->scan_bs, ctx->ranges, ctx->loss_part, ctx->state,
+                    ctx->dims, ctx->tile_base, ctx->gauss_off, ctx->pix_off, ctx->tmp_k,
+                    ctx->tmp_v};
+    for (void *p : bufs)
+        if (p) (void)hipFree(p);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (auto &p : ctx->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    delete ctx;
+    return GI_OK;
+}
+
+int gi_set_option(gi_ctx *ctx, int option, int64_t value) {
+    if (!ctx) return GI_ERR_INVALID_ARG;
+    switch (option) {
+        case GI_OPT_SYNC:
+            if (value != 0 && value != 1) return GI_ERR_INVALID_ARG;
+            ctx->sync = (int)value;
+            return GI_OK;
+        case GI_OPT_SORT_BITS:
+            if (value < 0 || value > 11) return GI_ERR_INVALID_ARG;
+            ctx->sort_bits = (int)value;
+            return GI_OK;
+        case GI_OPT_FWD_PIXELS:
+            if (value != 0 && value != 1 && value != 2 && value != 4) return GI_ERR_INVALID_ARG;
+            ctx->fwd_px = (int)value;
+            return GI_OK;
+        case GI_OPT_BINNING:
+            if (value < 0 || value > 2) return GI_ERR_INVALID_ARG;
+            ctx->binning = (int)value;
+            return GI_OK;
+        case GI_OPT_TIMING:
+            if (value != 0 && value != 1) return GI_ERR_INVALID_ARG;
+            ctx->timing = (int)value;
+            return GI_OK;
+        default:
+            return GI_ERR_INVALID_ARG;
+    }
+}
+
+int gi_reserve(gi_ctx *ctx, int64_t n_gauss, int64_t n_tiles, int64_t key_capacity) {
+    if (!ctx || n_gauss < 0 || n_tiles < 0 || key_capacity < 0) return GI_ERR_INVALID_ARG;
+    if (key_capacity > MAX_KEYS) return GI_ERR_CAPACITY;
+    DeviceGuard g(ctx->device);
+    int rc;
+    if ((rc = ensure_gauss(ctx, n_gauss)) != GI_OK) return rc;
+    if ((rc = ensure_tiles(ctx, n_tiles)) != GI_OK) return rc;
+    if ((rc = ensure_keys(ctx, key_capacity)) != GI_OK) return rc;
+    return GI_OK;
+}
+
+int gi_query(gi_ctx *ctx, int64_t *last_keys, uint32_t *flags, int clear) {
+    if (!ctx) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    CK(hipDeviceSynchronize());
+    DevState st;
+    CK(hipMemcpy(&st, ctx->state, sizeof(st), hipMemcpyDeviceToHost));
+    if (last_keys) *last_keys = (int64_t)st.keys_total;
+    if (flags) *flags = st.flags;
+    if (clear) {
+        st.flags = 0;
+        CK(hipMemcpy(&ctx->state->flags, &st.flags, sizeof(uint32_t), hipMemcpyHostToDevice));
+    }
+    return GI_OK;
+}
+
+int gi_get_option(gi_ctx *ctx, int option, int64_t *value) {
+    if (!ctx || !value) return GI_ERR_INVALID_ARG;
+    switch (option) {
+        case GI_OPT_SYNC: *value = ctx->sync; return GI_OK;
+        case GI_OPT_SORT_BITS: *value = ctx->sort_bits; return GI_OK;
+        case GI_OPT_FWD_PIXELS: *value = ctx->fwd_px; return GI_OK;
+        case GI_OPT_BINNING: *value = ctx->binning; return GI_OK;
+        case GI_OPT_TIMING: *value = ctx->timing; return GI_OK;
+        default: return GI_ERR_INVALID_ARG;
+    }
+}
+
+int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n, int32_t H,
+                int32_t W, const gi_batch *batch, int32_t reps, void *stream,
+                int32_t *fwd_pixels, int32_t *sort_bits) {
+    if (!ctx || !target || reps < 1 || reps > 1000) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    ImgTable tab;
+    int64_t T, n_pix;
+    if (batch) {
+        if (check_batch(batch) != GI_OK) return GI_ERR_INVALID_ARG;
+        n = batch->gauss_off_host[batch->count];
+        int64_t N;
+        int rc = upload_batch(ctx, batch, &tab, &T, &N, &n_pix);
+        if (rc != GI_OK) return rc;
+    } else {
+        if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+        tab = single_table(H, W);
+        T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+        n_pix = (int64_t)H * W;
+    }
+    if (n > 0 && (!params || !aligned16(params))) return GI_ERR_INVALID_ARG;
+    const std::pair<int, int> key = size_class(n, table_pixels(tab, T));
+    // scratch state: the caller's parameters are copied, never written
+    float *p = nullptr, *m = nullptr, *v = nullptr;
+    int32_t *step = nullptr;
+    const size_t bytes = sizeof(float) * 8 * (size_t)std::max<int64_t>(n, 1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = GI_OK;
+    struct Saved { int sync, px, bits, timing; } sv{ctx->sync, ctx->fwd_px, ctx->sort_bits, ctx->timing};
+    auto cleanup = [&]() {
+        if (p) (void)hipFree(p);
+        if (m) (void)hipFree(m);
+        if (v) (void)hipFree(v);
+        if (step) (void)hipFree(step);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        ctx->sync = sv.sync; ctx->fwd_px = sv.px; ctx->sort_bits = sv.bits; ctx->timing = sv.timing;
+    };
+    hipError_t e = hipMalloc((void **)&p, bytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&m, bytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&v, bytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&step, sizeof(int32_t));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(ctx, e, "gi_autotune scratch");
+    }
+    gi_adam hp{0.f, 0.f, 0.f, 0.9f, 0.999f, 1e-8f, 0.f};  // zero rates: the state stays fixed
+    const int pxs[3] = {1, 2, 4};
+    const int bits[5] = {0, 4, 6, 8, 11};
+    float best = 1e30f;
+    int best_px = 2, best_bits = 0;
+    ctx->timing = 0;
+    // one synchronous pass sizes the workspace, then steps do not wait on the host
+    ctx->sync = 1;
+    int64_t bound;
+    int which;
+    rc = run_binning(ctx, params, n, tab, T, s, &bound, &which);
+    if (rc == GI_OK) rc = ensure_keys(ctx, bound + bound / 4 + 4096);
+    ctx->sync = 0;
+    for (int bi = 0; bi < 5 && rc == GI_OK; ++bi) {
+        for (int pi = 0; pi < 3 && rc == GI_OK; ++pi) {
+            ctx->fwd_px = pxs[pi];
+            ctx->sort_bits = bits[bi];
+            if (bits[bi] > key_bits_for(T) + 3) continue;
+            e = hipMemcpyAsync(p, params, bytes, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipMemsetAsync(m, 0, bytes, s);
+            if (e == hipSuccess) e = hipMemsetAsync(v, 0, bytes, s);
+            const int32_t one = 1;
+            if (e == hipSuccess) e = hipMemcpyAsync(step, &one, sizeof(one), hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) { rc = hip_fail(ctx, e, "gi_autotune copy"); break; }
+            rc = do_fit(ctx, p, m, v, target, n, tab, T, &hp, step, nullptr, nullptr, s);
+            if (rc != GI_OK) break;
+            e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && rc == GI_OK && e == hipSuccess; ++r)
+                rc = do_fit(ctx, p, m, v, target, n, tab, T, &hp, step, nullptr, nullptr, s);
+            if (rc != GI_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { rc = hip_fail(ctx, e, "gi_autotune timing"); break; }
+            if (ms < best) {
+                best = ms;
+                best_px = pxs[pi];
+                best_bits = bits[bi];
+            }
+        }
+    }
+    if (rc == GI_OK) {
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = hip_fail(ctx, e, "gi_autotune sync");
+    }
+    cleanup();
+    if (rc != GI_OK) return rc;
+    ctx->tuned[key] = {best_px, best_bits};
+    if (fwd_pixels) *fwd_pixels = best_px;
+    if (sort_bits) *sort_bits = best_bits;
+    (void)n_pix;
+    return GI_OK;
+}
+
+int gi_timing(gi_ctx *ctx, int stage, double *total_ms, int64_t *launches, int reset) {
+    if (!ctx || stage < 0 || stage >= GI_STAGE_COUNT) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    for (auto &p : ctx->pending) {
+        CK(hipEventSynchronize(p.b));
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, p.a, p.b));
+        ctx->stage_ms[p.stage] += ms;
+        ctx->stage_n[p.stage] += 1;
+        ctx->event_pool.push_back(p.a);
+        ctx->event_pool.push_back(p.b);
+    }
+    ctx->pending.clear();
+    if (total_ms) *total_ms = ctx->stage_ms[stage];
+    if (launches) *launches = ctx->stage_n[stage];
+    if (reset) {
+        for (int i = 0; i < GI_STAGE_COUNT; ++i) {
+            ctx->stage_ms[i] = 0.0;
+            ctx->stage_n[i] = 0;
+        }
+    }
+    return GI_OK;
+}
+
+int gi_render(gi_ctx *ctx, const float *params, int64_t n, int32_t H, int32_t W, float *image,
+              void *stream) {
+    if (!ctx || !image || (n > 0 && !params)) return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    if (n > 0 && !aligned16(params)) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    const ImgTable tab = single_table(H, W);
+    const int64_t T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    return do_render(ctx, params, n, tab, T, image, (hipStream_t)stream);
+}
+
+int gi_grad(gi_ctx *ctx, const float *params, int64_t n, int32_t H, int32_t W,
+            const float *dl_dimage, float *dparams, void *stream) {
+    if (!ctx || !dl_dimage || (n > 0 && (!params || !dparams))) return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!aligned16(params) || !aligned16(dparams))) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    const ImgTable tab = single_table(H, W);
+    const int64_t T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    return do_grad(ctx, params, n, tab, T, dl_dimage, dparams, (hipStream_t)stream);
+}
+
+int gi_fit_step(gi_ctx *ctx, float *params, float *m, float *v, const float *target, int64_t n,
+                int32_t H, int32_t W, const gi_adam *hp, int32_t *step, float *image_out,
+                float *loss_out, void *stream) {
+    if (!ctx || !target || !step || (n > 0 && (!params || !m || !v))) return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK || check_adam(hp) != GI_OK) return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!aligned16(params) || !aligned16(m) || !aligned16(v))) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    const ImgTable tab = single_table(H, W);
+    const int64_t T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    return do_fit(ctx, params, m, v, target, n, tab, T, hp, step, image_out, loss_out,
+                  (hipStream_t)stream);
+}
+
+int gi_render_batched(gi_ctx *ctx, const float *params, const gi_batch *batch, float *images,
+                      void *stream) {
+    if (!ctx || !images || check_batch(batch) != GI_OK) return GI_ERR_INVALID_ARG;
+    const int64_t n = batch->gauss_off_host[batch->count];
+    if (n > 0 && (!params || !aligned16(params))) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    ImgTable tab;
+    int64_t T, N, P;
+    int rc = upload_batch(ctx, batch, &tab, &T, &N, &P);
+    if (rc != GI_OK) return rc;
+    return do_render(ctx, params, n, tab, T, images, (hipStream_t)stream);
+}
+
+int gi_grad_batched(gi_ctx *ctx, const float *params, const gi_batch *batch, const float *dl,
+                    float *dparams, void *stream) {
+    if (!ctx || !dl || check_batch(batch) != GI_OK) return GI_ERR_INVALID_ARG;
+    const int64_t n = batch->gauss_off_host[batch->count];
+    if (n > 0 && (!params || !dparams || !aligned16(params) || !aligned16(dparams)))
+        return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    ImgTable tab;
+    int64_t T, N, P;
+    int rc = upload_batch(ctx, batch, &tab, &T, &N, &P);
+    if (rc != GI_OK) return rc;
+    return do_grad(ctx, params, n, tab, T, dl, dparams, (hipStream_t)stream);
+}
+
+int gi_fit_step_batched(gi_ctx *ctx, float *params, float *m, float *v, const float *targets,
+                        const gi_batch *batch, const gi_adam *hp, int32_t *step,
+                        float *images_out, float *loss_out, void *stream) {
+    if (!ctx || !targets || !step || check_batch(batch) != GI_OK || check_adam(hp) != GI_OK)
+        return GI_ERR_INVALID_ARG;
+    const int64_t n = batch->gauss_off_host[batch->count];
+    if (n > 0 && (!params || !m || !v || !aligned16(params) || !aligned16(m) || !aligned16(v)))
+        return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    ImgTable tab;
+    int64_t T, N, P;
+    int rc = upload_batch(ctx, batch, &tab, &T, &N, &P);
+    if (rc != GI_OK) return rc;
+    return do_fit(ctx, params, m, v, targets, n, tab, T, hp, step, images_out, loss_out,
+                  (hipStream_t)stream);
+}
+
+int gi_fit_graph_create(gi_ctx *ctx, float *params, float *m, float *v, const float *target,
+                        int64_t n, int32_t H, int32_t W, const gi_batch *batch,
+                        const gi_adam *hp, int32_t *step, float *image_out, float *loss_out,
+                        void *stream, gi_graph **out) {
+    if (!out) return GI_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!ctx || !target || !step || check_adam(hp) != GI_OK) return GI_ERR_INVALID_ARG;
+    ImgTable tab;
+    int64_t T;
+    DeviceGuard g(ctx->device);
+    if (batch) {
+        if (check_batch(batch) != GI_OK) return GI_ERR_INVALID_ARG;
+        n = batch->gauss_off_host[batch->count];
+        int64_t N, P;
+        int rc = upload_batch(ctx, batch, &tab, &T, &N, &P);
+        if (rc != GI_OK) return rc;
+    } else {
+        if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+        tab = single_table(H, W);
+        T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    }
+    if (n > 0 && (!params || !m || !v || !aligned16(params) || !aligned16(m) || !aligned16(v)))
+        return GI_ERR_INVALID_ARG;
+    // one synchronous binning pass sizes the workspace: keys with a 25% margin
+    hipStream_t s = (hipStream_t)stream;
+    const int saved_sync = ctx->sync;
+    ctx->sync = 1;
+    int64_t bound;
+    int which;
+    int rc = run_binning(ctx, params, n, tab, T, s, &bound, &which);
+    if (rc == GI_OK) rc = ensure_keys(ctx, bound + bound / 4 + 4096);
+    if (rc != GI_OK) {
+        ctx->sync = saved_sync;
+        return rc;
+    }
+    CK(hipStreamSynchronize(s));
+    ctx->sync = 0;
+    gi_graph *gr = new gi_graph();
+    gr->ctx = ctx;
+    hipStream_t cs = ctx->capture_stream;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        ctx->sync = saved_sync;
+        delete gr;
+        return hip_fail(ctx, e, "hipStreamBeginCapture");
+    }
+    rc = do_fit(ctx, params, m, v, target, n, tab, T, hp, step, image_out, loss_out, cs);
+    e = hipStreamEndCapture(cs, &gr->graph);
+    ctx->sync = saved_sync;
+    if (rc != GI_OK || e != hipSuccess) {
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        delete gr;
+        return rc != GI_OK ? rc : hip_fail(ctx, e, "hipStreamEndCapture");
+    }
+    e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr->graph);
+        delete gr;
+        return hip_fail(ctx, e, "hipGraphInstantiate");
+    }
+    *out = gr;
+    return GI_OK;
+}
+
+int gi_fit_graph_launch(gi_graph *gr, int32_t steps, void *stream) {
+    if (!gr || steps < 0) return GI_ERR_INVALID_ARG;
+    gi_ctx *ctx = gr->ctx;
+    DeviceGuard g(ctx->device);
+    for (int32_t i = 0; i < steps; ++i) CK(hipGraphLaunch(gr->exec, (hipStream_t)stream));
+    return GI_OK;
+}
+
+int gi_fit_graph_destroy(gi_graph *gr) {
+    if (!gr) return GI_OK;
+    DeviceGuard g(gr->ctx->device);
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
+    return GI_OK;
+}
+
+int gi_binning(gi_ctx *ctx, const float *params, int64_t n, int32_t H, int32_t W, int32_t *rects,
+               uint32_t *counts, uint32_t *offsets, uint32_t *ranges, uint32_t *ids,
+               int64_t ids_capacity, int64_t *keys_host, void *stream) {
+    if (!ctx || (n > 0 && !params) || check_single(n, H, W) != GI_OK || ids_capacity < 0)
+        return GI_ERR_INVALID_ARG;
+    if (n > 0 && !aligned16(params)) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const ImgTable tab = single_table(H, W);
+    const int64_t T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    const int saved_sync = ctx->sync;
+    ctx->sync = 1;
+    int64_t bound;
+    int which;
+    int rc = run_binning(ctx, params, n, tab, T, s, &bound, &which);
+    ctx->sync = saved_sync;
+    if (rc != GI_OK) return rc;
+    if (n > 0) {
+        if (rects) CK(hipMemcpyAsync(rects, ctx->rect, sizeof(int4) * n, hipMemcpyDeviceToDevice, s));
+        if (counts) CK(hipMemcpyAsync(counts, ctx->count, 4 * n, hipMemcpyDeviceToDevice, s));
+        if (offsets) CK(hipMemcpyAsync(offsets, ctx->off, 4 * n, hipMemcpyDeviceToDevice, s));
+    }
+    if (ranges) CK(hipMemcpyAsync(ranges, ctx->ranges, sizeof(uint2) * T, hipMemcpyDeviceToDevice, s));
+    if (keys_host) *keys_host = bound;
+    if (ids && bound > 0) {
+        if (ids_capacity < bound) return GI_ERR_CAPACITY;
+        CK(hipMemcpyAsync(ids, ctx->vals[which], 4 * bound, hipMemcpyDeviceToDevice, s));
+    }
+    CK(hipStreamSynchronize(s));
+    return GI_OK;
+}
+
+int gi_scan_u32(gi_ctx *ctx, const uint32_t *in, uint32_t *out, int64_t n, uint64_t *total,
+                void *stream) {
+    if (!ctx || n < 0 || (n > 0 && (!in || !out))) return GI_ERR_INVALID_ARG;
+    if (n == 0) return GI_OK;
+    DeviceGuard g(ctx->device);
+    const int64_t need = scan_scratch_entries(n) + 1;
+    if (need > ctx->scan_cap) {
+        CK(hipDeviceSynchronize());
+        CK(grow(&ctx->scan_bs, need));
+        ctx->scan_cap = need;
+    }
+    CK(launch_scan_u32(in, out, n, ctx->scan_bs, reinterpret_cast<unsigned long long *>(total),
+                       (hipStream_t)stream));
+    return GI_OK;
+}
+
+int gi_sort_pairs(gi_ctx *ctx, const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                  uint32_t *vout, int64_t n, int32_t key_bits, void *stream) {
+    if (!ctx || n < 0 || key_bits < 1 || key_bits > 32) return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!kin || !vin || !kout || !vout)) return GI_ERR_INVALID_ARG;
+    if (n > 0 && (kin == kout || vin == vout || kin == vout || vin == kout))
+        return GI_ERR_INVALID_ARG;
+    if (n >= MAX_KEYS) return GI_ERR_CAPACITY;
+    if (n == 0) return GI_OK;
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    int digit = ctx->sort_bits > 0 ? ctx->sort_bits : auto_digit_bits(key_bits, n);
+    const int64_t hneed = sort_hist_entries(n, digit);
+    if (n > ctx->tmp_cap || hneed > ctx->hist_cap) {
+        CK(hipDeviceSynchronize());
+        if (n > ctx->tmp_cap) {
+            CK(grow(&ctx->tmp_k, n));
+            CK(grow(&ctx->tmp_v, n));
+            ctx->tmp_cap = n;
+        }
+        if (hneed > ctx->hist_cap) {
+            CK(grow(&ctx->hist, hneed));
+            ctx->hist_cap = hneed;
+        }
+    }
+    const int64_t sneed = scan_scratch_entries(hneed) + 1;
+    if (sneed > ctx->scan_cap) {
+        CK(hipDeviceSynchronize());
+        CK(grow(&ctx->scan_bs, sneed));
+        ctx->scan_cap = sneed;
+    }
+    int which = 0;
+    CK(launch_sort_pairs(kin, vin, kout, vout, ctx->tmp_k, ctx->tmp_v, n, nullptr, key_bits,
+                         digit, ctx->hist, ctx->scan_bs, &which, s));
+    if (which == 1) {
+        CK(hipMemcpyAsync(kout, ctx->tmp_k, 4 * n, hipMemcpyDeviceToDevice, s));
+        CK(hipMemcpyAsync(vout, ctx->tmp_v, 4 * n, hipMemcpyDeviceToDevice, s));
+    }
+    return GI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,616 @@
+// Binning kernels for gfx950: projection and 3-sigma tile culling, prefix scans, key
+// duplication, the stable LSD radix sort by tile id, and tile-range extraction with the gather
+// of records into tile order.
+//
+// The paper renders tile by tile (Sec. 4.1 builds on the tile-based rasteriser of 3D-GS) and
+// removes the depth sort because the accumulated sum does not depend on order (Sec. 3.2, after
+// Eq. rasterization3).  What remains is grouping Gaussians by tile: each Gaussian emits one
+// (tile id, Gaussian id) key per covered tile, in row-major order within its rectangle, and a
+// stable sort by tile id yields per-tile lists in ascending Gaussian order.
+#include "gi_common.h"
+
+namespace gi {
+
+namespace {
+
+constexpr int BLK = 256;           // threads per block for per-Gaussian and per-key kernels
+constexpr int SORT_T = 256;        // threads per sort block
+constexpr int SORT_IPT = 16;       // keys per thread
+constexpr int SORT_TILE = SORT_T * SORT_IPT;
+constexpr int SORT_WAVES = SORT_T / 64;
+constexpr int SCAN_T = 256;
+constexpr int SCAN_IPT = 16;
+constexpr int SCAN_TILE = SCAN_T * SCAN_IPT;
+
+// ---- small block-level helpers --------------------------------------------------------------
+
+template <typename T>
+__device__ inline T wave_inclusive_scan(T v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan over the block; returns this thread's exclusive prefix, *total the sum.
+// `tmp` holds one entry per wave.  Contains __syncthreads.
+template <typename T, int NT>
+__device__ inline T block_exclusive_scan(T v, T *tmp, T *total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T inc = wave_inclusive_scan(v);
+    if (lane == 63) tmp[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            T x = tmp[w];
+            tmp[w] = run;
+            run += x;
+        }
+        tmp[NT / 64] = run;
+    }
+    __syncthreads();
+    T res = inc - v + tmp[wave];
+    *total = tmp[NT / 64];
+    __syncthreads();
+    return res;
+}
+
+// ---- K1: projection and tile culling ---------------------------------------------------------
+
+// r^2 >= 9 lambda_max(Sigma), decided by the characteristic polynomial of Sigma at R/9 with
+// R = r^2: p = R - 9 s00, q = R - 9 s11, p + q >= 0 and p q >= 81 s01^2.  Every step is a
+// separately rounded IEEE float64 operation (no contraction) so that the decision is
+// reproducible on any IEEE machine that evaluates the same expression.
+__device__ inline bool covers(double r, double s00, double s01, double s11) {
+#pragma clang fp contract(off)
+    double R = r * r;
+    double p = R - 9.0 * s00;
+    double q = R - 9.0 * s11;
+    return ((p + q) >= 0.0) && ((p * q) >= 81.0 * (s01 * s01));
+}
+
+constexpr double R_MAX = 33554432.0;  // 2^25: covers any image once |mu| <= 2^24
+
+__global__ __launch_bounds__(BLK) void k_project(const float4 *__restrict__ params, int64_t n,
+                                                 ImgTable tab, float4 *__restrict__ proj,
+                                                 int4 *__restrict__ rect,
+                                                 uint2 *__restrict__ tinfo,
+                                                 uint32_t *__restrict__ count,
+                                                 unsigned long long *__restrict__ blocksum,
+                                                 DevState *state) {
+#pragma clang fp contract(off)
+    __shared__ unsigned long long tmp[BLK / 64 + 1];
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    uint32_t cnt = 0;
+    bool nonfinite = false;
+    if (i < n) {
+        const float4 q0 = params[2 * i], q1 = params[2 * i + 1];
+        const float q[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        int32_t TW, TH;
+        uint32_t tb;
+        if (tab.B == 1) {
+            TW = tab.TW; TH = (tab.H + TILE - 1) / TILE; tb = 0;
+        } else {
+            int32_t b = upper_index(tab.gauss_off, tab.B, (uint32_t)i);
+            int4 d = tab.dims[b];
+            TW = d.z; TH = d.w; tb = tab.tile_base[b];
+        }
+        bool finite = true;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) finite = finite && isfinite(q[k]);
+        nonfinite = !finite;
+        const double mx = q[0], my = q[1], l1 = q[2], l2 = q[3], l3 = q[4];
+        bool act = finite && fabs(l1) >= 0x1p-24 && fabs(l3) >= 0x1p-24 && fabs(l2) <= 0x1p24 &&
+                   fabs(mx) <= 0x1p24 && fabs(my) <= 0x1p24;
+        int4 rc = make_int4(0, 0, -1, -1);
+        float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
+        if (act) {
+            const double s00 = l1 * l1, s01 = l1 * l2, s11 = l2 * l2 + l3 * l3;
+            // starting guess from the eigenvalue formula, then the least r that covers
+            const double lam = 0.5 * (s00 + s11) + sqrt(0.25 * (s00 - s11) * (s00 - s11) + s01 * s01);
+            double r = ceil(3.0 * sqrt(lam));
+            if (!(r >= 0.0)) r = 0.0;
+            if (r > R_MAX) r = R_MAX;
+            while (r > 0.0 && covers(r - 1.0, s00, s01, s11)) r -= 1.0;
+            while (r < R_MAX && !covers(r, s00, s01, s11)) r += 1.0;
+            double fx0 = floor((mx - r) / 16.0), fx1 = floor((mx + r) / 16.0);
+            double fy0 = floor((my - r) / 16.0), fy1 = floor((my + r) / 16.0);
+            if (fx0 < 0.0) fx0 = 0.0;
+            if (fy0 < 0.0) fy0 = 0.0;
+            if (fx1 > TW - 1.0) fx1 = TW - 1.0;
+            if (fy1 > TH - 1.0) fy1 = TH - 1.0;
+            if (fx0 <= fx1 && fy0 <= fy1) {
+                rc = make_int4((int)fx0, (int)fy0, (int)fx1, (int)fy1);
+                cnt = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
+            }
+            p0 = make_float4(q[0], q[1], (float)(U_SCALE / l1), (float)(U_SCALE / l3));
+            p1 = make_float4((float)(U_SCALE * l2 / (l1 * l3)), q[5], q[6], q[7]);
+        }
+        proj[2 * i] = p0;
+        proj[2 * i + 1] = p1;
+        rect[i] = rc;
+        tinfo[i] = make_uint2(tb, (uint32_t)TW);
+        count[i] = cnt;
+    }
+    if (__ballot(nonfinite) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_NONFINITE);
+    unsigned long long tot;
+    block_exclusive_scan<unsigned long long, BLK>((unsigned long long)cnt, tmp, &tot);
+    if (threadIdx.x == 0) blocksum[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the per-block totals by one 1024-thread block; also the grand total.
+__global__ __launch_bounds__(1024) void k_scan_top(unsigned long long *__restrict__ bs, int64_t nb,
+                                                   unsigned long long *__restrict__ total) {
+    __shared__ unsigned long long tmp[1024 / 64 + 1];
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t beg = threadIdx.x * per;
+    const int64_t end = beg + per < nb ? beg + per : nb;
+    unsigned long long s = 0;
+    for (int64_t j = beg; j < end; ++j) s += bs[j];
+    unsigned long long tot;
+    unsigned long long run = block_exclusive_scan<unsigned long long, 1024>(s, tmp, &tot);
+    for (int64_t j = beg; j < end; ++j) {
+        unsigned long long x = bs[j];
+        bs[j] = run;
+        run += x;
+    }
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
+// ---- K2: key duplication --------------------------------------------------------------------
+
+// Block b handles Gaussians [256 b, 256 b + 256): it rebuilds their offsets from the scanned
+// block totals, then its threads stride over the block's keys so that writes are coalesced.
+__global__ __launch_bounds__(BLK) void k_duplicate(const uint32_t *__restrict__ count,
+                                                   const int4 *__restrict__ rect,
+                                                   const uint2 *__restrict__ tinfo,
+                                                   const unsigned long long *__restrict__ bs,
+                                                   int64_t n, int64_t cap,
+                                                   uint32_t *__restrict__ off,
+                                                   uint32_t *__restrict__ keys,
+                                                   uint32_t *__restrict__ vals,
+                                                   DevState *state) {
+    __shared__ unsigned long long tmp[BLK / 64 + 1];
+    __shared__ unsigned long long pre[BLK];
+    __shared__ int4 srect[BLK];
+    __shared__ uint2 sinfo[BLK];
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    const uint32_t c = i < n ? count[i] : 0u;
+    unsigned long long tot;
+    const unsigned long long loc = block_exclusive_scan<unsigned long long, BLK>(c, tmp, &tot);
+    const unsigned long long base = bs[blockIdx.x];
+    pre[threadIdx.x] = loc;
+    if (i < n) {
+        off[i] = (uint32_t)(base + loc);
+        srect[threadIdx.x] = rect[i];
+        sinfo[threadIdx.x] = tinfo[i];
+    }
+    __syncthreads();
+    unsigned long long limit = tot;
+    if (base >= (unsigned long long)cap) limit = 0;
+    else if (base + tot > (unsigned long long)cap) limit = (unsigned long long)cap - base;
+    if (limit < tot && threadIdx.x == 0) atomicOr(&state->flags, FLAG_KEY_OVERFLOW);
+    for (unsigned long long j = threadIdx.x; j < limit; j += BLK) {
+        int lo = 0, hi = BLK - 1;  // owner: largest g with pre[g] <= j
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+        }
+        const int4 r = srect[lo];
+        const uint2 inf = sinfo[lo];
+        const uint32_t li = (uint32_t)(j - pre[lo]);
+        const uint32_t w = (uint32_t)(r.z - r.x + 1);
+        const uint32_t tx = (uint32_t)r.x + li % w, ty = (uint32_t)r.y + li / w;
+        keys[base + j] = inf.x + ty * inf.y + tx;
+        vals[base + j] = (uint32_t)((int64_t)blockIdx.x * BLK + lo);
+    }
+}
+
+// ---- generic exclusive scan of uint32 --------------------------------------------------------
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n,
+                                                        unsigned long long *__restrict__ bs) {
+    __shared__ unsigned long long tmp[SCAN_T / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    unsigned long long s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_IPT; ++j) {
+        int64_t idx = base + j * SCAN_T + threadIdx.x;
+        if (idx < n) s += in[idx];
+    }
+    unsigned long long tot;
+    block_exclusive_scan<unsigned long long, SCAN_T>(s, tmp, &tot);
+    if (threadIdx.x == 0) bs[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_down(const uint32_t *__restrict__ in,
+                                                      uint32_t *__restrict__ out, int64_t n,
+                                                      const unsigned long long *__restrict__ bs) {
+    __shared__ unsigned long long tmp[SCAN_T / 64 + 1];
+    __shared__ uint32_t stage[SCAN_TILE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    // coalesced load into LDS, then each thread scans 16 consecutive values
+#pragma unroll
+    for (int j = 0; j < SCAN_IPT; ++j) {
+        int64_t idx = base + j * SCAN_T + threadIdx.x;
+        stage[j * SCAN_T + threadIdx.x] = idx < n ? in[idx] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[SCAN_IPT];
+    unsigned long long s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_IPT; ++j) {
+        v[j] = stage[threadIdx.x * SCAN_IPT + j];
+        s += v[j];
+    }
+    unsigned long long tot;
+    unsigned long long run = block_exclusive_scan<unsigned long long, SCAN_T>(s, tmp, &tot) +
+                             bs[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < SCAN_IPT; ++j) {
+        stage[threadIdx.x * SCAN_IPT + j] = (uint32_t)run;
+        run += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SCAN_IPT; ++j) {
+        int64_t idx = base + j * SCAN_T + threadIdx.x;
+        if (idx < n) out[idx] = stage[j * SCAN_T + threadIdx.x];
+    }
+}
+
+// Small arrays (n <= 1024 * 16): one block does the whole exclusive scan.
+__global__ __launch_bounds__(1024) void k_scan_single(const uint32_t *__restrict__ in,
+                                                      uint32_t *__restrict__ out, int64_t n,
+                                                      unsigned long long *__restrict__ total) {
+    __shared__ unsigned long long tmp[1024 / 64 + 1];
+    uint32_t v[16];
+    unsigned long long s = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        int64_t idx = (int64_t)threadIdx.x * 16 + j;
+        v[j] = idx < n ? in[idx] : 0u;
+        s += v[j];
+    }
+    unsigned long long tot;
+    unsigned long long run = block_exclusive_scan<unsigned long long, 1024>(s, tmp, &tot);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        int64_t idx = (int64_t)threadIdx.x * 16 + j;
+        if (idx < n) out[idx] = (uint32_t)run;
+        run += v[j];
+    }
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
+// ---- K3: stable LSD radix sort ---------------------------------------------------------------
+
+__device__ inline int64_t sort_count(const unsigned long long *n_dev, int64_t n_max) {
+    if (!n_dev) return n_max;
+    unsigned long long t = *n_dev;
+    return t < (unsigned long long)n_max ? (int64_t)t : n_max;
+}
+
+// Lanes of the wave whose digit equals this lane's (BITS ballots); `valid` lanes only.
+template <int BITS>
+__device__ inline unsigned long long match_digit(uint32_t d, bool valid) {
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const unsigned long long bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
+// Per-block digit histogram, written digit-major: hist[d * nblk + block].
+template <int BITS>
+__global__ __launch_bounds__(SORT_T) void k_radix_hist(const uint32_t *__restrict__ keys,
+                                                       const unsigned long long *n_dev,
+                                                       int64_t n_max, int shift,
+                                                       uint32_t *__restrict__ hist,
+                                                       int64_t nblk) {
+    constexpr int BINS = 1 << BITS;
+    __shared__ uint32_t h[SORT_WAVES][BINS];
+    const int64_t n = sort_count(n_dev, n_max);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < SORT_WAVES * BINS; d += SORT_T) (&h[0][0])[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE + (int64_t)wave * (SORT_TILE / SORT_WAVES);
+    for (int r = 0; r < SORT_TILE / SORT_WAVES / 64; ++r) {
+        const int64_t idx = base + r * 64 + lane;
+        const bool valid = idx < n;
+        const uint32_t d = valid ? (keys[idx] >> shift) & (BINS - 1) : 0u;
+        const unsigned long long peers = match_digit<BITS>(d, valid);
+        if (valid && lane == __ffsll((long long)peers) - 1) h[wave][d] += __popcll(peers);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < BINS; d += SORT_T) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int w = 0; w < SORT_WAVES; ++w) s += h[w][d];
+        hist[(int64_t)d * nblk + blockIdx.x] = s;
+    }
+}
+
+// Scatter with stable in-block ranks.  `hist` holds the exclusive scan of the digit-major
+// histogram: the output position of the first key with digit d from block b.
+template <int BITS>
+__global__ __launch_bounds__(SORT_T) void k_radix_scatter(const uint32_t *__restrict__ kin,
+                                                          const uint32_t *__restrict__ vin,
+                                                          uint32_t *__restrict__ kout,
+                                                          uint32_t *__restrict__ vout,
+                                                          const unsigned long long *n_dev,
+                                                          int64_t n_max, int shift,
+                                                          const uint32_t *__restrict__ hist,
+                                                          int64_t nblk) {
+    constexpr int BINS = 1 << BITS;
+    constexpr int ROUNDS = SORT_TILE / SORT_WAVES / 64;
+    __shared__ uint32_t wh[SORT_WAVES][BINS];   // per-wave digit counts, then wave offsets
+    __shared__ uint32_t dstart[BINS];            // first in-block position of each digit
+    __shared__ uint32_t sk[SORT_TILE];
+    __shared__ uint32_t sv[SORT_TILE];
+    __shared__ uint32_t tmp[SORT_T / 64 + 1];
+    const int64_t n = sort_count(n_dev, n_max);
+    const int64_t blk_base = (int64_t)blockIdx.x * SORT_TILE;
+    if (blk_base >= n) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < SORT_WAVES * BINS; d += SORT_T) (&wh[0][0])[d] = 0;
+    __syncthreads();
+    const int64_t base = blk_base + (int64_t)wave * (SORT_TILE / SORT_WAVES);
+    uint32_t key[ROUNDS], val[ROUNDS], rank[ROUNDS];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int64_t idx = base + r * 64 + lane;
+        const bool valid = idx < n;
+        key[r] = valid ? kin[idx] : 0u;
+        val[r] = valid ? vin[idx] : 0u;
+        const uint32_t d = (key[r] >> shift) & (BINS - 1);
+        const unsigned long long peers = match_digit<BITS>(d, valid);
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        const uint32_t old = valid ? wh[wave][d] : 0u;  // every peer reads before the leader writes
+        if (valid && lane == __ffsll((long long)peers) - 1) wh[wave][d] = old + __popcll(peers);
+        rank[r] = old + __popcll(peers & lt);
+    }
+    __syncthreads();
+    // wave offsets within each digit, and digit totals of the block
+    uint32_t my_total = 0;
+    for (int d = threadIdx.x; d < BINS; d += SORT_T) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < SORT_WAVES; ++w) {
+            uint32_t x = wh[w][d];
+            wh[w][d] = run;
+            run += x;
+        }
+        dstart[d] = run;  // total for now
+    }
+    __syncthreads();
+    // exclusive scan of the digit totals (BINS entries, SORT_T threads, contiguous chunks)
+    {
+        constexpr int PER = (BINS + SORT_T - 1) / SORT_T;
+        uint32_t loc[PER];
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int d = threadIdx.x * PER + j;
+            loc[j] = d < BINS ? dstart[d] : 0u;
+            s += loc[j];
+        }
+        uint32_t tot;
+        uint32_t run = block_exclusive_scan<uint32_t, SORT_T>(s, tmp, &tot);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int d = threadIdx.x * PER + j;
+            if (d < BINS) dstart[d] = run;
+            run += loc[j];
+        }
+        (void)my_total;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int64_t idx = base + r * 64 + lane;
+        if (idx < n) {
+            const uint32_t d = (key[r] >> shift) & (BINS - 1);
+            const uint32_t pos = dstart[d] + wh[wave][d] + rank[r];
+            sk[pos] = key[r];
+            sv[pos] = val[r];
+        }
+    }
+    __syncthreads();
+    const int64_t cnt = n - blk_base < SORT_TILE ? n - blk_base : SORT_TILE;
+    for (int j = threadIdx.x; j < cnt; j += SORT_T) {
+        const uint32_t k = sk[j];
+        const uint32_t d = (k >> shift) & (BINS - 1);
+        const uint32_t dst = hist[(int64_t)d * nblk + blockIdx.x] + (uint32_t)j - dstart[d];
+        kout[dst] = k;
+        vout[dst] = sv[j];
+    }
+}
+
+// ---- K3: tile ranges and the gather into tile order -----------------------------------------
+
+__global__ __launch_bounds__(BLK) void k_ranges_gather(const uint32_t *__restrict__ keys,
+                                                       const uint32_t *__restrict__ vals,
+                                                       const unsigned long long *n_dev,
+                                                       int64_t n_max,
+                                                       const float4 *__restrict__ proj,
+                                                       const int4 *__restrict__ rect,
+                                                       const uint2 *__restrict__ tinfo,
+                                                       const uint32_t *__restrict__ off,
+                                                       uint2 *__restrict__ ranges,
+                                                       float4 *__restrict__ rec,
+                                                       uint32_t *__restrict__ slot) {
+    const int64_t n = sort_count(n_dev, n_max);
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t key = keys[i];
+    if (i == 0 || keys[i - 1] != key) ranges[key].x = (uint32_t)i;
+    if (i == n - 1 || keys[i + 1] != key) ranges[key].y = (uint32_t)(i + 1);
+    const uint32_t g = vals[i];
+    rec[2 * i] = proj[2 * (int64_t)g];
+    rec[2 * i + 1] = proj[2 * (int64_t)g + 1];
+    const int4 r = rect[g];
+    const uint2 inf = tinfo[g];
+    const uint32_t lt = key - inf.x;
+    const int32_t tx = (int32_t)(lt % inf.y), ty = (int32_t)(lt / inf.y);
+    slot[i] = off[g] + (uint32_t)((ty - r.y) * (r.z - r.x + 1) + (tx - r.x));
+}
+
+__global__ __launch_bounds__(BLK) void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+// ---- launchers -----------------------------------------------------------------------------
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, BLK)), dim3(BLK), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const BinBuffers &b, const ImgTable &tab, hipStream_t s) {
+    if (b.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project, dim3(grid_for(b.n, BLK)), dim3(BLK), 0, s,
+                       reinterpret_cast<const float4 *>(b.params), b.n, tab,
+                       reinterpret_cast<float4 *>(b.proj), b.rect, b.tinfo, b.count, b.blocksum,
+                       b.state);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_scan(const BinBuffers &b, hipStream_t s) {
+    if (b.n <= 0) {
+        // zero keys: write the total directly (a fill kernel, so that graphs hold no memset)
+        return launch_fill_u32(reinterpret_cast<uint32_t *>(&b.state->keys_total), 0u, 2, s);
+    }
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, b.blocksum,
+                       (int64_t)grid_for(b.n, BLK), &b.state->keys_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_duplicate(const BinBuffers &b, hipStream_t s) {
+    if (b.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_duplicate, dim3(grid_for(b.n, BLK)), dim3(BLK), 0, s, b.count, b.rect,
+                       b.tinfo, b.blocksum, b.n, b.cap, b.off, b.keys[0], b.vals[0], b.state);
+    return hipGetLastError();
+}
+
+int64_t scan_scratch_entries(int64_t n) { return n <= 16384 ? 1 : (n + SCAN_TILE - 1) / SCAN_TILE; }
+
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n,
+                           unsigned long long *blocksum, unsigned long long *total,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n <= 16384) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, in, out, n, total);
+        return hipGetLastError();
+    }
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, blocksum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, blocksum, nb, total);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, blocksum);
+    return hipGetLastError();
+}
+
+int auto_digit_bits(int key_bits, int64_t n) {
+    if (key_bits <= 0) return 1;
+    if (key_bits <= 11 && n <= (int64_t)1 << 22) return key_bits;  // one counting pass
+    const int passes = (key_bits + 7) / 8;
+    return (key_bits + passes - 1) / passes;
+}
+
+int64_t sort_hist_entries(int64_t n, int digit_bits) {
+    const int64_t nblk = n > 0 ? (n + SORT_TILE - 1) / SORT_TILE : 1;
+    return nblk << digit_bits;
+}
+
+template <int BITS>
+static hipError_t sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                      int64_t n, const unsigned long long *n_dev, int shift, uint32_t *hist,
+                      unsigned long long *scan_bs, hipStream_t s) {
+    const int64_t nblk = (n + SORT_TILE - 1) / SORT_TILE;
+    hipLaunchKernelGGL(k_radix_hist<BITS>, dim3((unsigned)nblk), dim3(SORT_T), 0, s, kin, n_dev, n,
+                       shift, hist, nblk);
+    hipError_t e = launch_scan_u32(hist, hist, nblk << BITS, scan_bs, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter<BITS>, dim3((unsigned)nblk), dim3(SORT_T), 0, s, kin, vin,
+                       kout, vout, n_dev, n, shift, hist, nblk);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_pairs(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                             uint32_t *vout, uint32_t *ktmp, uint32_t *vtmp, int64_t n,
+                             const unsigned long long *n_dev, int key_bits, int digit_bits,
+                             uint32_t *hist, unsigned long long *scan_bs, int *which_out,
+                             hipStream_t s) {
+    // Passes alternate out -> tmp -> out ...; the number of passes decides where the result
+    // lands.  *which_out = 0: kout/vout, 1: ktmp/vtmp.
+    if (n <= 0) {
+        *which_out = 0;
+        return hipSuccess;
+    }
+    if (digit_bits <= 0) digit_bits = auto_digit_bits(key_bits, n);
+    if (digit_bits > 11) digit_bits = 11;
+    const int passes = (key_bits + digit_bits - 1) / digit_bits;
+    const uint32_t *ck = kin, *cv = vin;
+    int where = 0;
+    hipError_t e = hipSuccess;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * digit_bits;
+        const int bits = key_bits - shift < digit_bits ? key_bits - shift : digit_bits;
+        uint32_t *ok = (p % 2 == 0) ? kout : ktmp;
+        uint32_t *ov = (p % 2 == 0) ? vout : vtmp;
+        switch (bits) {
+#define GI_SORT_CASE(B) \
+    case B: e = sort_pass<B>(ck, cv, ok, ov, n, n_dev, shift, hist, scan_bs, s); break;
+            GI_SORT_CASE(1) GI_SORT_CASE(2) GI_SORT_CASE(3) GI_SORT_CASE(4) GI_SORT_CASE(5)
+            GI_SORT_CASE(6) GI_SORT_CASE(7) GI_SORT_CASE(8) GI_SORT_CASE(9) GI_SORT_CASE(10)
+            GI_SORT_CASE(11)
+#undef GI_SORT_CASE
+            default: return hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+        ck = ok;
+        cv = ov;
+        where = p % 2;
+    }
+    *which_out = where;
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(const BinBuffers &b, int key_bits, int digit_bits, int64_t n_max,
+                       int *which, hipStream_t s) {
+    // input keys[0]/vals[0]; passes go to keys[1], keys[0], ...
+    int w = 0;
+    hipError_t e = launch_sort_pairs(b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0],
+                                     b.vals[0], n_max, &b.state->keys_total, key_bits, digit_bits,
+                                     b.hist, b.scan_blocksum, &w, s);
+    // result in keys[1] when w == 0 (odd number of passes), in keys[0] when w == 1
+    *which = (n_max <= 0) ? 0 : (w == 0 ? 1 : 0);
+    return e;
+}
+
+hipError_t launch_ranges_gather(const BinBuffers &b, int which, const ImgTable &tab,
+                                int64_t n_max, hipStream_t s) {
+    (void)tab;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(b.ranges), 0u, 2 * b.n_tiles, s);
+    if (e != hipSuccess || n_max <= 0) return e;
+    hipLaunchKernelGGL(k_ranges_gather, dim3(grid_for(n_max, BLK)), dim3(BLK), 0, s, b.keys[which],
+                       b.vals[which], &b.state->keys_total, n_max,
+                       reinterpret_cast<const float4 *>(b.proj), b.rect, b.tinfo, b.off, b.ranges,
+                       reinterpret_cast<float4 *>(b.rec), b.slot);
+    return hipGetLastError();
+}
+
+}  // namespace gi

@@ -1,0 +1,414 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: tile rects, counts, offsets, key counts, tile ranges and per-tile id lists bit-exact;
+forward |gpu - oracle| <= 1e-5 A(p) + 1e-30 with A(p) = sum |c'| exp(-sigma) over the same
+support; gradients |gpu - oracle| <= 1e-4 A_theta + 1e-30 with A_theta the sum of absolute
+per-pixel contributions; fit steps as stated in their tests.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cref, ref
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FWD_RTOL = 1e-5
+GRAD_RTOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def gi():
+    import paper_2403_08551_amd as P
+    ctx = P.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def ragged_case():
+    h, w = 45, 70
+    p = synth.gaussians(150, h, w, seed=2, l_lo=0.5, l_hi=12.0)
+    p[:4, 0] = [-30.0, 200.0, 35.0, 0.0]
+    p[:4, 1] = [10.0, 10.0, -40.0, 0.0]
+    p[4] = [np.nan, 1, 1, 0, 1, 1, 1, 1]
+    p[5, 2] = 0.0
+    p[6, 5:8] = [-2.0, 3.0, -0.5]
+    return p, h, w
+
+
+def cases():
+    out = {}
+    w = synth.plain_256()
+    out["plain-256x256-2k"] = (w.params(), w.height, w.width)
+    out["ragged-45x70"] = ragged_case()
+    out["one-pixel"] = (synth.gaussians(5, 1, 1, seed=3), 1, 1)
+    out["empty"] = (np.zeros((0, 8), np.float32), 33, 17)
+    out["wide-l-100x120"] = (synth.gaussians(400, 100, 120, seed=8, l_lo=0.5, l_hi=32.0), 100, 120)
+    out["off-image"] = (synth.gaussians(50, 40, 40, seed=9) + np.array([500, 500, 0, 0, 0, 0, 0, 0],
+                                                                         np.float32), 40, 40)
+    return out
+
+
+CASES = cases()
+
+
+def assert_forward(g, o, A, what):
+    bad = np.abs(g - o) > FWD_RTOL * A + 1e-30
+    if bad.any():
+        i = np.argmax(np.abs(g - o) / (A + 1e-300))
+        raise AssertionError(f"{what}: {bad.sum()} values off; worst gpu {g.flat[i]} oracle "
+                             f"{o.flat[i]} A {A.flat[i]}")
+
+
+def assert_grads(g, o, A, what):
+    bad = np.abs(g - o) > GRAD_RTOL * A + 1e-30
+    if bad.any():
+        i = np.argmax(np.abs(g - o) / (A + 1e-300))
+        raise AssertionError(f"{what}: {bad.sum()} values off; worst gpu {g.flat[i]} oracle "
+                             f"{o.flat[i]} A {A.flat[i]} at {np.unravel_index(i, g.shape)}")
+
+
+# ------------------------------------------------------------------ binning (bit-exact)
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_binning_bit_exact(gi, name):
+    p, h, w = CASES[name]
+    b = gi.binning(dev(p), h, w)
+    rect, count = ref.tile_rects(p, h, w)
+    ranges, ids = ref.tile_lists(p, h, w)
+    if p.shape[0]:
+        np.testing.assert_array_equal(host(b["rects"]), rect)
+        np.testing.assert_array_equal(host(b["counts"]), count)
+        np.testing.assert_array_equal(host(b["offsets"]), np.concatenate([[0], np.cumsum(count)[:-1]]))
+    assert b["keys"] == int(count.sum())
+    np.testing.assert_array_equal(host(b["ranges"]), ranges)
+    np.testing.assert_array_equal(host(b["ids"]), ids)
+
+
+@pytest.mark.parametrize("bits", [1, 3, 5, 8, 11])
+def test_binning_independent_of_digit_width(gi, bits):
+    import paper_2403_08551_amd as P
+    p, h, w = CASES["wide-l-100x120"]
+    ranges, ids = ref.tile_lists(p, h, w)
+    gi.set_option(P._lib.GI_OPT_SORT_BITS, bits)
+    try:
+        b = gi.binning(dev(p), h, w)
+    finally:
+        gi.set_option(P._lib.GI_OPT_SORT_BITS, 0)
+    np.testing.assert_array_equal(host(b["ranges"]), ranges)
+    np.testing.assert_array_equal(host(b["ids"]), ids)
+
+
+# ------------------------------------------------------------------ sort and scan primitives
+
+@pytest.mark.parametrize("n,bits", [(1, 1), (100, 4), (4096, 8), (4097, 11), (70001, 13),
+                                    (300000, 21), (123457, 32)])
+def test_sort_pairs_is_a_stable_sort(gi, n, bits):
+    rng = np.random.default_rng(n + bits)
+    keys = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    keys_masked = keys & np.uint32((1 << bits) - 1) if bits < 32 else keys
+    if bits >= 4:  # many equal keys, to exercise stability
+        keys[::3] = keys[0]
+        keys_masked = keys & np.uint32((1 << bits) - 1) if bits < 32 else keys
+    vals = np.arange(n, dtype=np.uint32)
+    ko, vo = gi.sort_pairs(dev(keys.view(np.int32), torch.int32), dev(vals.view(np.int32), torch.int32), bits)
+    order = np.argsort(keys_masked, kind="stable")
+    np.testing.assert_array_equal(host(vo).view(np.uint32), vals[order])
+    np.testing.assert_array_equal(host(ko).view(np.uint32), keys[order])
+
+
+@pytest.mark.parametrize("n", [1, 17, 16384, 16385, 1 << 20])
+def test_scan_u32(gi, n):
+    x = np.random.default_rng(n).integers(0, 1000, n).astype(np.int32)
+    out, total = gi.scan_u32(dev(x, torch.int32))
+    want = np.concatenate([[0], np.cumsum(x.astype(np.int64))[:-1]])
+    np.testing.assert_array_equal(host(out).astype(np.int64), want)
+    assert int(host(total)[0]) == int(x.astype(np.int64).sum())
+
+
+# ------------------------------------------------------------------ forward
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_render_matches_oracle(gi, name):
+    p, h, w = CASES[name]
+    img = host(gi.render(dev(p), h, w))
+    o, A = ref.render_culled(p, h, w, with_abs=True)
+    assert_forward(img, o, A, name)
+
+
+def test_render_is_deterministic_and_independent_of_pixels_per_lane(gi):
+    import paper_2403_08551_amd as P
+    p, h, w = CASES["plain-256x256-2k"]
+    pd = dev(p)
+    base = host(gi.render(pd, h, w))
+    np.testing.assert_array_equal(host(gi.render(pd, h, w)), base)
+    for px in (1, 2, 4):
+        gi.set_option(P._lib.GI_OPT_FWD_PIXELS, px)
+        try:
+            np.testing.assert_array_equal(host(gi.render(pd, h, w)), base)
+        finally:
+            gi.set_option(P._lib.GI_OPT_FWD_PIXELS, 0)
+
+
+def test_render_is_permutation_invariant(gi):
+    p, h, w = CASES["plain-256x256-2k"]
+    perm = np.random.default_rng(0).permutation(p.shape[0])
+    a = host(gi.render(dev(p), h, w))
+    b = host(gi.render(dev(p[perm]), h, w))
+    _, A = ref.render_culled(p, h, w, with_abs=True)
+    assert np.all(np.abs(a - b) <= 2 * FWD_RTOL * A + 1e-30)
+
+
+# ------------------------------------------------------------------ backward
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_grad_matches_oracle(gi, name):
+    p, h, w = CASES[name]
+    G = synth.upstream_gradient(h, w, 17)
+    if p.shape[0] == 0:
+        d = gi.grad(dev(p), h, w, dev(G))
+        assert d.shape == (0, 8)
+        return
+    d = host(gi.grad(dev(p), h, w, dev(G)))
+    o, A = ref.grads(p, h, w, G, with_abs=True)
+    assert_grads(d, o, A, name)
+
+
+def test_grad_is_deterministic(gi):
+    p, h, w = CASES["plain-256x256-2k"]
+    G = dev(synth.upstream_gradient(h, w, 4))
+    a = host(gi.grad(dev(p), h, w, G))
+    b = host(gi.grad(dev(p), h, w, G))
+    np.testing.assert_array_equal(a, b)
+
+
+def test_autograd_function_matches_oracle(gi):
+    import paper_2403_08551_amd as P
+    p, h, w = CASES["ragged-45x70"]
+    p = p[6:]  # finite, active Gaussians
+    G = synth.upstream_gradient(h, w, 5)
+    pt = dev(p).requires_grad_(True)
+    img = P.render(pt, h, w, gi)
+    (img * dev(G)).sum().backward()
+    o, A = ref.grads(p, h, w, G, with_abs=True)
+    assert_grads(host(pt.grad), o, A, "autograd")
+
+
+# ------------------------------------------------------------------ fit steps
+
+def _hp32(hp):
+    # the ABI takes float32 hyper-parameters: give the oracle the same numbers
+    return {k: float(np.float32(v)) for k, v in hp.items()}
+
+
+def test_fit_steps_match_oracle(gi):
+    import paper_2403_08551_amd as P
+    w = synth.plain_256()
+    p0, T = w.params(), w.target()
+    hp = dict(ref.DEFAULT_ADAM)
+    cfg = P.AdamConfig(**hp)
+    pd, md, vd = dev(p0), torch.zeros(p0.shape, device="cuda"), torch.zeros(p0.shape, device="cuda")
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    img = torch.empty(w.height, w.width, 3, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    po, mo, vo = p0.astype(np.float64), np.zeros_like(p0, np.float64), np.zeros_like(p0, np.float64)
+    hp32 = _hp32(hp)
+    lr = np.array([hp32["lr_mu"]] * 2 + [hp32["lr_l"]] * 3 + [hp32["lr_c"]] * 3)
+    for t in range(1, 4):
+        pin = host(pd).copy()
+        gi.fit_step(pd, md, vd, dev(T), step, cfg, image_out=img, loss_out=loss)
+        o, A = ref.render_culled(pin, w.height, w.width, with_abs=True)
+        assert_forward(host(img), o, A, f"fit step {t} image")
+        np.testing.assert_allclose(host(loss)[0], ref.mse(o, T), rtol=1e-5)
+        G = ref.mse_grad(o, T)
+        g, Ag = ref.grads(pin, w.height, w.width, G, with_abs=True)
+        po, mo, vo = ref.adam_step(pin, mo, vo, g, t, hp32)
+        got = host(pd)
+        # the Adam step divides by sqrt(v): where |g| is within the gradient tolerance of zero the
+        # direction is not determined by the gradient, so only the step bound applies there
+        firm = np.abs(g) > 10 * GRAD_RTOL * Ag + 1e-20
+        tol = 1e-4 * lr + 1e-6 * np.abs(po)
+        assert np.all(np.abs(got - po)[firm] <= np.broadcast_to(tol, po.shape)[firm]), t
+        assert np.all(np.abs(got - po) <= 2.0 * lr + 1e-6 * np.abs(po))
+        assert firm.mean() > 0.95
+        assert int(host(step)[0]) == t + 1
+
+
+# ------------------------------------------------------------------ batched == plain
+
+def small_batch():
+    rng = np.random.default_rng(12)
+    hs = [int(x) for x in rng.integers(20, 90, 5)]
+    ws = [int(x) for x in rng.integers(20, 90, 5)]
+    ns = [int(h * w // 12) for h, w in zip(hs, ws)]
+    ps = [synth.gaussians(n, h, w, seed=100 + i) for i, (n, h, w) in enumerate(zip(ns, hs, ws))]
+    ts = [synth.target_noise_rects(h, w, seed=200 + i) for i, (h, w) in enumerate(zip(hs, ws))]
+    return hs, ws, ps, ts
+
+
+def test_batched_render_and_grad_equal_plain(gi):
+    import paper_2403_08551_amd as P
+    hs, ws, ps, ts = small_batch()
+    off = np.concatenate([[0], np.cumsum([p.shape[0] for p in ps])])
+    batch = P.Batch(hs, ws, off)
+    allp = dev(np.concatenate(ps))
+    imgs = gi.render_batched(allp, batch)
+    Gs = [synth.upstream_gradient(h, w, 30 + i) for i, (h, w) in enumerate(zip(hs, ws))]
+    Gall = dev(np.concatenate([g.reshape(-1, 3) for g in Gs]))
+    dall = host(gi.grad_batched(allp, batch, Gall))
+    for b in range(len(hs)):
+        single = host(gi.render(dev(ps[b]), hs[b], ws[b]))
+        np.testing.assert_array_equal(host(batch.image(imgs, b)), single)
+        ds = host(gi.grad(dev(ps[b]), hs[b], ws[b], dev(Gs[b])))
+        np.testing.assert_array_equal(dall[off[b]:off[b + 1]], ds)
+
+
+def test_batched_fit_equals_plain_fit(gi):
+    import paper_2403_08551_amd as P
+    hs, ws, ps, ts = small_batch()
+    off = np.concatenate([[0], np.cumsum([p.shape[0] for p in ps])])
+    batch = P.Batch(hs, ws, off)
+    allp = dev(np.concatenate(ps))
+    m = torch.zeros_like(allp)
+    v = torch.zeros_like(allp)
+    T = dev(np.concatenate([t.reshape(-1, 3) for t in ts]))
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    loss = torch.empty(len(hs), device="cuda")
+    for _ in range(3):
+        gi.fit_step_batched(allp, m, v, T, batch, step, loss_out=loss)
+    for b in range(len(hs)):
+        pb = dev(ps[b])
+        mb, vb = torch.zeros_like(pb), torch.zeros_like(pb)
+        sb = torch.ones(1, dtype=torch.int32, device="cuda")
+        lb = torch.empty(1, device="cuda")
+        for _ in range(3):
+            gi.fit_step(pb, mb, vb, dev(ts[b]), sb, loss_out=lb)
+        np.testing.assert_array_equal(host(allp)[off[b]:off[b + 1]], host(pb))
+        np.testing.assert_allclose(host(loss)[b], host(lb)[0], rtol=1e-6)
+
+
+# ------------------------------------------------------------------ captured steps
+
+def test_graph_replay_matches_eager_steps(gi):
+    w = synth.plain_256()
+    p0, T = w.params(), dev(w.target())
+    pa, pb = dev(p0), dev(p0)
+    ma, va, mb, vb = (torch.zeros_like(pa) for _ in range(4))
+    sa = torch.ones(1, dtype=torch.int32, device="cuda")
+    sb = torch.ones(1, dtype=torch.int32, device="cuda")
+    for _ in range(4):
+        gi.fit_step(pa, ma, va, T, sa)
+    import paper_2403_08551_amd as P
+    g = P.Context(0)
+    graph = g.fit_graph(pb, mb, vb, T, sb)
+    for _ in range(2):  # eager work and synchronisation between replays
+        graph.launch(2)
+        torch.cuda.synchronize()
+        _ = torch.zeros(10, device="cuda").sum().item()
+    graph.close()
+    g.close()
+    np.testing.assert_array_equal(host(pb), host(pa))
+    assert int(host(sb)[0]) == 5
+
+
+# ------------------------------------------------------------------ flags and edge cases
+
+def test_nonfinite_flag(gi):
+    p, h, w = CASES["ragged-45x70"]
+    gi.query(clear=True)
+    gi.render(dev(p), h, w)
+    _, flags = gi.query(clear=True)
+    assert flags & 2
+
+
+def test_key_overflow_skips_the_update():
+    import paper_2403_08551_amd as P
+    ctx = P.Context(0)
+    try:
+        ctx.set_option(P._lib.GI_OPT_SYNC, 0)
+        ctx.reserve(2000, 256, 4096)  # cfg1 needs ~15k keys
+        w = synth.plain_256()
+        p = dev(w.params())
+        p_before = host(p).copy()
+        m, v = torch.zeros_like(p), torch.zeros_like(p)
+        step = torch.ones(1, dtype=torch.int32, device="cuda")
+        ctx.fit_step(p, m, v, dev(w.target()), step)
+        keys, flags = ctx.query(clear=True)
+        assert flags & 1
+        assert keys > 4096
+        np.testing.assert_array_equal(host(p), p_before)
+    finally:
+        ctx.close()
+
+
+# ------------------------------------------------------------------ full-size workloads, sampled
+
+@pytest.mark.parametrize("n", [70_000])
+def test_kodak_size_full_run_sampled(gi, n):
+    w = synth.kodak_like(n)
+    p, h, wd = w.params(), w.height, w.width
+    pd = dev(p)
+    b = gi.binning(pd, h, wd)
+    ranges, ids = cref.tile_lists(p, h, wd)
+    assert b["keys"] == ids.size
+    np.testing.assert_array_equal(host(b["ranges"]), ranges)
+    np.testing.assert_array_equal(host(b["ids"]), ids)
+    img = host(gi.render(pd, h, wd))
+    rng = np.random.default_rng(1)
+    pix = rng.choice(h * wd, 3000, replace=False)
+    o, A = cref.render_pixels(p, h, wd, pix, with_abs=True)
+    assert_forward(img.reshape(-1, 3)[pix], o, A, "kodak sampled pixels")
+    G = synth.upstream_gradient(h, wd, 3)
+    d = host(gi.grad(pd, h, wd, dev(G)))
+    which = rng.choice(n, 200, replace=False)
+    od, Ad = cref.grads_subset(p, h, wd, G, which, with_abs=True)
+    assert_grads(d[which], od, Ad, "kodak sampled gradients")
+
+
+@pytest.mark.parametrize("n", [100_000, 300_000])
+def test_div2k_size_sampled(gi, n):
+    w = synth.div2k_full(n)
+    p, h, wd = w.params(), w.height, w.width
+    pd = dev(p)
+    rect, count = cref.tile_rects(p, h, wd)
+    b = gi.binning(pd, h, wd)
+    assert b["keys"] == int(count.sum())
+    np.testing.assert_array_equal(host(b["counts"]), count)
+    img = host(gi.render(pd, h, wd))
+    rng = np.random.default_rng(2)
+    pix = rng.choice(h * wd, 1500, replace=False)
+    o, A = cref.render_pixels(p, h, wd, pix, with_abs=True)
+    assert_forward(img.reshape(-1, 3)[pix], o, A, f"div2k {n} sampled pixels")
+    G = synth.upstream_gradient(h, wd, 4)
+    d = host(gi.grad(pd, h, wd, dev(G)))
+    which = rng.choice(n, 64, replace=False)
+    od, Ad = cref.grads_subset(p, h, wd, G, which, with_abs=True)
+    assert_grads(d[which], od, Ad, f"div2k {n} sampled gradients")
+
+
+# ------------------------------------------------------------------ autotuner
+
+def test_autotune_reads_but_never_writes_and_keeps_results_exact(gi):
+    import paper_2403_08551_amd as P
+    w = synth.plain_256()
+    p = dev(w.params())
+    T = dev(w.target())
+    before = host(p).copy()
+    ref_img = host(gi.render(p, w.height, w.width))
+    px, bits = gi.autotune(p, T, reps=2)
+    assert px in (1, 2, 4) and bits in (0, 4, 6, 8, 11)
+    np.testing.assert_array_equal(host(p), before)
+    assert gi.get_option(P._lib.GI_OPT_FWD_PIXELS) == 0  # explicit options untouched
+    np.testing.assert_array_equal(host(gi.render(p, w.height, w.width)), ref_img)
