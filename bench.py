@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--n", type=int, default=70_000, help="Gaussians (10k, 30k or 70k)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle fit steps (0: auto ~15 s)")
+    ap.add_argument("--batch-images", type=int, default=64,
+                    help="images of the batched-vs-plain comparison (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=50)
     return ap.parse_args()
 
 
@@ -73,6 +76,58 @@ def cpu_baseline(w, steps):
     return {"value": k / dt, "unit": "it/s", "cores": cref.num_threads(), "kind": "oracle",
             "sample": f"{k} FP64 fit steps (culled render, L2 loss, gradients, Adam) of the "
                       f"same {w.width}x{w.height} / {n} Gaussian workload, after one untimed step"}
+
+
+def batched_vs_plain(ctx, images, steps, P, torch, np):
+    """Fit `images` uneven images for `steps` steps as one batch (one launch per stage) and as
+    sequential single-image fits; both graph-replayed.  The batched fit is bit-identical to the
+    plain one, so the final losses are equal."""
+    import synth
+    ws = synth.batch_small(images)
+    dev = ctx.device
+    ps = [w.params() for w in ws]
+    ts = [w.target() for w in ws]
+    off = np.concatenate([[0], np.cumsum([p.shape[0] for p in ps])])
+    batch = P.Batch([w.height for w in ws], [w.width for w in ws], off)
+    allp = torch.tensor(np.concatenate(ps), device=dev)
+    allt = torch.tensor(np.concatenate([t.reshape(-1, 3) for t in ts]), device=dev)
+    m, v = torch.zeros_like(allp), torch.zeros_like(allp)
+    step = torch.ones(1, dtype=torch.int32, device=dev)
+    loss_b = torch.empty(images, device=dev)
+    g = ctx.fit_graph(allp, m, v, allt, step, batch=batch, loss_out=loss_b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.launch(steps)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    g.close()
+    # plain: one graph per image, replayed in turn
+    singles = []
+    for w, p, t in zip(ws, ps, ts):
+        pd = torch.tensor(p, device=dev)
+        td = torch.tensor(t, device=dev)
+        md, vd = torch.zeros_like(pd), torch.zeros_like(pd)
+        sd = torch.ones(1, dtype=torch.int32, device=dev)
+        ld = torch.empty(1, device=dev)
+        singles.append((ctx.fit_graph(pd, md, vd, td, sd, loss_out=ld), pd, ld))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for gr, _, _ in singles:
+        gr.launch(steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    lb = loss_b.cpu().numpy()
+    lp = np.array([float(ld.item()) for _, _, ld in singles])
+    same_params = all(torch.equal(allp[off[i]:off[i + 1]], pd) for i, (_, pd, _) in
+                      enumerate(singles))
+    for gr, _, _ in singles:
+        gr.close()
+    return {"images": images, "steps": steps, "gaussians": int(off[-1]),
+            "pixels": int(batch.n_pix), "batched_s": t_batched, "plain_s": t_plain,
+            "speedup": t_plain / t_batched,
+            "batched_image_steps_per_s": images * steps / t_batched,
+            "final_mse_max_rel_diff": float(np.max(np.abs(lb - lp) / np.abs(lp))),
+            "params_bit_identical": bool(same_params)}
 
 
 def main():
@@ -154,6 +209,10 @@ def main():
     torch.cuda.synchronize()
     fps = n_render / (time.perf_counter() - t0)
     ctx.set_option(P._lib.GI_OPT_TIMING, 0)
+    ctx.set_option(P._lib.GI_OPT_SYNC, 1)
+    bvp = None
+    if args.batch_images > 0:
+        bvp = batched_vs_plain(ctx, args.batch_images, args.batch_steps, P, torch, np)
     ctx.close()
 
     out = {
@@ -179,6 +238,7 @@ def main():
                      "unit": "T FP32 op/s", "frac": achieved / VALU_PEAK, "traffic": None,
                      "kernel": "k_raster_fit<2>", "ops_per_pair": OPS_PER_PAIR_FIT,
                      "pairs_per_launch": P_prof, "avg_launch_ms": fit_ms / fit_n},
+        "batched_vs_plain": bvp,
         "paper_context": {"render_fps_v100_kodak_70k": 2092.17,
                           "fit_its_v100_kodak_70k_derived": 50000 / 106.59},
     }

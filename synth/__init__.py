@@ -82,13 +82,10 @@ def _value_noise(height: int, width: int, rng: np.random.Generator) -> np.ndarra
         tx = xs - x0
         ty = ty * ty * (3.0 - 2.0 * ty)
         tx = tx * tx * (3.0 - 2.0 * tx)
-        v00 = lattice[np.ix_(y0, x0)]
-        v01 = lattice[np.ix_(y0, x0 + 1)]
-        v10 = lattice[np.ix_(y0 + 1, x0)]
-        v11 = lattice[np.ix_(y0 + 1, x0 + 1)]
-        top = v00 + (v01 - v00) * tx[None, :]
-        bot = v10 + (v11 - v10) * tx[None, :]
-        acc += amp * (top + (bot - top) * ty[:, None])
+        # smoothstep bilinear interpolation, done separably: along x on the lattice rows, then y
+        rows = lattice[:, x0] + (lattice[:, x0 + 1] - lattice[:, x0]) * tx[None, :]
+        top = rows[y0]
+        acc += amp * (top + (rows[y0 + 1] - top) * ty[:, None])
         total += amp
     return acc / total
 
