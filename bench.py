@@ -37,12 +37,21 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=70_000, help="Gaussians (10k, 30k or 70k)")
+    ap.add_argument("--workload", default="kodak", choices=["kodak", "div2k"],
+                    help="kodak: 768x512 (the metric's workload); div2k: 2040x1356")
+    ap.add_argument("--n", type=int, default=0,
+                    help="Gaussians (default 70k for kodak, 100k for div2k)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle fit steps (0: auto ~15 s)")
     ap.add_argument("--batch-images", type=int, default=64,
                     help="images of the batched-vs-plain comparison (0 skips it)")
+    ap.add_argument("--batch-set", default="small", choices=["small", "large"],
+                    help="small: sides 128-1024, 1k-50k Gaussians; large: sides 512-2048, "
+                         "20k-200k Gaussians")
     ap.add_argument("--batch-steps", type=int, default=50)
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--binning", type=int, default=0,
+                    help="0 auto, 1 duplication + radix sort, 2 one-pass counting sort")
     return ap.parse_args()
 
 
@@ -78,15 +87,23 @@ def cpu_baseline(w, steps):
                       f"same {w.width}x{w.height} / {n} Gaussian workload, after one untimed step"}
 
 
-def batched_vs_plain(ctx, images, steps, P, torch, np):
-    """Fit `images` uneven images for `steps` steps as one batch (one launch per stage) and as
-    sequential single-image fits; both graph-replayed.  The batched fit is bit-identical to the
-    plain one, so the final losses are equal."""
+def batch_inputs(images, which):
+    """Workloads, parameters and targets of the batch (targets made in worker processes; call
+    this before the process touches the GPU)."""
     import synth
-    ws = synth.batch_small(images)
-    dev = ctx.device
+    ws = synth.batch_small(images) if which == "small" else synth.batch_large(images)
     ps = [w.params() for w in ws]
-    ts = [w.target() for w in ws]
+    ts = synth.targets(ws, processes=min(8, os.cpu_count() or 1))
+    return ws, ps, ts
+
+
+def batched_vs_plain(ctx, inputs, steps, P, torch, np):
+    """Fit uneven images for `steps` steps as one batch (one launch per stage) and as sequential
+    single-image fits; both graph-replayed.  The batched fit is bit-identical to the plain one,
+    so the final losses are equal."""
+    ws, ps, ts = inputs
+    images = len(ws)
+    dev = ctx.device
     off = np.concatenate([[0], np.cumsum([p.shape[0] for p in ps])])
     batch = P.Batch([w.height for w in ws], [w.width for w in ws], off)
     allp = torch.tensor(np.concatenate(ps), device=dev)
@@ -137,17 +154,25 @@ def main():
               "batch per GPU; sharding is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
+
+    binputs = batch_inputs(args.batch_images, args.batch_set) if args.batch_images > 0 else None
+
     import torch
 
     import paper_2403_08551_amd as P
     import synth
 
-    w = synth.kodak_like(args.n)
+    if args.workload == "kodak":
+        w = synth.kodak_like(args.n or 70_000)
+    else:
+        w = synth.div2k_full(args.n or 100_000)
+    n_gauss = w.n
     H, W = w.height, w.width
     dev = torch.device("cuda", 0)
     params0 = torch.tensor(w.params(), device=dev)
     target = torch.tensor(w.target(), device=dev)
     ctx = P.Context(0)
+    ctx.set_option(P._lib.GI_OPT_BINNING, args.binning)
 
     # exact work of this workload
     b = ctx.binning(params0, H, W)
@@ -155,7 +180,8 @@ def main():
     P_pairs = pairs_from_ranges(ranges, H, W)
     K = b["keys"]
 
-    # ---- fit steps, captured once and replayed
+    # ---- tune the kernel settings for this size class, then capture and replay fit steps
+    tuned = ctx.autotune(params0, target, reps=5) if not args.no_tune else (0, 0)
     params = params0.clone()
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
@@ -171,9 +197,9 @@ def main():
     dt = time.perf_counter() - t0
     its = args.steps / dt
     loss_end = float(loss.item())
-    keys_now, flags = ctx.query(clear=True)
-    if flags & P._lib.GI_FLAG_KEY_OVERFLOW:
-        raise RuntimeError("key capacity overflowed during the timed steps")
+    keys_now, flags = graph.query(clear=True)
+    if flags & (P._lib.GI_FLAG_KEY_OVERFLOW | P._lib.GI_FLAG_SCAN_STALL):
+        raise RuntimeError(f"flags {flags} raised during the timed steps")
     graph.close()
 
     # ---- dominant kernel: the fused raster kernel, timed with events on its stream (eager
@@ -212,7 +238,7 @@ def main():
     ctx.set_option(P._lib.GI_OPT_SYNC, 1)
     bvp = None
     if args.batch_images > 0:
-        bvp = batched_vs_plain(ctx, args.batch_images, args.batch_steps, P, torch, np)
+        bvp = batched_vs_plain(ctx, binputs, args.batch_steps, P, torch, np)
     ctx.close()
 
     out = {
@@ -228,15 +254,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded value noise + rectangles target, random Gaussians)",
-        "config": {"workload": w.name, "height": H, "width": W, "gaussians": args.n,
+        "config": {"workload": w.name, "height": H, "width": W, "gaussians": n_gauss,
                    "keys": K, "pairs": P_pairs, "fit_steps": "hip graph replay"},
         "render_fps": fps,
+        "tuned": {"fwd_pixels_per_lane": tuned[0], "radix_digit_bits": tuned[1]},
         "stage_ms": {"binning": bin_ms / max(bin_n, 1), "raster_fit": fit_ms / max(fit_n, 1),
                      "update": upd_ms / max(upd_n, 1)},
         "loss": {"after_warmup": loss_start, "after_timed": loss_end},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "T FP32 op/s", "frac": achieved / VALU_PEAK, "traffic": None,
-                     "kernel": "k_raster_fit<2>", "ops_per_pair": OPS_PER_PAIR_FIT,
+                     "kernel": f"k_raster_fit<{tuned[0] or 2}>", "ops_per_pair": OPS_PER_PAIR_FIT,
                      "pairs_per_launch": P_prof, "avg_launch_ms": fit_ms / fit_n},
         "batched_vs_plain": bvp,
         "paper_context": {"render_fps_v100_kodak_70k": 2092.17,

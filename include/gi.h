@@ -54,6 +54,7 @@ enum {
 /* Sticky device flags read by gi_query. */
 #define GI_FLAG_KEY_OVERFLOW 1u /* more (tile, Gaussian) keys than capacity: outputs undefined */
 #define GI_FLAG_NONFINITE 2u    /* some parameter was NaN or Inf (that Gaussian took no part) */
+#define GI_FLAG_SCAN_STALL 4u   /* a one-pass scan block waited past its bound: outputs undefined */
 
 typedef struct gi_ctx gi_ctx;
 typedef struct gi_graph gi_graph;
@@ -85,7 +86,8 @@ enum {
                                  capacity, never wait, report overflow through flags */
     GI_OPT_SORT_BITS = 2,     /* radix digit width 1..11, 0 = automatic */
     GI_OPT_FWD_PIXELS = 3,    /* pixels per lane in the forward kernels: 1, 2 or 4; 0 = auto */
-    GI_OPT_BINNING = 4,       /* 0 = auto, 1 = generic radix sort, 2 = one-pass counting sort */
+    GI_OPT_BINNING = 4,       /* 0 = auto (one pass when the tiles number at most 2048),
+                                 1 = key duplication + LSD radix sort, 2 = one pass if possible */
     GI_OPT_TIMING = 5         /* 1: bracket each stage of non-captured calls with HIP events on
                                  the call's stream (read with gi_timing); 0 (default): off */
 };
@@ -180,9 +182,12 @@ int gi_fit_step_batched(gi_ctx *ctx, float *params_dev, float *m_dev, float *v_d
 /* ---- captured fit steps ------------------------------------------------------------------- */
 
 /* Capture one fit step (batch == NULL: the single image n x height x width; else the batch)
- * into a HIP graph.  The context switches to non-waiting mode for the graph's kernels and uses
- * key_capacity (at least the current key count is reserved first, with a 1.25x margin, by one
- * synchronous binning pass).  All pointers are baked into the graph and must stay valid. */
+ * into a HIP graph.  The graph owns a private workspace (a context created on ctx's device with
+ * ctx's options and autotuned settings), sized by one synchronous binning pass of the current
+ * parameters with a 1.25x margin on the key count, so later calls on ctx never move memory the
+ * graph uses.  Its kernels never wait on the host: if the key count outgrows the capacity the
+ * overflow flag is set and the update skipped (read it with gi_fit_graph_query, then re-create
+ * the graph).  The caller's pointers are baked into the graph and must stay valid. */
 int gi_fit_graph_create(gi_ctx *ctx, float *params_dev, float *m_dev, float *v_dev,
                         const float *target_dev, int64_t n, int32_t height, int32_t width,
                         const gi_batch *batch, const gi_adam *hp, int32_t *step_dev,
@@ -190,6 +195,9 @@ int gi_fit_graph_create(gi_ctx *ctx, float *params_dev, float *m_dev, float *v_d
                         gi_graph **out);
 /* Replay the captured step `steps` times on `stream`. */
 int gi_fit_graph_launch(gi_graph *graph, int32_t steps, void *stream);
+/* gi_query on the graph's private workspace (waits for the device). */
+int gi_fit_graph_query(gi_graph *graph, int64_t *last_keys, uint32_t *flags, int clear);
+/* Wait for the device, then release the graph and its workspace. */
 int gi_fit_graph_destroy(gi_graph *graph);
 
 /* ---- the binning stages, for inspection and testing ---------------------------------------- */

@@ -316,6 +316,40 @@ def fd_grads(params, height: int, width: int, dl_dimage, which=None, rel_step=1e
     return out
 
 
+def fd_local(params, height: int, width: int, dl_dimage, n: int, rel_step=1e-6):
+    """Central finite differences of S = <dL/dC, C> for Gaussian n alone, float64.
+
+    Only Gaussian n's own term changes when its parameters move, so S(theta + h) - S(theta - h)
+    is evaluated over n's tile support (held at the unperturbed rectangle, which the caller
+    checks does not move) without touching the other Gaussians.  Returns the 8 derivatives.
+    """
+    p = _f64(params)[n].copy()
+    G = np.asarray(dl_dimage, dtype=np.float64).reshape(height, width, 3)
+    rect, count = tile_rects(np.asarray(params, np.float32)[n:n + 1], height, width)
+    out = np.zeros(8)
+    if count[0] == 0:
+        return out
+    x0, x1, y0, y1 = _gauss_box(rect[0], height, width)
+    xs = np.arange(x0, x1, dtype=np.float64)
+    ys = np.arange(y0, y1, dtype=np.float64)
+    g = G[y0:y1, x0:x1]
+
+    def term(q):
+        l1, l2, l3 = q[2], q[3], q[4]
+        det = (l1 * l3) ** 2
+        inv = ((l2 * l2 + l3 * l3) / det, -(l1 * l2) / det, (l1 * l1) / det)
+        s, _, _ = _sigma(q, inv, xs, ys)
+        return np.sum(g * (np.exp(-s)[:, :, None] * q[5:8]))
+
+    for k in range(8):
+        h = rel_step * max(1.0, abs(p[k]))
+        qp, qm = p.copy(), p.copy()
+        qp[k] += h
+        qm[k] -= h
+        out[k] = (term(qp) - term(qm)) / (2.0 * h)
+    return out
+
+
 def _render64(p64, height, width, culled, rect0, moved):
     """Render float64 parameters (no float32 rounding), used by finite differences only.  With
     ``culled`` the support is the unperturbed ``rect0``, after checking that the perturbed

@@ -334,6 +334,14 @@ class FitGraph:
                                                        _stream(self.ctx.device)),
                         "gi_fit_graph_launch")
 
+    def query(self, clear: bool = False):
+        """(key count of the last binning, sticky flags) of the graph's own workspace."""
+        k = ctypes.c_int64()
+        f = ctypes.c_uint32()
+        self.ctx._raise(_lib.lib().gi_fit_graph_query(self._g, ctypes.byref(k), ctypes.byref(f),
+                                                      int(clear)), "gi_fit_graph_query")
+        return k.value, f.value
+
     def close(self):
         if self._g is not None and self._g.value:
             _lib.lib().gi_fit_graph_destroy(self._g)

@@ -20,6 +20,7 @@ GI_ERR_NO_DEVICE = -6
 
 GI_FLAG_KEY_OVERFLOW = 1
 GI_FLAG_NONFINITE = 2
+GI_FLAG_SCAN_STALL = 4
 
 GI_OPT_SYNC = 1
 GI_OPT_SORT_BITS = 2
@@ -39,7 +40,7 @@ EXPORTS = (
     "gi_last_error", "gi_render", "gi_grad", "gi_fit_step", "gi_render_batched",
     "gi_grad_batched", "gi_fit_step_batched", "gi_fit_graph_create", "gi_fit_graph_launch",
     "gi_fit_graph_destroy", "gi_binning", "gi_scan_u32", "gi_sort_pairs", "gi_timing",
-    "gi_get_option", "gi_autotune",
+    "gi_get_option", "gi_autotune", "gi_fit_graph_query",
 )
 
 
@@ -102,6 +103,8 @@ def lib():
                                     ctypes.c_int),
             "gi_fit_graph_launch": ([P, I32, P], ctypes.c_int),
             "gi_fit_graph_destroy": ([P], ctypes.c_int),
+            "gi_fit_graph_query": ([P, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_uint32),
+                                    ctypes.c_int], ctypes.c_int),
             "gi_binning": ([P, P, I64, I32, I32, P, P, P, P, P, I64, ctypes.POINTER(I64), P],
                            ctypes.c_int),
             "gi_scan_u32": ([P, P, P, I64, P, P], ctypes.c_int),

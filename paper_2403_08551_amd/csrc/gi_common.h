@@ -25,6 +25,8 @@ constexpr int TILE = 16;
 constexpr int TILE_PX = TILE * TILE;
 constexpr uint32_t FLAG_KEY_OVERFLOW = 1u;
 constexpr uint32_t FLAG_NONFINITE = 2u;
+constexpr uint32_t FLAG_SCAN_STALL = 4u;
+constexpr int64_t FUSED_MAX_TILES = 2048;
 
 // sqrt(log2(e) / 2): scales L^{-1} d so that exp(-sigma) = exp2(-|u|^2)
 constexpr double U_SCALE = 0.84932180028801904272;
@@ -33,6 +35,8 @@ constexpr double U_SCALE = 0.84932180028801904272;
 struct DevState {
     unsigned long long keys_total;  // keys of the last binning (may exceed capacity)
     uint32_t flags;                 // sticky FLAG_*
+    uint32_t spare;
+    uint32_t scan_epoch;            // launch tag of the one-pass scan's status words
     uint32_t pad;
 };
 
@@ -117,6 +121,19 @@ hipError_t launch_ranges_gather(const BinBuffers &b, int which, const ImgTable &
                                 int64_t n_max, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 
+// One-pass binning (n_tiles <= FUSED_MAX_TILES): A = projection + per-chunk tile counts +
+// chained scan (writes state->keys_total); C = stable scatter into tile order + ranges.
+struct FusedBuffers {
+    BinBuffers b;
+    uint32_t *scan;                 // [fused_scan_entries]
+    unsigned long long *status;     // [fused_scan_blocks], epoch-tagged
+};
+int64_t fused_chunks(int64_t n);
+int64_t fused_scan_entries(int64_t n, int64_t n_tiles);
+int64_t fused_scan_blocks(int64_t n, int64_t n_tiles);
+hipError_t launch_fused_a(const FusedBuffers &f, const ImgTable &tab, hipStream_t s);
+hipError_t launch_fused_c(const FusedBuffers &f, uint32_t *ids, hipStream_t s);
+
 // generic pieces, also exported for testing
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n,
                            unsigned long long *blocksum, unsigned long long *total,
@@ -151,15 +168,17 @@ struct UpdateArgs {
     const uint32_t *count;
     const uint32_t *off;
     const float *part;
-    const DevState *state;
+    DevState *state;
     int64_t cap;
 };
 hipError_t launch_grad_out(const UpdateArgs &u, float *dparams, hipStream_t s);
 struct AdamArgs {
     float lr_mu, lr_l, lr_c, beta1, beta2, eps, l_min;
 };
+// Adam update; also finishes the step (per-image loss when loss_out != nullptr, step += 1).
 hipError_t launch_adam(const UpdateArgs &u, float *params, float *m, float *v,
-                       int32_t *step, const AdamArgs &hp, hipStream_t s);
+                       int32_t *step, const AdamArgs &hp, const float *loss_part,
+                       const ImgTable &tab, int64_t n_tiles, float *loss_out, hipStream_t s);
 // Per-image loss from the per-tile sums (when loss_out != nullptr) and step += 1 (when
 // step != nullptr).
 hipError_t launch_finish(const float *loss_part, const ImgTable &tab, int64_t n_tiles,

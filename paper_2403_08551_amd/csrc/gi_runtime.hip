@@ -22,6 +22,7 @@ struct gi_ctx {
     int sort_bits = 0;
     int fwd_px = 0;
     int binning = 0;
+    int want_ids = 0;  // the one-pass binning writes sorted Gaussian ids only for gi_binning
     int64_t cap_n = 0, cap_t = 0, cap_k = 0;
     int64_t last_keys = 0;
     // per Gaussian
@@ -41,6 +42,12 @@ struct gi_ctx {
     int64_t hist_cap = 0;
     unsigned long long *scan_bs = nullptr;
     int64_t scan_cap = 0;
+    // one-pass binning scratch
+    uint32_t *fscan = nullptr;
+    int64_t fscan_cap = 0;
+    unsigned long long *fstatus = nullptr;
+    int64_t fstatus_cap = 0;
+    const uint32_t *off_cur = nullptr;  // key offsets of the last binning
     // per tile
     uint2 *ranges = nullptr;
     float *loss_part = nullptr;
@@ -356,6 +363,58 @@ BinBuffers bin_buffers(gi_ctx *ctx, const float *params, int64_t n, int64_t n_ti
     return b;
 }
 
+int ensure_fused(gi_ctx *ctx, int64_t n, int64_t n_tiles) {
+    const int64_t ent = fused_scan_entries(n, n_tiles);
+    const int64_t blocks = fused_scan_blocks(n, n_tiles);
+    if (ent > ctx->fscan_cap) {
+        CK(hipDeviceSynchronize());
+        const int64_t c = ent + ent / 4;
+        CK(grow(&ctx->fscan, c));
+        ctx->fscan_cap = c;
+    }
+    if (blocks > ctx->fstatus_cap) {
+        CK(hipDeviceSynchronize());
+        const int64_t c = std::max<int64_t>(blocks + blocks / 4, 64);
+        CK(grow(&ctx->fstatus, c));
+        CK(hipMemset(ctx->fstatus, 0, sizeof(unsigned long long) * c));  // no flag: unpublished
+        ctx->fstatus_cap = c;
+    }
+    return GI_OK;
+}
+
+// One-pass binning: projection with per-chunk tile counts, one chained scan, and the stable
+// scatter of records into tile order (n >= 1, n_tiles <= FUSED_MAX_TILES).
+int run_binning_fused(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab,
+                      int64_t n_tiles, hipStream_t s, int64_t *bound, int *which) {
+    int rc;
+    if ((rc = ensure_fused(ctx, n, n_tiles)) != GI_OK) return rc;
+    FusedBuffers f;
+    f.b = bin_buffers(ctx, params, n, n_tiles);
+    f.scan = ctx->fscan;
+    f.status = ctx->fstatus;
+    StageTimer tm(ctx, s, GI_STAGE_BINNING);
+    CK(launch_fused_a(f, tab, s));
+    int64_t K = ctx->cap_k;
+    if (ctx->sync) {
+        CK(hipMemcpyAsync(ctx->pinned, &ctx->state->keys_total, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        K = (int64_t)*ctx->pinned;
+        ctx->last_keys = K;
+        if (K > MAX_KEYS) return GI_ERR_CAPACITY;
+        if (K > ctx->cap_k) {
+            if ((rc = ensure_keys(ctx, K + K / 4)) != GI_OK) return rc;
+            f.b = bin_buffers(ctx, params, n, n_tiles);
+        }
+    }
+    CK(launch_fused_c(f, ctx->want_ids ? ctx->vals[0] : nullptr, s));
+    tm.stop();
+    ctx->off_cur = ctx->fscan;
+    *which = 0;
+    *bound = K;
+    return GI_OK;
+}
+
 // Projection, scan, duplication, sort, ranges and gather.  *bound receives the key bound the
 // later kernels are sized for; *which the ping-pong buffer holding the sorted pairs.
 int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab,
@@ -364,6 +423,9 @@ int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab
     if ((rc = ensure_gauss(ctx, n)) != GI_OK) return rc;
     if ((rc = ensure_tiles(ctx, n_tiles)) != GI_OK) return rc;
     if (ctx->cap_k == 0 && (rc = ensure_keys(ctx, 4096)) != GI_OK) return rc;
+    if (ctx->binning != 1 && n > 0 && n_tiles <= FUSED_MAX_TILES)
+        return run_binning_fused(ctx, params, n, tab, n_tiles, s, bound, which);
+    ctx->off_cur = ctx->off;
     BinBuffers b = bin_buffers(ctx, params, n, n_tiles);
     StageTimer tm(ctx, s, GI_STAGE_BINNING);
     CK(launch_project(b, tab, s));
@@ -415,7 +477,7 @@ int do_grad(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab, in
     StageTimer tm(ctx, s, GI_STAGE_RASTER_BWD);
     CK(launch_raster_bwd(a, dl, ctx->part, s));
     tm.stop();
-    UpdateArgs u{params, nullptr, n, ctx->count, ctx->off, ctx->part, ctx->state, ctx->cap_k};
+    UpdateArgs u{params, nullptr, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k};
     StageTimer tu(ctx, s, GI_STAGE_UPDATE);
     CK(launch_grad_out(u, dparams, s));
     tu.stop();
@@ -434,12 +496,11 @@ int do_fit(gi_ctx *ctx, float *params, float *m, float *v, const float *target, 
     CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
                          pick_px(ctx, n, table_pixels(tab, n_tiles)), s));
     tm.stop();
-    UpdateArgs u{params, params, n, ctx->count, ctx->off, ctx->part, ctx->state, ctx->cap_k};
+    UpdateArgs u{params, params, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k};
     AdamArgs h{hp->lr_mu, hp->lr_l, hp->lr_c, hp->beta1, hp->beta2, hp->eps, hp->l_min};
     StageTimer tu(ctx, s, GI_STAGE_UPDATE);
-    CK(launch_adam(u, params, m, v, step, h, s));
+    CK(launch_adam(u, params, m, v, step, h, ctx->loss_part, tab, n_tiles, loss_out, s));
     tu.stop();
-    CK(launch_finish(ctx->loss_part, tab, n_tiles, loss_out, step, s));
     return GI_OK;
 }
 
@@ -502,7 +563,7 @@ int gi_destroy(gi_ctx *ctx) {
                     ctx->keys[0], ctx->keys[1], ctx->vals[0], ctx->vals[1], ctx->rec, ctx->slot,
                     ctx->part, ctx->hist, ctx->scan_bs, ctx->ranges, ctx->loss_part, ctx->state,
                     ctx->dims, ctx->tile_base, ctx->gauss_off, ctx->pix_off, ctx->tmp_k,
-                    ctx->tmp_v};
+                    ctx->tmp_v, ctx->fscan, ctx->fstatus};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -788,66 +849,71 @@ int gi_fit_step_batched(gi_ctx *ctx, float *params, float *m, float *v, const fl
                   (hipStream_t)stream);
 }
 
-int gi_fit_graph_create(gi_ctx *ctx, float *params, float *m, float *v, const float *target,
+int gi_fit_graph_create(gi_ctx *user, float *params, float *m, float *v, const float *target,
                         int64_t n, int32_t H, int32_t W, const gi_batch *batch,
                         const gi_adam *hp, int32_t *step, float *image_out, float *loss_out,
                         void *stream, gi_graph **out) {
     if (!out) return GI_ERR_INVALID_ARG;
     *out = nullptr;
-    if (!ctx || !target || !step || check_adam(hp) != GI_OK) return GI_ERR_INVALID_ARG;
-    ImgTable tab;
-    int64_t T;
-    DeviceGuard g(ctx->device);
+    if (!user || !target || !step || check_adam(hp) != GI_OK) return GI_ERR_INVALID_ARG;
     if (batch) {
         if (check_batch(batch) != GI_OK) return GI_ERR_INVALID_ARG;
         n = batch->gauss_off_host[batch->count];
-        int64_t N, P;
-        int rc = upload_batch(ctx, batch, &tab, &T, &N, &P);
-        if (rc != GI_OK) return rc;
-    } else {
-        if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
-        tab = single_table(H, W);
-        T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    } else if (check_single(n, H, W) != GI_OK) {
+        return GI_ERR_INVALID_ARG;
     }
     if (n > 0 && (!params || !m || !v || !aligned16(params) || !aligned16(m) || !aligned16(v)))
         return GI_ERR_INVALID_ARG;
+    // The graph bakes in workspace addresses, so it gets a workspace of its own that no later
+    // call can reallocate: a private context with the caller's settings.
+    gi_ctx *ctx = nullptr;
+    int rc = gi_create(&ctx, user->device);
+    if (rc != GI_OK) return rc;
+    ctx->sort_bits = user->sort_bits;
+    ctx->fwd_px = user->fwd_px;
+    ctx->binning = user->binning;
+    ctx->tuned = user->tuned;
+    gi_graph *gr = new gi_graph();
+    gr->ctx = ctx;
+    auto fail = [&](int code) {
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        delete gr;
+        user->err = ctx->err;
+        gi_destroy(ctx);
+        return code;
+    };
+    DeviceGuard g(ctx->device);
+    ImgTable tab;
+    int64_t T;
+    if (batch) {
+        int64_t N, P;
+        rc = upload_batch(ctx, batch, &tab, &T, &N, &P);
+        if (rc != GI_OK) return fail(rc);
+    } else {
+        tab = single_table(H, W);
+        T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    }
     // one synchronous binning pass sizes the workspace: keys with a 25% margin
     hipStream_t s = (hipStream_t)stream;
-    const int saved_sync = ctx->sync;
     ctx->sync = 1;
     int64_t bound;
     int which;
-    int rc = run_binning(ctx, params, n, tab, T, s, &bound, &which);
+    rc = run_binning(ctx, params, n, tab, T, s, &bound, &which);
     if (rc == GI_OK) rc = ensure_keys(ctx, bound + bound / 4 + 4096);
-    if (rc != GI_OK) {
-        ctx->sync = saved_sync;
-        return rc;
-    }
-    CK(hipStreamSynchronize(s));
+    if (rc != GI_OK) return fail(rc);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamSynchronize"));
     ctx->sync = 0;
-    gi_graph *gr = new gi_graph();
-    gr->ctx = ctx;
     hipStream_t cs = ctx->capture_stream;
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) {
-        ctx->sync = saved_sync;
-        delete gr;
-        return hip_fail(ctx, e, "hipStreamBeginCapture");
-    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamBeginCapture"));
     rc = do_fit(ctx, params, m, v, target, n, tab, T, hp, step, image_out, loss_out, cs);
     e = hipStreamEndCapture(cs, &gr->graph);
-    ctx->sync = saved_sync;
-    if (rc != GI_OK || e != hipSuccess) {
-        if (gr->graph) (void)hipGraphDestroy(gr->graph);
-        delete gr;
-        return rc != GI_OK ? rc : hip_fail(ctx, e, "hipStreamEndCapture");
-    }
+    if (rc != GI_OK) return fail(rc);
+    if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamEndCapture"));
     e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(gr->graph);
-        delete gr;
-        return hip_fail(ctx, e, "hipGraphInstantiate");
-    }
+    if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipGraphInstantiate"));
     *out = gr;
     return GI_OK;
 }
@@ -860,11 +926,20 @@ int gi_fit_graph_launch(gi_graph *gr, int32_t steps, void *stream) {
     return GI_OK;
 }
 
+int gi_fit_graph_query(gi_graph *gr, int64_t *last_keys, uint32_t *flags, int clear) {
+    if (!gr) return GI_ERR_INVALID_ARG;
+    return gi_query(gr->ctx, last_keys, flags, clear);
+}
+
 int gi_fit_graph_destroy(gi_graph *gr) {
     if (!gr) return GI_OK;
-    DeviceGuard g(gr->ctx->device);
-    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
-    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    {
+        DeviceGuard g(gr->ctx->device);
+        (void)hipDeviceSynchronize();
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    }
+    gi_destroy(gr->ctx);
     delete gr;
     return GI_OK;
 }
@@ -881,15 +956,17 @@ int gi_binning(gi_ctx *ctx, const float *params, int64_t n, int32_t H, int32_t W
     const int64_t T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
     const int saved_sync = ctx->sync;
     ctx->sync = 1;
+    ctx->want_ids = 1;
     int64_t bound;
     int which;
     int rc = run_binning(ctx, params, n, tab, T, s, &bound, &which);
     ctx->sync = saved_sync;
+    ctx->want_ids = 0;
     if (rc != GI_OK) return rc;
     if (n > 0) {
         if (rects) CK(hipMemcpyAsync(rects, ctx->rect, sizeof(int4) * n, hipMemcpyDeviceToDevice, s));
         if (counts) CK(hipMemcpyAsync(counts, ctx->count, 4 * n, hipMemcpyDeviceToDevice, s));
-        if (offsets) CK(hipMemcpyAsync(offsets, ctx->off, 4 * n, hipMemcpyDeviceToDevice, s));
+        if (offsets) CK(hipMemcpyAsync(offsets, ctx->off_cur, 4 * n, hipMemcpyDeviceToDevice, s));
     }
     if (ranges) CK(hipMemcpyAsync(ranges, ctx->ranges, sizeof(uint2) * T, hipMemcpyDeviceToDevice, s));
     if (keys_host) *keys_host = bound;

@@ -75,6 +75,68 @@ __device__ inline bool covers(double r, double s00, double s01, double s11) {
 
 constexpr double R_MAX = 33554432.0;  // 2^25: covers any image once |mu| <= 2^24
 
+// Projection and tile rectangle of Gaussian i (see the file header of k_raster.hip for the
+// stored record).  Writes proj, rect, tinfo and count; returns the count.
+__device__ inline uint32_t project_one(const float4 *__restrict__ params, int64_t i,
+                                       const ImgTable &tab, float4 *__restrict__ proj,
+                                       int4 *__restrict__ rect, uint2 *__restrict__ tinfo,
+                                       uint32_t *__restrict__ count, bool *nonfinite,
+                                       int4 *rc_out, uint2 *inf_out) {
+#pragma clang fp contract(off)
+    uint32_t cnt = 0;
+    const float4 q0 = params[2 * i], q1 = params[2 * i + 1];
+    const float q[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    int32_t TW, TH;
+    uint32_t tb;
+    if (tab.B == 1) {
+        TW = tab.TW; TH = (tab.H + TILE - 1) / TILE; tb = 0;
+    } else {
+        int32_t b = upper_index(tab.gauss_off, tab.B, (uint32_t)i);
+        int4 d = tab.dims[b];
+        TW = d.z; TH = d.w; tb = tab.tile_base[b];
+    }
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) finite = finite && isfinite(q[k]);
+    *nonfinite = !finite;
+    const double mx = q[0], my = q[1], l1 = q[2], l2 = q[3], l3 = q[4];
+    bool act = finite && fabs(l1) >= 0x1p-24 && fabs(l3) >= 0x1p-24 && fabs(l2) <= 0x1p24 &&
+               fabs(mx) <= 0x1p24 && fabs(my) <= 0x1p24;
+    int4 rc = make_int4(0, 0, -1, -1);
+    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
+    if (act) {
+        const double s00 = l1 * l1, s01 = l1 * l2, s11 = l2 * l2 + l3 * l3;
+        // starting guess from the eigenvalue formula, then the least r that covers
+        const double lam = 0.5 * (s00 + s11) + sqrt(0.25 * (s00 - s11) * (s00 - s11) + s01 * s01);
+        double r = ceil(3.0 * sqrt(lam));
+        if (!(r >= 0.0)) r = 0.0;
+        if (r > R_MAX) r = R_MAX;
+        while (r > 0.0 && covers(r - 1.0, s00, s01, s11)) r -= 1.0;
+        while (r < R_MAX && !covers(r, s00, s01, s11)) r += 1.0;
+        double fx0 = floor((mx - r) / 16.0), fx1 = floor((mx + r) / 16.0);
+        double fy0 = floor((my - r) / 16.0), fy1 = floor((my + r) / 16.0);
+        if (fx0 < 0.0) fx0 = 0.0;
+        if (fy0 < 0.0) fy0 = 0.0;
+        if (fx1 > TW - 1.0) fx1 = TW - 1.0;
+        if (fy1 > TH - 1.0) fy1 = TH - 1.0;
+        if (fx0 <= fx1 && fy0 <= fy1) {
+            rc = make_int4((int)fx0, (int)fy0, (int)fx1, (int)fy1);
+            cnt = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
+        }
+        p0 = make_float4(q[0], q[1], (float)(U_SCALE / l1), (float)(U_SCALE / l3));
+        p1 = make_float4((float)(U_SCALE * l2 / (l1 * l3)), q[5], q[6], q[7]);
+    }
+    proj[2 * i] = p0;
+    proj[2 * i + 1] = p1;
+    rect[i] = rc;
+    const uint2 inf = make_uint2(tb, (uint32_t)TW);
+    tinfo[i] = inf;
+    count[i] = cnt;
+    *rc_out = rc;
+    *inf_out = inf;
+    return cnt;
+}
+
 __global__ __launch_bounds__(BLK) void k_project(const float4 *__restrict__ params, int64_t n,
                                                  ImgTable tab, float4 *__restrict__ proj,
                                                  int4 *__restrict__ rect,
@@ -82,59 +144,14 @@ __global__ __launch_bounds__(BLK) void k_project(const float4 *__restrict__ para
                                                  uint32_t *__restrict__ count,
                                                  unsigned long long *__restrict__ blocksum,
                                                  DevState *state) {
-#pragma clang fp contract(off)
     __shared__ unsigned long long tmp[BLK / 64 + 1];
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     uint32_t cnt = 0;
     bool nonfinite = false;
     if (i < n) {
-        const float4 q0 = params[2 * i], q1 = params[2 * i + 1];
-        const float q[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-        int32_t TW, TH;
-        uint32_t tb;
-        if (tab.B == 1) {
-            TW = tab.TW; TH = (tab.H + TILE - 1) / TILE; tb = 0;
-        } else {
-            int32_t b = upper_index(tab.gauss_off, tab.B, (uint32_t)i);
-            int4 d = tab.dims[b];
-            TW = d.z; TH = d.w; tb = tab.tile_base[b];
-        }
-        bool finite = true;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) finite = finite && isfinite(q[k]);
-        nonfinite = !finite;
-        const double mx = q[0], my = q[1], l1 = q[2], l2 = q[3], l3 = q[4];
-        bool act = finite && fabs(l1) >= 0x1p-24 && fabs(l3) >= 0x1p-24 && fabs(l2) <= 0x1p24 &&
-                   fabs(mx) <= 0x1p24 && fabs(my) <= 0x1p24;
-        int4 rc = make_int4(0, 0, -1, -1);
-        float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
-        if (act) {
-            const double s00 = l1 * l1, s01 = l1 * l2, s11 = l2 * l2 + l3 * l3;
-            // starting guess from the eigenvalue formula, then the least r that covers
-            const double lam = 0.5 * (s00 + s11) + sqrt(0.25 * (s00 - s11) * (s00 - s11) + s01 * s01);
-            double r = ceil(3.0 * sqrt(lam));
-            if (!(r >= 0.0)) r = 0.0;
-            if (r > R_MAX) r = R_MAX;
-            while (r > 0.0 && covers(r - 1.0, s00, s01, s11)) r -= 1.0;
-            while (r < R_MAX && !covers(r, s00, s01, s11)) r += 1.0;
-            double fx0 = floor((mx - r) / 16.0), fx1 = floor((mx + r) / 16.0);
-            double fy0 = floor((my - r) / 16.0), fy1 = floor((my + r) / 16.0);
-            if (fx0 < 0.0) fx0 = 0.0;
-            if (fy0 < 0.0) fy0 = 0.0;
-            if (fx1 > TW - 1.0) fx1 = TW - 1.0;
-            if (fy1 > TH - 1.0) fy1 = TH - 1.0;
-            if (fx0 <= fx1 && fy0 <= fy1) {
-                rc = make_int4((int)fx0, (int)fy0, (int)fx1, (int)fy1);
-                cnt = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
-            }
-            p0 = make_float4(q[0], q[1], (float)(U_SCALE / l1), (float)(U_SCALE / l3));
-            p1 = make_float4((float)(U_SCALE * l2 / (l1 * l3)), q[5], q[6], q[7]);
-        }
-        proj[2 * i] = p0;
-        proj[2 * i + 1] = p1;
-        rect[i] = rc;
-        tinfo[i] = make_uint2(tb, (uint32_t)TW);
-        count[i] = cnt;
+        int4 rc;
+        uint2 inf;
+        cnt = project_one(params, i, tab, proj, rect, tinfo, count, &nonfinite, &rc, &inf);
     }
     if (__ballot(nonfinite) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_NONFINITE);
     unsigned long long tot;
@@ -468,6 +485,308 @@ __global__ __launch_bounds__(BLK) void k_fill_u32(uint32_t *__restrict__ p, uint
     if (i < n) p[i] = v;
 }
 
+// ---- one-pass binning for up to FUSED_MAX_TILES tiles --------------------------------------
+//
+// (A) k_project_hist: projection of a chunk of 256 Gaussians and the chunk's per-tile key
+//     counts, written tile-major after the Gaussian counts: scan[n + t * nchunk + chunk].
+// (B) k_chained_scan: exclusive scan of scan[0 .. n + T nchunk) in one pass (each block
+//     publishes its sum and looks back over its predecessors).  The first n entries become the
+//     key offsets of the Gaussians; entry n + t nchunk + c becomes K + the position of chunk c's
+//     first key of tile t in tile order.
+// (C) k_fused_scatter: each chunk enumerates its keys again in Gaussian-major order, ranks them
+//     stably per tile, and writes the records, slots and Gaussian ids straight into tile order,
+//     plus the tile ranges.  No key array is written or sorted: this is the counting sort by
+//     tile id in one pass, and the result equals that of the stable radix sort.
+
+constexpr int FB = 256;
+constexpr int FUSED_WAVES = FB / 64;
+constexpr int XCDS = 8;
+
+// Workgroup i runs on XCD i mod 8.  Give each XCD a contiguous range of chunks, so that the
+// chunks writing neighbouring positions of a tile's list share one L2 and their partial-line
+// writes combine there before reaching memory.
+__device__ inline uint32_t xcd_chunk(uint32_t i, uint32_t nchunk) {
+    const uint32_t q = nchunk / XCDS, rem = nchunk % XCDS;
+    const uint32_t x = i % XCDS, k = i / XCDS;
+    return x * q + (x < rem ? x : rem) + k;
+}
+constexpr int CS_T = 256;
+constexpr int CS_IPT = 16;
+constexpr int CS_TILE = CS_T * CS_IPT;
+// status word: epoch tag (29 bits) | flag (2 bits: 1 = block sum, 2 = inclusive prefix) |
+// value (33 bits; every prefix is at most twice the key count)
+constexpr int CS_EPOCH_SHIFT = 35;
+constexpr int CS_FLAG_SHIFT = 33;
+constexpr unsigned long long CS_TAG_MASK = 0x1fffffffull << CS_EPOCH_SHIFT;
+constexpr unsigned long long CS_FLAG_MASK = 3ull << CS_FLAG_SHIFT;
+constexpr unsigned long long CS_AGG = 1ull << CS_FLAG_SHIFT;
+constexpr unsigned long long CS_PRE = 2ull << CS_FLAG_SHIFT;
+constexpr unsigned long long CS_VAL = (1ull << CS_FLAG_SHIFT) - 1;
+constexpr long SPIN_LIMIT = 1l << 20;
+
+__global__ __launch_bounds__(FB) void k_project_hist(const float4 *__restrict__ params, int64_t n,
+                                                     ImgTable tab, float4 *__restrict__ proj,
+                                                     int4 *__restrict__ rect,
+                                                     uint2 *__restrict__ tinfo,
+                                                     uint32_t *__restrict__ count,
+                                                     uint32_t *__restrict__ scan, int32_t T,
+                                                     int64_t nchunk, DevState *state) {
+    extern __shared__ uint32_t h[];  // [T]
+    // a new epoch for the scan that follows (see k_chained_scan)
+    if (blockIdx.x == 0 && threadIdx.x == 0) state->scan_epoch += 1u;
+    for (int t = threadIdx.x; t < T; t += FB) h[t] = 0;
+    __syncthreads();
+    const uint32_t chunk = xcd_chunk(blockIdx.x, (uint32_t)nchunk);
+    const int64_t i = (int64_t)chunk * FB + threadIdx.x;
+    bool nonfinite = false;
+    if (i < n) {
+        int4 rc;
+        uint2 inf;
+        const uint32_t cnt = project_one(params, i, tab, proj, rect, tinfo, count, &nonfinite,
+                                         &rc, &inf);
+        scan[i] = cnt;
+        if (cnt) {
+            for (int ty = rc.y; ty <= rc.w; ++ty)
+                for (int tx = rc.x; tx <= rc.z; ++tx)
+                    atomicAdd(&h[inf.x + (uint32_t)ty * inf.y + (uint32_t)tx], 1u);
+        }
+    }
+    if (__ballot(nonfinite) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_NONFINITE);
+    __syncthreads();
+    for (int t = threadIdx.x; t < T; t += FB) scan[n + (int64_t)t * nchunk + chunk] = h[t];
+}
+
+__device__ inline unsigned long long load_status(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive scan of data[0 .. L) in place, one pass.  Block w publishes its sum (flag CS_AGG)
+// and then its inclusive prefix (flag CS_PRE) in status[w]; its first wave looks back over
+// predecessors 64 at a time.  Each status word carries the launch's epoch (read from the context
+// state, advanced by the kernel that runs just before every scan), so words left by earlier
+// launches read as "not yet published" and nothing needs clearing between launches.  Blocks are dispatched in
+// index order, so every predecessor a block waits for is already running; every wait is still
+// bounded (SPIN_LIMIT polls, then a stall flag), so the grid always drains.
+// *mark_out (if not null) receives the exclusive prefix at index `mark`.
+__global__ __launch_bounds__(CS_T) void k_chained_scan(uint32_t *__restrict__ data, int64_t L,
+                                                       unsigned long long *__restrict__ status,
+                                                       int64_t mark,
+                                                       unsigned long long *__restrict__ mark_out,
+                                                       DevState *state) {
+    __shared__ unsigned long long s_prefix;
+    __shared__ unsigned long long tmp[CS_T / 64 + 1];
+    __shared__ uint32_t stage[CS_TILE];
+    const uint32_t w = blockIdx.x;
+    const unsigned long long tag = (unsigned long long)(state->scan_epoch & 0x1fffffffu) << CS_EPOCH_SHIFT;
+    const int64_t base = (int64_t)w * CS_TILE;
+#pragma unroll
+    for (int j = 0; j < CS_IPT; ++j) {
+        const int64_t idx = base + j * CS_T + threadIdx.x;
+        stage[j * CS_T + threadIdx.x] = idx < L ? data[idx] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[CS_IPT];
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int j = 0; j < CS_IPT; ++j) {
+        v[j] = stage[threadIdx.x * CS_IPT + j];
+        sum += v[j];
+    }
+    unsigned long long agg;
+    const unsigned long long loc = block_exclusive_scan<unsigned long long, CS_T>(sum, tmp, &agg);
+    if (threadIdx.x == 0) {
+        // relaxed: the word carries all it publishes, nothing else needs ordering with it
+        __hip_atomic_store(&status[w], tag | (w == 0 ? CS_PRE : CS_AGG) | (agg & CS_VAL),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (w == 0) s_prefix = 0;
+    }
+    if (w > 0 && threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        unsigned long long excl = 0;
+        int64_t j = (int64_t)w - 1;
+        bool stalled = false;
+        while (true) {
+            const int64_t q = j - lane;
+            unsigned long long fl = 2, val = 0;  // before block 0: prefix 0
+            if (q >= 0) {
+                long spins = 0;
+                unsigned long long st = load_status(&status[q]);
+                // published in this launch: the tag matches and a flag is set
+                while (((st & CS_TAG_MASK) != tag || (st & CS_FLAG_MASK) == 0) &&
+                       spins < SPIN_LIMIT) {
+                    st = load_status(&status[q]);
+                    ++spins;
+                }
+                if ((st & CS_TAG_MASK) != tag || (st & CS_FLAG_MASK) == 0) {
+                    stalled = true;
+                    fl = 2;
+                    val = 0;
+                } else {
+                    fl = (st >> CS_FLAG_SHIFT) & 3ull;
+                    val = st & CS_VAL;
+                }
+            }
+            const unsigned long long pre_mask = __ballot(fl == 2);
+            const int first = pre_mask ? __ffsll((long long)pre_mask) - 1 : 64;
+            unsigned long long contrib = lane <= first ? val : 0ull;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) contrib += __shfl_xor(contrib, d, 64);
+            excl += contrib;
+            if (pre_mask) break;
+            j -= 64;
+        }
+        if (__ballot(stalled) && lane == 0) atomicOr(&state->flags, FLAG_SCAN_STALL);
+        if (lane == 0) {
+            __hip_atomic_store(&status[w], tag | CS_PRE | ((excl + agg) & CS_VAL),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_prefix = excl;
+        }
+    }
+    __syncthreads();
+    unsigned long long run = s_prefix + loc;
+#pragma unroll
+    for (int j = 0; j < CS_IPT; ++j) {
+        const int64_t idx = base + threadIdx.x * CS_IPT + j;
+        if (mark_out && idx == mark) *mark_out = run;
+        stage[threadIdx.x * CS_IPT + j] = (uint32_t)run;
+        run += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < CS_IPT; ++j) {
+        const int64_t idx = base + j * CS_T + threadIdx.x;
+        if (idx < L) data[idx] = stage[j * CS_T + threadIdx.x];
+    }
+}
+
+// Lanes of the wave whose tile equals this lane's, deciding `nbits` bits.
+__device__ inline unsigned long long match_bits(uint32_t d, bool valid, int nbits) {
+    unsigned long long peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const unsigned long long bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
+__global__ __launch_bounds__(FB) void k_fused_scatter(
+    const uint32_t *__restrict__ count, const int4 *__restrict__ rect,
+    const uint2 *__restrict__ tinfo, const float4 *__restrict__ proj,
+    const uint32_t *__restrict__ scan, int64_t n, int32_t T, int32_t tbits, int64_t nchunk,
+    int64_t cap, float4 *__restrict__ rec, uint32_t *__restrict__ slot,
+    uint32_t *__restrict__ ids, uint2 *__restrict__ ranges, DevState *state) {
+    extern __shared__ uint32_t dyn[];  // wh [FUSED_WAVES][T], then tbase [T]
+    uint32_t *wh = dyn;
+    uint32_t *tbase = dyn + FUSED_WAVES * T;
+    __shared__ unsigned long long tmp[FB / 64 + 1];
+    __shared__ uint32_t pre[FB];
+    __shared__ int4 srect[FB];
+    __shared__ uint2 sinfo[FB];
+    __shared__ uint32_t soff[FB];
+    __shared__ float4 sproj[2 * FB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t chunk = xcd_chunk(blockIdx.x, (uint32_t)nchunk);
+    const int64_t i = (int64_t)chunk * FB + threadIdx.x;
+    const uint32_t c = i < n ? count[i] : 0u;
+    const uint32_t K = scan[n];  // exclusive prefix after all Gaussian counts = key total
+    unsigned long long tot;
+    const unsigned long long loc = block_exclusive_scan<unsigned long long, FB>(c, tmp, &tot);
+    pre[threadIdx.x] = (uint32_t)loc;
+    if (i < n) {
+        srect[threadIdx.x] = rect[i];
+        sinfo[threadIdx.x] = tinfo[i];
+        soff[threadIdx.x] = scan[i];
+        sproj[2 * threadIdx.x] = proj[2 * i];
+        sproj[2 * threadIdx.x + 1] = proj[2 * i + 1];
+    }
+    for (int k = threadIdx.x; k < FUSED_WAVES * T; k += FB) wh[k] = 0u;
+    // first position of this chunk's keys of each tile, in tile order
+    for (int t = threadIdx.x; t < T; t += FB) tbase[t] = scan[n + (int64_t)t * nchunk + chunk] - K;
+    // tile ranges: this chunk writes tiles chunk, chunk + nchunk, ...
+    for (int64_t t = chunk + (int64_t)threadIdx.x * nchunk; t < T; t += (int64_t)FB * nchunk) {
+        uint32_t a = scan[n + t * nchunk] - K;
+        uint32_t b = t + 1 < T ? scan[n + (t + 1) * nchunk] - K : K;
+        if (a > cap) a = (uint32_t)cap;
+        if (b > cap) b = (uint32_t)cap;
+        ranges[t] = make_uint2(a, b);
+    }
+    __syncthreads();
+    const uint32_t total = (uint32_t)tot;
+    const uint32_t q = (total + FUSED_WAVES - 1) / FUSED_WAVES;
+    const uint32_t j0 = (uint32_t)wave * q;
+    const uint32_t j1 = j0 + q < total ? j0 + q : total;
+    uint32_t *my = wh + wave * T;
+    // pass 1: per-wave counts per tile
+    for (uint32_t base = j0; base < j1; base += 64) {
+        const uint32_t j = base + lane;
+        const bool valid = j < j1;
+        uint32_t t = 0;
+        if (valid) {
+            int lo = 0, hi = FB - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+            }
+            const int4 r = srect[lo];
+            const uint2 inf = sinfo[lo];
+            const uint32_t li = j - pre[lo], wd = (uint32_t)(r.z - r.x + 1);
+            t = inf.x + ((uint32_t)r.y + li / wd) * inf.y + (uint32_t)r.x + li % wd;
+        }
+        const unsigned long long peers = match_bits(t, valid, tbits);
+        if (valid && lane == __ffsll((long long)peers) - 1) my[t] += __popcll(peers);
+    }
+    __syncthreads();
+    // wave offsets within the chunk, per tile, on top of the chunk's base in tile order
+    for (int t = threadIdx.x; t < T; t += FB) {
+        uint32_t run = tbase[t];
+#pragma unroll
+        for (int w = 0; w < FUSED_WAVES; ++w) {
+            const uint32_t x = wh[w * T + t];
+            wh[w * T + t] = run;
+            run += x;
+        }
+    }
+    __syncthreads();
+    // pass 2: stable ranks and the writes into tile order
+    bool overflow = false;
+    for (uint32_t base = j0; base < j1; base += 64) {
+        const uint32_t j = base + lane;
+        const bool valid = j < j1;
+        uint32_t t = 0, li = 0;
+        int g = 0;
+        if (valid) {
+            int lo = 0, hi = FB - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+            }
+            g = lo;
+            const int4 r = srect[lo];
+            const uint2 inf = sinfo[lo];
+            li = j - pre[lo];
+            const uint32_t wd = (uint32_t)(r.z - r.x + 1);
+            t = inf.x + ((uint32_t)r.y + li / wd) * inf.y + (uint32_t)r.x + li % wd;
+        }
+        const unsigned long long peers = match_bits(t, valid, tbits);
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        const uint32_t old = valid ? my[t] : 0u;
+        if (valid && lane == __ffsll((long long)peers) - 1) my[t] = old + __popcll(peers);
+        if (valid) {
+            const uint32_t pos = old + __popcll(peers & lt);
+            if (pos < cap) {
+                rec[2 * (int64_t)pos] = sproj[2 * g];
+                rec[2 * (int64_t)pos + 1] = sproj[2 * g + 1];
+                slot[pos] = soff[g] + li;
+                if (ids) ids[pos] = chunk * FB + (uint32_t)g;
+            } else {
+                overflow = true;
+            }
+        }
+    }
+    if (__ballot(overflow) && lane == 0) atomicOr(&state->flags, FLAG_KEY_OVERFLOW);
+}
+
 inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -599,6 +918,40 @@ hipError_t launch_sort(const BinBuffers &b, int key_bits, int digit_bits, int64_
     // result in keys[1] when w == 0 (odd number of passes), in keys[0] when w == 1
     *which = (n_max <= 0) ? 0 : (w == 0 ? 1 : 0);
     return e;
+}
+
+int64_t fused_chunks(int64_t n) { return (n + FB - 1) / FB; }
+int64_t fused_scan_entries(int64_t n, int64_t n_tiles) { return n + n_tiles * fused_chunks(n); }
+int64_t fused_scan_blocks(int64_t n, int64_t n_tiles) {
+    return (fused_scan_entries(n, n_tiles) + CS_TILE - 1) / CS_TILE;
+}
+
+hipError_t launch_fused_a(const FusedBuffers &f, const ImgTable &tab, hipStream_t s) {
+    const int64_t nchunk = fused_chunks(f.b.n);
+    hipLaunchKernelGGL(k_project_hist, dim3((unsigned)nchunk), dim3(FB),
+                       sizeof(uint32_t) * (size_t)f.b.n_tiles, s,
+                       reinterpret_cast<const float4 *>(f.b.params), f.b.n, tab,
+                       reinterpret_cast<float4 *>(f.b.proj), f.b.rect, f.b.tinfo, f.b.count,
+                       f.scan, (int32_t)f.b.n_tiles, nchunk, f.b.state);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t L = fused_scan_entries(f.b.n, f.b.n_tiles);
+    hipLaunchKernelGGL(k_chained_scan, dim3((unsigned)fused_scan_blocks(f.b.n, f.b.n_tiles)),
+                       dim3(CS_T), 0, s, f.scan, L, f.status, f.b.n, &f.b.state->keys_total,
+                       f.b.state);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_c(const FusedBuffers &f, uint32_t *ids, hipStream_t s) {
+    const int64_t nchunk = fused_chunks(f.b.n);
+    int tbits = 1;
+    while (((int64_t)1 << tbits) < f.b.n_tiles) ++tbits;
+    hipLaunchKernelGGL(k_fused_scatter, dim3((unsigned)nchunk), dim3(FB),
+                       sizeof(uint32_t) * (FUSED_WAVES + 1) * (size_t)f.b.n_tiles, s, f.b.count,
+                       f.b.rect, f.b.tinfo, reinterpret_cast<const float4 *>(f.b.proj), f.scan,
+                       f.b.n, (int32_t)f.b.n_tiles, tbits, nchunk, f.b.cap,
+                       reinterpret_cast<float4 *>(f.b.rec), f.b.slot, ids, f.b.ranges, f.b.state);
+    return hipGetLastError();
 }
 
 hipError_t launch_ranges_gather(const BinBuffers &b, int which, const ImgTable &tab,

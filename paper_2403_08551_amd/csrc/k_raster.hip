@@ -28,41 +28,79 @@ constexpr int BWD_T = 256;
 
 __device__ inline float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// Forward accumulation for the PX pixels (one column) of this thread.
+// One Gaussian's contribution to the PX pixels of this lane (A = mu_x, mu_y, a, b;
+// B = k, c0, c1, c2).
+template <int PX>
+__device__ inline void fwd_eval(const float4 A, const float4 B, float px, const float (&py)[PX],
+                                float (&part)[PX][3]) {
+    const float dx = px - A.x;
+    const float u1 = A.z * dx;
+    const float u1s = u1 * u1;
+    const float t = B.x * dx;
+#pragma unroll
+    for (int j = 0; j < PX; ++j) {
+        const float dy = py[j] - A.y;
+        const float u2 = fmaf(dy, A.w, -t);
+        const float e = ex2(-fmaf(u2, u2, u1s));
+        part[j][0] = fmaf(B.y, e, part[j][0]);
+        part[j][1] = fmaf(B.z, e, part[j][1]);
+        part[j][2] = fmaf(B.w, e, part[j][2]);
+    }
+}
+
+// Forward accumulation for the PX pixels (one column) of this thread.  Records are read in
+// groups of four through the scalar unit; the next group is requested before the current one is
+// evaluated, so its latency overlaps the arithmetic.  Partial sums are folded into the totals
+// every 32 Gaussians.
 template <int PX>
 __device__ inline void fwd_tile(const float4 *__restrict__ rec, uint2 r, float px,
                                 const float (&py)[PX], float (&acc)[PX][3]) {
+    float part[PX][3];
 #pragma unroll
-    for (int j = 0; j < PX; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.f;
-    for (uint32_t c0 = r.x; c0 < r.y; c0 += CHUNK) {
-        const uint32_t c1 = c0 + CHUNK < r.y ? c0 + CHUNK : r.y;
-        float part[PX][3];
+    for (int j = 0; j < PX; ++j) {
+        acc[j][0] = acc[j][1] = acc[j][2] = 0.f;
+        part[j][0] = part[j][1] = part[j][2] = 0.f;
+    }
+    const uint32_t ng = (r.y - r.x) / 4;
+    uint32_t i = r.x;
+    float4 cur[8];
+    if (ng) {
 #pragma unroll
-        for (int j = 0; j < PX; ++j) part[j][0] = part[j][1] = part[j][2] = 0.f;
-#pragma unroll 4
-        for (uint32_t i = c0; i < c1; ++i) {
-            const float4 A = rec[2 * i];      // mu_x, mu_y, a, b
-            const float4 B = rec[2 * i + 1];  // k, c0, c1, c2
-            const float dx = px - A.x;
-            const float u1 = A.z * dx;
-            const float u1s = u1 * u1;
-            const float t = B.x * dx;
+        for (int k = 0; k < 8; ++k) cur[k] = rec[2 * (int64_t)i + k];
+        // scalar loads complete out of order and can only be awaited all together: wait here so
+        // that inside the loop only the prefetched group is outstanding during the arithmetic
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    }
+    for (uint32_t g = 0; g < ng; ++g) {
+        float4 nxt[8];
+        const bool more = g + 1 < ng;
+        if (more) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) nxt[k] = rec[2 * (int64_t)(i + 4) + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fwd_eval<PX>(cur[2 * k], cur[2 * k + 1], px, py, part);
+        i += 4;
+        if (((i - r.x) & (CHUNK - 1)) == 0) {
 #pragma unroll
             for (int j = 0; j < PX; ++j) {
-                const float dy = py[j] - A.y;
-                const float u2 = fmaf(dy, A.w, -t);
-                const float e = ex2(-fmaf(u2, u2, u1s));
-                part[j][0] = fmaf(B.y, e, part[j][0]);
-                part[j][1] = fmaf(B.z, e, part[j][1]);
-                part[j][2] = fmaf(B.w, e, part[j][2]);
+                acc[j][0] += part[j][0];
+                acc[j][1] += part[j][1];
+                acc[j][2] += part[j][2];
+                part[j][0] = part[j][1] = part[j][2] = 0.f;
             }
         }
+        if (more) {
 #pragma unroll
-        for (int j = 0; j < PX; ++j) {
-            acc[j][0] += part[j][0];
-            acc[j][1] += part[j][1];
-            acc[j][2] += part[j][2];
+            for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
         }
+    }
+    for (; i < r.y; ++i) fwd_eval<PX>(rec[2 * (int64_t)i], rec[2 * (int64_t)i + 1], px, py, part);
+#pragma unroll
+    for (int j = 0; j < PX; ++j) {
+        acc[j][0] += part[j][0];
+        acc[j][1] += part[j][1];
+        acc[j][2] += part[j][2];
     }
 }
 
@@ -290,46 +328,53 @@ __global__ __launch_bounds__(256) void k_grad_out(const float4 *__restrict__ par
     dparams[2 * i + 1] = make_float4(g[4], g[5], g[6], g[7]);
 }
 
+// Adam on every Gaussian.  Bias corrections are computed once per block in float64.
 __global__ __launch_bounds__(256) void k_adam(float4 *__restrict__ params, int64_t n,
                                               const uint32_t *__restrict__ count,
                                               const uint32_t *__restrict__ off,
-                                              const float4 *__restrict__ part,
-                                              const DevState *__restrict__ st, int64_t cap,
-                                              float4 *__restrict__ m4, float4 *__restrict__ v4,
-                                              const int32_t *__restrict__ step, AdamArgs hp) {
+                                              const float4 *__restrict__ part, DevState *st,
+                                              int64_t cap, float4 *__restrict__ m4,
+                                              float4 *__restrict__ v4, int32_t *step,
+                                              AdamArgs hp) {
+    __shared__ float s_bc[2];
+    if (threadIdx.x == 0) {
+        const double t = (double)*step;
+        s_bc[0] = (float)(1.0 - pow((double)hp.beta1, t));
+        s_bc[1] = (float)(1.0 - pow((double)hp.beta2, t));
+    }
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    if (st->flags & FLAG_KEY_OVERFLOW) return;  // gradients incomplete: leave the state alone
-    unsigned long long keys = st->keys_total;
-    if (keys > (unsigned long long)cap) keys = (unsigned long long)cap;
-    float g[8];
-    float4 q0, q1;
-    gauss_grad(params, i, count, off, part, keys, g, q0, q1);
-    const double t = (double)*step;
-    const float bc1 = (float)(1.0 - pow((double)hp.beta1, t));
-    const float bc2 = (float)(1.0 - pow((double)hp.beta2, t));
-    float p[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-    const float4 m0 = m4[2 * i], m1 = m4[2 * i + 1], v0 = v4[2 * i], v1 = v4[2 * i + 1];
-    float m[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
-    float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    // gradients incomplete on key overflow: leave the state alone
+    if (i < n && !(st->flags & FLAG_KEY_OVERFLOW)) {
+        unsigned long long keys = st->keys_total;
+        if (keys > (unsigned long long)cap) keys = (unsigned long long)cap;
+        float g[8];
+        float4 q0, q1;
+        gauss_grad(params, i, count, off, part, keys, g, q0, q1);
+        const float bc1 = s_bc[0], bc2 = s_bc[1];
+        float p[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        const float4 m0 = m4[2 * i], m1 = m4[2 * i + 1], v0 = v4[2 * i], v1 = v4[2 * i + 1];
+        float m[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+        float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const float lr = k < 2 ? hp.lr_mu : (k < 5 ? hp.lr_l : hp.lr_c);
-        m[k] = hp.beta1 * m[k] + (1.f - hp.beta1) * g[k];
-        v[k] = hp.beta2 * v[k] + (1.f - hp.beta2) * g[k] * g[k];
-        const float mh = m[k] / bc1, vh = v[k] / bc2;
-        p[k] -= lr * mh / (sqrtf(vh) + hp.eps);
+        for (int k = 0; k < 8; ++k) {
+            const float lr = k < 2 ? hp.lr_mu : (k < 5 ? hp.lr_l : hp.lr_c);
+            m[k] = hp.beta1 * m[k] + (1.f - hp.beta1) * g[k];
+            v[k] = hp.beta2 * v[k] + (1.f - hp.beta2) * g[k] * g[k];
+            const float mh = m[k] / bc1, vh = v[k] / bc2;
+            p[k] -= lr * mh / (sqrtf(vh) + hp.eps);
+        }
+        if (hp.l_min > 0.f) {
+            if (fabsf(p[2]) < hp.l_min) p[2] = copysignf(hp.l_min, p[2]);
+            if (fabsf(p[4]) < hp.l_min) p[4] = copysignf(hp.l_min, p[4]);
+        }
+        params[2 * i] = make_float4(p[0], p[1], p[2], p[3]);
+        params[2 * i + 1] = make_float4(p[4], p[5], p[6], p[7]);
+        m4[2 * i] = make_float4(m[0], m[1], m[2], m[3]);
+        m4[2 * i + 1] = make_float4(m[4], m[5], m[6], m[7]);
+        v4[2 * i] = make_float4(v[0], v[1], v[2], v[3]);
+        v4[2 * i + 1] = make_float4(v[4], v[5], v[6], v[7]);
     }
-    if (hp.l_min > 0.f) {
-        if (fabsf(p[2]) < hp.l_min) p[2] = copysignf(hp.l_min, p[2]);
-        if (fabsf(p[4]) < hp.l_min) p[4] = copysignf(hp.l_min, p[4]);
-    }
-    params[2 * i] = make_float4(p[0], p[1], p[2], p[3]);
-    params[2 * i + 1] = make_float4(p[4], p[5], p[6], p[7]);
-    m4[2 * i] = make_float4(m[0], m[1], m[2], m[3]);
-    m4[2 * i + 1] = make_float4(m[4], m[5], m[6], m[7]);
-    v4[2 * i] = make_float4(v[0], v[1], v[2], v[3]);
-    v4[2 * i + 1] = make_float4(v[4], v[5], v[6], v[7]);
 }
 
 // Per-image mean of the squared residuals from the per-tile sums (float64 accumulation), and the
@@ -404,13 +449,17 @@ hipError_t launch_grad_out(const UpdateArgs &u, float *dparams, hipStream_t s) {
 }
 
 hipError_t launch_adam(const UpdateArgs &u, float *params, float *m, float *v, int32_t *step,
-                       const AdamArgs &hp, hipStream_t s) {
-    if (u.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((u.n + 255) / 256)), dim3(256), 0, s,
-                       reinterpret_cast<float4 *>(params), u.n, u.count, u.off,
-                       reinterpret_cast<const float4 *>(u.part), u.state, u.cap,
-                       reinterpret_cast<float4 *>(m), reinterpret_cast<float4 *>(v), step, hp);
-    return hipGetLastError();
+                       const AdamArgs &hp, const float *loss_part, const ImgTable &tab,
+                       int64_t n_tiles, float *loss_out, hipStream_t s) {
+    if (u.n > 0) {
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((u.n + 255) / 256)), dim3(256), 0, s,
+                           reinterpret_cast<float4 *>(params), u.n, u.count, u.off,
+                           reinterpret_cast<const float4 *>(u.part), u.state, u.cap,
+                           reinterpret_cast<float4 *>(m), reinterpret_cast<float4 *>(v), step, hp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_finish(loss_part, tab, n_tiles, loss_out, step, s);
 }
 
 hipError_t launch_finish(const float *loss_part, const ImgTable &tab, int64_t n_tiles,

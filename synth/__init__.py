@@ -177,3 +177,17 @@ def batch_large(count: int = 256) -> list[Workload]:
         n = int(min(200_000, max(20_000, round(h * w * 200_000 / 2048 ** 2))))
         out.append(Workload(f"batch256-{i}", h, w, n, param_seed=5000 + i, target_seed=500 + i))
     return out
+
+
+def _target_of(w: "Workload") -> np.ndarray:
+    return w.target()
+
+
+def targets(workloads: list[Workload], processes: int = 0) -> list[np.ndarray]:
+    """Targets of many workloads, generated in worker processes (same values as w.target())."""
+    if processes <= 1 or len(workloads) < 4:
+        return [w.target() for w in workloads]
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    with ctx.Pool(processes) as pool:
+        return pool.map(_target_of, workloads, chunksize=1)

@@ -236,6 +236,15 @@ def test_gradients_match_finite_differences(culled):
     assert np.all(np.abs(an - fd) <= 1e-6 * scale + 1e-9 * np.abs(an).max()), (an - fd) / scale
 
 
+def test_local_finite_differences_equal_global_ones():
+    h, w = 40, 44
+    p = synth.gaussians(9, h, w, seed=23, l_lo=1.5, l_hi=6.0)
+    G = synth.upstream_gradient(h, w, 6)
+    glob = ref.fd_grads(p, h, w, G, which=[2, 5])
+    for n in (2, 5):
+        np.testing.assert_allclose(ref.fd_local(p, h, w, G, n), glob[n], rtol=1e-6, atol=1e-9)
+
+
 def test_gradient_closed_forms_for_one_gaussian():
     # S = sum over pixels of C^k for one Gaussian far from the border: S = 2 pi l1 l3 c^k
     # (Poisson error negligible), so dS/dc = 2 pi l1 l3, dS/dl1 = 2 pi l3 c, dS/dl3 = 2 pi l1 c,
