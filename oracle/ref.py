@@ -42,35 +42,64 @@ def _f64(params) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- Gaussian formation (Sec. 3.1)
+#
+# Two factorisations of the covariance (Sec. 3.1): ``cov="chol"`` reads the record as
+# (mu_x, mu_y, l1, l2, l3, c0, c1, c2) with Sigma = L L^T, L = [[l1, 0], [l2, l3]]
+# (Eq. cholesky); ``cov="rs"`` reads it as (mu_x, mu_y, s1, s2, theta, c0, c1, c2) with
+# Sigma = (R S)(R S)^T, R the rotation by theta and S = diag(s1, s2) (Eq. RSSR, rot_scale).
 
-def covariance(params):
-    """Sigma = L L^T from the Cholesky vector l = (l1, l2, l3) (Sec. 3.1, Eq. cholesky).
+def _cov_from(p, cov):
+    """Sigma entries (s00, s01, s11) of float64 records (no float32 rounding)."""
+    if cov == "chol":
+        l1, l2, l3 = p[:, 2], p[:, 3], p[:, 4]
+        return l1 * l1, l1 * l2, l2 * l2 + l3 * l3
+    if cov == "rs":
+        s1, s2, th = p[:, 2], p[:, 3], p[:, 4]
+        c, s = np.cos(th), np.sin(th)
+        a, b = s1 * s1, s2 * s2
+        return c * c * a + s * s * b, c * s * (a - b), s * s * a + c * c * b
+    raise ValueError(cov)
 
-    Returns the entries ``(s00, s01, s11)`` = (l1^2, l1 l2, l2^2 + l3^2).
-    """
-    p = _f64(params)
-    l1, l2, l3 = p[:, 2], p[:, 3], p[:, 4]
-    return l1 * l1, l1 * l2, l2 * l2 + l3 * l3
+
+def _det_from(p, cov):
+    """det Sigma in product form: (l1 l3)^2 or (s1 s2)^2."""
+    if cov == "chol":
+        return (p[:, 2] * p[:, 4]) ** 2
+    return (p[:, 2] * p[:, 3]) ** 2
 
 
-def inverse_covariance(params):
-    """Sigma^{-1} = [[s11, -s01], [-s01, s00]] / det with det = (l1 l3)^2 (Sec. 3.2, Eq.
-    rasterization2 needs Sigma^{-1}).  Returns ``(i00, i01, i11)``."""
-    p = _f64(params)
-    s00, s01, s11 = covariance(params)
-    det = (p[:, 2] * p[:, 4]) ** 2
+def _inv_from(p, cov):
+    s00, s01, s11 = _cov_from(p, cov)
+    det = _det_from(p, cov)
     with np.errstate(divide="ignore", invalid="ignore"):
         return s11 / det, -s01 / det, s00 / det
 
 
-def active(params) -> np.ndarray:
-    """Which Gaussians take part (the domain reading in the module header)."""
+def covariance(params, cov="chol"):
+    """Sigma entries ``(s00, s01, s11)`` of the records (Sec. 3.1, Eq. cholesky or Eq. RSSR):
+    for the Cholesky vector (l1^2, l1 l2, l2^2 + l3^2)."""
+    return _cov_from(_f64(params), cov)
+
+
+def inverse_covariance(params, cov="chol"):
+    """Sigma^{-1} = [[s11, -s01], [-s01, s00]] / det (Sec. 3.2, Eq. rasterization2 needs
+    Sigma^{-1}), det in product form.  Returns ``(i00, i01, i11)``."""
+    return _inv_from(_f64(params), cov)
+
+
+def active(params, cov="chol") -> np.ndarray:
+    """Which Gaussians take part (the domain reading in the module header; for the
+    rotation-scale form |s1|, |s2| >= 2^-24 and |theta| <= 2^24)."""
     p = _f64(params)
     finite = np.all(np.isfinite(p), axis=1)
     with np.errstate(invalid="ignore"):
-        dom = ((np.abs(p[:, 2]) >= L_MIN_ABS) & (np.abs(p[:, 4]) >= L_MIN_ABS)
-               & (np.abs(p[:, 3]) <= BIG_ABS) & (np.abs(p[:, 0]) <= BIG_ABS)
-               & (np.abs(p[:, 1]) <= BIG_ABS))
+        if cov == "chol":
+            dom = ((np.abs(p[:, 2]) >= L_MIN_ABS) & (np.abs(p[:, 4]) >= L_MIN_ABS)
+                   & (np.abs(p[:, 3]) <= BIG_ABS))
+        else:
+            dom = ((np.abs(p[:, 2]) >= L_MIN_ABS) & (np.abs(p[:, 3]) >= L_MIN_ABS)
+                   & (np.abs(p[:, 4]) <= BIG_ABS))
+        dom &= (np.abs(p[:, 0]) <= BIG_ABS) & (np.abs(p[:, 1]) <= BIG_ABS)
     return finite & dom
 
 
@@ -91,16 +120,16 @@ def _covers(r: np.ndarray, s00, s01, s11) -> np.ndarray:
     return ((p + q) >= 0.0) & ((p * q) >= 81.0 * (s01 * s01))
 
 
-def radius(params) -> np.ndarray:
+def radius(params, cov="chol") -> np.ndarray:
     """Box half-width r = ceil(3 sqrt(lambda_max)) in pixels, capped at 2^25 (int64, 0 if
     inactive).  The cap covers any image once |mu| <= 2^24.
 
     Defined as the least integer r in [0, 2^25] for which ``_covers`` holds (2^25 if none).  The
     float64 square root only gives the starting guess; the search then moves to that least r.
     """
-    act = active(params)
-    s00, s01, s11 = covariance(params)
+    act = active(params, cov)
     with np.errstate(invalid="ignore", over="ignore"):
+        s00, s01, s11 = covariance(params, cov)
         lam = 0.5 * (s00 + s11) + np.sqrt(0.25 * (s00 - s11) ** 2 + s01 * s01)
         guess = np.ceil(3.0 * np.sqrt(lam))
     guess = np.where(act & np.isfinite(guess), guess, 0.0)
@@ -126,7 +155,7 @@ def grid_tiles(height: int, width: int):
     return -(-width // TILE), -(-height // TILE)
 
 
-def tile_rects(params, height: int, width: int):
+def tile_rects(params, height: int, width: int, cov="chol"):
     """Per Gaussian, the inclusive tile rectangle (tx0, ty0, tx1, ty1) its 3-sigma box touches,
     and the tile count.  Inactive or off-image Gaussians get count 0 and rect (0, 0, -1, -1).
 
@@ -135,8 +164,8 @@ def tile_rects(params, height: int, width: int):
     """
     p = _f64(params)
     tw, th = grid_tiles(height, width)
-    r = radius(params).astype(np.float64)
-    act = active(params)
+    r = radius(params, cov).astype(np.float64)
+    act = active(params, cov)
     mx = np.where(act, p[:, 0], 0.0)
     my = np.where(act, p[:, 1], 0.0)
     fx0 = np.maximum(np.floor((mx - r) / TILE), 0.0)
@@ -150,7 +179,7 @@ def tile_rects(params, height: int, width: int):
     return rect, count.astype(np.int64)
 
 
-def tile_lists(params, height: int, width: int):
+def tile_lists(params, height: int, width: int, cov="chol"):
     """The per-tile Gaussian lists with depth order removed (Sec. 3.2: the sum does not depend on
     order, so only membership matters; ties are listed by ascending Gaussian index).
 
@@ -158,7 +187,7 @@ def tile_lists(params, height: int, width: int):
     ``ids[ranges[t, 0]:ranges[t, 1]]``, found by enumerating each rectangle.
     """
     tw, th = grid_tiles(height, width)
-    rect, count = tile_rects(params, height, width)
+    rect, count = tile_rects(params, height, width, cov)
     tiles, owners = [], []
     for n in np.nonzero(count)[0]:
         tx0, ty0, tx1, ty1 = rect[n]
@@ -196,12 +225,12 @@ def _sigma(pn, inv, xs, ys):
     return 0.5 * (i00 * dx * dx + 2.0 * i01 * dx * dy + i11 * dy * dy), dx, dy
 
 
-def render_full(params, height: int, width: int) -> np.ndarray:
+def render_full(params, height: int, width: int, cov="chol") -> np.ndarray:
     """C_i = sum over all Gaussians of c'_n exp(-sigma_n) at every pixel (Sec. 3.2,
     Eq. rasterization4), with no culling.  float64 ``[H, W, 3]``."""
     p = _f64(params)
-    act = active(params)
-    i00, i01, i11 = inverse_covariance(params)
+    act = active(params, cov)
+    i00, i01, i11 = inverse_covariance(params, cov)
     img = np.zeros((height, width, 3))
     xs = np.arange(width, dtype=np.float64)
     ys = np.arange(height, dtype=np.float64)
@@ -211,13 +240,13 @@ def render_full(params, height: int, width: int) -> np.ndarray:
     return img
 
 
-def render_culled(params, height: int, width: int, with_abs: bool = False):
+def render_culled(params, height: int, width: int, with_abs: bool = False, cov="chol"):
     """Eq. rasterization4 restricted to the tile support: Gaussian n reaches pixel p only when the
     tile of p lies in n's tile rectangle.  Returns the float64 image, and with ``with_abs`` also
     A(p) = sum |c'_n| exp(-sigma_n(p)) over the same support (the scale for relative error)."""
     p = _f64(params)
-    rect, count = tile_rects(params, height, width)
-    i00, i01, i11 = inverse_covariance(params)
+    rect, count = tile_rects(params, height, width, cov)
+    i00, i01, i11 = inverse_covariance(params, cov)
     img = np.zeros((height, width, 3))
     aimg = np.zeros((height, width, 3)) if with_abs else None
     for n in np.nonzero(count)[0]:
@@ -236,7 +265,8 @@ def render_culled(params, height: int, width: int, with_abs: bool = False):
 
 # ---------------------------------------------------------------- backward (App. A)
 
-def grads(params, height: int, width: int, dl_dimage, culled: bool = True, with_abs=False):
+def grads(params, height: int, width: int, dl_dimage, culled: bool = True, with_abs=False,
+          cov="chol"):
     """dL/dparams from dL/dC (App. A), float64 ``[N, 8]`` in record order.
 
     Per pixel and Gaussian (App. A.1): dC^k/dc'^k = e with e = exp(-sigma); dC^k/dsigma =
@@ -245,6 +275,9 @@ def grads(params, height: int, width: int, dl_dimage, culled: bool = True, with_
     Sigma^{-1}.  Per Gaussian (App. A.2), with G = dL/dSigma = [[g1, g2], [g2, g3]]:
     dL/dl1 = 2 g1 l1 + 2 g2 l2, dL/dl2 = 2 g2 l1 + 2 g3 l2 (the printed "+ g2 l2" is a slip:
     <G, dSigma/dl2> with dSigma/dl2 = [[0, l1], [l1, 2 l2]] gives 2 g3 l2), dL/dl3 = 2 g3 l3.
+    For the rotation-scale form (App. A.2, second part), dL/dtheta = <G, R' S S^T R^T +
+    R S S^T R'^T>, dL/ds1 = <G, R diag(2 s1, 0) R^T>, dL/ds2 = <G, R diag(0, 2 s2) R^T> (the
+    printed lines drop the inner product with G and write s1 for s2 in the last one).
 
     With ``with_abs`` also returns, per parameter, the sum over pixels of the absolute value of
     each pixel's contribution (the scale for relative error).
@@ -254,9 +287,9 @@ def grads(params, height: int, width: int, dl_dimage, culled: bool = True, with_
     n_g = p.shape[0]
     out = np.zeros((n_g, 8))
     absd = np.zeros((n_g, 8))
-    rect, count = tile_rects(params, height, width)
-    act = active(params)
-    i00, i01, i11 = inverse_covariance(params)
+    rect, count = tile_rects(params, height, width, cov)
+    act = active(params, cov)
+    i00, i01, i11 = inverse_covariance(params, cov)
     which = np.nonzero(count)[0] if culled else np.nonzero(act)[0]
     for n in which:
         if culled:
@@ -277,11 +310,26 @@ def grads(params, height: int, width: int, dl_dimage, culled: bool = True, with_
         g1 = dsig * (-0.5 * vx * vx)                             # dL/dSigma per pixel
         g2 = dsig * (-0.5 * vx * vy)
         g3 = dsig * (-0.5 * vy * vy)
-        l1, l2, l3 = p[n, 2], p[n, 3], p[n, 4]
-        dl1 = 2.0 * g1 * l1 + 2.0 * g2 * l2
-        dl2 = 2.0 * g2 * l1 + 2.0 * g3 * l2
-        dl3 = 2.0 * g3 * l3
-        parts = [dmx, dmy, dl1, dl2, dl3, dc[..., 0], dc[..., 1], dc[..., 2]]
+        if cov == "chol":
+            l1, l2, l3 = p[n, 2], p[n, 3], p[n, 4]
+            dl1 = 2.0 * g1 * l1 + 2.0 * g2 * l2
+            dl2 = 2.0 * g2 * l1 + 2.0 * g3 * l2
+            dl3 = 2.0 * g3 * l3
+            shape = [dl1, dl2, dl3]
+        else:
+            s1, s2, th = p[n, 2], p[n, 3], p[n, 4]
+            c, sn = math.cos(th), math.sin(th)
+            R = np.array([[c, -sn], [sn, c]])
+            dR = np.array([[-sn, -c], [c, -sn]])
+            SS = np.diag([s1 * s1, s2 * s2])
+            dS_th = dR @ SS @ R.T + R @ SS @ dR.T
+            dS_s1 = R @ np.diag([2.0 * s1, 0.0]) @ R.T
+            dS_s2 = R @ np.diag([0.0, 2.0 * s2]) @ R.T
+
+            def inner(M):  # <G, M> with G = [[g1, g2], [g2, g3]] per pixel
+                return g1 * M[0, 0] + g2 * (M[0, 1] + M[1, 0]) + g3 * M[1, 1]
+            shape = [inner(dS_s1), inner(dS_s2), inner(dS_th)]
+        parts = [dmx, dmy, *shape, dc[..., 0], dc[..., 1], dc[..., 2]]
         for k, q in enumerate(parts):
             out[n, k] = q.sum()
             if with_abs:
@@ -292,7 +340,7 @@ def grads(params, height: int, width: int, dl_dimage, culled: bool = True, with_
 
 
 def fd_grads(params, height: int, width: int, dl_dimage, which=None, rel_step=1e-6,
-             culled: bool = True):
+             culled: bool = True, cov="chol"):
     """Central finite differences of S = <dL/dC, C> in float64, h = rel_step * max(1, |theta|).
 
     For the culled sum the tile rectangles must not move under +-h; the perturbed Gaussian's
@@ -303,7 +351,7 @@ def fd_grads(params, height: int, width: int, dl_dimage, which=None, rel_step=1e
     G = np.asarray(dl_dimage, dtype=np.float64).reshape(height, width, 3)
     idx = range(base.shape[0]) if which is None else which
     out = np.zeros((base.shape[0], 8))
-    rect0, _ = tile_rects(base.astype(np.float32), height, width) if culled else (None, None)
+    rect0, _ = tile_rects(base.astype(np.float32), height, width, cov) if culled else (None, None)
     for n in idx:
         for k in range(8):
             h = rel_step * max(1.0, abs(base[n, k]))
@@ -311,12 +359,12 @@ def fd_grads(params, height: int, width: int, dl_dimage, which=None, rel_step=1e
             for sgn in (1.0, -1.0):
                 q = base.copy()
                 q[n, k] += sgn * h
-                vals.append(np.sum(G * _render64(q, height, width, culled, rect0, n)))
+                vals.append(np.sum(G * _render64(q, height, width, culled, rect0, n, cov)))
             out[n, k] = (vals[0] - vals[1]) / (2.0 * h)
     return out
 
 
-def fd_local(params, height: int, width: int, dl_dimage, n: int, rel_step=1e-6):
+def fd_local(params, height: int, width: int, dl_dimage, n: int, rel_step=1e-6, cov="chol"):
     """Central finite differences of S = <dL/dC, C> for Gaussian n alone, float64.
 
     Only Gaussian n's own term changes when its parameters move, so S(theta + h) - S(theta - h)
@@ -325,7 +373,7 @@ def fd_local(params, height: int, width: int, dl_dimage, n: int, rel_step=1e-6):
     """
     p = _f64(params)[n].copy()
     G = np.asarray(dl_dimage, dtype=np.float64).reshape(height, width, 3)
-    rect, count = tile_rects(np.asarray(params, np.float32)[n:n + 1], height, width)
+    rect, count = tile_rects(np.asarray(params, np.float32)[n:n + 1], height, width, cov)
     out = np.zeros(8)
     if count[0] == 0:
         return out
@@ -335,9 +383,7 @@ def fd_local(params, height: int, width: int, dl_dimage, n: int, rel_step=1e-6):
     g = G[y0:y1, x0:x1]
 
     def term(q):
-        l1, l2, l3 = q[2], q[3], q[4]
-        det = (l1 * l3) ** 2
-        inv = ((l2 * l2 + l3 * l3) / det, -(l1 * l2) / det, (l1 * l1) / det)
+        inv = tuple(v[0] for v in _inv_from(q[None, :], cov))
         s, _, _ = _sigma(q, inv, xs, ys)
         return np.sum(g * (np.exp(-s)[:, :, None] * q[5:8]))
 
@@ -350,20 +396,16 @@ def fd_local(params, height: int, width: int, dl_dimage, n: int, rel_step=1e-6):
     return out
 
 
-def _render64(p64, height, width, culled, rect0, moved):
+def _render64(p64, height, width, culled, rect0, moved, cov="chol"):
     """Render float64 parameters (no float32 rounding), used by finite differences only.  With
     ``culled`` the support is the unperturbed ``rect0``, after checking that the perturbed
     Gaussian's own float64 rect equals it."""
     img = np.zeros((height, width, 3))
-    l1, l2, l3 = p64[:, 2], p64[:, 3], p64[:, 4]
-    det = (l1 * l3) ** 2
-    i00 = (l2 * l2 + l3 * l3) / det
-    i01 = -(l1 * l2) / det
-    i11 = (l1 * l1) / det
+    i00, i01, i11 = _inv_from(p64, cov)
     xs_all = np.arange(width, dtype=np.float64)
     ys_all = np.arange(height, dtype=np.float64)
     if culled:
-        s00, s01, s11 = l1[moved] ** 2, l1[moved] * l2[moved], l2[moved] ** 2 + l3[moved] ** 2
+        s00, s01, s11 = (v[0] for v in _cov_from(p64[moved:moved + 1], cov))
         lam = 0.5 * (s00 + s11) + math.sqrt(0.25 * (s00 - s11) ** 2 + s01 ** 2)
         r = math.ceil(3.0 * math.sqrt(lam))
         tw, th = grid_tiles(height, width)
@@ -404,10 +446,11 @@ DEFAULT_ADAM = dict(lr_mu=0.05, lr_l=0.01, lr_c=0.005, beta1=0.9, beta2=0.999, e
                     l_min=0.5)
 
 
-def adam_step(params, m, v, grad, step: int, hp=None):
+def adam_step(params, m, v, grad, step: int, hp=None, cov="chol"):
     """One Adam update with bias correction (Kingma and Ba), per-group learning rates for
-    position, Cholesky vector and colour, then |l1|, |l3| held at >= l_min (the paper keeps the
-    diagonal away from zero by adding 0.5, App. C; outside the record, so here a floor).
+    position, covariance factors and colour, then |l1|, |l3| (or |s1|, |s2|) held at >= l_min
+    (the paper keeps them away from zero by adding 0.5, App. C; outside the record, so here a
+    floor).
 
     Returns new float64 ``(params, m, v)``; ``step`` counts from 1.
     """
@@ -421,7 +464,7 @@ def adam_step(params, m, v, grad, step: int, hp=None):
     lr = np.array([hp["lr_mu"]] * 2 + [hp["lr_l"]] * 3 + [hp["lr_c"]] * 3)
     p = p - lr * mhat / (np.sqrt(vhat) + hp["eps"])
     if hp["l_min"] > 0:
-        for k in (2, 4):
+        for k in ((2, 4) if cov == "chol" else (2, 3)):
             small = np.abs(p[:, k]) < hp["l_min"]
             p[small, k] = np.copysign(hp["l_min"], p[small, k])
     return p, m, v

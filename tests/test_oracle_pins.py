@@ -403,3 +403,91 @@ def test_degenerate_gaussians_are_inactive():
     assert list(count) == [0, 0, 0, 0, 0, 0, 0, 1]
     img = ref.render_culled(p, 32, 32)
     np.testing.assert_allclose(img, ref.render_culled(p[7:], 32, 32), rtol=0)
+
+
+# ----------------------------------------------------------------- rotation-scale covariance
+# Record (mu_x, mu_y, s1, s2, theta, c0, c1, c2), Sigma = (R S)(R S)^T (Sec. 3.1, Eq. RSSR).
+
+def rs_gaussians(n, h, w, seed):
+    rng = np.random.default_rng(seed)
+    p = np.empty((n, 8), np.float32)
+    p[:, 0] = rng.uniform(0, w, n)
+    p[:, 1] = rng.uniform(0, h, n)
+    p[:, 2] = np.exp(rng.uniform(math.log(1.2), math.log(6.0), n))
+    p[:, 3] = np.exp(rng.uniform(math.log(1.2), math.log(6.0), n))
+    p[:, 4] = rng.uniform(-math.pi, math.pi, n)
+    p[:, 5:8] = rng.uniform(-0.5, 1.0, (n, 3))
+    return p
+
+
+def test_rs_forward_matches_library_density():
+    from scipy.spatial.transform import Rotation
+    from scipy.stats import multivariate_normal
+    h, w = 22, 26
+    p = rs_gaussians(10, h, w, 5)
+    ys, xs = np.meshgrid(np.arange(h) + 0.5, np.arange(w) + 0.5, indexing="ij")
+    pts = np.stack([xs.ravel(), ys.ravel()], axis=1)
+    want = np.zeros((h * w, 3))
+    for q in p.astype(np.float64):
+        R = Rotation.from_euler("z", q[4]).as_matrix()[:2, :2]  # library rotation
+        S = R @ np.diag([q[2] ** 2, q[3] ** 2]) @ R.T
+        dens = multivariate_normal(mean=q[:2], cov=S).pdf(pts) * 2 * math.pi * abs(q[2] * q[3])
+        want += dens[:, None] * q[5:8]
+    np.testing.assert_allclose(ref.render_full(p, h, w, cov="rs"), want.reshape(h, w, 3),
+                               rtol=1e-11, atol=1e-14)
+
+
+def test_rs_closed_forms_and_symmetries():
+    s1, s2, th, c = 2.5, 1.5, 0.7, 0.8
+    p = np.array([[60.3, 59.7, s1, s2, th, c, 0.0, 0.0]], np.float32)
+    pf = p.astype(np.float64)[0]
+    img = ref.render_full(p, 120, 120, cov="rs")
+    np.testing.assert_allclose(img[..., 0].sum(), 2 * math.pi * pf[2] * pf[3] * pf[5], rtol=1e-8)
+    G = np.zeros((120, 120, 3))
+    G[..., 0] = 1.0
+    d = ref.grads(p, 120, 120, G, culled=False, cov="rs")[0]
+    np.testing.assert_allclose(d[2], 2 * math.pi * pf[3] * pf[5], rtol=1e-7)
+    np.testing.assert_allclose(d[3], 2 * math.pi * pf[2] * pf[5], rtol=1e-7)
+    assert abs(d[4]) < 1e-7 and abs(d[0]) < 1e-7 and abs(d[1]) < 1e-7
+    # theta + pi and (s1, s2, theta) -> (s2, s1, theta + pi/2) describe the same Sigma
+    q = rs_gaussians(20, 48, 48, 9).astype(np.float64)
+    a = ref.render_full(q.astype(np.float32), 48, 48, cov="rs")
+    q2 = q.copy()
+    q2[:, 4] += math.pi
+    q3 = q.copy()
+    q3[:, 2], q3[:, 3], q3[:, 4] = q[:, 3], q[:, 2], q[:, 4] + math.pi / 2
+    for alt in (q2, q3):
+        b = np.zeros((48, 48, 3))
+        for n in range(alt.shape[0]):  # float64 parameters, no float32 rounding of theta
+            inv = tuple(v[0] for v in ref._inv_from(alt[n:n + 1], "rs"))
+            s, _, _ = ref._sigma(alt[n], inv, np.arange(48.0), np.arange(48.0))
+            b += np.exp(-s)[:, :, None] * alt[n, 5:8]
+        np.testing.assert_allclose(b, a, rtol=1e-6, atol=1e-9)
+
+
+def test_rs_with_zero_angle_reduces_to_the_cholesky_tile_rule():
+    h, w = 70, 90
+    p = rs_gaussians(200, h, w, 3)
+    p[:, 4] = 0.0
+    chol = p.copy()
+    chol[:, 2], chol[:, 3], chol[:, 4] = p[:, 2], 0.0, p[:, 3]
+    r1, c1 = ref.tile_rects(p, h, w, cov="rs")
+    r2, c2 = ref.tile_rects(chol, h, w)
+    assert np.array_equal(r1, r2) and np.array_equal(c1, c2)
+    np.testing.assert_allclose(ref.render_culled(p, h, w, cov="rs"), ref.render_culled(chol, h, w),
+                               rtol=1e-14, atol=1e-300)
+
+
+@pytest.mark.parametrize("culled", [True, False])
+def test_rs_gradients_match_finite_differences(culled):
+    h, w = 36, 40
+    p = rs_gaussians(7, h, w, 21)
+    G = synth.upstream_gradient(h, w, 8)
+    an = ref.grads(p, h, w, G, culled=culled, cov="rs")
+    fd = ref.fd_grads(p, h, w, G, culled=culled, cov="rs")
+    scale = np.abs(an).max(axis=0) + 1e-12
+    assert np.all(np.abs(an - fd) <= 1e-6 * scale + 1e-9 * np.abs(an).max()), (an - fd) / scale
+    if culled:  # the local difference covers the tile support only
+        for n in (0, 3):
+            np.testing.assert_allclose(ref.fd_local(p, h, w, G, n, cov="rs"), fd[n], rtol=1e-5,
+                                       atol=1e-8)
