@@ -128,6 +128,8 @@ def radius(params, cov="chol") -> np.ndarray:
     float64 square root only gives the starting guess; the search then moves to that least r.
     """
     act = active(params, cov)
+    if cov == "rs":
+        return _radius_rs(params, act)
     with np.errstate(invalid="ignore", over="ignore"):
         s00, s01, s11 = covariance(params, cov)
         lam = 0.5 * (s00 + s11) + np.sqrt(0.25 * (s00 - s11) ** 2 + s01 * s01)
@@ -144,6 +146,32 @@ def radius(params, cov="chol") -> np.ndarray:
         r = r - down
     while True:  # step up while r does not cover
         up = act & (r < R_MAX) & ~_covers(r, s00, s01, s11)
+        if not up.any():
+            break
+        r = r + up
+    return np.where(act, r, 0)
+
+
+def _radius_rs(params, act) -> np.ndarray:
+    """Box half-width of the rotation-scale form.  Sigma = R S S^T R^T has the eigenvalues s1^2
+    and s2^2 (Eq. RSSR: R is orthogonal), so lambda_max = max(s1^2, s2^2) and r is the least
+    integer in [0, 2^25] with r^2 >= 9 max(s1^2, s2^2).  For float32 s1, s2 every product below
+    is exact in float64, so the decision involves no rounding and no trigonometry.
+    """
+    p = _f64(params)
+    m = np.where(act, np.maximum(p[:, 2] * p[:, 2], p[:, 3] * p[:, 3]), 0.0)
+    with np.errstate(invalid="ignore", over="ignore"):
+        guess = np.ceil(3.0 * np.sqrt(m))
+    r = np.clip(np.where(act & np.isfinite(guess), guess, 0.0), 0, R_MAX).astype(np.int64)
+    while True:
+        rr = (r - 1).astype(np.float64)
+        down = act & (r > 0) & (rr * rr >= 9.0 * m)
+        if not down.any():
+            break
+        r = r - down
+    while True:
+        rr = r.astype(np.float64)
+        up = act & (r < R_MAX) & (rr * rr < 9.0 * m)
         if not up.any():
             break
         r = r + up

@@ -44,6 +44,72 @@ def gaussians(n: int, height: int, width: int, seed: int, l_lo: float = 1.0,
     return out
 
 
+def gaussians_rs(n: int, height: int, width: int, seed: int, s_lo: float = 1.2,
+                 s_hi: float = 6.0, c_lo: float = -0.5, c_hi: float = 1.0) -> np.ndarray:
+    """Random rotation-scale records ``(mu_x, mu_y, s1, s2, theta, c0, c1, c2)``, float32
+    ``[n, 8]`` (the covariance factorisation of Sec. 3.1, Eq. RSSR).
+
+    Means are uniform over ``[0, W) x [0, H)``; the scales ``s1, s2`` are
+    ``exp(U(log s_lo, log s_hi))`` pixels; the angle is ``U(-pi, pi)``; the weighted colours are
+    ``U[c_lo, c_hi]^3``.
+    """
+    rng = np.random.default_rng(seed)
+    p = np.empty((n, PARAMS_PER_GAUSSIAN), np.float32)
+    p[:, 0] = rng.uniform(0, width, n)
+    p[:, 1] = rng.uniform(0, height, n)
+    p[:, 2] = np.exp(rng.uniform(math.log(s_lo), math.log(s_hi), n))
+    p[:, 3] = np.exp(rng.uniform(math.log(s_lo), math.log(s_hi), n))
+    p[:, 4] = rng.uniform(-math.pi, math.pi, n)
+    p[:, 5:8] = rng.uniform(c_lo, c_hi, (n, 3))
+    np.minimum(p[:, 0], np.nextafter(np.float32(width), np.float32(0)), out=p[:, 0])
+    np.minimum(p[:, 1], np.nextafter(np.float32(height), np.float32(0)), out=p[:, 1])
+    return p
+
+
+@dataclasses.dataclass
+class CodecSet:
+    """A compressed Gaussian set in the layout of Sec. 3.3 (arrays on the CPU)."""
+    mu_bits: np.ndarray     # [N, 2] uint16, binary16 bit patterns of the positions
+    codes: np.ndarray       # [N, 3] uint8, b-bit covariance codes
+    index: np.ndarray       # [N, M] uint8, residual-VQ indices
+    codebooks: np.ndarray   # [M, B, 3] float32
+    gamma: np.ndarray       # [3] float32 scales
+    beta: np.ndarray        # [3] float32 offsets
+    bits: int
+
+
+def codec_set(n: int, height: int, width: int, seed: int, bits: int = 6, stages: int = 2,
+              book: int = 8, rotation_scale: bool = False) -> CodecSet:
+    """Random compressed set with the paper's codec settings by default (16-bit positions, 6-bit
+    covariance codes, 2 RVQ stages of 8 colours; Sec. 4.1).
+
+    Positions are U[0, W) x U[0, H) drawn in float64 and stored as binary16; codes are uniform
+    over [0, 2^bits - 1]; scales and offsets map the codes onto l1, l3 in [1, 8] px and l2 in
+    [-1.5, 1.5] (or s1, s2 in [1, 8] px and theta in [-pi, pi]); stage 0 colours are U[0, 1]^3,
+    later stages N(0, 0.1^2).
+    """
+    rng = np.random.default_rng(seed)
+    mu = np.stack([rng.uniform(0, width, n), rng.uniform(0, height, n)], axis=1)
+    mu16 = mu.astype(np.float16)
+    # keep the rounded positions inside the frame
+    mu16[:, 0] = np.minimum(mu16[:, 0], np.nextafter(np.float16(width), np.float16(0)))
+    mu16[:, 1] = np.minimum(mu16[:, 1], np.nextafter(np.float16(height), np.float16(0)))
+    top = (1 << bits) - 1
+    codes = rng.integers(0, top + 1, (n, 3)).astype(np.uint8)
+    index = rng.integers(0, book, (n, stages)).astype(np.uint8)
+    books = np.empty((stages, book, 3), np.float32)
+    books[0] = rng.uniform(0, 1, (book, 3))
+    if stages > 1:
+        books[1:] = rng.normal(0, 0.1, (stages - 1, book, 3))
+    if rotation_scale:
+        lo, hi = np.array([1.0, 1.0, -math.pi]), np.array([8.0, 8.0, math.pi])
+    else:
+        lo, hi = np.array([1.0, -1.5, 1.0]), np.array([8.0, 1.5, 8.0])
+    gamma = ((hi - lo) / top).astype(np.float32)
+    beta = lo.astype(np.float32)
+    return CodecSet(mu16.view(np.uint16), codes, index, books, gamma, beta, bits)
+
+
 def target_sinusoids(height: int, width: int, seed: int) -> np.ndarray:
     """Smooth target: per channel, 1/2 plus 1/16 times a sum of 8 random plane sinusoids.
 

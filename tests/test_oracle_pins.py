@@ -409,15 +409,30 @@ def test_degenerate_gaussians_are_inactive():
 # Record (mu_x, mu_y, s1, s2, theta, c0, c1, c2), Sigma = (R S)(R S)^T (Sec. 3.1, Eq. RSSR).
 
 def rs_gaussians(n, h, w, seed):
-    rng = np.random.default_rng(seed)
-    p = np.empty((n, 8), np.float32)
-    p[:, 0] = rng.uniform(0, w, n)
-    p[:, 1] = rng.uniform(0, h, n)
-    p[:, 2] = np.exp(rng.uniform(math.log(1.2), math.log(6.0), n))
-    p[:, 3] = np.exp(rng.uniform(math.log(1.2), math.log(6.0), n))
-    p[:, 4] = rng.uniform(-math.pi, math.pi, n)
-    p[:, 5:8] = rng.uniform(-0.5, 1.0, (n, 3))
-    return p
+    return synth.gaussians_rs(n, h, w, seed)
+
+
+def test_rs_radius_is_the_least_integer_covering_three_sigma():
+    # exact rational check: r is the least integer with r^2 >= 9 max(s1^2, s2^2)
+    from fractions import Fraction
+    rng = np.random.default_rng(17)
+    s = np.concatenate([np.exp(rng.uniform(-3, 5, (300, 2))),
+                        np.array([[2.0, 1.0], [1.0, 2.0], [1 / 3, 0.25], [4.0 / 3, -5.0 / 3],
+                                  [0.5, 0.5], [7.0, -7.0], [2 ** -24, 2 ** -24]])])
+    p = np.zeros((s.shape[0], 8), np.float32)
+    p[:, 2:4] = s
+    p[:, 4] = rng.uniform(-4, 4, s.shape[0])
+    got = ref.radius(p, cov="rs")
+    for q, r in zip(p.astype(np.float64), got):
+        m = max(Fraction(q[2]) ** 2, Fraction(q[3]) ** 2)
+        assert r * r >= 9 * m and (r == 0 or (r - 1) ** 2 < 9 * m), (q[2:4], r)
+    # the eigenvalue rule agrees with the characteristic-polynomial rule on the trigonometric
+    # covariance away from rounding ties
+    s00, s01, s11 = ref.covariance(p, cov="rs")
+    lam = 0.5 * (s00 + s11) + np.sqrt(0.25 * (s00 - s11) ** 2 + s01 ** 2)
+    far = np.abs(3 * np.sqrt(lam) - np.round(3 * np.sqrt(lam))) > 1e-9
+    assert far.sum() > 250
+    np.testing.assert_array_equal(got[far], np.ceil(3 * np.sqrt(lam[far])).astype(np.int64))
 
 
 def test_rs_forward_matches_library_density():
