@@ -205,3 +205,16 @@ def fd_grads_blend(params, opacity, height, width, dl_dimage, mode="alpha", cov=
                 dn = loss(p, o)
             out[n, k] = (up - dn) / (2 * h)
     return out[:, :8], out[:, 8]
+
+
+def adam_opacity_step(opacity, m, v, grad, step: int, hp=None):
+    """Adam with bias correction on the opacities (learning rate lr_c, no floor): the same
+    update as ``ref.adam_step`` applies to the colour slots.  Returns float64 (o, m, v)."""
+    hp = dict(ref.DEFAULT_ADAM if hp is None else hp)
+    g = np.asarray(grad, np.float64)
+    m = hp["beta1"] * np.asarray(m, np.float64) + (1.0 - hp["beta1"]) * g
+    v = hp["beta2"] * np.asarray(v, np.float64) + (1.0 - hp["beta2"]) * g * g
+    mhat = m / (1.0 - hp["beta1"] ** step)
+    vhat = v / (1.0 - hp["beta2"] ** step)
+    o = np.asarray(opacity, np.float64) - hp["lr_c"] * mhat / (np.sqrt(vhat) + hp["eps"])
+    return o, m, v

@@ -111,3 +111,24 @@ def test_alpha_gradient_of_the_front_gaussian_sees_what_it_hides():
     np.testing.assert_allclose(do[1], e * (1 - a1) * 0.5, rtol=1e-6)
     np.testing.assert_allclose(dp[0, 5], a1, rtol=1e-6)
     np.testing.assert_allclose(dp[1, 5], a2 * (1 - a1), rtol=1e-6)
+
+
+def test_opacity_adam_matches_the_colour_slot_update():
+    # the opacity update is the colour-slot update of ref.adam_step run on the same numbers
+    rng = np.random.default_rng(14)
+    o = rng.uniform(0.1, 0.9, 50)
+    g = rng.normal(size=50)
+    m = rng.normal(size=50) * 0.01
+    v = rng.uniform(0, 0.01, 50)
+    got = blend.adam_opacity_step(o, m, v, g, 3)
+    P = np.zeros((50, 8))
+    P[:, 5] = o
+    G = np.zeros((50, 8))
+    G[:, 5] = g
+    M = np.zeros((50, 8))
+    M[:, 5] = m
+    V = np.zeros((50, 8))
+    V[:, 5] = v
+    want = ref.adam_step(P, M, V, G, 3, dict(ref.DEFAULT_ADAM, l_min=0.0))
+    for a, b in zip(got, want):
+        np.testing.assert_allclose(a, b[:, 5], rtol=1e-15)
