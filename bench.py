@@ -22,9 +22,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Peak VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one FP32 operation per lane per
-# cycle (packed FP32 is not used), in lane-operations per second.
-VALU_PEAK = 256 * 4 * 16 * 2.4e9
+# FP32 vector peak of the chip in operations per second (an FMA counted once): 157.3 TFLOP/s /
+# 2 = 256 CUs x 4 SIMDs x 16 lanes x 2 (packed dual FP32) x 2.4 GHz.  These kernels do not emit
+# packed FP32 instructions (kept out for correctness), so their own ceiling is half of it:
+# 39.3 T lane-operations per second.
+VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
+VALU_PEAK_UNPACKED = VALU_PEAK / 2
 # Algorithmic work per pixel-Gaussian pair (the unit), in FP32 operations: forward 10 VALU
 # operations + 1 exp2, adjoint 26 VALU operations + 1 exp2 (plain per-pair forms, before any
 # sharing of per-column terms); each exp2 is counted as one operation.
@@ -50,6 +53,15 @@ def parse():
                          "20k-200k Gaussians")
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--no-codec", action="store_true",
+                    help="skip the codec decode leg (Sec. 3.3, Table 2)")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the rasterisation ablation leg (Table 3 rows, 768x512 / 30k)")
+    ap.add_argument("--no-rs", action="store_true",
+                    help="skip the rotation-scale leg (Sec. 3.1, Eq. RSSR)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device-to-device 10 times (scales rocprof FETCH_SIZE "
+                         "and WRITE_SIZE to bytes)")
     ap.add_argument("--binning", type=int, default=0,
                     help="0 auto, 1 duplication + radix sort, 2 one-pass counting sort")
     return ap.parse_args()
@@ -147,8 +159,186 @@ def batched_vs_plain(ctx, inputs, steps, P, torch, np):
             "params_bit_identical": bool(same_params)}
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic-k_raster_fit-kodak-768x512-70k.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused raster kernel from the committed counter record, if it
+    was taken on the current source of the kernel (else None)."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_2403_08551_amd", "csrc", "k_raster.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("k_raster_sha256") != digest:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def copy_calibration():
+    import torch
+    n = 256 << 20
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 10}), flush=True)
+
+
+def rotation_scale_leg(P, torch, w, steps, tuned):
+    """Fit it/s (graph replay) and render FPS of the same workload with rotation-scale records
+    (s1, s2 with the Cholesky diagonals' distribution, theta uniform)."""
+    import synth
+    dev = torch.device("cuda", 0)
+    ctx = P.Context(0, covariance="rotation_scale")
+    if tuned[0]:
+        ctx.set_option(P._lib.GI_OPT_FWD_PIXELS, tuned[0])
+    if tuned[1]:
+        ctx.set_option(P._lib.GI_OPT_SORT_BITS, tuned[1])
+    p0 = torch.tensor(synth.gaussians_rs(w.n, w.height, w.width, w.param_seed, s_lo=w.l_lo,
+                                         s_hi=w.l_hi, c_lo=0.0, c_hi=1.0), device=dev)
+    target = torch.tensor(w.target(), device=dev)
+    b = ctx.binning(p0, w.height, w.width)
+    pairs = pairs_from_ranges(b["ranges"].cpu().numpy(), w.height, w.width)
+    params = p0.clone()
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    step = torch.ones(1, dtype=torch.int32, device=dev)
+    graph = ctx.fit_graph(params, m, v, target, step)
+    graph.launch(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    graph.launch(steps)
+    torch.cuda.synchronize()
+    its = steps / (time.perf_counter() - t0)
+    _, flags = graph.query(clear=True)
+    graph.close()
+    if flags & (P._lib.GI_FLAG_KEY_OVERFLOW | P._lib.GI_FLAG_SCAN_STALL):
+        raise RuntimeError(f"flags {flags} raised during the rotation-scale steps")
+    ctx.set_option(P._lib.GI_OPT_SYNC, 0)
+    img = torch.empty(w.height, w.width, 3, device=dev)
+    for _ in range(10):
+        ctx.render(p0, w.height, w.width, out=img)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.render(p0, w.height, w.width, out=img)
+    torch.cuda.synchronize()
+    fps = steps / (time.perf_counter() - t0)
+    ctx.close()
+    return {"fit_its": its, "render_fps": fps, "keys": b["keys"], "pairs": pairs,
+            "steps": steps, "paper_context_render_fps_ours_rs": 2321.0}
+
+
+def codec_leg(P, torch, w, steps):
+    """Decode FPS: fused dequantisation + render of a compressed set of the workload's size (the
+    paper's codec settings: binary16 positions, 6-bit covariance codes, 2 x 8 RVQ colours)."""
+    import numpy as np
+    import synth
+    dev = torch.device("cuda", 0)
+    cs = synth.codec_set(w.n, w.height, w.width, seed=w.param_seed)
+    c = P.Codec(mu=torch.tensor(cs.mu_bits.view(np.int16), device=dev),
+                codes=torch.tensor(cs.codes, device=dev), index=torch.tensor(cs.index, device=dev),
+                codebooks=torch.tensor(cs.codebooks, device=dev),
+                gamma=tuple(float(x) for x in cs.gamma), beta=tuple(float(x) for x in cs.beta),
+                bits=cs.bits)
+    ctx = P.Context(0)
+    img = torch.empty(w.height, w.width, 3, device=dev)
+    ctx.render_codec(c, w.height, w.width, out=img)  # grows the workspace
+    ctx.set_option(P._lib.GI_OPT_SYNC, 0)
+    for _ in range(10):
+        ctx.render_codec(c, w.height, w.width, out=img)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.render_codec(c, w.height, w.width, out=img)
+    torch.cuda.synchronize()
+    fps = steps / (time.perf_counter() - t0)
+    _, flags = ctx.query(clear=True)
+    ctx.close()
+    if flags & (P._lib.GI_FLAG_KEY_OVERFLOW | P._lib.GI_FLAG_SCAN_STALL | P._lib.GI_FLAG_BAD_CODE):
+        raise RuntimeError(f"flags {flags} raised during the codec renders")
+    bits = 2 * 16 + 3 * cs.bits + cs.index.shape[1] * int(np.log2(cs.codebooks.shape[1]))
+    return {"decode_fps": fps, "steps": steps, "bits_per_gaussian": bits,
+            "paper_context_decode_fps_v100_div2k": [1970.76, 1980.54]}
+
+
+def ablation_leg(P, torch, steps):
+    """Table 3's speed ablation on this GPU (768x512, 30k Gaussians): fit it/s and render FPS of
+    accumulated summation with merged colours, with a separate opacity, and alpha blending.
+    Eager non-waiting calls on one context."""
+    import numpy as np
+    import synth
+    dev = torch.device("cuda", 0)
+    w = synth.kodak_like(30_000)
+    H, W = w.height, w.width
+    p0 = torch.tensor(w.params(), device=dev)
+    o0 = torch.tensor(np.random.default_rng(7).uniform(0.05, 0.95, w.n).astype(np.float32),
+                      device=dev)
+    target = torch.tensor(w.target(), device=dev)
+    p_rs = torch.tensor(synth.gaussians_rs(w.n, H, W, w.param_seed, s_lo=w.l_lo, s_hi=w.l_hi,
+                                           c_lo=0.0, c_hi=1.0), device=dev)
+    ctx = P.Context(0)
+    ctx_rs = P.Context(0, covariance="rotation_scale")
+    out = {}
+    for name in ("merged", "sum", "alpha", "rotation_scale"):
+        params, opac = (p_rs if name == "rotation_scale" else p0).clone(), o0.clone()
+        m, v = torch.zeros_like(params), torch.zeros_like(params)
+        mo, vo = torch.zeros_like(opac), torch.zeros_like(opac)
+        step = torch.ones(1, dtype=torch.int32, device=dev)
+        img = torch.empty(H, W, 3, device=dev)
+
+        c = ctx_rs if name == "rotation_scale" else ctx
+
+        def fit():
+            if name in ("merged", "rotation_scale"):
+                c.fit_step(params, m, v, target, step)
+            else:
+                c.fit_step_opacity(params, opac, m, v, mo, vo, target, step, name)
+
+        def render():
+            if name == "merged":
+                c.render(p0, H, W, out=img)
+            elif name == "rotation_scale":
+                c.render(p_rs, H, W, out=img)
+            else:
+                c.render_opacity(p0, o0, H, W, name, out=img)
+
+        c.set_option(P._lib.GI_OPT_SYNC, 1)
+        fit()
+        render()
+        c.set_option(P._lib.GI_OPT_SYNC, 0)
+        res = {}
+        for label, fn in (("fit_its", fit), ("render_fps", render)):
+            for _ in range(5):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            res[label] = steps / (time.perf_counter() - t0)
+        out[name] = res
+    flags = ctx.query(clear=True)[1] | ctx_rs.query(clear=True)[1]
+    ctx.close()
+    ctx_rs.close()
+    if flags & (P._lib.GI_FLAG_KEY_OVERFLOW | P._lib.GI_FLAG_SCAN_STALL):
+        raise RuntimeError(f"flags {flags} raised during the ablation leg")
+    out["workload"] = w.name
+    out["steps"] = steps
+    # Table 3 (V100, 50k steps): FPS and training seconds per variant
+    out["paper_context_table3"] = {"merged": [2565, 91.06], "sum": [2555, 98.54],
+                                   "alpha": [2340, 104.76], "rotation_scale": [2321, 98.55]}
+    return out
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one image or one "
               "batch per GPU; sharding is described in DESIGN.md)", file=sys.stderr)
@@ -204,12 +394,13 @@ def main():
 
     # ---- dominant kernel: the fused raster kernel, timed with events on its stream (eager
     # steps without host waits, same parameters as the timed region's end state)
-    ctx.set_option(P._lib.GI_OPT_SYNC, 0)
-    ctx.set_option(P._lib.GI_OPT_TIMING, 1)
     n_prof = min(args.steps, 100)
-    for _ in range(5):
+    for _ in range(5):  # waiting calls: the key buffers grow to this state's count (+25%)
         ctx.fit_step(params, m, v, target, step)
     torch.cuda.synchronize()
+    ctx.query(clear=True)
+    ctx.set_option(P._lib.GI_OPT_SYNC, 0)
+    ctx.set_option(P._lib.GI_OPT_TIMING, 1)
     ctx.timing(0, reset=True)
     for _ in range(n_prof):
         ctx.fit_step(params, m, v, target, step)
@@ -217,6 +408,9 @@ def main():
     fit_ms, fit_n = ctx.timing(P._lib.GI_STAGE_RASTER_FIT)
     bin_ms, bin_n = ctx.timing(P._lib.GI_STAGE_BINNING)
     upd_ms, upd_n = ctx.timing(P._lib.GI_STAGE_UPDATE, reset=True)
+    _, flags = ctx.query(clear=True)
+    if flags & (P._lib.GI_FLAG_KEY_OVERFLOW | P._lib.GI_FLAG_SCAN_STALL):
+        raise RuntimeError(f"flags {flags} raised during the profiled steps")
     b2 = ctx.binning(params, H, W)  # pairs of the state that was profiled
     P_prof = pairs_from_ranges(b2["ranges"].cpu().numpy(), H, W)
     ctx.set_option(P._lib.GI_OPT_SYNC, 0)
@@ -236,6 +430,10 @@ def main():
     fps = n_render / (time.perf_counter() - t0)
     ctx.set_option(P._lib.GI_OPT_TIMING, 0)
     ctx.set_option(P._lib.GI_OPT_SYNC, 1)
+    rs = None if args.no_rs else rotation_scale_leg(P, torch, w, min(max(args.steps, 100), 300),
+                                                     tuned)
+    cod = None if args.no_codec else codec_leg(P, torch, w, max(args.steps, 100))
+    abl = None if args.no_ablation else ablation_leg(P, torch, 100)
     bvp = None
     if args.batch_images > 0:
         bvp = batched_vs_plain(ctx, binputs, args.batch_steps, P, torch, np)
@@ -262,10 +460,15 @@ def main():
                      "update": upd_ms / max(upd_n, 1)},
         "loss": {"after_warmup": loss_start, "after_timed": loss_end},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T FP32 op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                     "unit": "T FP32 op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
+                     "peak_unpacked": VALU_PEAK_UNPACKED / 1e12,
+                     "frac_unpacked": achieved / VALU_PEAK_UNPACKED,
                      "kernel": f"k_raster_fit<{tuned[0] or 2}>", "ops_per_pair": OPS_PER_PAIR_FIT,
                      "pairs_per_launch": P_prof, "avg_launch_ms": fit_ms / fit_n},
         "batched_vs_plain": bvp,
+        "rotation_scale": rs,
+        "codec": cod,
+        "ablation": abl,
         "paper_context": {"render_fps_v100_kodak_70k": 2092.17,
                           "fit_its_v100_kodak_70k_derived": 50000 / 106.59},
     }

@@ -16,6 +16,14 @@
  *   non-finite number, |l1| or |l3| < 2^-24, or |l2|, |mu_x|, |mu_y| > 2^24 takes no part.
  *   Gradients follow App. A (with dC/dsigma = -c' exp(-sigma) and dL/dl2 = 2 g2 l1 + 2 g3 l2).
  *
+ *   Rotation-scale records (GI_OPT_COVARIANCE = GI_COV_ROTATION_SCALE; Sec. 3.1, Eq. RSSR):
+ *   the record is (mu_x, mu_y, s1, s2, theta, c0, c1, c2) with Sigma = (R S)(R S)^T, R the
+ *   rotation by theta (radians, counter-clockwise in (x, y)) and S = diag(s1, s2).  Since the
+ *   eigenvalues of Sigma are s1^2 and s2^2, the box half-width is the least integer r with
+ *   r^2 >= 9 max(s1^2, s2^2) (exact in float64).  Such a Gaussian takes no part when a number
+ *   is not finite, |s1| or |s2| < 2^-24, or |theta|, |mu_x|, |mu_y| > 2^24.  Gradients are
+ *   with respect to (s1, s2, theta) in slots 2..4; the rest is as above.
+ *
  * Conventions for every call:
  *   - Pointers named *_dev are device pointers owned by the caller (for example torch tensor
  *     storage); the library never frees them.  Pointers named *_host are host memory.
@@ -55,14 +63,17 @@ enum {
 #define GI_FLAG_KEY_OVERFLOW 1u /* more (tile, Gaussian) keys than capacity: outputs undefined */
 #define GI_FLAG_NONFINITE 2u    /* some parameter was NaN or Inf (that Gaussian took no part) */
 #define GI_FLAG_SCAN_STALL 4u   /* a one-pass scan block waited past its bound: outputs undefined */
+#define GI_FLAG_BAD_CODE 8u     /* a compressed Gaussian had a code or index out of range (it took
+                                   no part) */
 
 typedef struct gi_ctx gi_ctx;
 typedef struct gi_graph gi_graph;
 
 /* Adam hyper-parameters of the fused update (fit calls).  lr_* are per group: position (mu),
- * Cholesky vector (l1, l2, l3) and colour (c').  After each update |l1| and |l3| are raised to
- * at least l_min (0 disables), keeping Sigma away from singular (the paper adds 0.5 to the
- * diagonal for the same reason, App. C).  Bias correction uses the step number t >= 1. */
+ * covariance slots 2..4 ((l1, l2, l3) or (s1, s2, theta)) and colour (c').  After each update
+ * |l1| and |l3| (|s1| and |s2| in the rotation-scale form) are raised to at least l_min
+ * (0 disables), keeping Sigma away from singular (the paper adds 0.5 to the diagonal for the
+ * same reason, App. C).  Bias correction uses the step number t >= 1. */
 typedef struct gi_adam {
     float lr_mu, lr_l, lr_c;
     float beta1, beta2, eps;
@@ -88,8 +99,17 @@ enum {
     GI_OPT_FWD_PIXELS = 3,    /* pixels per lane in the forward kernels: 1, 2 or 4; 0 = auto */
     GI_OPT_BINNING = 4,       /* 0 = auto (one pass when the tiles number at most 2048),
                                  1 = key duplication + LSD radix sort, 2 = one pass if possible */
-    GI_OPT_TIMING = 5         /* 1: bracket each stage of non-captured calls with HIP events on
+    GI_OPT_TIMING = 5,        /* 1: bracket each stage of non-captured calls with HIP events on
                                  the call's stream (read with gi_timing); 0 (default): off */
+    GI_OPT_COVARIANCE = 6     /* how params[2..4] describe Sigma (Sec. 3.1): GI_COV_CHOLESKY
+                                 (default) or GI_COV_ROTATION_SCALE; read by every later call,
+                                 and fixed into a captured step when it is created */
+};
+
+/* Values of GI_OPT_COVARIANCE. */
+enum {
+    GI_COV_CHOLESKY = 0,        /* (l1, l2, l3): Sigma = L L^T, L = [[l1, 0], [l2, l3]] */
+    GI_COV_ROTATION_SCALE = 1   /* (s1, s2, theta): Sigma = R(theta) diag(s1^2, s2^2) R^T */
 };
 
 /* Stages timed when GI_OPT_TIMING is on. */
@@ -178,6 +198,74 @@ int gi_fit_step_batched(gi_ctx *ctx, float *params_dev, float *m_dev, float *v_d
                         const float *targets_dev, const gi_batch *batch, const gi_adam *hp,
                         int32_t *step_dev, float *images_out_dev, float *loss_out_dev,
                         void *stream);
+
+/* ---- opacity renderings (Sec. 3.2, the ablation rows of Table 3) --------------------------- */
+
+/* Values of `blend`. */
+enum {
+    GI_BLEND_SUM = 1,    /* C = sum_n c_n o_n exp(-sigma_n): summation with a separate opacity
+                            (Eq. rasterization3) */
+    GI_BLEND_ALPHA = 2   /* C = sum_n c_n alpha_n T_n, T_n = prod_{m<n} (1 - alpha_m),
+                            alpha_n = min(o_n exp(-sigma_n), 0.99): alpha blending
+                            (Eq. rasterization1, rasterization2) in ascending Gaussian order
+                            within each tile (no depth exists); the clamp keeps 1 - alpha >= 0.01.
+                            No alpha threshold and no early stop. */
+};
+
+/* Render with colours c (params slots 5..7, not merged with the opacity) and opacities
+ * opacity_dev [N] (float32).  Support, records and covariance form as in gi_render.  A
+ * non-finite opacity makes its Gaussian take no part (GI_FLAG_NONFINITE). */
+int gi_render_opacity(gi_ctx *ctx, const float *params_dev, const float *opacity_dev, int64_t n,
+                      int32_t height, int32_t width, int32_t blend, float *image_dev,
+                      void *stream);
+/* Gradients of an opacity rendering: dparams_dev [N][8] (slots 5..7 = dL/dc) and
+ * dopacity_dev [N].  Where alpha is clamped it depends on neither o nor sigma. */
+int gi_grad_opacity(gi_ctx *ctx, const float *params_dev, const float *opacity_dev, int64_t n,
+                    int32_t height, int32_t width, int32_t blend, const float *dl_dimage_dev,
+                    float *dparams_dev, float *dopacity_dev, void *stream);
+
+/* One fit step of an opacity rendering (as gi_fit_step): loss, gradients, then Adam on params
+ * (moments m_dev, v_dev [N][8]) and on the opacities (moments m_opacity_dev, v_opacity_dev [N],
+ * learning rate lr_c, no floor). */
+int gi_fit_step_opacity(gi_ctx *ctx, float *params_dev, float *opacity_dev, float *m_dev,
+                        float *v_dev, float *m_opacity_dev, float *v_opacity_dev,
+                        const float *target_dev, int64_t n, int32_t height, int32_t width,
+                        int32_t blend, const gi_adam *hp, int32_t *step_dev,
+                        float *image_out_dev, float *loss_out_dev, void *stream);
+
+/* ---- codec decode (Sec. 3.3) ------------------------------------------------------------- */
+
+/* A compressed Gaussian set (Sec. 3.3, attribute quantisation).  Device arrays, caller owned:
+ *   mu_dev        [N][2] uint16   IEEE binary16 bit patterns of (mu_x, mu_y) (16-bit positions);
+ *                                 the array must be 4-byte aligned
+ *   codes_dev     [N][3] uint8    b-bit codes of params[2..4] (LSQ+ with a scale gamma[i] and an
+ *                                 offset beta[i] shared by all Gaussians): value = code * gamma
+ *                                 + beta
+ *   index_dev     [N][M] uint8    residual vector quantisation indices, stage 0 first
+ *   codebook_dev  [M][B][3] float stage codebooks; the colour is the sum over stages of
+ *                                 codebook[m][index[m]]
+ * gamma and beta are host values.  Dequantisation and the colour sum are formed in float64
+ * (exact products; sums in stage order) and rounded once to float32.  1 <= bits <= 8,
+ * 1 <= stages <= 8, 1 <= codebook_size <= 256.  A Gaussian with a code above 2^bits - 1 or an
+ * index >= codebook_size takes no part and raises GI_FLAG_BAD_CODE.  Slots 2..4 are read in
+ * the context's GI_OPT_COVARIANCE form. */
+typedef struct gi_codec {
+    const uint16_t *mu_dev;
+    const uint8_t *codes_dev;
+    const uint8_t *index_dev;
+    const float *codebook_dev;
+    float gamma[3], beta[3];
+    int32_t bits, stages, codebook_size;
+} gi_codec;
+
+/* Decode a compressed set into float records params_dev [N][8] (16-byte aligned); a Gaussian
+ * with an invalid code or index decodes to NaN in every slot. */
+int gi_codec_decode(gi_ctx *ctx, const gi_codec *codec, int64_t n, float *params_dev,
+                    void *stream);
+/* Decode and render (the paper's decoder, Table 2): as gi_render of the decoded records, with
+ * the dequantisation fused into the projection so that no [N][8] intermediate is written. */
+int gi_render_codec(gi_ctx *ctx, const gi_codec *codec, int64_t n, int32_t height,
+                    int32_t width, float *image_dev, void *stream);
 
 /* ---- captured fit steps ------------------------------------------------------------------- */
 

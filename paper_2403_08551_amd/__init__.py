@@ -1,7 +1,8 @@
 """MI355X (gfx950) differentiable renderer of 2-D Gaussians by accumulated summation.
 
 The image representation of GaussianImage (arXiv 2403.08551): N Gaussians, each with mean mu,
-Cholesky factor L (Sigma = L L^T, Sec. 3.1) and weighted colour c', render an image as
+Cholesky factor L (Sigma = L L^T, Sec. 3.1; or rotation and scales, Sigma = R S S^T R^T, chosen
+per context) and weighted colour c', render an image as
 C(p) = sum_n c'_n exp(-1/2 d^T Sigma_n^{-1} d) with no depth order and no alpha blending
 (Sec. 3.2, Eq. rasterization4); the gradients follow App. A.  Parameters are float32 tensors of
 shape [N, 8] = (mu_x, mu_y, l1, l2, l3, c0, c1, c2) in pixel units; images are [H, W, 3].
@@ -20,7 +21,7 @@ import torch
 from . import _lib
 from ._lib import GiError
 
-__all__ = ["Context", "Batch", "AdamConfig", "GaussianRender", "render", "default_context",
+__all__ = ["Context", "Batch", "AdamConfig", "Codec", "GaussianRender", "render", "default_context",
            "GiError"]
 
 
@@ -99,10 +100,52 @@ def _check(t: torch.Tensor, name: str, device, shape=None, dtype=torch.float32):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
 
 
+@dataclass
+class Codec:
+    """A compressed Gaussian set (Sec. 3.3) on the device: ``mu`` [N, 2] int16 holding binary16
+    bit patterns, ``codes`` [N, 3] uint8 b-bit covariance codes (value = code * gamma + beta),
+    ``index`` [N, M] uint8 residual-VQ indices, ``codebooks`` [M, B, 3] float32."""
+    mu: torch.Tensor
+    codes: torch.Tensor
+    index: torch.Tensor
+    codebooks: torch.Tensor
+    gamma: tuple
+    beta: tuple
+    bits: int = 6
+
+    @property
+    def n(self) -> int:
+        return int(self.codes.shape[0])
+
+    def c(self, device) -> _lib.gi_codec:
+        n = self.n
+        _check(self.mu, "mu", device, (n, 2), torch.int16)
+        _check(self.codes, "codes", device, (n, 3), torch.uint8)
+        M, B = int(self.codebooks.shape[0]), int(self.codebooks.shape[1])
+        _check(self.index, "index", device, (n, M), torch.uint8)
+        _check(self.codebooks, "codebooks", device, (M, B, 3))
+        g = _lib.gi_codec()
+        g.mu_dev, g.codes_dev = self.mu.data_ptr(), self.codes.data_ptr()
+        g.index_dev, g.codebook_dev = self.index.data_ptr(), self.codebooks.data_ptr()
+        for k in range(3):
+            g.gamma[k] = float(self.gamma[k])
+            g.beta[k] = float(self.beta[k])
+        g.bits, g.stages, g.codebook_size = int(self.bits), M, B
+        return g
+
+
+_BLEND = {"sum": _lib.GI_BLEND_SUM, "alpha": _lib.GI_BLEND_ALPHA}
+_COVARIANCE = {"cholesky": _lib.GI_COV_CHOLESKY, "rotation_scale": _lib.GI_COV_ROTATION_SCALE}
+
+
 class Context:
     """One gi_ctx: owns the device workspace.  Use from one thread at a time."""
 
-    def __init__(self, device: int | torch.device = 0):
+    def __init__(self, device: int | torch.device = 0, covariance: str = "cholesky"):
+        """``covariance`` names how params[:, 2:5] describe Sigma (Sec. 3.1): "cholesky"
+        (l1, l2, l3) or "rotation_scale" (s1, s2, theta)."""
+        if covariance not in _COVARIANCE:
+            raise ValueError(f"covariance must be one of {sorted(_COVARIANCE)}")
         dev = torch.device(device) if not isinstance(device, int) else torch.device("cuda", device)
         if dev.type != "cuda":
             raise ValueError("the renderer runs on a GPU device only")
@@ -110,6 +153,8 @@ class Context:
         handle = ctypes.c_void_p()
         self._raise(_lib.lib().gi_create(ctypes.byref(handle), self.device.index), "gi_create")
         self._h = handle
+        if covariance != "cholesky":
+            self.set_option(_lib.GI_OPT_COVARIANCE, _COVARIANCE[covariance])
 
     # -- plumbing
     def _raise(self, status: int, what: str):
@@ -186,6 +231,57 @@ class Context:
                                          _ptr(out), _stream(self.device)), "gi_render")
         return out
 
+    def render_opacity(self, params, opacity, height: int, width: int, blend: str = "alpha",
+                       out=None) -> torch.Tensor:
+        """Render with separate colours and opacities: blend "sum" (Eq. rasterization3) or
+        "alpha" (Eq. rasterization1, index order)."""
+        n = params.shape[0]
+        _check(params, "params", self.device, (n, 8))
+        _check(opacity, "opacity", self.device, (n,))
+        if out is None:
+            out = torch.empty(height, width, 3, device=self.device, dtype=torch.float32)
+        _check(out, "out", self.device, (height, width, 3))
+        self._raise(_lib.lib().gi_render_opacity(self._h, _ptr(params), _ptr(opacity), n, height,
+                                                 width, _BLEND[blend], _ptr(out),
+                                                 _stream(self.device)), "gi_render_opacity")
+        return out
+
+    def grad_opacity(self, params, opacity, height: int, width: int, dl_dimage,
+                     blend: str = "alpha"):
+        """(dL/dparams [N, 8], dL/dopacity [N]) of an opacity rendering."""
+        n = params.shape[0]
+        _check(params, "params", self.device, (n, 8))
+        _check(opacity, "opacity", self.device, (n,))
+        _check(dl_dimage, "dl_dimage", self.device, (height, width, 3))
+        dp = torch.empty(n, 8, device=self.device, dtype=torch.float32)
+        do = torch.empty(n, device=self.device, dtype=torch.float32)
+        self._raise(_lib.lib().gi_grad_opacity(self._h, _ptr(params), _ptr(opacity), n, height,
+                                               width, _BLEND[blend], _ptr(dl_dimage), _ptr(dp),
+                                               _ptr(do), _stream(self.device)),
+                    "gi_grad_opacity")
+        return dp, do
+
+    def codec_decode(self, codec: Codec, out=None) -> torch.Tensor:
+        """Decoded float records [N, 8] of a compressed set."""
+        g = codec.c(self.device)
+        if out is None:
+            out = torch.empty(codec.n, 8, device=self.device, dtype=torch.float32)
+        _check(out, "out", self.device, (codec.n, 8))
+        self._raise(_lib.lib().gi_codec_decode(self._h, ctypes.byref(g), codec.n, _ptr(out),
+                                               _stream(self.device)), "gi_codec_decode")
+        return out
+
+    def render_codec(self, codec: Codec, height: int, width: int, out=None) -> torch.Tensor:
+        """Decode and render in one pass (dequantisation fused into the projection)."""
+        g = codec.c(self.device)
+        if out is None:
+            out = torch.empty(height, width, 3, device=self.device, dtype=torch.float32)
+        _check(out, "out", self.device, (height, width, 3))
+        self._raise(_lib.lib().gi_render_codec(self._h, ctypes.byref(g), codec.n, height, width,
+                                               _ptr(out), _stream(self.device)),
+                    "gi_render_codec")
+        return out
+
     def grad(self, params, height, width, dl_dimage, out=None) -> torch.Tensor:
         _check(params, "params", self.device, (params.shape[0], 8))
         _check(dl_dimage, "dl_dimage", self.device, (height, width, 3))
@@ -215,6 +311,28 @@ class Context:
                                            n, h, w, ctypes.byref(hpc), _ptr(step),
                                            _ptr(image_out), _ptr(loss_out),
                                            _stream(self.device)), "gi_fit_step")
+
+    def fit_step_opacity(self, params, opacity, m, v, m_o, v_o, target, step,
+                         blend: str = "alpha", hp: AdamConfig | None = None, image_out=None,
+                         loss_out=None):
+        """One fit step of an opacity rendering, in place on params, opacity and the moments."""
+        n = params.shape[0]
+        h, w = target.shape[0], target.shape[1]
+        for t, name in ((params, "params"), (m, "m"), (v, "v")):
+            _check(t, name, self.device, (n, 8))
+        for t, name in ((opacity, "opacity"), (m_o, "m_o"), (v_o, "v_o")):
+            _check(t, name, self.device, (n,))
+        _check(target, "target", self.device, (h, w, 3))
+        _check(step, "step", self.device, (1,), torch.int32)
+        if image_out is not None:
+            _check(image_out, "image_out", self.device, (h, w, 3))
+        if loss_out is not None:
+            _check(loss_out, "loss_out", self.device, (1,))
+        hpc = (hp or AdamConfig()).c()
+        self._raise(_lib.lib().gi_fit_step_opacity(
+            self._h, _ptr(params), _ptr(opacity), _ptr(m), _ptr(v), _ptr(m_o), _ptr(v_o),
+            _ptr(target), n, h, w, _BLEND[blend], ctypes.byref(hpc), _ptr(step), _ptr(image_out),
+            _ptr(loss_out), _stream(self.device)), "gi_fit_step_opacity")
 
     # -- batched
     def render_batched(self, params, batch: Batch, out=None) -> torch.Tensor:

@@ -21,12 +21,20 @@ GI_ERR_NO_DEVICE = -6
 GI_FLAG_KEY_OVERFLOW = 1
 GI_FLAG_NONFINITE = 2
 GI_FLAG_SCAN_STALL = 4
+GI_FLAG_BAD_CODE = 8
 
 GI_OPT_SYNC = 1
 GI_OPT_SORT_BITS = 2
 GI_OPT_FWD_PIXELS = 3
 GI_OPT_BINNING = 4
 GI_OPT_TIMING = 5
+GI_OPT_COVARIANCE = 6
+
+GI_BLEND_SUM = 1
+GI_BLEND_ALPHA = 2
+
+GI_COV_CHOLESKY = 0
+GI_COV_ROTATION_SCALE = 1
 
 GI_STAGE_BINNING = 0
 GI_STAGE_RASTER_FWD = 1
@@ -40,7 +48,8 @@ EXPORTS = (
     "gi_last_error", "gi_render", "gi_grad", "gi_fit_step", "gi_render_batched",
     "gi_grad_batched", "gi_fit_step_batched", "gi_fit_graph_create", "gi_fit_graph_launch",
     "gi_fit_graph_destroy", "gi_binning", "gi_scan_u32", "gi_sort_pairs", "gi_timing",
-    "gi_get_option", "gi_autotune", "gi_fit_graph_query",
+    "gi_get_option", "gi_autotune", "gi_fit_graph_query", "gi_codec_decode", "gi_render_codec",
+    "gi_render_opacity", "gi_grad_opacity", "gi_fit_step_opacity",
 )
 
 
@@ -55,6 +64,14 @@ class gi_batch(ctypes.Structure):
                 ("height_host", ctypes.POINTER(ctypes.c_int32)),
                 ("width_host", ctypes.POINTER(ctypes.c_int32)),
                 ("gauss_off_host", ctypes.POINTER(ctypes.c_int64))]
+
+
+class gi_codec(ctypes.Structure):
+    _fields_ = [("mu_dev", ctypes.c_void_p), ("codes_dev", ctypes.c_void_p),
+                ("index_dev", ctypes.c_void_p), ("codebook_dev", ctypes.c_void_p),
+                ("gamma", ctypes.c_float * 3), ("beta", ctypes.c_float * 3),
+                ("bits", ctypes.c_int32), ("stages", ctypes.c_int32),
+                ("codebook_size", ctypes.c_int32)]
 
 
 class GiError(RuntimeError):
@@ -112,6 +129,12 @@ def lib():
             "gi_get_option": ([P, ctypes.c_int, ctypes.POINTER(I64)], ctypes.c_int),
             "gi_autotune": ([P, P, P, I64, I32, I32, ctypes.POINTER(gi_batch), I32, P,
                              ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
+            "gi_fit_step_opacity": ([P, P, P, P, P, P, P, P, I64, I32, I32, I32,
+                                     ctypes.POINTER(gi_adam), P, P, P, P], ctypes.c_int),
+            "gi_render_opacity": ([P, P, P, I64, I32, I32, I32, P, P], ctypes.c_int),
+            "gi_grad_opacity": ([P, P, P, I64, I32, I32, I32, P, P, P, P], ctypes.c_int),
+            "gi_codec_decode": ([P, ctypes.POINTER(gi_codec), I64, P, P], ctypes.c_int),
+            "gi_render_codec": ([P, ctypes.POINTER(gi_codec), I64, I32, I32, P, P], ctypes.c_int),
             "gi_timing": ([P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64),
                            ctypes.c_int], ctypes.c_int),
         }

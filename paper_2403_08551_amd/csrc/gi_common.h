@@ -26,6 +26,7 @@ constexpr int TILE_PX = TILE * TILE;
 constexpr uint32_t FLAG_KEY_OVERFLOW = 1u;
 constexpr uint32_t FLAG_NONFINITE = 2u;
 constexpr uint32_t FLAG_SCAN_STALL = 4u;
+constexpr uint32_t FLAG_BAD_CODE = 8u;
 constexpr int64_t FUSED_MAX_TILES = 2048;
 
 // sqrt(log2(e) / 2): scales L^{-1} d so that exp(-sigma) = exp2(-|u|^2)
@@ -40,10 +41,16 @@ struct DevState {
     uint32_t pad;
 };
 
+// Covariance factorisation read from params[2..4] (Sec. 3.1): (l1, l2, l3) of the Cholesky
+// factor (Eq. cholesky), or (s1, s2, theta) of Sigma = (R S)(R S)^T (Eq. RSSR).
+constexpr int32_t COV_CHOLESKY = 0;
+constexpr int32_t COV_ROTATION_SCALE = 1;
+
 // Image geometry, passed by value.  B == 1 uses the scalar fields; B > 1 reads the tables.
 struct ImgTable {
     int32_t B;
     int32_t H, W, TW;                 // single image
+    int32_t cov;                      // COV_* of the records
     const int4 *dims;                 // [B] (H, W, TW, TH)
     const uint32_t *tile_base;        // [B+1] first global tile id of each image
     const uint32_t *gauss_off;        // [B+1]
@@ -84,10 +91,43 @@ __device__ inline TileInfo tile_info(const ImgTable &t, uint32_t tile) {
     return ti;
 }
 
+// A compressed Gaussian set (Sec. 3.3): binary16 positions [N][2], b-bit covariance codes
+// [N][3] with shared scale/offset, residual-VQ indices [N][M] into codebooks [M][B][3].
+struct CodecArgs {
+    const uint16_t *mu;
+    const uint8_t *codes;
+    const uint8_t *index;
+    const float *book;
+    float gamma[3], beta[3];
+    int32_t bits, stages, size;
+};
+
+// Opacity renderings (Sec. 3.2): BLEND_SUM is C = sum c o exp(-sigma) (Eq. rasterization3),
+// BLEND_ALPHA is alpha blending in index order (Eq. rasterization1) with alpha = min(o exp(-sigma),
+// ALPHA_MAX).
+constexpr int32_t BLEND_NONE = 0;
+constexpr int32_t BLEND_SUM = 1;
+constexpr int32_t BLEND_ALPHA = 2;
+constexpr float ALPHA_MAX = 0.99f;
+
+// Where the projection reads Gaussian records: float params, or (codec.mu != nullptr) a
+// compressed set decoded on the fly; with an opacity per Gaussian for the opacity renderings
+// (BLEND_SUM stores o * c as the record colour).  Passed to kernels by value.
+struct RecordSrc {
+    const float4 *params;
+    CodecArgs codec;
+    const float *opacity;
+    int32_t blend;
+};
+
 // ---- host-side launchers (defined next to their kernels) ------------------------------------
 
 struct BinBuffers {
     const float *params;
+    const CodecArgs *codec;  // non-null: decode the records from this compressed set instead
+    const float *opacity;    // [N] for the opacity renderings, else null
+    int32_t blend;           // BLEND_*
+    float *rec_o;            // [cap] opacity in tile order (BLEND_ALPHA), else null
     int64_t n;
     float *proj;
     int4 *rect;
@@ -120,6 +160,9 @@ hipError_t launch_sort(const BinBuffers &b, int key_bits, int digit_bits, int64_
 hipError_t launch_ranges_gather(const BinBuffers &b, int which, const ImgTable &tab,
                                 int64_t n_max, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+// Decode a compressed set into float records [N][8] (invalid Gaussians: NaN records).
+hipError_t launch_codec_decode(const CodecArgs &c, int64_t n, float *params, DevState *state,
+                               hipStream_t s);
 
 // One-pass binning (n_tiles <= FUSED_MAX_TILES): A = projection + per-chunk tile counts +
 // chained scan (writes state->keys_total); C = stable scatter into tile order + ranges.
@@ -160,9 +203,16 @@ hipError_t launch_raster_bwd(const RasterArgs &a, const float *dl_dimage, float 
                              hipStream_t s);
 hipError_t launch_raster_fit(const RasterArgs &a, const float *target, float *part,
                              float *image_out, float *loss_part, int px_per_lane, hipStream_t s);
+// Alpha blending (BLEND_ALPHA): rec_o [cap] holds the opacities in tile order; part12 has
+// three float4 per key (colour sums, P1; P2, Q11, Q12, Q22; opacity sum).
+hipError_t launch_alpha_fwd(const RasterArgs &a, const float *rec_o, float *image, hipStream_t s);
+hipError_t launch_alpha_bwd(const RasterArgs &a, const float *rec_o, const float *dl_dimage,
+                            float *part12, hipStream_t s);
+hipError_t launch_alpha_fit(const RasterArgs &a, const float *rec_o, const float *target,
+                            float *part12, float *image_out, float *loss_part, hipStream_t s);
 
 struct UpdateArgs {
-    const float *params_in;  // read (l1, l2, l3) and, for Adam, updated in place
+    const float *params_in;  // read (l1, l2, l3) or (s1, s2, theta); Adam updates in place
     float *params_out;
     int64_t n;
     const uint32_t *count;
@@ -170,8 +220,14 @@ struct UpdateArgs {
     const float *part;
     DevState *state;
     int64_t cap;
+    int32_t cov;             // COV_*
 };
 hipError_t launch_grad_out(const UpdateArgs &u, float *dparams, hipStream_t s);
+// Gradient of the opacity renderings: dparams [N][8] (colour slots = dL/dc) and dopacity [N].
+// For BLEND_SUM u.part holds the merged-colour sums (8 floats per key); for BLEND_ALPHA the
+// 12-float sums of launch_alpha_bwd.
+hipError_t launch_grad_opacity(const UpdateArgs &u, const float *opacity, int32_t blend,
+                               float *dparams, float *dopacity, hipStream_t s);
 struct AdamArgs {
     float lr_mu, lr_l, lr_c, beta1, beta2, eps, l_min;
 };
@@ -179,6 +235,12 @@ struct AdamArgs {
 hipError_t launch_adam(const UpdateArgs &u, float *params, float *m, float *v,
                        int32_t *step, const AdamArgs &hp, const float *loss_part,
                        const ImgTable &tab, int64_t n_tiles, float *loss_out, hipStream_t s);
+// Adam over params and opacities of an opacity rendering (opacity uses the colour rate), then
+// launch_finish.
+hipError_t launch_adam_opacity(const UpdateArgs &u, float *params, float *opacity, float *m,
+                               float *v, float *mo, float *vo, int32_t *step, const AdamArgs &hp,
+                               int32_t blend, const float *loss_part, const ImgTable &tab,
+                               int64_t n_tiles, float *loss_out, hipStream_t s);
 // Per-image loss from the per-tile sums (when loss_out != nullptr) and step += 1 (when
 // step != nullptr).
 hipError_t launch_finish(const float *loss_part, const ImgTable &tab, int64_t n_tiles,

@@ -22,6 +22,13 @@ struct gi_ctx {
     int sort_bits = 0;
     int fwd_px = 0;
     int binning = 0;
+    int cov = COV_CHOLESKY;  // GI_OPT_COVARIANCE
+    const CodecArgs *codec = nullptr;  // set for the duration of a codec render
+    const float *opac_cur = nullptr;   // set for the duration of an opacity render / grad
+    int blend_cur = BLEND_NONE;
+    float *rec_o = nullptr;            // [cap_a] opacities in tile order (alpha blending)
+    float *part_a = nullptr;           // [cap_a][12] alpha-blending partial sums
+    int64_t cap_a = 0;
     int want_ids = 0;  // the one-pass binning writes sorted Gaussian ids only for gi_binning
     int64_t cap_n = 0, cap_t = 0, cap_k = 0;
     int64_t last_keys = 0;
@@ -214,7 +221,22 @@ int ensure_keys(gi_ctx *ctx, int64_t k) {
     const int64_t sc = scan_scratch_entries(hc) + 1;
     CK(grow(&ctx->scan_bs, sc));
     ctx->scan_cap = sc;
+    if (ctx->cap_a) {
+        CK(grow(&ctx->rec_o, c));
+        CK(grow(&ctx->part_a, 12 * c));
+        ctx->cap_a = c;
+    }
     ctx->cap_k = c;
+    return GI_OK;
+}
+
+// Buffers of alpha blending, sized like the key buffers from the first use on.
+int ensure_alpha(gi_ctx *ctx) {
+    if (ctx->cap_a >= ctx->cap_k) return GI_OK;
+    CK(hipDeviceSynchronize());
+    CK(grow(&ctx->rec_o, ctx->cap_k));
+    CK(grow(&ctx->part_a, 12 * ctx->cap_k));
+    ctx->cap_a = ctx->cap_k;
     return GI_OK;
 }
 
@@ -339,6 +361,10 @@ int64_t table_pixels(const ImgTable &tab, int64_t n_tiles) {
 BinBuffers bin_buffers(gi_ctx *ctx, const float *params, int64_t n, int64_t n_tiles) {
     BinBuffers b;
     b.params = params;
+    b.codec = ctx->codec;
+    b.opacity = ctx->opac_cur;
+    b.blend = ctx->blend_cur;
+    b.rec_o = ctx->blend_cur == BLEND_ALPHA ? ctx->rec_o : nullptr;
     b.n = n;
     b.proj = ctx->proj;
     b.rect = ctx->rect;
@@ -417,12 +443,15 @@ int run_binning_fused(gi_ctx *ctx, const float *params, int64_t n, const ImgTabl
 
 // Projection, scan, duplication, sort, ranges and gather.  *bound receives the key bound the
 // later kernels are sized for; *which the ping-pong buffer holding the sorted pairs.
-int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab,
+int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab_in,
                 int64_t n_tiles, hipStream_t s, int64_t *bound, int *which) {
     int rc;
+    ImgTable tab = tab_in;
+    tab.cov = ctx->cov;
     if ((rc = ensure_gauss(ctx, n)) != GI_OK) return rc;
     if ((rc = ensure_tiles(ctx, n_tiles)) != GI_OK) return rc;
     if (ctx->cap_k == 0 && (rc = ensure_keys(ctx, 4096)) != GI_OK) return rc;
+    if (ctx->blend_cur == BLEND_ALPHA && (rc = ensure_alpha(ctx)) != GI_OK) return rc;
     if (ctx->binning != 1 && n > 0 && n_tiles <= FUSED_MAX_TILES)
         return run_binning_fused(ctx, params, n, tab, n_tiles, s, bound, which);
     ctx->off_cur = ctx->off;
@@ -477,7 +506,8 @@ int do_grad(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab, in
     StageTimer tm(ctx, s, GI_STAGE_RASTER_BWD);
     CK(launch_raster_bwd(a, dl, ctx->part, s));
     tm.stop();
-    UpdateArgs u{params, nullptr, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k};
+    UpdateArgs u{params, nullptr, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k,
+                 ctx->cov};
     StageTimer tu(ctx, s, GI_STAGE_UPDATE);
     CK(launch_grad_out(u, dparams, s));
     tu.stop();
@@ -496,10 +526,95 @@ int do_fit(gi_ctx *ctx, float *params, float *m, float *v, const float *target, 
     CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
                          pick_px(ctx, n, table_pixels(tab, n_tiles)), s));
     tm.stop();
-    UpdateArgs u{params, params, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k};
+    UpdateArgs u{params, params, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k,
+                 ctx->cov};
     AdamArgs h{hp->lr_mu, hp->lr_l, hp->lr_c, hp->beta1, hp->beta2, hp->eps, hp->l_min};
     StageTimer tu(ctx, s, GI_STAGE_UPDATE);
     CK(launch_adam(u, params, m, v, step, h, ctx->loss_part, tab, n_tiles, loss_out, s));
+    tu.stop();
+    return GI_OK;
+}
+
+// The opacity renderings (Sec. 3.2): binning with the opacity source, then the summation
+// kernels (BLEND_SUM, colours merged at projection) or the alpha-blending kernels.
+struct OpacityScope {
+    gi_ctx *c;
+    OpacityScope(gi_ctx *ctx, const float *o, int blend) : c(ctx) {
+        ctx->opac_cur = o;
+        ctx->blend_cur = blend;
+    }
+    ~OpacityScope() {
+        c->opac_cur = nullptr;
+        c->blend_cur = BLEND_NONE;
+    }
+};
+
+int do_render_opacity(gi_ctx *ctx, const float *params, const float *opacity, int64_t n,
+                      const ImgTable &tab, int64_t n_tiles, int blend, float *image,
+                      hipStream_t s) {
+    OpacityScope scope(ctx, opacity, blend);
+    int64_t bound;
+    int which;
+    int rc = run_binning(ctx, params, n, tab, n_tiles, s, &bound, &which);
+    if (rc != GI_OK) return rc;
+    RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
+    StageTimer tm(ctx, s, GI_STAGE_RASTER_FWD);
+    if (blend == BLEND_ALPHA)
+        CK(launch_alpha_fwd(a, ctx->rec_o, image, s));
+    else
+        CK(launch_raster_fwd(a, image, pick_px(ctx, n, table_pixels(tab, n_tiles)), s));
+    tm.stop();
+    return GI_OK;
+}
+
+int do_grad_opacity(gi_ctx *ctx, const float *params, const float *opacity, int64_t n,
+                    const ImgTable &tab, int64_t n_tiles, int blend, const float *dl,
+                    float *dparams, float *dopacity, hipStream_t s) {
+    OpacityScope scope(ctx, opacity, blend);
+    int64_t bound;
+    int which;
+    int rc = run_binning(ctx, params, n, tab, n_tiles, s, &bound, &which);
+    if (rc != GI_OK) return rc;
+    RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
+    float *part = blend == BLEND_ALPHA ? ctx->part_a : ctx->part;
+    StageTimer tm(ctx, s, GI_STAGE_RASTER_BWD);
+    if (blend == BLEND_ALPHA)
+        CK(launch_alpha_bwd(a, ctx->rec_o, dl, part, s));
+    else
+        CK(launch_raster_bwd(a, dl, part, s));
+    tm.stop();
+    UpdateArgs u{params, nullptr, n, ctx->count, ctx->off_cur, part, ctx->state, ctx->cap_k,
+                 ctx->cov};
+    StageTimer tu(ctx, s, GI_STAGE_UPDATE);
+    CK(launch_grad_opacity(u, opacity, blend, dparams, dopacity, s));
+    tu.stop();
+    return GI_OK;
+}
+
+int do_fit_opacity(gi_ctx *ctx, float *params, float *opacity, float *m, float *v, float *mo,
+                   float *vo, const float *target, int64_t n, const ImgTable &tab,
+                   int64_t n_tiles, int blend, const gi_adam *hp, int32_t *step,
+                   float *image_out, float *loss_out, hipStream_t s) {
+    OpacityScope scope(ctx, opacity, blend);
+    int64_t bound;
+    int which;
+    int rc = run_binning(ctx, params, n, tab, n_tiles, s, &bound, &which);
+    if (rc != GI_OK) return rc;
+    RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
+    float *part = blend == BLEND_ALPHA ? ctx->part_a : ctx->part;
+    StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
+    if (blend == BLEND_ALPHA)
+        CK(launch_alpha_fit(a, ctx->rec_o, target, part, image_out, ctx->loss_part, s));
+    else
+        CK(launch_raster_fit(a, target, part, image_out, ctx->loss_part,
+                             pick_px(ctx, n, table_pixels(tab, n_tiles)), s));
+    tm.stop();
+    UpdateArgs u{params, params, n, ctx->count, ctx->off_cur, part, ctx->state, ctx->cap_k,
+                 ctx->cov};
+    AdamArgs h{hp->lr_mu, hp->lr_l, hp->lr_c, hp->beta1, hp->beta2, hp->eps, hp->l_min};
+    StageTimer tu(ctx, s, GI_STAGE_UPDATE);
+    CK(launch_adam_opacity(u, params, opacity, m, v, mo, vo, step, h, blend, ctx->loss_part, tab,
+                           n_tiles, loss_out, s));
     tu.stop();
     return GI_OK;
 }
@@ -600,6 +715,11 @@ int gi_set_option(gi_ctx *ctx, int option, int64_t value) {
             if (value != 0 && value != 1) return GI_ERR_INVALID_ARG;
             ctx->timing = (int)value;
             return GI_OK;
+        case GI_OPT_COVARIANCE:
+            if (value != GI_COV_CHOLESKY && value != GI_COV_ROTATION_SCALE)
+                return GI_ERR_INVALID_ARG;
+            ctx->cov = (int)value;
+            return GI_OK;
         default:
             return GI_ERR_INVALID_ARG;
     }
@@ -639,6 +759,7 @@ int gi_get_option(gi_ctx *ctx, int option, int64_t *value) {
         case GI_OPT_FWD_PIXELS: *value = ctx->fwd_px; return GI_OK;
         case GI_OPT_BINNING: *value = ctx->binning; return GI_OK;
         case GI_OPT_TIMING: *value = ctx->timing; return GI_OK;
+        case GI_OPT_COVARIANCE: *value = ctx->cov; return GI_OK;
         default: return GI_ERR_INVALID_ARG;
     }
 }
@@ -770,6 +891,98 @@ int gi_timing(gi_ctx *ctx, int stage, double *total_ms, int64_t *launches, int r
     return GI_OK;
 }
 
+// Checks a gi_codec and converts it; GI_OK or GI_ERR_INVALID_ARG.
+static int codec_args(const gi_codec *c, int64_t n, CodecArgs *out) {
+    if (!c) return GI_ERR_INVALID_ARG;
+    if (c->bits < 1 || c->bits > 8 || c->stages < 1 || c->stages > 8 || c->codebook_size < 1 ||
+        c->codebook_size > 256)
+        return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!c->mu_dev || !c->codes_dev || !c->index_dev || !c->codebook_dev))
+        return GI_ERR_INVALID_ARG;
+    if (n > 0 && ((uintptr_t)c->mu_dev & 3u)) return GI_ERR_INVALID_ARG;
+    out->mu = c->mu_dev;
+    out->codes = c->codes_dev;
+    out->index = c->index_dev;
+    out->book = c->codebook_dev;
+    for (int k = 0; k < 3; ++k) {
+        out->gamma[k] = c->gamma[k];
+        out->beta[k] = c->beta[k];
+    }
+    out->bits = c->bits;
+    out->stages = c->stages;
+    out->size = c->codebook_size;
+    return GI_OK;
+}
+
+int gi_codec_decode(gi_ctx *ctx, const gi_codec *codec, int64_t n, float *params, void *stream) {
+    if (!ctx || n < 0 || n >= ((int64_t)1 << 31) || (n > 0 && !params)) return GI_ERR_INVALID_ARG;
+    if (n > 0 && !aligned16(params)) return GI_ERR_INVALID_ARG;
+    CodecArgs c;
+    if (codec_args(codec, n, &c) != GI_OK) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    CK(launch_codec_decode(c, n, params, ctx->state, (hipStream_t)stream));
+    return GI_OK;
+}
+
+int gi_render_codec(gi_ctx *ctx, const gi_codec *codec, int64_t n, int32_t H, int32_t W,
+                    float *image, void *stream) {
+    if (!ctx || !image) return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    CodecArgs c;
+    if (codec_args(codec, n, &c) != GI_OK) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    const ImgTable tab = single_table(H, W);
+    const int64_t T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    ctx->codec = &c;
+    const int rc = do_render(ctx, nullptr, n, tab, T, image, (hipStream_t)stream);
+    ctx->codec = nullptr;
+    return rc;
+}
+
+int gi_render_opacity(gi_ctx *ctx, const float *params, const float *opacity, int64_t n,
+                      int32_t H, int32_t W, int32_t blend, float *image, void *stream) {
+    if (!ctx || !image || (n > 0 && (!params || !opacity))) return GI_ERR_INVALID_ARG;
+    if (blend != GI_BLEND_SUM && blend != GI_BLEND_ALPHA) return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    if (n > 0 && !aligned16(params)) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    const ImgTable tab = single_table(H, W);
+    const int64_t T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    return do_render_opacity(ctx, params, opacity, n, tab, T, blend, image, (hipStream_t)stream);
+}
+
+int gi_grad_opacity(gi_ctx *ctx, const float *params, const float *opacity, int64_t n,
+                    int32_t H, int32_t W, int32_t blend, const float *dl_dimage, float *dparams,
+                    float *dopacity, void *stream) {
+    if (!ctx || !dl_dimage || (n > 0 && (!params || !opacity || !dparams || !dopacity)))
+        return GI_ERR_INVALID_ARG;
+    if (blend != GI_BLEND_SUM && blend != GI_BLEND_ALPHA) return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!aligned16(params) || !aligned16(dparams))) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    const ImgTable tab = single_table(H, W);
+    const int64_t T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    return do_grad_opacity(ctx, params, opacity, n, tab, T, blend, dl_dimage, dparams, dopacity,
+                           (hipStream_t)stream);
+}
+
+int gi_fit_step_opacity(gi_ctx *ctx, float *params, float *opacity, float *m, float *v,
+                        float *m_opacity, float *v_opacity, const float *target, int64_t n,
+                        int32_t H, int32_t W, int32_t blend, const gi_adam *hp, int32_t *step,
+                        float *image_out, float *loss_out, void *stream) {
+    if (!ctx || !target || !step || check_adam(hp) != GI_OK) return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!params || !opacity || !m || !v || !m_opacity || !v_opacity))
+        return GI_ERR_INVALID_ARG;
+    if (blend != GI_BLEND_SUM && blend != GI_BLEND_ALPHA) return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!aligned16(params) || !aligned16(m) || !aligned16(v))) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    const ImgTable tab = single_table(H, W);
+    const int64_t T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    return do_fit_opacity(ctx, params, opacity, m, v, m_opacity, v_opacity, target, n, tab, T,
+                          blend, hp, step, image_out, loss_out, (hipStream_t)stream);
+}
+
 int gi_render(gi_ctx *ctx, const float *params, int64_t n, int32_t H, int32_t W, float *image,
               void *stream) {
     if (!ctx || !image || (n > 0 && !params)) return GI_ERR_INVALID_ARG;
@@ -872,6 +1085,7 @@ int gi_fit_graph_create(gi_ctx *user, float *params, float *m, float *v, const f
     ctx->sort_bits = user->sort_bits;
     ctx->fwd_px = user->fwd_px;
     ctx->binning = user->binning;
+    ctx->cov = user->cov;
     ctx->tuned = user->tuned;
     gi_graph *gr = new gi_graph();
     gr->ctx = ctx;

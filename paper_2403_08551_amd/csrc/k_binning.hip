@@ -7,6 +7,8 @@
 // Eq. rasterization3).  What remains is grouping Gaussians by tile: each Gaussian emits one
 // (tile id, Gaussian id) key per covered tile, in row-major order within its rectangle, and a
 // stable sort by tile id yields per-tile lists in ascending Gaussian order.
+#include <cstring>
+
 #include "gi_common.h"
 
 namespace gi {
@@ -21,6 +23,10 @@ constexpr int SORT_WAVES = SORT_T / 64;
 constexpr int SCAN_T = 256;
 constexpr int SCAN_IPT = 16;
 constexpr int SCAN_TILE = SCAN_T * SCAN_IPT;
+
+// LDS staging index with one pad word per 32: both the coalesced (j * 256 + t) and the
+// thread-contiguous (16 t + j) access patterns then hit 32 distinct banks.
+__device__ inline int spad(int i) { return i + (i >> 5); }
 
 // ---- small block-level helpers --------------------------------------------------------------
 
@@ -75,17 +81,62 @@ __device__ inline bool covers(double r, double s00, double s01, double s11) {
 
 constexpr double R_MAX = 33554432.0;  // 2^25: covers any image once |mu| <= 2^24
 
+// Record of Gaussian i from the source.  A compressed record is decoded as in Sec. 3.3: the
+// binary16 positions exactly, each covariance code as code * gamma + beta and the colour as the
+// sum of the stage codebook entries in stage order, all in float64 (the products are exact)
+// and rounded once to float32.  Returns false when a code or an index is out of range.
+__device__ inline bool load_record(const RecordSrc &src, int64_t i, float (&q)[8]) {
+#pragma clang fp contract(off)
+    if (!src.codec.mu) {
+        const float4 q0 = src.params[2 * i], q1 = src.params[2 * i + 1];
+        q[0] = q0.x; q[1] = q0.y; q[2] = q0.z; q[3] = q0.w;
+        q[4] = q1.x; q[5] = q1.y; q[6] = q1.z; q[7] = q1.w;
+        return true;
+    }
+    const CodecArgs &c = src.codec;
+    const uint32_t mu = reinterpret_cast<const uint32_t *>(c.mu)[i];
+    q[0] = (float)__builtin_bit_cast(_Float16, (uint16_t)(mu & 0xffffu));
+    q[1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(mu >> 16));
+    const uint32_t lim = (1u << c.bits) - 1u;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t code = c.codes[3 * i + k];
+        ok = ok && code <= lim;
+        q[2 + k] = (float)((double)code * (double)c.gamma[k] + (double)c.beta[k]);
+    }
+    double col0 = 0.0, col1 = 0.0, col2 = 0.0;
+    for (int m = 0; m < c.stages; ++m) {
+        uint32_t ix = c.index[i * c.stages + m];
+        if (ix >= (uint32_t)c.size) {
+            ok = false;
+            ix = 0;
+        }
+        const float *e = c.book + ((int64_t)m * c.size + ix) * 3;
+        col0 += (double)e[0];
+        col1 += (double)e[1];
+        col2 += (double)e[2];
+    }
+    q[5] = (float)col0;
+    q[6] = (float)col1;
+    q[7] = (float)col2;
+    return ok;
+}
+
 // Projection and tile rectangle of Gaussian i (see the file header of k_raster.hip for the
 // stored record).  Writes proj, rect, tinfo and count; returns the count.
-__device__ inline uint32_t project_one(const float4 *__restrict__ params, int64_t i,
+__device__ inline uint32_t project_one(const RecordSrc &src, int64_t i,
                                        const ImgTable &tab, float4 *__restrict__ proj,
                                        int4 *__restrict__ rect, uint2 *__restrict__ tinfo,
                                        uint32_t *__restrict__ count, bool *nonfinite,
-                                       int4 *rc_out, uint2 *inf_out) {
+                                       bool *bad_code, int4 *rc_out, uint2 *inf_out) {
 #pragma clang fp contract(off)
     uint32_t cnt = 0;
-    const float4 q0 = params[2 * i], q1 = params[2 * i + 1];
-    const float q[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    float q[8];
+    const bool code_ok = load_record(src, i, q);
+    *bad_code = !code_ok;
+    float o = 1.f;
+    if (src.opacity) o = src.opacity[i];
     int32_t TW, TH;
     uint32_t tb;
     if (tab.B == 1) {
@@ -98,21 +149,48 @@ __device__ inline uint32_t project_one(const float4 *__restrict__ params, int64_
     bool finite = true;
 #pragma unroll
     for (int k = 0; k < 8; ++k) finite = finite && isfinite(q[k]);
+    finite = finite && isfinite(o);
     *nonfinite = !finite;
-    const double mx = q[0], my = q[1], l1 = q[2], l2 = q[3], l3 = q[4];
-    bool act = finite && fabs(l1) >= 0x1p-24 && fabs(l3) >= 0x1p-24 && fabs(l2) <= 0x1p24 &&
-               fabs(mx) <= 0x1p24 && fabs(my) <= 0x1p24;
+    const double mx = q[0], my = q[1];
+    const bool rs = tab.cov == COV_ROTATION_SCALE;
+    // (q2, q3, q4) = (l1, l2, l3), or (s1, s2, theta) in the rotation-scale form
+    bool act = code_ok && finite && fabs(mx) <= 0x1p24 && fabs(my) <= 0x1p24 &&
+               (rs ? fabs(q[2]) >= 0x1p-24 && fabs(q[3]) >= 0x1p-24 && fabs(q[4]) <= 0x1p24
+                   : fabs(q[2]) >= 0x1p-24 && fabs(q[4]) >= 0x1p-24 && fabs(q[3]) <= 0x1p24);
     int4 rc = make_int4(0, 0, -1, -1);
     float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
     if (act) {
-        const double s00 = l1 * l1, s01 = l1 * l2, s11 = l2 * l2 + l3 * l3;
-        // starting guess from the eigenvalue formula, then the least r that covers
-        const double lam = 0.5 * (s00 + s11) + sqrt(0.25 * (s00 - s11) * (s00 - s11) + s01 * s01);
-        double r = ceil(3.0 * sqrt(lam));
-        if (!(r >= 0.0)) r = 0.0;
-        if (r > R_MAX) r = R_MAX;
-        while (r > 0.0 && covers(r - 1.0, s00, s01, s11)) r -= 1.0;
-        while (r < R_MAX && !covers(r, s00, s01, s11)) r += 1.0;
+        double l1, l2, l3, r;
+        if (rs) {
+            // Sigma = R diag(s1^2, s2^2) R^T (Eq. RSSR) and its Cholesky factor: l1 = sqrt(s00),
+            // l2 = s01 / l1, l3 = |s1 s2| / l1 (det Sigma = (l1 l3)^2 = (s1 s2)^2).  The
+            // eigenvalues are s1^2 and s2^2, so r is the least integer with
+            // r^2 >= 9 max(s1^2, s2^2); 3|s| and the squares are exact in float64.
+            const double s1 = q[2], s2 = q[3];
+            double sn, cs;
+            sincos((double)q[4], &sn, &cs);
+            const double A = s1 * s1, B = s2 * s2;
+            const double s00 = cs * cs * A + sn * sn * B, s01 = cs * sn * (A - B);
+            l1 = sqrt(s00);
+            l2 = s01 / l1;
+            l3 = fabs(s1 * s2) / l1;
+            const double m = A > B ? A : B;
+            r = ceil(3.0 * sqrt(m));
+            if (r > R_MAX) r = R_MAX;
+            while (r > 0.0 && (r - 1.0) * (r - 1.0) >= 9.0 * m) r -= 1.0;
+            while (r < R_MAX && r * r < 9.0 * m) r += 1.0;
+        } else {
+            l1 = q[2]; l2 = q[3]; l3 = q[4];
+            const double s00 = l1 * l1, s01 = l1 * l2, s11 = l2 * l2 + l3 * l3;
+            // starting guess from the eigenvalue formula, then the least r that covers
+            const double lam =
+                0.5 * (s00 + s11) + sqrt(0.25 * (s00 - s11) * (s00 - s11) + s01 * s01);
+            r = ceil(3.0 * sqrt(lam));
+            if (!(r >= 0.0)) r = 0.0;
+            if (r > R_MAX) r = R_MAX;
+            while (r > 0.0 && covers(r - 1.0, s00, s01, s11)) r -= 1.0;
+            while (r < R_MAX && !covers(r, s00, s01, s11)) r += 1.0;
+        }
         double fx0 = floor((mx - r) / 16.0), fx1 = floor((mx + r) / 16.0);
         double fy0 = floor((my - r) / 16.0), fy1 = floor((my + r) / 16.0);
         if (fx0 < 0.0) fx0 = 0.0;
@@ -124,6 +202,11 @@ __device__ inline uint32_t project_one(const float4 *__restrict__ params, int64_
             cnt = (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1);
         }
         p0 = make_float4(q[0], q[1], (float)(U_SCALE / l1), (float)(U_SCALE / l3));
+        if (src.blend == BLEND_SUM) {  // Eq. rasterization3: the record colour is o c
+            q[5] *= o;
+            q[6] *= o;
+            q[7] *= o;
+        }
         p1 = make_float4((float)(U_SCALE * l2 / (l1 * l3)), q[5], q[6], q[7]);
     }
     proj[2 * i] = p0;
@@ -137,7 +220,7 @@ __device__ inline uint32_t project_one(const float4 *__restrict__ params, int64_
     return cnt;
 }
 
-__global__ __launch_bounds__(BLK) void k_project(const float4 *__restrict__ params, int64_t n,
+__global__ __launch_bounds__(BLK) void k_project(const RecordSrc src, int64_t n,
                                                  ImgTable tab, float4 *__restrict__ proj,
                                                  int4 *__restrict__ rect,
                                                  uint2 *__restrict__ tinfo,
@@ -147,13 +230,14 @@ __global__ __launch_bounds__(BLK) void k_project(const float4 *__restrict__ para
     __shared__ unsigned long long tmp[BLK / 64 + 1];
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     uint32_t cnt = 0;
-    bool nonfinite = false;
+    bool nonfinite = false, bad = false;
     if (i < n) {
         int4 rc;
         uint2 inf;
-        cnt = project_one(params, i, tab, proj, rect, tinfo, count, &nonfinite, &rc, &inf);
+        cnt = project_one(src, i, tab, proj, rect, tinfo, count, &nonfinite, &bad, &rc, &inf);
     }
     if (__ballot(nonfinite) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_NONFINITE);
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_BAD_CODE);
     unsigned long long tot;
     block_exclusive_scan<unsigned long long, BLK>((unsigned long long)cnt, tmp, &tot);
     if (threadIdx.x == 0) blocksum[blockIdx.x] = tot;
@@ -248,20 +332,20 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_down(const uint32_t *__restrict
                                                       uint32_t *__restrict__ out, int64_t n,
                                                       const unsigned long long *__restrict__ bs) {
     __shared__ unsigned long long tmp[SCAN_T / 64 + 1];
-    __shared__ uint32_t stage[SCAN_TILE];
+    __shared__ uint32_t stage[SCAN_TILE + SCAN_TILE / 32];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     // coalesced load into LDS, then each thread scans 16 consecutive values
 #pragma unroll
     for (int j = 0; j < SCAN_IPT; ++j) {
         int64_t idx = base + j * SCAN_T + threadIdx.x;
-        stage[j * SCAN_T + threadIdx.x] = idx < n ? in[idx] : 0u;
+        stage[spad(j * SCAN_T + threadIdx.x)] = idx < n ? in[idx] : 0u;
     }
     __syncthreads();
     uint32_t v[SCAN_IPT];
     unsigned long long s = 0;
 #pragma unroll
     for (int j = 0; j < SCAN_IPT; ++j) {
-        v[j] = stage[threadIdx.x * SCAN_IPT + j];
+        v[j] = stage[spad(threadIdx.x * SCAN_IPT + j)];
         s += v[j];
     }
     unsigned long long tot;
@@ -269,14 +353,14 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_down(const uint32_t *__restrict
                              bs[blockIdx.x];
 #pragma unroll
     for (int j = 0; j < SCAN_IPT; ++j) {
-        stage[threadIdx.x * SCAN_IPT + j] = (uint32_t)run;
+        stage[spad(threadIdx.x * SCAN_IPT + j)] = (uint32_t)run;
         run += v[j];
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < SCAN_IPT; ++j) {
         int64_t idx = base + j * SCAN_T + threadIdx.x;
-        if (idx < n) out[idx] = stage[j * SCAN_T + threadIdx.x];
+        if (idx < n) out[idx] = stage[spad(j * SCAN_T + threadIdx.x)];
     }
 }
 
@@ -463,7 +547,9 @@ __global__ __launch_bounds__(BLK) void k_ranges_gather(const uint32_t *__restric
                                                        const uint32_t *__restrict__ off,
                                                        uint2 *__restrict__ ranges,
                                                        float4 *__restrict__ rec,
-                                                       uint32_t *__restrict__ slot) {
+                                                       uint32_t *__restrict__ slot,
+                                                       const float *__restrict__ opac,
+                                                       float *__restrict__ rec_o) {
     const int64_t n = sort_count(n_dev, n_max);
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     if (i >= n) return;
@@ -473,6 +559,7 @@ __global__ __launch_bounds__(BLK) void k_ranges_gather(const uint32_t *__restric
     const uint32_t g = vals[i];
     rec[2 * i] = proj[2 * (int64_t)g];
     rec[2 * i + 1] = proj[2 * (int64_t)g + 1];
+    if (rec_o) rec_o[i] = opac[g];
     const int4 r = rect[g];
     const uint2 inf = tinfo[g];
     const uint32_t lt = key - inf.x;
@@ -500,6 +587,7 @@ __global__ __launch_bounds__(BLK) void k_fill_u32(uint32_t *__restrict__ p, uint
 
 constexpr int FB = 256;
 constexpr int FUSED_WAVES = FB / 64;
+constexpr uint32_t OWN_CAP = 4096;
 constexpr int XCDS = 8;
 
 // Workgroup i runs on XCD i mod 8.  Give each XCD a contiguous range of chunks, so that the
@@ -524,7 +612,7 @@ constexpr unsigned long long CS_PRE = 2ull << CS_FLAG_SHIFT;
 constexpr unsigned long long CS_VAL = (1ull << CS_FLAG_SHIFT) - 1;
 constexpr long SPIN_LIMIT = 1l << 20;
 
-__global__ __launch_bounds__(FB) void k_project_hist(const float4 *__restrict__ params, int64_t n,
+__global__ __launch_bounds__(FB) void k_project_hist(const RecordSrc src, int64_t n,
                                                      ImgTable tab, float4 *__restrict__ proj,
                                                      int4 *__restrict__ rect,
                                                      uint2 *__restrict__ tinfo,
@@ -538,11 +626,11 @@ __global__ __launch_bounds__(FB) void k_project_hist(const float4 *__restrict__ 
     __syncthreads();
     const uint32_t chunk = xcd_chunk(blockIdx.x, (uint32_t)nchunk);
     const int64_t i = (int64_t)chunk * FB + threadIdx.x;
-    bool nonfinite = false;
+    bool nonfinite = false, bad = false;
     if (i < n) {
         int4 rc;
         uint2 inf;
-        const uint32_t cnt = project_one(params, i, tab, proj, rect, tinfo, count, &nonfinite,
+        const uint32_t cnt = project_one(src, i, tab, proj, rect, tinfo, count, &nonfinite, &bad,
                                          &rc, &inf);
         scan[i] = cnt;
         if (cnt) {
@@ -552,6 +640,7 @@ __global__ __launch_bounds__(FB) void k_project_hist(const float4 *__restrict__ 
         }
     }
     if (__ballot(nonfinite) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_NONFINITE);
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_BAD_CODE);
     __syncthreads();
     for (int t = threadIdx.x; t < T; t += FB) scan[n + (int64_t)t * nchunk + chunk] = h[t];
 }
@@ -575,21 +664,21 @@ __global__ __launch_bounds__(CS_T) void k_chained_scan(uint32_t *__restrict__ da
                                                        DevState *state) {
     __shared__ unsigned long long s_prefix;
     __shared__ unsigned long long tmp[CS_T / 64 + 1];
-    __shared__ uint32_t stage[CS_TILE];
+    __shared__ uint32_t stage[CS_TILE + CS_TILE / 32];
     const uint32_t w = blockIdx.x;
     const unsigned long long tag = (unsigned long long)(state->scan_epoch & 0x1fffffffu) << CS_EPOCH_SHIFT;
     const int64_t base = (int64_t)w * CS_TILE;
 #pragma unroll
     for (int j = 0; j < CS_IPT; ++j) {
         const int64_t idx = base + j * CS_T + threadIdx.x;
-        stage[j * CS_T + threadIdx.x] = idx < L ? data[idx] : 0u;
+        stage[spad(j * CS_T + threadIdx.x)] = idx < L ? data[idx] : 0u;
     }
     __syncthreads();
     uint32_t v[CS_IPT];
     unsigned long long sum = 0;
 #pragma unroll
     for (int j = 0; j < CS_IPT; ++j) {
-        v[j] = stage[threadIdx.x * CS_IPT + j];
+        v[j] = stage[spad(threadIdx.x * CS_IPT + j)];
         sum += v[j];
     }
     unsigned long long agg;
@@ -648,14 +737,14 @@ __global__ __launch_bounds__(CS_T) void k_chained_scan(uint32_t *__restrict__ da
     for (int j = 0; j < CS_IPT; ++j) {
         const int64_t idx = base + threadIdx.x * CS_IPT + j;
         if (mark_out && idx == mark) *mark_out = run;
-        stage[threadIdx.x * CS_IPT + j] = (uint32_t)run;
+        stage[spad(threadIdx.x * CS_IPT + j)] = (uint32_t)run;
         run += v[j];
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < CS_IPT; ++j) {
         const int64_t idx = base + j * CS_T + threadIdx.x;
-        if (idx < L) data[idx] = stage[j * CS_T + threadIdx.x];
+        if (idx < L) data[idx] = stage[spad(j * CS_T + threadIdx.x)];
     }
 }
 
@@ -675,7 +764,8 @@ __global__ __launch_bounds__(FB) void k_fused_scatter(
     const uint2 *__restrict__ tinfo, const float4 *__restrict__ proj,
     const uint32_t *__restrict__ scan, int64_t n, int32_t T, int32_t tbits, int64_t nchunk,
     int64_t cap, float4 *__restrict__ rec, uint32_t *__restrict__ slot,
-    uint32_t *__restrict__ ids, uint2 *__restrict__ ranges, DevState *state) {
+    uint32_t *__restrict__ ids, uint2 *__restrict__ ranges, const float *__restrict__ opac,
+    float *__restrict__ rec_o, DevState *state) {
     extern __shared__ uint32_t dyn[];  // wh [FUSED_WAVES][T], then tbase [T]
     uint32_t *wh = dyn;
     uint32_t *tbase = dyn + FUSED_WAVES * T;
@@ -685,6 +775,7 @@ __global__ __launch_bounds__(FB) void k_fused_scatter(
     __shared__ uint2 sinfo[FB];
     __shared__ uint32_t soff[FB];
     __shared__ float4 sproj[2 * FB];
+    __shared__ uint8_t owner[OWN_CAP];  // chunk-local key -> its Gaussian, when the keys fit
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t chunk = xcd_chunk(blockIdx.x, (uint32_t)nchunk);
     const int64_t i = (int64_t)chunk * FB + threadIdx.x;
@@ -693,6 +784,9 @@ __global__ __launch_bounds__(FB) void k_fused_scatter(
     unsigned long long tot;
     const unsigned long long loc = block_exclusive_scan<unsigned long long, FB>(c, tmp, &tot);
     pre[threadIdx.x] = (uint32_t)loc;
+    const bool table = tot <= OWN_CAP;  // same for the whole block
+    if (table)
+        for (uint32_t k = 0; k < c; ++k) owner[loc + k] = (uint8_t)threadIdx.x;
     if (i < n) {
         srect[threadIdx.x] = rect[i];
         sinfo[threadIdx.x] = tinfo[i];
@@ -723,10 +817,16 @@ __global__ __launch_bounds__(FB) void k_fused_scatter(
         const bool valid = j < j1;
         uint32_t t = 0;
         if (valid) {
-            int lo = 0, hi = FB - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+            int lo;
+            if (table) {
+                lo = owner[j];
+            } else {
+                lo = 0;
+                int hi = FB - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+                }
             }
             const int4 r = srect[lo];
             const uint2 inf = sinfo[lo];
@@ -756,10 +856,16 @@ __global__ __launch_bounds__(FB) void k_fused_scatter(
         uint32_t t = 0, li = 0;
         int g = 0;
         if (valid) {
-            int lo = 0, hi = FB - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+            int lo;
+            if (table) {
+                lo = owner[j];
+            } else {
+                lo = 0;
+                int hi = FB - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+                }
             }
             g = lo;
             const int4 r = srect[lo];
@@ -779,6 +885,7 @@ __global__ __launch_bounds__(FB) void k_fused_scatter(
                 rec[2 * (int64_t)pos + 1] = sproj[2 * g + 1];
                 slot[pos] = soff[g] + li;
                 if (ids) ids[pos] = chunk * FB + (uint32_t)g;
+                if (rec_o) rec_o[pos] = opac[(int64_t)chunk * FB + g];
             } else {
                 overflow = true;
             }
@@ -789,9 +896,40 @@ __global__ __launch_bounds__(FB) void k_fused_scatter(
 
 inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// Compressed set -> float records [N][8]; a Gaussian with an invalid code or index gets NaN
+// in every slot (so that rendering the records leaves it out, as the fused decode does).
+__global__ __launch_bounds__(BLK) void k_codec_decode(const CodecArgs c, int64_t n,
+                                                      float4 *__restrict__ out,
+                                                      DevState *state) {
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    bool bad = false;
+    if (i < n) {
+        RecordSrc src;
+        src.params = nullptr;
+        src.codec = c;
+        float q[8];
+        bad = !load_record(src, i, q);
+        if (bad) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) q[k] = __builtin_nanf("");
+        }
+        out[2 * i] = make_float4(q[0], q[1], q[2], q[3]);
+        out[2 * i + 1] = make_float4(q[4], q[5], q[6], q[7]);
+    }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_BAD_CODE);
+}
+
 }  // namespace
 
 // ---- launchers -----------------------------------------------------------------------------
+
+hipError_t launch_codec_decode(const CodecArgs &c, int64_t n, float *params, DevState *state,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_codec_decode, dim3(grid_for(n, BLK)), dim3(BLK), 0, s, c, n,
+                       reinterpret_cast<float4 *>(params), state);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
@@ -799,10 +937,19 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+static RecordSrc record_src(const BinBuffers &b) {
+    RecordSrc r;
+    memset(&r, 0, sizeof(r));
+    r.params = reinterpret_cast<const float4 *>(b.params);
+    if (b.codec) r.codec = *b.codec;
+    r.opacity = b.opacity;
+    r.blend = b.blend;
+    return r;
+}
+
 hipError_t launch_project(const BinBuffers &b, const ImgTable &tab, hipStream_t s) {
     if (b.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project, dim3(grid_for(b.n, BLK)), dim3(BLK), 0, s,
-                       reinterpret_cast<const float4 *>(b.params), b.n, tab,
+    hipLaunchKernelGGL(k_project, dim3(grid_for(b.n, BLK)), dim3(BLK), 0, s, record_src(b), b.n, tab,
                        reinterpret_cast<float4 *>(b.proj), b.rect, b.tinfo, b.count, b.blocksum,
                        b.state);
     return hipGetLastError();
@@ -930,7 +1077,7 @@ hipError_t launch_fused_a(const FusedBuffers &f, const ImgTable &tab, hipStream_
     const int64_t nchunk = fused_chunks(f.b.n);
     hipLaunchKernelGGL(k_project_hist, dim3((unsigned)nchunk), dim3(FB),
                        sizeof(uint32_t) * (size_t)f.b.n_tiles, s,
-                       reinterpret_cast<const float4 *>(f.b.params), f.b.n, tab,
+                       record_src(f.b), f.b.n, tab,
                        reinterpret_cast<float4 *>(f.b.proj), f.b.rect, f.b.tinfo, f.b.count,
                        f.scan, (int32_t)f.b.n_tiles, nchunk, f.b.state);
     hipError_t e = hipGetLastError();
@@ -950,7 +1097,8 @@ hipError_t launch_fused_c(const FusedBuffers &f, uint32_t *ids, hipStream_t s) {
                        sizeof(uint32_t) * (FUSED_WAVES + 1) * (size_t)f.b.n_tiles, s, f.b.count,
                        f.b.rect, f.b.tinfo, reinterpret_cast<const float4 *>(f.b.proj), f.scan,
                        f.b.n, (int32_t)f.b.n_tiles, tbits, nchunk, f.b.cap,
-                       reinterpret_cast<float4 *>(f.b.rec), f.b.slot, ids, f.b.ranges, f.b.state);
+                       reinterpret_cast<float4 *>(f.b.rec), f.b.slot, ids, f.b.ranges,
+                       f.b.opacity, f.b.rec_o, f.b.state);
     return hipGetLastError();
 }
 
@@ -962,7 +1110,7 @@ hipError_t launch_ranges_gather(const BinBuffers &b, int which, const ImgTable &
     hipLaunchKernelGGL(k_ranges_gather, dim3(grid_for(n_max, BLK)), dim3(BLK), 0, s, b.keys[which],
                        b.vals[which], &b.state->keys_total, n_max,
                        reinterpret_cast<const float4 *>(b.proj), b.rect, b.tinfo, b.off, b.ranges,
-                       reinterpret_cast<float4 *>(b.rec), b.slot);
+                       reinterpret_cast<float4 *>(b.rec), b.slot, b.opacity, b.rec_o);
     return hipGetLastError();
 }
 

@@ -67,3 +67,17 @@ def test_product_path_has_no_cpu_fallback(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         _lib.lib()
+
+
+def test_header_constants_match_the_binding():
+    src = open(os.path.join(ROOT, "include", "gi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    found = dict(re.findall(r"\b(GI_[A-Z0-9_]+)\s*=\s*(-?\d+)", src))
+    found.update(re.findall(r"#define\s+(GI_FLAG_[A-Z_]+)\s+(\d+)u", src))
+    assert len(found) > 20
+    for name, value in found.items():
+        if hasattr(_lib, name):
+            assert getattr(_lib, name) == int(value), name
+    for name in ("GI_OPT_COVARIANCE", "GI_COV_CHOLESKY", "GI_COV_ROTATION_SCALE",
+                 "GI_FLAG_SCAN_STALL", "GI_STAGE_UPDATE"):
+        assert name in found and hasattr(_lib, name), name
