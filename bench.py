@@ -57,6 +57,8 @@ def parse():
                     help="skip the codec decode leg (Sec. 3.3, Table 2)")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the rasterisation ablation leg (Table 3 rows, 768x512 / 30k)")
+    ap.add_argument("--no-recipe", action="store_true",
+                    help="skip the fitting-recipe and fine-tuning leg (Sec. 4.1, Sec. 3.3)")
     ap.add_argument("--no-rs", action="store_true",
                     help="skip the rotation-scale leg (Sec. 3.1, Eq. RSSR)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -162,17 +164,30 @@ def batched_vs_plain(ctx, inputs, steps, P, torch, np):
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic-k_raster_fit-kodak-768x512-70k.json")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused raster kernel from the committed counter record, if it
-    was taken on the current source of the kernel (else None)."""
+def raster_fit_digest():
+    """sha256 of the source of the fused fit kernel and the device functions it calls (the
+    marked region of k_raster.hip)."""
     import hashlib
+    src = open(os.path.join(ROOT, "paper_2403_08551_amd", "csrc", "k_raster.hip")).read()
+    a = src.index("// ---- begin: the fused fit kernel")
+    b = src.index("// ---- end: the fused fit kernel")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the fused raster kernel instance `kernel` from the committed
+    counter record, if it was taken on the current source of the kernel (else None)."""
     try:
         rec = json.load(open(TRAFFIC_RECORD))
     except (OSError, ValueError):
         return None
-    src = os.path.join(ROOT, "paper_2403_08551_amd", "csrc", "k_raster.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("k_raster_sha256") != digest:
+    if rec.get("kernel") != kernel:
+        return None
+    return _traffic_if_current(rec)
+
+
+def _traffic_if_current(rec):
+    if rec.get("kernel_source_sha256") != raster_fit_digest():
         return None
     return rec.get("bytes_per_launch")
 
@@ -334,6 +349,71 @@ def ablation_leg(P, torch, steps):
     return out
 
 
+def recipe_leg(P, torch, w, steps):
+    """Fit it/s of the paper's recipe (raw records, App. C parametrisation, Adan) and of the
+    quantisation-aware fine-tuning (b = 6, M = 2, B = 8), eager non-waiting steps on the
+    workload's size; also the quantiser set-up and encoding times."""
+    import numpy as np
+    dev = torch.device("cuda", 0)
+    H, W = w.height, w.width
+    rng = np.random.default_rng(w.param_seed)
+    raw = np.zeros((w.n, 8), np.float32)
+    raw[:, 0:2] = np.arctanh(rng.uniform(-0.999, 0.999, (w.n, 2)))
+    raw[:, 2] = rng.uniform(0.5, 7.5, w.n)
+    raw[:, 3] = rng.normal(0.0, 0.5, w.n)
+    raw[:, 4] = rng.uniform(0.5, 7.5, w.n)
+    raw[:, 5:8] = rng.uniform(0.0, 1.0, (w.n, 3))
+    target = torch.tensor(w.target(), device=dev)
+    ctx = P.Context(0)
+    out = {}
+    rd = torch.tensor(raw, device=dev)
+    state = torch.zeros(4, w.n, 8, device=dev)
+    step = torch.ones(1, dtype=torch.int32, device=dev)
+    ctx.fit_step_recipe(rd, state, target, step)
+    ctx.set_option(P._lib.GI_OPT_SYNC, 0)
+    for _ in range(5):
+        ctx.fit_step_recipe(rd, state, target, step)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.fit_step_recipe(rd, state, target, step)
+    torch.cuda.synchronize()
+    out["recipe_fit_its"] = steps / (time.perf_counter() - t0)
+    ctx.set_option(P._lib.GI_OPT_SYNC, 1)
+    params = ctx.recipe_params(rd, H, W)
+    q = P.Quantiser.zeros(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.qat_init(params, q, 5)
+    torch.cuda.synchronize()
+    out["quantiser_init_ms"] = 1e3 * (time.perf_counter() - t0)
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    step.fill_(1)
+    ctx.fit_step_qat(params, m, v, target, step, q)
+    ctx.set_option(P._lib.GI_OPT_SYNC, 0)
+    for _ in range(5):
+        ctx.fit_step_qat(params, m, v, target, step, q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.fit_step_qat(params, m, v, target, step, q)
+    torch.cuda.synchronize()
+    out["qat_fit_its"] = steps / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    codec = ctx.qat_encode(params, q)
+    torch.cuda.synchronize()
+    out["encode_ms"] = 1e3 * (time.perf_counter() - t0)
+    _, flags = ctx.query(clear=True)
+    ctx.close()
+    if flags & (P._lib.GI_FLAG_KEY_OVERFLOW | P._lib.GI_FLAG_SCAN_STALL):
+        raise RuntimeError(f"flags {flags} raised during the recipe leg")
+    out["steps"] = steps
+    out["bits_per_gaussian"] = 2 * 16 + 3 * q.bits + q.stages * int(np.log2(q.size))
+    out["paper_context"] = {"training_s_50k_steps_v100_kodak_70k": 106.59}
+    del codec
+    return out
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -434,6 +514,7 @@ def main():
                                                      tuned)
     cod = None if args.no_codec else codec_leg(P, torch, w, max(args.steps, 100))
     abl = None if args.no_ablation else ablation_leg(P, torch, 100)
+    rcp = None if args.no_recipe else recipe_leg(P, torch, w, 100)
     bvp = None
     if args.batch_images > 0:
         bvp = batched_vs_plain(ctx, binputs, args.batch_steps, P, torch, np)
@@ -460,7 +541,7 @@ def main():
                      "update": upd_ms / max(upd_n, 1)},
         "loss": {"after_warmup": loss_start, "after_timed": loss_end},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T FP32 op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
+                     "unit": "T FP32 op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(f"k_raster_fit<{tuned[0] or 2}>"),
                      "peak_unpacked": VALU_PEAK_UNPACKED / 1e12,
                      "frac_unpacked": achieved / VALU_PEAK_UNPACKED,
                      "kernel": f"k_raster_fit<{tuned[0] or 2}>", "ops_per_pair": OPS_PER_PAIR_FIT,
@@ -469,6 +550,7 @@ def main():
         "rotation_scale": rs,
         "codec": cod,
         "ablation": abl,
+        "recipe_and_fine_tuning": rcp,
         "paper_context": {"render_fps_v100_kodak_70k": 2092.17,
                           "fit_its_v100_kodak_70k_derived": 50000 / 106.59},
     }

@@ -233,6 +233,73 @@ int gi_fit_step_opacity(gi_ctx *ctx, float *params_dev, float *opacity_dev, floa
                         int32_t blend, const gi_adam *hp, int32_t *step_dev,
                         float *image_out_dev, float *loss_out_dev, void *stream);
 
+/* ---- the paper's fitting recipe (Sec. 4.1, App. C) ---------------------------------------- */
+
+/* Adan hyper-parameters (Xie et al. 2022, as used in Sec. 4.1): decay rates beta1..beta3 of the
+ * gradient, gradient-difference and squared-Nesterov-gradient moments (published defaults 0.98,
+ * 0.92, 0.99), learning rate lr (1e-3 in the paper) halved every halve_every steps (20000;
+ * 0 = constant), decoupled weight decay. */
+typedef struct gi_adan {
+    float lr, beta1, beta2, beta3, eps, weight_decay;
+    int32_t halve_every;
+} gi_adan;
+
+/* One fit step on raw records (App. C): the renderer sees mu = extent (tanh(rho) + 1) / 2 per
+ * axis, l1 + 0.5 and l3 + 0.5 (s1 + 0.5 and s2 + 0.5 in the rotation-scale form), the rest as
+ * stored; L2 loss and gradients as gi_fit_step, chained to the raw records; then Adan:
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) d,  n = b3 n + (1 - b3) (g + b2 d)^2,
+ *   raw = (raw - lr_k (m / (1 - b1^k) + b2 v / (1 - b2^k)) / (sqrt(n / (1 - b3^k)) + eps))
+ *         / (1 + lr_k wd),
+ * with d = g - (previous gradient) (0 on step 1) and k = *step_dev (then incremented).
+ * state_dev holds m, v, n and the previous gradient, each [N][8] float32, one after another
+ * (caller-initialised, usually zeros). */
+int gi_fit_step_recipe(gi_ctx *ctx, float *raw_dev, float *state_dev, const float *target_dev,
+                       int64_t n, int32_t height, int32_t width, const gi_adan *hp,
+                       int32_t *step_dev, float *image_out_dev, float *loss_out_dev,
+                       void *stream);
+/* Effective records [N][8] of raw recipe records (for gi_render and the other calls). */
+int gi_recipe_params(gi_ctx *ctx, const float *raw_dev, int64_t n, int32_t height, int32_t width,
+                     float *params_dev, void *stream);
+
+/* ---- quantisation-aware fine-tuning (Sec. 3.3, Sec. 4.1) ------------------------------------ */
+
+/* The quantiser being fine-tuned, on the device (caller owned, float32):
+ *   quant_dev   [6 + 3 M B]: gamma[3], beta[3] of the b-bit covariance codes (LSQ+), then the
+ *               residual-VQ codebooks [M][B][3]
+ *   quant_m_dev, quant_v_dev: Adam moments of quant_dev (same size, caller-initialised, zeros)
+ * 1 <= bits <= 8, 1 <= stages <= 8, 1 <= codebook_size <= 64, stages * codebook_size <= 64.
+ * lambda weights the commitment loss; lr_q is the quantiser's Adam rate. */
+typedef struct gi_qat {
+    float *quant_dev;
+    float *quant_m_dev, *quant_v_dev;
+    int32_t bits, stages, codebook_size;
+    float lambda, lr_q;
+} gi_qat;
+
+/* Initialise quant_dev from float records params_dev [N][8] (N >= 1): beta_i = min of slot i,
+ * gamma_i = the least float32 >= (max - min) / (2^b - 1); codebooks by kmeans_iters Lloyd
+ * iterations per stage on the residual colours (float64), seeded with the points
+ * floor(j N / B), an emptied centroid staying put.  Allocates scratch on first use. */
+int gi_qat_init(gi_ctx *ctx, const float *params_dev, int64_t n, const gi_qat *q,
+                int32_t kmeans_iters, void *stream);
+/* One fine-tuning step (as gi_fit_step, on float records): render the fake-quantised records
+ * (binary16 positions; covariance slot i as code * gamma_i + beta_i, code =
+ * round-half-even(clamp((l - beta_i) / gamma_i, 0, 2^b - 1)); colours by greedy residual VQ,
+ * nearest entry by squared distance, lowest index on ties; all in float64, rounded once), loss
+ * = mean (C - target)^2 + lambda L_c with L_c = 1/(N B) sum over stages and Gaussians of
+ * |C^m[i^m] - r^{m-1}|^2 (r the residual before stage m); straight-through gradients to the
+ * records (covariance slots only inside the code range), LSQ+ gradients to gamma and beta,
+ * commitment-loss gradients to the codebooks; Adam on records (hp) and quantiser (lr_q). */
+int gi_fit_step_qat(gi_ctx *ctx, float *params_dev, float *m_dev, float *v_dev,
+                    const float *target_dev, int64_t n, int32_t height, int32_t width,
+                    const gi_adam *hp, const gi_qat *q, int32_t *step_dev, float *image_out_dev,
+                    float *loss_out_dev, void *stream);
+/* Encode float records with the quantiser into the codec layout of gi_codec: mu_dev [N][2]
+ * binary16 bits (4-byte aligned), codes_dev [N][3], index_dev [N][M]; gi_render_codec of the
+ * result with this quantiser's gamma, beta and codebooks renders what the fine-tuning rendered. */
+int gi_qat_encode(gi_ctx *ctx, const float *params_dev, int64_t n, const gi_qat *q,
+                  uint16_t *mu_dev, uint8_t *codes_dev, uint8_t *index_dev, void *stream);
+
 /* ---- codec decode (Sec. 3.3) ------------------------------------------------------------- */
 
 /* A compressed Gaussian set (Sec. 3.3, attribute quantisation).  Device arrays, caller owned:

@@ -21,7 +21,7 @@ import torch
 from . import _lib
 from ._lib import GiError
 
-__all__ = ["Context", "Batch", "AdamConfig", "Codec", "GaussianRender", "render", "default_context",
+__all__ = ["Context", "Batch", "AdamConfig", "AdanConfig", "Codec", "Quantiser", "GaussianRender", "render", "default_context",
            "GiError"]
 
 
@@ -98,6 +98,70 @@ def _check(t: torch.Tensor, name: str, device, shape=None, dtype=torch.float32):
         raise ValueError(f"{name} must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+@dataclass
+class AdanConfig:
+    """Adan of the paper's recipe (Sec. 4.1): lr 1e-3 halved every 20000 steps."""
+    lr: float = 1e-3
+    beta1: float = 0.98
+    beta2: float = 0.92
+    beta3: float = 0.99
+    eps: float = 1e-8
+    weight_decay: float = 0.0
+    halve_every: int = 20000
+
+    def c(self) -> _lib.gi_adan:
+        return _lib.gi_adan(self.lr, self.beta1, self.beta2, self.beta3, self.eps,
+                            self.weight_decay, int(self.halve_every))
+
+
+@dataclass
+class Quantiser:
+    """The quantiser of the fine-tuning (Sec. 3.3) on the device: ``quant`` holds gamma[3],
+    beta[3] and the codebooks [stages, size, 3]; ``quant_m``, ``quant_v`` its Adam moments."""
+    quant: torch.Tensor
+    quant_m: torch.Tensor
+    quant_v: torch.Tensor
+    bits: int = 6
+    stages: int = 2
+    size: int = 8
+    lam: float = 1.0
+    lr_q: float = 1e-3
+
+    @staticmethod
+    def zeros(device, bits=6, stages=2, size=8, lam=1.0, lr_q=1e-3) -> "Quantiser":
+        nq = 6 + 3 * stages * size
+        z = [torch.zeros(nq, device=device, dtype=torch.float32) for _ in range(3)]
+        return Quantiser(*z, bits=bits, stages=stages, size=size, lam=lam, lr_q=lr_q)
+
+    @property
+    def gamma(self):
+        return self.quant[0:3]
+
+    @property
+    def beta(self):
+        return self.quant[3:6]
+
+    @property
+    def codebooks(self):
+        return self.quant[6:].view(self.stages, self.size, 3)
+
+    def c(self, device) -> _lib.gi_qat:
+        nq = 6 + 3 * self.stages * self.size
+        for t, name in ((self.quant, "quant"), (self.quant_m, "quant_m"),
+                        (self.quant_v, "quant_v")):
+            _check(t, name, device, (nq,))
+        return _lib.gi_qat(self.quant.data_ptr(), self.quant_m.data_ptr(),
+                           self.quant_v.data_ptr(), int(self.bits), int(self.stages),
+                           int(self.size), float(self.lam), float(self.lr_q))
+
+    def codec(self, mu, codes, index) -> "Codec":
+        """The codec record set of an encoding (gamma and beta copied to the host)."""
+        g = [float(x) for x in self.gamma.cpu()]
+        b = [float(x) for x in self.beta.cpu()]
+        return Codec(mu=mu, codes=codes, index=index, codebooks=self.codebooks.contiguous(),
+                     gamma=tuple(g), beta=tuple(b), bits=self.bits)
 
 
 @dataclass
@@ -333,6 +397,76 @@ class Context:
             self._h, _ptr(params), _ptr(opacity), _ptr(m), _ptr(v), _ptr(m_o), _ptr(v_o),
             _ptr(target), n, h, w, _BLEND[blend], ctypes.byref(hpc), _ptr(step), _ptr(image_out),
             _ptr(loss_out), _stream(self.device)), "gi_fit_step_opacity")
+
+    def fit_step_recipe(self, raw, state, target, step, hp: AdanConfig | None = None,
+                        image_out=None, loss_out=None):
+        """One fit step of the paper's recipe on raw records (App. C parametrisation, Adan);
+        ``state`` is [4, N, 8] (m, v, n, previous gradient)."""
+        n = raw.shape[0]
+        h, w = target.shape[0], target.shape[1]
+        _check(raw, "raw", self.device, (n, 8))
+        _check(state, "state", self.device, (4, n, 8))
+        _check(target, "target", self.device, (h, w, 3))
+        _check(step, "step", self.device, (1,), torch.int32)
+        if image_out is not None:
+            _check(image_out, "image_out", self.device, (h, w, 3))
+        if loss_out is not None:
+            _check(loss_out, "loss_out", self.device, (1,))
+        hpc = (hp or AdanConfig()).c()
+        self._raise(_lib.lib().gi_fit_step_recipe(
+            self._h, _ptr(raw), _ptr(state), _ptr(target), n, h, w, ctypes.byref(hpc),
+            _ptr(step), _ptr(image_out), _ptr(loss_out), _stream(self.device)),
+            "gi_fit_step_recipe")
+
+    def qat_init(self, params, quant: "Quantiser", kmeans_iters: int = 5):
+        """Set gamma, beta from the records' covariance range and the codebooks by K-means."""
+        _check(params, "params", self.device, (params.shape[0], 8))
+        q = quant.c(self.device)
+        self._raise(_lib.lib().gi_qat_init(self._h, _ptr(params), params.shape[0],
+                                           ctypes.byref(q), kmeans_iters, _stream(self.device)),
+                    "gi_qat_init")
+
+    def fit_step_qat(self, params, m, v, target, step, quant: "Quantiser",
+                     hp: AdamConfig | None = None, image_out=None, loss_out=None):
+        """One quantisation-aware fine-tuning step (in place on params, m, v and quant)."""
+        n = params.shape[0]
+        h, w = target.shape[0], target.shape[1]
+        for t, name in ((params, "params"), (m, "m"), (v, "v")):
+            _check(t, name, self.device, (n, 8))
+        _check(target, "target", self.device, (h, w, 3))
+        _check(step, "step", self.device, (1,), torch.int32)
+        if image_out is not None:
+            _check(image_out, "image_out", self.device, (h, w, 3))
+        if loss_out is not None:
+            _check(loss_out, "loss_out", self.device, (1,))
+        hpc = (hp or AdamConfig()).c()
+        q = quant.c(self.device)
+        self._raise(_lib.lib().gi_fit_step_qat(
+            self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(target), n, h, w, ctypes.byref(hpc),
+            ctypes.byref(q), _ptr(step), _ptr(image_out), _ptr(loss_out), _stream(self.device)),
+            "gi_fit_step_qat")
+
+    def qat_encode(self, params, quant: "Quantiser") -> "Codec":
+        """Encode float records with the quantiser; returns the codec record set."""
+        n = params.shape[0]
+        _check(params, "params", self.device, (n, 8))
+        mu = torch.empty(n, 2, device=self.device, dtype=torch.int16)
+        codes = torch.empty(n, 3, device=self.device, dtype=torch.uint8)
+        index = torch.empty(n, quant.stages, device=self.device, dtype=torch.uint8)
+        q = quant.c(self.device)
+        self._raise(_lib.lib().gi_qat_encode(self._h, _ptr(params), n, ctypes.byref(q), _ptr(mu),
+                                             _ptr(codes), _ptr(index), _stream(self.device)),
+                    "gi_qat_encode")
+        return quant.codec(mu, codes, index)
+
+    def recipe_params(self, raw, height: int, width: int) -> torch.Tensor:
+        """Effective records of raw recipe records."""
+        n = raw.shape[0]
+        _check(raw, "raw", self.device, (n, 8))
+        out = torch.empty(n, 8, device=self.device, dtype=torch.float32)
+        self._raise(_lib.lib().gi_recipe_params(self._h, _ptr(raw), n, height, width, _ptr(out),
+                                                _stream(self.device)), "gi_recipe_params")
+        return out
 
     # -- batched
     def render_batched(self, params, batch: Batch, out=None) -> torch.Tensor:

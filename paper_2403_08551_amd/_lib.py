@@ -49,7 +49,8 @@ EXPORTS = (
     "gi_grad_batched", "gi_fit_step_batched", "gi_fit_graph_create", "gi_fit_graph_launch",
     "gi_fit_graph_destroy", "gi_binning", "gi_scan_u32", "gi_sort_pairs", "gi_timing",
     "gi_get_option", "gi_autotune", "gi_fit_graph_query", "gi_codec_decode", "gi_render_codec",
-    "gi_render_opacity", "gi_grad_opacity", "gi_fit_step_opacity",
+    "gi_render_opacity", "gi_grad_opacity", "gi_fit_step_opacity", "gi_fit_step_recipe",
+    "gi_recipe_params", "gi_qat_init", "gi_fit_step_qat", "gi_qat_encode",
 )
 
 
@@ -64,6 +65,19 @@ class gi_batch(ctypes.Structure):
                 ("height_host", ctypes.POINTER(ctypes.c_int32)),
                 ("width_host", ctypes.POINTER(ctypes.c_int32)),
                 ("gauss_off_host", ctypes.POINTER(ctypes.c_int64))]
+
+
+class gi_adan(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("beta3", ctypes.c_float), ("eps", ctypes.c_float),
+                ("weight_decay", ctypes.c_float), ("halve_every", ctypes.c_int32)]
+
+
+class gi_qat(ctypes.Structure):
+    _fields_ = [("quant_dev", ctypes.c_void_p), ("quant_m_dev", ctypes.c_void_p),
+                ("quant_v_dev", ctypes.c_void_p), ("bits", ctypes.c_int32),
+                ("stages", ctypes.c_int32), ("codebook_size", ctypes.c_int32),
+                ("lambda_", ctypes.c_float), ("lr_q", ctypes.c_float)]
 
 
 class gi_codec(ctypes.Structure):
@@ -131,6 +145,13 @@ def lib():
                              ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
             "gi_fit_step_opacity": ([P, P, P, P, P, P, P, P, I64, I32, I32, I32,
                                      ctypes.POINTER(gi_adam), P, P, P, P], ctypes.c_int),
+            "gi_fit_step_recipe": ([P, P, P, P, I64, I32, I32, ctypes.POINTER(gi_adan), P, P, P,
+                                    P], ctypes.c_int),
+            "gi_recipe_params": ([P, P, I64, I32, I32, P, P], ctypes.c_int),
+            "gi_qat_init": ([P, P, I64, ctypes.POINTER(gi_qat), I32, P], ctypes.c_int),
+            "gi_fit_step_qat": ([P, P, P, P, P, I64, I32, I32, ctypes.POINTER(gi_adam),
+                                 ctypes.POINTER(gi_qat), P, P, P, P], ctypes.c_int),
+            "gi_qat_encode": ([P, P, I64, ctypes.POINTER(gi_qat), P, P, P, P], ctypes.c_int),
             "gi_render_opacity": ([P, P, P, I64, I32, I32, I32, P, P], ctypes.c_int),
             "gi_grad_opacity": ([P, P, P, I64, I32, I32, I32, P, P, P, P], ctypes.c_int),
             "gi_codec_decode": ([P, ctypes.POINTER(gi_codec), I64, P, P], ctypes.c_int),

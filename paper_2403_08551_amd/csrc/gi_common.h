@@ -113,12 +113,95 @@ constexpr float ALPHA_MAX = 0.99f;
 // Where the projection reads Gaussian records: float params, or (codec.mu != nullptr) a
 // compressed set decoded on the fly; with an opacity per Gaussian for the opacity renderings
 // (BLEND_SUM stores o * c as the record colour).  Passed to kernels by value.
+// Quantiser of the quantisation-aware fine-tuning (Sec. 3.3): quant = gamma[3], beta[3], then
+// codebooks [stages][size][3], all float32 on the device.
+struct QatArgs {
+    const float *quant;
+    int32_t bits, stages, size;
+};
+constexpr int QAT_MAX_STAGES = 8;
+constexpr int QAT_MAX_ENTRIES = 64;  // stages * size
+constexpr int QAT_KMAX = 64;         // codebook size
+
 struct RecordSrc {
     const float4 *params;
     CodecArgs codec;
     const float *opacity;
     int32_t blend;
+    int32_t recipe;  // 1: params are raw records of the fitting recipe (see recipe_effective)
+    QatArgs qat;     // quant != nullptr: render the fake-quantised records
 };
+
+// What the fake quantiser decided for one Gaussian (for its gradients).
+struct QuantFacts {
+    double x[3];      // scaled covariance values (l - beta) / gamma
+    double code[3];   // their codes
+    int32_t idx[8];   // RVQ index per stage
+};
+
+// Fake quantisation of one record (Sec. 3.3), in place: binary16 positions, LSQ+ codes
+// code = round-to-even(clamp((l - beta) / gamma, 0, 2^b - 1)) dequantised as code * gamma + beta,
+// and greedy residual VQ of the colour (nearest entry by squared distance, the lowest index on
+// ties) summed over the stages.  Everything in float64 without contraction, each result rounded
+// once to float32, so any IEEE machine that follows these steps decides the same codes.
+__device__ inline void qat_fake_quant(float (&q)[8], const QatArgs &a, QuantFacts *f) {
+#pragma clang fp contract(off)
+    q[0] = (float)(_Float16)q[0];
+    q[1] = (float)(_Float16)q[1];
+    const double top = (double)((1 << a.bits) - 1);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double g = a.quant[i], b = a.quant[3 + i];
+        const double x = ((double)q[2 + i] - b) / g;
+        const double c = rint(x < 0.0 ? 0.0 : (x > top ? top : x));
+        q[2 + i] = (float)(c * g + b);
+        if (f) {
+            f->x[i] = x;
+            f->code[i] = c;
+        }
+    }
+    const float *books = a.quant + 6;
+    double r0 = q[5], r1 = q[6], r2 = q[7];
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+    for (int m = 0; m < a.stages; ++m) {
+        const float *bk = books + (int64_t)m * a.size * 3;
+        int best = 0;
+        double bd = 0.0;
+        for (int k = 0; k < a.size; ++k) {
+            const double d0 = r0 - (double)bk[3 * k], d1 = r1 - (double)bk[3 * k + 1];
+            const double d2 = r2 - (double)bk[3 * k + 2];
+            const double d = (d0 * d0 + d1 * d1) + d2 * d2;
+            if (k == 0 || d < bd) {
+                bd = d;
+                best = k;
+            }
+        }
+        if (f) f->idx[m] = best;
+        const double e0 = bk[3 * best], e1 = bk[3 * best + 1], e2 = bk[3 * best + 2];
+        c0 += e0;
+        c1 += e1;
+        c2 += e2;
+        r0 -= e0;
+        r1 -= e1;
+        r2 -= e2;
+    }
+    q[5] = (float)c0;
+    q[6] = (float)c1;
+    q[7] = (float)c2;
+}
+
+// The fitting recipe's parametrisation (App. C): raw (rho_x, rho_y, lam1, lam2, lam3, c) ->
+// mu = extent (tanh(rho) + 1) / 2, and 0.5 added to l1, l3 (Cholesky) or s1, s2 (rotation-scale),
+// in float64, rounded once to float32.
+__device__ inline void recipe_effective(float (&q)[8], int32_t H, int32_t W, bool rs) {
+    q[0] = (float)((double)W * (tanh((double)q[0]) + 1.0) * 0.5);
+    q[1] = (float)((double)H * (tanh((double)q[1]) + 1.0) * 0.5);
+    q[2] = (float)((double)q[2] + 0.5);
+    if (rs)
+        q[3] = (float)((double)q[3] + 0.5);
+    else
+        q[4] = (float)((double)q[4] + 0.5);
+}
 
 // ---- host-side launchers (defined next to their kernels) ------------------------------------
 
@@ -128,6 +211,8 @@ struct BinBuffers {
     const float *opacity;    // [N] for the opacity renderings, else null
     int32_t blend;           // BLEND_*
     float *rec_o;            // [cap] opacity in tile order (BLEND_ALPHA), else null
+    int32_t recipe;          // 1: raw records of the fitting recipe
+    QatArgs qat;             // quant != nullptr: fake-quantised records
     int64_t n;
     float *proj;
     int4 *rect;
@@ -137,6 +222,8 @@ struct BinBuffers {
     unsigned long long *blocksum;  // [ceil(n/256)]
     uint32_t *keys[2];
     uint32_t *vals[2];
+    uint32_t *own;                  // [cap] Gaussian of each Gaussian-major key (radix path)
+    uint32_t *ids_out;              // sorted Gaussian ids, when wanted (radix path), else null
     float *rec;
     uint32_t *slot;
     uint2 *ranges;
@@ -201,15 +288,19 @@ struct RasterArgs {
 hipError_t launch_raster_fwd(const RasterArgs &a, float *image, int px_per_lane, hipStream_t s);
 hipError_t launch_raster_bwd(const RasterArgs &a, const float *dl_dimage, float *part,
                              hipStream_t s);
+// step_inc (may be null): advanced by one by the kernel; the update kernel that follows reads
+// the step number as *step - 1.
 hipError_t launch_raster_fit(const RasterArgs &a, const float *target, float *part,
-                             float *image_out, float *loss_part, int px_per_lane, hipStream_t s);
+                             float *image_out, float *loss_part, int px_per_lane,
+                             int32_t *step_inc, hipStream_t s);
 // Alpha blending (BLEND_ALPHA): rec_o [cap] holds the opacities in tile order; part12 has
 // three float4 per key (colour sums, P1; P2, Q11, Q12, Q22; opacity sum).
 hipError_t launch_alpha_fwd(const RasterArgs &a, const float *rec_o, float *image, hipStream_t s);
 hipError_t launch_alpha_bwd(const RasterArgs &a, const float *rec_o, const float *dl_dimage,
                             float *part12, hipStream_t s);
 hipError_t launch_alpha_fit(const RasterArgs &a, const float *rec_o, const float *target,
-                            float *part12, float *image_out, float *loss_part, hipStream_t s);
+                            float *part12, float *image_out, float *loss_part, int32_t *step_inc,
+                            hipStream_t s);
 
 struct UpdateArgs {
     const float *params_in;  // read (l1, l2, l3) or (s1, s2, theta); Adam updates in place
@@ -231,19 +322,47 @@ hipError_t launch_grad_opacity(const UpdateArgs &u, const float *opacity, int32_
 struct AdamArgs {
     float lr_mu, lr_l, lr_c, beta1, beta2, eps, l_min;
 };
-// Adam update; also finishes the step (per-image loss when loss_out != nullptr, step += 1).
+// Adam update with step number *step - 1 (the fit kernel advanced the counter); also writes the
+// per-image losses when loss_out != nullptr.
 hipError_t launch_adam(const UpdateArgs &u, float *params, float *m, float *v,
                        int32_t *step, const AdamArgs &hp, const float *loss_part,
                        const ImgTable &tab, int64_t n_tiles, float *loss_out, hipStream_t s);
-// Adam over params and opacities of an opacity rendering (opacity uses the colour rate), then
-// launch_finish.
+// Adam over params and opacities of an opacity rendering (opacity uses the colour rate), as
+// launch_adam.
 hipError_t launch_adam_opacity(const UpdateArgs &u, float *params, float *opacity, float *m,
                                float *v, float *mo, float *vo, int32_t *step, const AdamArgs &hp,
                                int32_t blend, const float *loss_part, const ImgTable &tab,
                                int64_t n_tiles, float *loss_out, hipStream_t s);
-// Per-image loss from the per-tile sums (when loss_out != nullptr) and step += 1 (when
-// step != nullptr).
+// The fitting recipe's update (App. C parametrisation, Adan): gradients of the raw records and
+// the Adan step; state = m, v, n, previous gradient, each [N][8].
+struct AdanArgs {
+    float lr, beta1, beta2, beta3, eps, weight_decay;
+    int32_t halve_every;
+};
+hipError_t launch_adan(const UpdateArgs &u, float *raw, float *state, int32_t *step,
+                       const AdanArgs &hp, const ImgTable &tab, const float *loss_part,
+                       int64_t n_tiles, float *loss_out, hipStream_t s);
+// Quantisation-aware fine-tuning update: the Gaussians' Adam step (straight-through gradients
+// of the fake-quantised records), then the quantiser's Adam step (LSQ+ and commitment-loss
+// gradients); qpart holds qat_part_floats(n, stages, size) floats of block sums.
+hipError_t launch_qat_update(const UpdateArgs &u, float *params, float *m, float *v,
+                             int32_t *step, const AdamArgs &hp, const QatArgs &qa, float lambda,
+                             float lr_q, float *quant_m, float *quant_v, float *qpart,
+                             const float *loss_part, const ImgTable &tab, int64_t n_tiles,
+                             float *loss_out, hipStream_t s);
+int64_t qat_part_floats(int64_t n, int stages, int size);
+// Quantiser initialisation and encoding (k_qat.hip): gamma, beta from the covariance range,
+// codebooks by K-means per stage; scratch: at least qat_init_scratch_bytes(n, size) bytes.
+size_t qat_init_scratch_bytes(int64_t n, int size);
+hipError_t launch_qat_init(const float *params, int64_t n, const QatArgs &qa, int kmeans_iters,
+                           void *scratch, hipStream_t s);
+hipError_t launch_qat_encode(const float *params, int64_t n, const QatArgs &qa, uint16_t *mu,
+                             uint8_t *codes, uint8_t *index, hipStream_t s);
+// Effective records of raw recipe records.
+hipError_t launch_recipe_effective(const float *raw, int64_t n, const ImgTable &tab, int32_t cov,
+                                   float *params, hipStream_t s);
+// Per-image loss from the per-tile sums when loss_out != nullptr (used when no update kernel runs).
 hipError_t launch_finish(const float *loss_part, const ImgTable &tab, int64_t n_tiles,
-                         float *loss_out, int32_t *step, hipStream_t s);
+                         float *loss_out, hipStream_t s);
 
 }  // namespace gi

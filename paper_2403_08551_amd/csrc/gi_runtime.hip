@@ -26,6 +26,12 @@ struct gi_ctx {
     const CodecArgs *codec = nullptr;  // set for the duration of a codec render
     const float *opac_cur = nullptr;   // set for the duration of an opacity render / grad
     int blend_cur = BLEND_NONE;
+    int recipe_cur = 0;                // 1 for the duration of a recipe fit step
+    QatArgs qat_cur = {nullptr, 0, 0, 0};  // set for the duration of a fine-tuning step
+    float *qpart = nullptr;            // block sums of the quantiser gradient
+    int64_t qpart_cap = 0;
+    void *qscratch = nullptr;          // quantiser set-up scratch
+    size_t qscratch_cap = 0;
     float *rec_o = nullptr;            // [cap_a] opacities in tile order (alpha blending)
     float *part_a = nullptr;           // [cap_a][12] alpha-blending partial sums
     int64_t cap_a = 0;
@@ -42,6 +48,8 @@ struct gi_ctx {
     // per key
     uint32_t *keys[2] = {nullptr, nullptr};
     uint32_t *vals[2] = {nullptr, nullptr};
+    uint32_t *own = nullptr;            // [cap_k] Gaussian of each Gaussian-major key
+    const uint32_t *ids_at = nullptr;   // sorted ids of the last gi_binning
     float *rec = nullptr;
     uint32_t *slot = nullptr;
     float *part = nullptr;
@@ -212,6 +220,7 @@ int ensure_keys(gi_ctx *ctx, int64_t k) {
         CK(grow(&ctx->keys[i], c));
         CK(grow(&ctx->vals[i], c));
     }
+    CK(grow(&ctx->own, c));
     CK(grow(&ctx->rec, 8 * c));
     CK(grow(&ctx->slot, c));
     CK(grow(&ctx->part, 8 * c));
@@ -365,6 +374,8 @@ BinBuffers bin_buffers(gi_ctx *ctx, const float *params, int64_t n, int64_t n_ti
     b.opacity = ctx->opac_cur;
     b.blend = ctx->blend_cur;
     b.rec_o = ctx->blend_cur == BLEND_ALPHA ? ctx->rec_o : nullptr;
+    b.recipe = ctx->recipe_cur;
+    b.qat = ctx->qat_cur;
     b.n = n;
     b.proj = ctx->proj;
     b.rect = ctx->rect;
@@ -376,6 +387,8 @@ BinBuffers bin_buffers(gi_ctx *ctx, const float *params, int64_t n, int64_t n_ti
     b.keys[1] = ctx->keys[1];
     b.vals[0] = ctx->vals[0];
     b.vals[1] = ctx->vals[1];
+    b.own = ctx->own;
+    b.ids_out = nullptr;
     b.rec = ctx->rec;
     b.slot = ctx->slot;
     b.ranges = ctx->ranges;
@@ -434,6 +447,7 @@ int run_binning_fused(gi_ctx *ctx, const float *params, int64_t n, const ImgTabl
         }
     }
     CK(launch_fused_c(f, ctx->want_ids ? ctx->vals[0] : nullptr, s));
+    ctx->ids_at = ctx->vals[0];
     tm.stop();
     ctx->off_cur = ctx->fscan;
     *which = 0;
@@ -476,6 +490,9 @@ int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab
     const int kb = key_bits_for(n_tiles);
     const int digit = pick_digit(ctx, n, table_pixels(tab, n_tiles), kb, K);
     CK(launch_sort(b, kb, digit, K, which, s));
+    // the sort's other buffer is free again: sorted ids go there when wanted
+    b.ids_out = ctx->want_ids ? ctx->vals[1 - *which] : nullptr;
+    ctx->ids_at = ctx->vals[1 - *which];
     CK(launch_ranges_gather(b, *which, tab, K, s));
     tm.stop();
     *bound = K;
@@ -524,7 +541,7 @@ int do_fit(gi_ctx *ctx, float *params, float *m, float *v, const float *target, 
     RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
     CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
-                         pick_px(ctx, n, table_pixels(tab, n_tiles)), s));
+                         pick_px(ctx, n, table_pixels(tab, n_tiles)), step, s));
     tm.stop();
     UpdateArgs u{params, params, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k,
                  ctx->cov};
@@ -604,10 +621,10 @@ int do_fit_opacity(gi_ctx *ctx, float *params, float *opacity, float *m, float *
     float *part = blend == BLEND_ALPHA ? ctx->part_a : ctx->part;
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
     if (blend == BLEND_ALPHA)
-        CK(launch_alpha_fit(a, ctx->rec_o, target, part, image_out, ctx->loss_part, s));
+        CK(launch_alpha_fit(a, ctx->rec_o, target, part, image_out, ctx->loss_part, step, s));
     else
         CK(launch_raster_fit(a, target, part, image_out, ctx->loss_part,
-                             pick_px(ctx, n, table_pixels(tab, n_tiles)), s));
+                             pick_px(ctx, n, table_pixels(tab, n_tiles)), step, s));
     tm.stop();
     UpdateArgs u{params, params, n, ctx->count, ctx->off_cur, part, ctx->state, ctx->cap_k,
                  ctx->cov};
@@ -616,6 +633,91 @@ int do_fit_opacity(gi_ctx *ctx, float *params, float *opacity, float *m, float *
     CK(launch_adam_opacity(u, params, opacity, m, v, mo, vo, step, h, blend, ctx->loss_part, tab,
                            n_tiles, loss_out, s));
     tu.stop();
+    return GI_OK;
+}
+
+int do_fit_recipe(gi_ctx *ctx, float *raw, float *state, const float *target, int64_t n,
+                  const ImgTable &tab, int64_t n_tiles, const gi_adan *hp, int32_t *step,
+                  float *image_out, float *loss_out, hipStream_t s) {
+    struct Scope {
+        gi_ctx *c;
+        ~Scope() { c->recipe_cur = 0; }
+    } scope{ctx};
+    ctx->recipe_cur = 1;
+    int64_t bound;
+    int which;
+    int rc = run_binning(ctx, raw, n, tab, n_tiles, s, &bound, &which);
+    if (rc != GI_OK) return rc;
+    RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
+    StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
+    CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
+                         pick_px(ctx, n, table_pixels(tab, n_tiles)), step, s));
+    tm.stop();
+    UpdateArgs u{raw, raw, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k,
+                 ctx->cov};
+    AdanArgs h{hp->lr, hp->beta1, hp->beta2, hp->beta3, hp->eps, hp->weight_decay,
+               hp->halve_every};
+    StageTimer tu(ctx, s, GI_STAGE_UPDATE);
+    CK(launch_adan(u, raw, state, step, h, tab, ctx->loss_part, n_tiles, loss_out, s));
+    tu.stop();
+    return GI_OK;
+}
+
+int qat_args(const gi_qat *q, QatArgs *out) {
+    if (!q || !q->quant_dev || ((uintptr_t)q->quant_dev & 3u)) return GI_ERR_INVALID_ARG;
+    if (q->bits < 1 || q->bits > 8 || q->stages < 1 || q->stages > QAT_MAX_STAGES ||
+        q->codebook_size < 1 || q->codebook_size > QAT_KMAX ||
+        q->stages * q->codebook_size > QAT_MAX_ENTRIES)
+        return GI_ERR_INVALID_ARG;
+    out->quant = q->quant_dev;
+    out->bits = q->bits;
+    out->stages = q->stages;
+    out->size = q->codebook_size;
+    return GI_OK;
+}
+
+int do_fit_qat(gi_ctx *ctx, float *params, float *m, float *v, const float *target, int64_t n,
+               const ImgTable &tab, int64_t n_tiles, const gi_adam *hp, const gi_qat *q,
+               const QatArgs &qa, int32_t *step, float *image_out, float *loss_out,
+               hipStream_t s) {
+    const int64_t need = qat_part_floats(n, qa.stages, qa.size);
+    if (need > ctx->qpart_cap) {
+        CK(hipDeviceSynchronize());
+        CK(grow(&ctx->qpart, need));
+        ctx->qpart_cap = need;
+    }
+    struct Scope {
+        gi_ctx *c;
+        ~Scope() { c->qat_cur = QatArgs{nullptr, 0, 0, 0}; }
+    } scope{ctx};
+    ctx->qat_cur = qa;
+    int64_t bound;
+    int which;
+    int rc = run_binning(ctx, params, n, tab, n_tiles, s, &bound, &which);
+    if (rc != GI_OK) return rc;
+    RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
+    StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
+    CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
+                         pick_px(ctx, n, table_pixels(tab, n_tiles)), step, s));
+    tm.stop();
+    UpdateArgs u{params, params, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k,
+                 ctx->cov};
+    AdamArgs h{hp->lr_mu, hp->lr_l, hp->lr_c, hp->beta1, hp->beta2, hp->eps, hp->l_min};
+    StageTimer tu(ctx, s, GI_STAGE_UPDATE);
+    CK(launch_qat_update(u, params, m, v, step, h, qa, q->lambda, q->lr_q, q->quant_m_dev,
+                         q->quant_v_dev, ctx->qpart, ctx->loss_part, tab, n_tiles, loss_out, s));
+    tu.stop();
+    return GI_OK;
+}
+
+int check_adan(const gi_adan *hp) {
+    if (!hp) return GI_ERR_INVALID_ARG;
+    const float b[3] = {hp->beta1, hp->beta2, hp->beta3};
+    for (float x : b)
+        if (!(x >= 0.f && x < 1.f)) return GI_ERR_INVALID_ARG;
+    if (!(hp->eps >= 0.f) || !(hp->weight_decay >= 0.f) || !(hp->lr >= 0.f) ||
+        hp->halve_every < 0)
+        return GI_ERR_INVALID_ARG;
     return GI_OK;
 }
 
@@ -678,7 +780,8 @@ int gi_destroy(gi_ctx *ctx) {
                     ctx->keys[0], ctx->keys[1], ctx->vals[0], ctx->vals[1], ctx->rec, ctx->slot,
                     ctx->part, ctx->hist, ctx->scan_bs, ctx->ranges, ctx->loss_part, ctx->state,
                     ctx->dims, ctx->tile_base, ctx->gauss_off, ctx->pix_off, ctx->tmp_k,
-                    ctx->tmp_v, ctx->fscan, ctx->fstatus};
+                    ctx->tmp_v, ctx->fscan, ctx->fstatus, ctx->own, ctx->rec_o, ctx->part_a,
+                    ctx->qpart, ctx->qscratch};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -983,6 +1086,82 @@ int gi_fit_step_opacity(gi_ctx *ctx, float *params, float *opacity, float *m, fl
                           blend, hp, step, image_out, loss_out, (hipStream_t)stream);
 }
 
+int gi_fit_step_recipe(gi_ctx *ctx, float *raw, float *state, const float *target, int64_t n,
+                       int32_t H, int32_t W, const gi_adan *hp, int32_t *step, float *image_out,
+                       float *loss_out, void *stream) {
+    if (!ctx || !target || !step || check_adan(hp) != GI_OK) return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!raw || !state || !aligned16(raw) || !aligned16(state)))
+        return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    const ImgTable tab = single_table(H, W);
+    const int64_t T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    return do_fit_recipe(ctx, raw, state, target, n, tab, T, hp, step, image_out, loss_out,
+                         (hipStream_t)stream);
+}
+
+int gi_qat_init(gi_ctx *ctx, const float *params, int64_t n, const gi_qat *q,
+                int32_t kmeans_iters, void *stream) {
+    QatArgs qa;
+    if (!ctx || n < 1 || n >= ((int64_t)1 << 31) || !params || !aligned16(params) ||
+        kmeans_iters < 0 || kmeans_iters > 1000 || qat_args(q, &qa) != GI_OK)
+        return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    const size_t need = qat_init_scratch_bytes(n, qa.size);
+    if (need > ctx->qscratch_cap) {
+        CK(hipDeviceSynchronize());
+        if (ctx->qscratch) CK(hipFree(ctx->qscratch));
+        ctx->qscratch = nullptr;
+        ctx->qscratch_cap = 0;
+        CK(hipMalloc(&ctx->qscratch, need));
+        ctx->qscratch_cap = need;
+    }
+    CK(launch_qat_init(params, n, qa, kmeans_iters, ctx->qscratch, (hipStream_t)stream));
+    return GI_OK;
+}
+
+int gi_fit_step_qat(gi_ctx *ctx, float *params, float *m, float *v, const float *target,
+                    int64_t n, int32_t H, int32_t W, const gi_adam *hp, const gi_qat *q,
+                    int32_t *step, float *image_out, float *loss_out, void *stream) {
+    QatArgs qa;
+    if (!ctx || !target || !step || check_adam(hp) != GI_OK || qat_args(q, &qa) != GI_OK)
+        return GI_ERR_INVALID_ARG;
+    if (!q->quant_m_dev || !q->quant_v_dev || !(q->lambda >= 0.f) || !(q->lr_q >= 0.f))
+        return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!params || !m || !v || !aligned16(params) || !aligned16(m) || !aligned16(v)))
+        return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    const ImgTable tab = single_table(H, W);
+    const int64_t T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
+    return do_fit_qat(ctx, params, m, v, target, n, tab, T, hp, q, qa, step, image_out, loss_out,
+                      (hipStream_t)stream);
+}
+
+int gi_qat_encode(gi_ctx *ctx, const float *params, int64_t n, const gi_qat *q, uint16_t *mu,
+                  uint8_t *codes, uint8_t *index, void *stream) {
+    QatArgs qa;
+    if (!ctx || n < 0 || n >= ((int64_t)1 << 31) || qat_args(q, &qa) != GI_OK)
+        return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!params || !mu || !codes || !index || !aligned16(params) ||
+                  ((uintptr_t)mu & 3u)))
+        return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    CK(launch_qat_encode(params, n, qa, mu, codes, index, (hipStream_t)stream));
+    return GI_OK;
+}
+
+int gi_recipe_params(gi_ctx *ctx, const float *raw, int64_t n, int32_t H, int32_t W,
+                     float *params, void *stream) {
+    if (!ctx || (n > 0 && (!raw || !params || !aligned16(raw) || !aligned16(params))))
+        return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->device);
+    ImgTable tab = single_table(H, W);
+    CK(launch_recipe_effective(raw, n, tab, ctx->cov, params, (hipStream_t)stream));
+    return GI_OK;
+}
+
 int gi_render(gi_ctx *ctx, const float *params, int64_t n, int32_t H, int32_t W, float *image,
               void *stream) {
     if (!ctx || !image || (n > 0 && !params)) return GI_ERR_INVALID_ARG;
@@ -1186,7 +1365,7 @@ int gi_binning(gi_ctx *ctx, const float *params, int64_t n, int32_t H, int32_t W
     if (keys_host) *keys_host = bound;
     if (ids && bound > 0) {
         if (ids_capacity < bound) return GI_ERR_CAPACITY;
-        CK(hipMemcpyAsync(ids, ctx->vals[which], 4 * bound, hipMemcpyDeviceToDevice, s));
+        CK(hipMemcpyAsync(ids, ctx->ids_at, 4 * bound, hipMemcpyDeviceToDevice, s));
     }
     CK(hipStreamSynchronize(s));
     return GI_OK;

@@ -137,15 +137,19 @@ __device__ inline uint32_t project_one(const RecordSrc &src, int64_t i,
     *bad_code = !code_ok;
     float o = 1.f;
     if (src.opacity) o = src.opacity[i];
-    int32_t TW, TH;
+    int32_t TW, TH, IH, IW;
     uint32_t tb;
     if (tab.B == 1) {
         TW = tab.TW; TH = (tab.H + TILE - 1) / TILE; tb = 0;
+        IH = tab.H; IW = tab.W;
     } else {
         int32_t b = upper_index(tab.gauss_off, tab.B, (uint32_t)i);
         int4 d = tab.dims[b];
         TW = d.z; TH = d.w; tb = tab.tile_base[b];
+        IH = d.x; IW = d.y;
     }
+    if (src.recipe) recipe_effective(q, IH, IW, tab.cov == COV_ROTATION_SCALE);
+    if (src.qat.quant) qat_fake_quant(q, src.qat, nullptr);
     bool finite = true;
 #pragma unroll
     for (int k = 0; k < 8; ++k) finite = finite && isfinite(q[k]);
@@ -274,6 +278,7 @@ __global__ __launch_bounds__(BLK) void k_duplicate(const uint32_t *__restrict__ 
                                                    uint32_t *__restrict__ off,
                                                    uint32_t *__restrict__ keys,
                                                    uint32_t *__restrict__ vals,
+                                                   uint32_t *__restrict__ own,
                                                    DevState *state) {
     __shared__ unsigned long long tmp[BLK / 64 + 1];
     __shared__ unsigned long long pre[BLK];
@@ -306,8 +311,10 @@ __global__ __launch_bounds__(BLK) void k_duplicate(const uint32_t *__restrict__ 
         const uint32_t li = (uint32_t)(j - pre[lo]);
         const uint32_t w = (uint32_t)(r.z - r.x + 1);
         const uint32_t tx = (uint32_t)r.x + li % w, ty = (uint32_t)r.y + li / w;
+        // the sort carries each key's own position (its slot); own[] maps it to the Gaussian
         keys[base + j] = inf.x + ty * inf.y + tx;
-        vals[base + j] = (uint32_t)((int64_t)blockIdx.x * BLK + lo);
+        vals[base + j] = (uint32_t)(base + j);
+        own[base + j] = (uint32_t)((int64_t)blockIdx.x * BLK + lo);
     }
 }
 
@@ -539,32 +546,29 @@ __global__ __launch_bounds__(SORT_T) void k_radix_scatter(const uint32_t *__rest
 
 __global__ __launch_bounds__(BLK) void k_ranges_gather(const uint32_t *__restrict__ keys,
                                                        const uint32_t *__restrict__ vals,
+                                                       const uint32_t *__restrict__ own,
                                                        const unsigned long long *n_dev,
                                                        int64_t n_max,
                                                        const float4 *__restrict__ proj,
-                                                       const int4 *__restrict__ rect,
-                                                       const uint2 *__restrict__ tinfo,
-                                                       const uint32_t *__restrict__ off,
                                                        uint2 *__restrict__ ranges,
                                                        float4 *__restrict__ rec,
                                                        uint32_t *__restrict__ slot,
                                                        const float *__restrict__ opac,
-                                                       float *__restrict__ rec_o) {
+                                                       float *__restrict__ rec_o,
+                                                       uint32_t *__restrict__ ids) {
     const int64_t n = sort_count(n_dev, n_max);
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     if (i >= n) return;
     const uint32_t key = keys[i];
     if (i == 0 || keys[i - 1] != key) ranges[key].x = (uint32_t)i;
     if (i == n - 1 || keys[i + 1] != key) ranges[key].y = (uint32_t)(i + 1);
-    const uint32_t g = vals[i];
+    const uint32_t sl = vals[i];  // the key's position in Gaussian-major order
+    const uint32_t g = own[sl];
     rec[2 * i] = proj[2 * (int64_t)g];
     rec[2 * i + 1] = proj[2 * (int64_t)g + 1];
+    slot[i] = sl;
     if (rec_o) rec_o[i] = opac[g];
-    const int4 r = rect[g];
-    const uint2 inf = tinfo[g];
-    const uint32_t lt = key - inf.x;
-    const int32_t tx = (int32_t)(lt % inf.y), ty = (int32_t)(lt / inf.y);
-    slot[i] = off[g] + (uint32_t)((ty - r.y) * (r.z - r.x + 1) + (tx - r.x));
+    if (ids) ids[i] = g;
 }
 
 __global__ __launch_bounds__(BLK) void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t n) {
@@ -586,7 +590,9 @@ __global__ __launch_bounds__(BLK) void k_fill_u32(uint32_t *__restrict__ p, uint
 //     tile id in one pass, and the result equals that of the stable radix sort.
 
 constexpr int FB = 256;
-constexpr int FUSED_WAVES = FB / 64;
+// waves that split a chunk's keys in the scatter: 8 where a workgroup may hold the 9 T words of
+// per-wave tile counters (more waves per CU hide the scatter's latency), else 4
+constexpr int SCATTER_WAVES_MAX = 8;
 constexpr uint32_t OWN_CAP = 4096;
 constexpr int XCDS = 8;
 
@@ -759,7 +765,8 @@ __device__ inline unsigned long long match_bits(uint32_t d, bool valid, int nbit
     return peers;
 }
 
-__global__ __launch_bounds__(FB) void k_fused_scatter(
+template <int FUSED_WAVES>
+__global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
     const uint32_t *__restrict__ count, const int4 *__restrict__ rect,
     const uint2 *__restrict__ tinfo, const float4 *__restrict__ proj,
     const uint32_t *__restrict__ scan, int64_t n, int32_t T, int32_t tbits, int64_t nchunk,
@@ -769,7 +776,8 @@ __global__ __launch_bounds__(FB) void k_fused_scatter(
     extern __shared__ uint32_t dyn[];  // wh [FUSED_WAVES][T], then tbase [T]
     uint32_t *wh = dyn;
     uint32_t *tbase = dyn + FUSED_WAVES * T;
-    __shared__ unsigned long long tmp[FB / 64 + 1];
+    constexpr int NT = 64 * FUSED_WAVES;  // threads; the first FB own the chunk's Gaussians
+    __shared__ unsigned long long tmp[NT / 64 + 1];
     __shared__ uint32_t pre[FB];
     __shared__ int4 srect[FB];
     __shared__ uint2 sinfo[FB];
@@ -778,27 +786,28 @@ __global__ __launch_bounds__(FB) void k_fused_scatter(
     __shared__ uint8_t owner[OWN_CAP];  // chunk-local key -> its Gaussian, when the keys fit
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t chunk = xcd_chunk(blockIdx.x, (uint32_t)nchunk);
-    const int64_t i = (int64_t)chunk * FB + threadIdx.x;
-    const uint32_t c = i < n ? count[i] : 0u;
+    const bool own = threadIdx.x < FB;
+    const int64_t i = (int64_t)chunk * FB + threadIdx.x;  // this thread's Gaussian when own
+    const uint32_t c = own && i < n ? count[i] : 0u;
     const uint32_t K = scan[n];  // exclusive prefix after all Gaussian counts = key total
     unsigned long long tot;
-    const unsigned long long loc = block_exclusive_scan<unsigned long long, FB>(c, tmp, &tot);
-    pre[threadIdx.x] = (uint32_t)loc;
+    const unsigned long long loc = block_exclusive_scan<unsigned long long, NT>(c, tmp, &tot);
+    if (own) pre[threadIdx.x] = (uint32_t)loc;
     const bool table = tot <= OWN_CAP;  // same for the whole block
     if (table)
         for (uint32_t k = 0; k < c; ++k) owner[loc + k] = (uint8_t)threadIdx.x;
-    if (i < n) {
+    if (own && i < n) {
         srect[threadIdx.x] = rect[i];
         sinfo[threadIdx.x] = tinfo[i];
         soff[threadIdx.x] = scan[i];
         sproj[2 * threadIdx.x] = proj[2 * i];
         sproj[2 * threadIdx.x + 1] = proj[2 * i + 1];
     }
-    for (int k = threadIdx.x; k < FUSED_WAVES * T; k += FB) wh[k] = 0u;
+    for (int k = threadIdx.x; k < FUSED_WAVES * T; k += NT) wh[k] = 0u;
     // first position of this chunk's keys of each tile, in tile order
-    for (int t = threadIdx.x; t < T; t += FB) tbase[t] = scan[n + (int64_t)t * nchunk + chunk] - K;
+    for (int t = threadIdx.x; t < T; t += NT) tbase[t] = scan[n + (int64_t)t * nchunk + chunk] - K;
     // tile ranges: this chunk writes tiles chunk, chunk + nchunk, ...
-    for (int64_t t = chunk + (int64_t)threadIdx.x * nchunk; t < T; t += (int64_t)FB * nchunk) {
+    for (int64_t t = chunk + (int64_t)threadIdx.x * nchunk; t < T; t += (int64_t)NT * nchunk) {
         uint32_t a = scan[n + t * nchunk] - K;
         uint32_t b = t + 1 < T ? scan[n + (t + 1) * nchunk] - K : K;
         if (a > cap) a = (uint32_t)cap;
@@ -838,7 +847,7 @@ __global__ __launch_bounds__(FB) void k_fused_scatter(
     }
     __syncthreads();
     // wave offsets within the chunk, per tile, on top of the chunk's base in tile order
-    for (int t = threadIdx.x; t < T; t += FB) {
+    for (int t = threadIdx.x; t < T; t += NT) {
         uint32_t run = tbase[t];
 #pragma unroll
         for (int w = 0; w < FUSED_WAVES; ++w) {
@@ -944,6 +953,8 @@ static RecordSrc record_src(const BinBuffers &b) {
     if (b.codec) r.codec = *b.codec;
     r.opacity = b.opacity;
     r.blend = b.blend;
+    r.recipe = b.recipe;
+    r.qat = b.qat;
     return r;
 }
 
@@ -968,7 +979,8 @@ hipError_t launch_count_scan(const BinBuffers &b, hipStream_t s) {
 hipError_t launch_duplicate(const BinBuffers &b, hipStream_t s) {
     if (b.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_duplicate, dim3(grid_for(b.n, BLK)), dim3(BLK), 0, s, b.count, b.rect,
-                       b.tinfo, b.blocksum, b.n, b.cap, b.off, b.keys[0], b.vals[0], b.state);
+                       b.tinfo, b.blocksum, b.n, b.cap, b.off, b.keys[0], b.vals[0], b.own,
+                       b.state);
     return hipGetLastError();
 }
 
@@ -1089,16 +1101,49 @@ hipError_t launch_fused_a(const FusedBuffers &f, const ImgTable &tab, hipStream_
     return hipGetLastError();
 }
 
+// Whether the 8-wave scatter fits this device's per-workgroup LDS at the largest tile count of
+// the one-pass path.  Decided once per device (at the first one-pass binning, which is never
+// inside a graph capture: captured steps are preceded by an eager sizing pass); the kernel's
+// dynamic LDS limit is raised then, once.
+static bool scatter_wide_fits() {
+    static int dev_cached = -1;
+    static bool wide = false;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (dev != dev_cached) {
+        dev_cached = dev;
+        wide = false;
+        int v = 0;
+        hipFuncAttributes fa;
+        const void *fn = reinterpret_cast<const void *>(&k_fused_scatter<SCATTER_WAVES_MAX>);
+        const size_t dyn = sizeof(uint32_t) * (SCATTER_WAVES_MAX + 1) * (size_t)FUSED_MAX_TILES;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                hipSuccess &&
+            hipFuncGetAttributes(&fa, fn) == hipSuccess && fa.sharedSizeBytes + dyn <= (size_t)v &&
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) ==
+                hipSuccess)
+            wide = true;
+        (void)hipGetLastError();
+    }
+    return wide;
+}
+
 hipError_t launch_fused_c(const FusedBuffers &f, uint32_t *ids, hipStream_t s) {
     const int64_t nchunk = fused_chunks(f.b.n);
     int tbits = 1;
     while (((int64_t)1 << tbits) < f.b.n_tiles) ++tbits;
-    hipLaunchKernelGGL(k_fused_scatter, dim3((unsigned)nchunk), dim3(FB),
-                       sizeof(uint32_t) * (FUSED_WAVES + 1) * (size_t)f.b.n_tiles, s, f.b.count,
-                       f.b.rect, f.b.tinfo, reinterpret_cast<const float4 *>(f.b.proj), f.scan,
-                       f.b.n, (int32_t)f.b.n_tiles, tbits, nchunk, f.b.cap,
-                       reinterpret_cast<float4 *>(f.b.rec), f.b.slot, ids, f.b.ranges,
-                       f.b.opacity, f.b.rec_o, f.b.state);
+#define GI_LAUNCH_SCATTER(WV)                                                                   \
+    hipLaunchKernelGGL(k_fused_scatter<WV>, dim3((unsigned)nchunk), dim3(64 * (WV)),            \
+                       sizeof(uint32_t) * ((WV) + 1) * (size_t)f.b.n_tiles, s, f.b.count,      \
+                       f.b.rect, f.b.tinfo, reinterpret_cast<const float4 *>(f.b.proj), f.scan, \
+                       f.b.n, (int32_t)f.b.n_tiles, tbits, nchunk, f.b.cap,                     \
+                       reinterpret_cast<float4 *>(f.b.rec), f.b.slot, ids, f.b.ranges,          \
+                       f.b.opacity, f.b.rec_o, f.b.state)
+    if (scatter_wide_fits())
+        GI_LAUNCH_SCATTER(SCATTER_WAVES_MAX);
+    else
+        GI_LAUNCH_SCATTER(4);
+#undef GI_LAUNCH_SCATTER
     return hipGetLastError();
 }
 
@@ -1108,9 +1153,9 @@ hipError_t launch_ranges_gather(const BinBuffers &b, int which, const ImgTable &
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(b.ranges), 0u, 2 * b.n_tiles, s);
     if (e != hipSuccess || n_max <= 0) return e;
     hipLaunchKernelGGL(k_ranges_gather, dim3(grid_for(n_max, BLK)), dim3(BLK), 0, s, b.keys[which],
-                       b.vals[which], &b.state->keys_total, n_max,
-                       reinterpret_cast<const float4 *>(b.proj), b.rect, b.tinfo, b.off, b.ranges,
-                       reinterpret_cast<float4 *>(b.rec), b.slot, b.opacity, b.rec_o);
+                       b.vals[which], b.own, &b.state->keys_total, n_max,
+                       reinterpret_cast<const float4 *>(b.proj), b.ranges,
+                       reinterpret_cast<float4 *>(b.rec), b.slot, b.opacity, b.rec_o, b.ids_out);
     return hipGetLastError();
 }
 

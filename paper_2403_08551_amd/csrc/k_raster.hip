@@ -26,7 +26,14 @@ namespace {
 constexpr int CHUNK = 32;
 constexpr int BWD_T = 256;
 
+// ---- begin: the fused fit kernel and the device functions it calls ----
 __device__ inline float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// v of this lane plus v of the other lane of its pair (lanes 2j, 2j + 1), one DPP add.
+__device__ inline float pair_add(float v) {
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                             0, __builtin_bit_cast(int, v), 0xb1, 0xf, 0xf, false));
+}
 
 // One Gaussian's contribution to the PX pixels of this lane (A = mu_x, mu_y, a, b;
 // B = k, c0, c1, c2).
@@ -112,30 +119,34 @@ __device__ inline void fwd_tile(const float4 *__restrict__ rec, uint2 r, float p
     }
 }
 
-// Adjoint of one tile: Gaussian-per-lane over the tile's list, dL/dC of the tile in LDS.
+// Adjoint of one tile: one (Gaussian, column parity) task per lane over the tile's list, dL/dC
+// of the tile in LDS.  Lanes 2j and 2j + 1 take the even and the odd columns of the same
+// Gaussian (neighbouring LDS words, so the two broadcast reads hit different banks) and add
+// their sums with one DPP step at the end.  Splitting each Gaussian in two halves the idle
+// lanes of a tile's last round (lists are a few hundred long, rounds are NT lanes wide).
 template <int NT>
 __device__ inline void bwd_tile(const float4 *__restrict__ rec, const uint32_t *__restrict__ slot,
                                 uint2 r, const TileInfo &ti, const float4 *sg,
                                 float4 *__restrict__ part) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const float x0 = (float)(ti.tx * TILE) + 0.5f;
+    const int par = lane & 1;
+    const float x0 = (float)(ti.tx * TILE + par) + 0.5f;
     const float y0 = (float)(ti.ty * TILE) + 0.5f;
-    for (uint32_t c = r.x + (uint32_t)wave * 64u; c < r.y; c += NT) {
-        const uint32_t i = c + (uint32_t)lane;
+    for (uint32_t c = r.x + (uint32_t)wave * 32u; c < r.y; c += NT / 2) {
+        const uint32_t i = c + (uint32_t)(lane >> 1);
         const bool act = i < r.y;
         float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
-        uint32_t sl = 0;
         if (act) {
             A = rec[2 * i];
             B = rec[2 * i + 1];
-            sl = slot[i];
         }
         float dy[TILE];
 #pragma unroll
         for (int rr = 0; rr < TILE; ++rr) dy[rr] = (y0 + (float)rr) - A.y;
         float C0 = 0.f, C1 = 0.f, C2 = 0.f, P1 = 0.f, P2 = 0.f, Q11 = 0.f, Q12 = 0.f, Q22 = 0.f;
-        for (int cc = 0; cc < TILE; ++cc) {
-            const float dx = (x0 + (float)cc) - A.x;
+        for (int k = 0; k < TILE / 2; ++k) {
+            const int cc = 2 * k + par;
+            const float dx = (x0 + (float)(2 * k)) - A.x;
             const float u1 = A.z * dx;
             const float u1s = u1 * u1;
             const float t = B.x * dx;
@@ -161,9 +172,19 @@ __device__ inline void bwd_tile(const float4 *__restrict__ rec, const uint32_t *
             P2 += WU2;
             Q22 += WU22;
         }
-        if (act) {
-            part[2 * (int64_t)sl] = make_float4(C0, C1, C2, P1);
-            part[2 * (int64_t)sl + 1] = make_float4(P2, Q11, Q12, Q22);
+        // even lane + odd lane (quad_perm [1, 0, 3, 2])
+        C0 = pair_add(C0);
+        C1 = pair_add(C1);
+        C2 = pair_add(C2);
+        P1 = pair_add(P1);
+        P2 = pair_add(P2);
+        Q11 = pair_add(Q11);
+        Q12 = pair_add(Q12);
+        Q22 = pair_add(Q22);
+        if (act && par == 0) {
+            const int64_t sl = slot[i];
+            part[2 * sl] = make_float4(C0, C1, C2, P1);
+            part[2 * sl + 1] = make_float4(P2, Q11, Q12, Q22);
         }
     }
 }
@@ -226,7 +247,8 @@ __global__ __launch_bounds__(256 / PX) void k_raster_fit(const float4 *__restric
                                                          const float *__restrict__ target,
                                                          float4 *__restrict__ part,
                                                          float *__restrict__ image_out,
-                                                         float *__restrict__ loss_part) {
+                                                         float *__restrict__ loss_part,
+                                                         int32_t *__restrict__ step_inc) {
     constexpr int NT = 256 / PX;
     constexpr int ROWS = TILE / PX;
     __shared__ float4 sg[TILE_PX];
@@ -272,9 +294,13 @@ __global__ __launch_bounds__(256 / PX) void k_raster_fit(const float4 *__restric
 #pragma unroll
         for (int w = 0; w < NT / 64; ++w) s += red[w];
         loss_part[tile] = s;
+        // the step counter advances here; the update kernel that follows uses *step - 1
+        if (step_inc && tile == 0) *step_inc += 1;
     }
     bwd_tile<NT>(rec, slot, r, ti, sg, part);
 }
+
+// ---- end: the fused fit kernel and the device functions it calls ----
 
 // ---- alpha blending (Eq. rasterization1 with Eq. rasterization2) -----------------------------
 //
@@ -343,6 +369,24 @@ __global__ __launch_bounds__(256 / PX) void k_alpha_fwd(const float4 *__restrict
     }
 }
 
+// Sum over the 64 lanes with DPP adds (no LDS traffic); the total is valid in lane 63.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline float dpp_add(float v) {
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                             0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf,
+                                             false));
+}
+
+__device__ inline float wave_sum_to_last(float v) {
+    v = dpp_add<0xb1>(v);         // quad_perm [1, 0, 3, 2]: pairs
+    v = dpp_add<0x4e>(v);         // quad_perm [2, 3, 0, 1]: quads
+    v = dpp_add<0x141>(v);        // row_half_mirror: eights
+    v = dpp_add<0x140>(v);        // row_mirror: rows of 16
+    v = dpp_add<0x142, 0xa>(v);   // row_bcast15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);   // row_bcast31 into rows 2 and 3: lane 63 holds the total
+    return v;
+}
+
 __device__ inline float wave_sum(float v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
@@ -393,13 +437,14 @@ __device__ inline void alpha_adjoint(const float4 *__restrict__ rec,
             WU22 = fmaf(wu2, u2, WU22);
             T[j] *= 1.f - a;
         }
-        const float P1 = wave_sum(u1 * W), Q11 = wave_sum(u1s * W), Q12 = wave_sum(u1 * WU2);
-        const float P2 = wave_sum(WU2), Q22 = wave_sum(WU22);
-        C0 = wave_sum(C0);
-        C1 = wave_sum(C1);
-        C2 = wave_sum(C2);
-        SO = wave_sum(SO);
-        if (threadIdx.x == 0) {
+        const float P1 = wave_sum_to_last(u1 * W), Q11 = wave_sum_to_last(u1s * W);
+        const float Q12 = wave_sum_to_last(u1 * WU2), P2 = wave_sum_to_last(WU2);
+        const float Q22 = wave_sum_to_last(WU22);
+        C0 = wave_sum_to_last(C0);
+        C1 = wave_sum_to_last(C1);
+        C2 = wave_sum_to_last(C2);
+        SO = wave_sum_to_last(SO);
+        if (threadIdx.x == 63) {
             const int64_t sl = slot[i];
             part[3 * sl] = make_float4(C0, C1, C2, P1);
             part[3 * sl + 1] = make_float4(P2, Q11, Q12, Q22);
@@ -448,7 +493,8 @@ __global__ __launch_bounds__(64) void k_alpha_fit(const float4 *__restrict__ rec
                                                   const float *__restrict__ target,
                                                   float4 *__restrict__ part,
                                                   float *__restrict__ image_out,
-                                                  float *__restrict__ loss_part) {
+                                                  float *__restrict__ loss_part,
+                                                  int32_t *__restrict__ step_inc) {
     constexpr int PX = 4, ROWS = TILE / PX;
     const uint32_t tile = blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
@@ -483,8 +529,38 @@ __global__ __launch_bounds__(64) void k_alpha_fit(const float4 *__restrict__ rec
         }
     }
     sq = wave_sum(sq);
-    if (threadIdx.x == 0) loss_part[tile] = sq;
+    if (threadIdx.x == 0) {
+        loss_part[tile] = sq;
+        if (step_inc && tile == 0) *step_inc += 1;
+    }
     alpha_adjoint(rec, rec_o, slot, r, px, py, D, g, part);
+}
+
+// Per-image mean of the squared residuals from the per-tile sums (float64 accumulation): blocks
+// take images blockIdx.x, blockIdx.x + gridDim.x, ...  256 threads; call from all of them.
+__device__ inline void block_image_losses(const float *__restrict__ loss_part, const ImgTable &tab,
+                                          int64_t n_tiles, float *__restrict__ loss_out,
+                                          double *red) {
+    for (int b = blockIdx.x; b < tab.B; b += gridDim.x) {
+        uint32_t t0 = 0, t1 = (uint32_t)n_tiles;
+        double npx;
+        if (tab.B == 1) {
+            npx = (double)tab.H * tab.W;
+        } else {
+            t0 = tab.tile_base[b];
+            t1 = tab.tile_base[b + 1];
+            npx = (double)tab.dims[b].x * tab.dims[b].y;
+        }
+        double s = 0.0;
+        for (uint32_t t = t0 + threadIdx.x; t < t1; t += 256) s += (double)loss_part[t];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+        __syncthreads();  // red is free
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            loss_out[b] = (float)((red[0] + red[1] + red[2] + red[3]) / (3.0 * npx));
+    }
 }
 
 // Per-Gaussian gradient: the (tile, Gaussian) partial sums of Gaussian i, then the chain rule
@@ -509,12 +585,13 @@ __global__ __launch_bounds__(64) void k_alpha_fit(const float4 *__restrict__ rec
 constexpr int UPD_T = 256;
 constexpr int UPD_G = UPD_T / 4;  // Gaussians per block
 
-template <int COV, int NV = 2>
+template <int COV, int NV = 2, bool RECIPE = false>
 __device__ inline void quad_grad(const float4 *__restrict__ params, int64_t i, int q,
                                  const uint32_t *__restrict__ count,
                                  const uint32_t *__restrict__ off,
                                  const float4 *__restrict__ part, unsigned long long keys,
-                                 float (&g)[8], float4 &q0, float4 &q1, float *extra = nullptr) {
+                                 float (&g)[8], float4 &q0, float4 &q1, float *extra = nullptr,
+                                 const float *at = nullptr) {
     constexpr int NS = NV == 3 ? 9 : 8;  // sums per key: 8, or 9 with the opacity sum
     q0 = params[2 * i];
     q1 = params[2 * i + 1];
@@ -542,10 +619,15 @@ __device__ inline void quad_grad(const float4 *__restrict__ params, int64_t i, i
         for (int k = 0; k < 8; ++k) g[k] = 0.f;
         return;
     }
+    // the chain rule runs at the record that was rendered: the effective record of the recipe
+    // (raw + 0.5 on the diagonal / scales), or the slots given in `at` (fake-quantised values)
+    const float e2 = at ? at[0] : (RECIPE ? q0.z + 0.5f : q0.z);
+    const float e3 = at ? at[1] : (RECIPE && COV == COV_ROTATION_SCALE ? q0.w + 0.5f : q0.w);
+    const float e4 = at ? at[2] : (RECIPE && COV != COV_ROTATION_SCALE ? q1.x + 0.5f : q1.x);
     if (COV == COV_ROTATION_SCALE) {
-        const double s1 = q0.z, s2 = q0.w;
+        const double s1 = e2, s2 = e3;
         double sn, cs;
-        sincos((double)q1.x, &sn, &cs);
+        sincos((double)e4, &sn, &cs);
         const double A = s1 * s1, B = s2 * s2;
         const double l1 = sqrt(cs * cs * A + sn * sn * B);
         const double l2 = cs * sn * (A - B) / l1;
@@ -566,7 +648,7 @@ __device__ inline void quad_grad(const float4 *__restrict__ params, int64_t i, i
         g[3] = (float)(V22 / s2);
         g[4] = (float)((A - B) * V12 / (s1 * s2));
     } else {
-        const float l1 = q0.z, l2 = q0.w, l3 = q1.x;
+        const float l1 = e2, l2 = e3, l3 = e4;
         const float is = (float)(1.0 / U_SCALE);
         const float is2 = (float)(1.0 / (U_SCALE * U_SCALE));
         const float r23 = l2 / l3;
@@ -644,10 +726,15 @@ __global__ __launch_bounds__(UPD_T) void k_adam(float4 *__restrict__ params, int
                                                 float2 *__restrict__ v2, int32_t *step,
                                                 AdamArgs hp, float *__restrict__ opacity,
                                                 float *__restrict__ m_op,
-                                                float *__restrict__ v_op) {
+                                                float *__restrict__ v_op,
+                                                const float *__restrict__ loss_part,
+                                                ImgTable tab, int64_t n_tiles,
+                                                float *__restrict__ loss_out) {
     __shared__ float s_bc[2];
+    __shared__ double red[4];
+    if (loss_out) block_image_losses(loss_part, tab, n_tiles, loss_out, red);
     if (threadIdx.x == 0) {
-        const double t = (double)*step;
+        const double t = (double)(*step - 1);  // the fit kernel has advanced the counter
         s_bc[0] = (float)(1.0 - pow((double)hp.beta1, t));
         s_bc[1] = (float)(1.0 - pow((double)hp.beta2, t));
     }
@@ -701,32 +788,261 @@ __global__ __launch_bounds__(UPD_T) void k_adam(float4 *__restrict__ params, int
     }
 }
 
+// The fitting recipe's step on the raw records (App. C, Sec. 4.1): gradients at the effective
+// record, the position chain factor extent / 2 (1 - tanh(rho)^2), then Adan with the learning
+// rate halved every `halve_every` steps; on the first step the previous gradient is the current
+// one.  Bias corrections and the rate are formed once per block in float64.
+template <int COV>
+__global__ __launch_bounds__(UPD_T) void k_adan(float4 *__restrict__ raw, int64_t n,
+                                                const uint32_t *__restrict__ count,
+                                                const uint32_t *__restrict__ off,
+                                                const float4 *__restrict__ part, DevState *st,
+                                                int64_t cap, float2 *__restrict__ state,
+                                                const int32_t *__restrict__ step, AdanArgs hp,
+                                                ImgTable tab, const float *__restrict__ loss_part,
+                                                int64_t n_tiles, float *__restrict__ loss_out) {
+    __shared__ float s_c[4];
+    __shared__ double red[4];
+    if (loss_out) block_image_losses(loss_part, tab, n_tiles, loss_out, red);
+    const int32_t k = *step - 1;  // the fit kernel has advanced the counter
+    if (threadIdx.x == 0) {
+        const double lr = hp.halve_every > 0
+                              ? (double)hp.lr * exp2(-(double)((k - 1) / hp.halve_every))
+                              : (double)hp.lr;
+        s_c[0] = (float)(1.0 - pow((double)hp.beta1, (double)k));
+        s_c[1] = (float)(1.0 - pow((double)hp.beta2, (double)k));
+        s_c[2] = (float)(1.0 - pow((double)hp.beta3, (double)k));
+        s_c[3] = (float)lr;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * UPD_G + (threadIdx.x >> 2);
+    const int q = threadIdx.x & 3;
+    if (i >= n || (st->flags & FLAG_KEY_OVERFLOW)) return;
+    unsigned long long keys = st->keys_total;
+    if (keys > (unsigned long long)cap) keys = (unsigned long long)cap;
+    float g[8];
+    float4 q0, q1;
+    quad_grad<COV, 2, true>(raw, i, q, count, off, part, keys, g, q0, q1);
+    int32_t H = tab.H, W = tab.W;
+    if (tab.B > 1) {
+        const int4 d = tab.dims[upper_index(tab.gauss_off, tab.B, (uint32_t)i)];
+        H = d.x;
+        W = d.y;
+    }
+    const float tx = tanhf(q0.x), ty = tanhf(q0.y);
+    g[0] *= 0.5f * (float)W * (1.f - tx * tx);
+    g[1] *= 0.5f * (float)H * (1.f - ty * ty);
+    const float pv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    const int64_t stride = 4 * n;  // float2 entries per state array
+    float2 *m2 = state, *v2 = state + stride, *n2 = state + 2 * stride, *p2 = state + 3 * stride;
+    const float2 mo = m2[4 * i + q], vo = v2[4 * i + q], no = n2[4 * i + q], go = p2[4 * i + q];
+    const float bc1 = s_c[0], bc2 = s_c[1], bc3 = s_c[2], lr = s_c[3];
+    float p[2] = {pv[2 * q], pv[2 * q + 1]};
+    float m[2] = {mo.x, mo.y}, v[2] = {vo.x, vo.y}, nn[2] = {no.x, no.y};
+    const float gprev[2] = {go.x, go.y};
+    float gk[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        gk[e] = g[2 * q + e];
+        const float diff = k == 1 ? 0.f : gk[e] - gprev[e];
+        m[e] = hp.beta1 * m[e] + (1.f - hp.beta1) * gk[e];
+        v[e] = hp.beta2 * v[e] + (1.f - hp.beta2) * diff;
+        const float t = fmaf(hp.beta2, diff, gk[e]);
+        nn[e] = hp.beta3 * nn[e] + (1.f - hp.beta3) * t * t;
+        const float upd = (m[e] / bc1 + hp.beta2 * v[e] / bc2) / (sqrtf(nn[e] / bc3) + hp.eps);
+        p[e] = (p[e] - lr * upd) / (1.f + lr * hp.weight_decay);
+    }
+    // every lane of the quad has read the record before any lane writes
+    __builtin_amdgcn_wave_barrier();
+    reinterpret_cast<float2 *>(raw)[4 * i + q] = make_float2(p[0], p[1]);
+    m2[4 * i + q] = make_float2(m[0], m[1]);
+    v2[4 * i + q] = make_float2(v[0], v[1]);
+    n2[4 * i + q] = make_float2(nn[0], nn[1]);
+    p2[4 * i + q] = make_float2(gk[0], gk[1]);
+}
+
+// Quantisation-aware fine-tuning (Sec. 3.3): the Gaussians' Adam step with straight-through
+// gradients of the fake-quantised record, and per-block sums of the quantiser's gradient: LSQ+
+// terms for gamma, beta; for the codebooks, per entry, the sums of C[i] - r over the Gaussians
+// that chose it (scaled by 2 lambda / (N B) later); and the commitment sum |C[i] - r|^2.
+// Per-Gaussian terms go through LDS and are added in Gaussian order, so the sums do not
+// depend on scheduling.  qpart: [gridDim.x][qat_nq + 1].
+__host__ __device__ constexpr int qat_nq(int stages, int size) { return 6 + 3 * stages * size; }
+
+template <int COV>
+__global__ __launch_bounds__(UPD_T) void k_qat_adam(float4 *__restrict__ params, int64_t n,
+                                                    const uint32_t *__restrict__ count,
+                                                    const uint32_t *__restrict__ off,
+                                                    const float4 *__restrict__ part,
+                                                    DevState *st, int64_t cap,
+                                                    float2 *__restrict__ m2,
+                                                    float2 *__restrict__ v2,
+                                                    const int32_t *__restrict__ step, AdamArgs hp,
+                                                    QatArgs qa, float *__restrict__ qpart,
+                                                    const float *__restrict__ loss_part,
+                                                    ImgTable tab, int64_t n_tiles,
+                                                    float *__restrict__ loss_out) {
+    constexpr int W = 7 + 3 * QAT_MAX_STAGES;  // 6 LSQ terms, commitment, 3 per stage
+    __shared__ float s_bc[2];
+    __shared__ double red[4];
+    __shared__ float rows[UPD_G][W];
+    __shared__ int32_t sidx[UPD_G][QAT_MAX_STAGES];
+    if (loss_out) block_image_losses(loss_part, tab, n_tiles, loss_out, red);
+    if (threadIdx.x == 0) {
+        const double t = (double)(*step - 1);  // the fit kernel has advanced the counter
+        s_bc[0] = (float)(1.0 - pow((double)hp.beta1, t));
+        s_bc[1] = (float)(1.0 - pow((double)hp.beta2, t));
+    }
+    const int gl = threadIdx.x >> 2;  // Gaussian of this quad within the block
+    const int64_t i = (int64_t)blockIdx.x * UPD_G + gl;
+    const int q = threadIdx.x & 3;
+    const bool live = i < n && !(st->flags & FLAG_KEY_OVERFLOW);
+    if (q == 0) {
+        for (int k = 0; k < W; ++k) rows[gl][k] = 0.f;
+        for (int m = 0; m < QAT_MAX_STAGES; ++m) sidx[gl][m] = -1;
+    }
+    __syncthreads();
+    if (live) {
+        unsigned long long keys = st->keys_total;
+        if (keys > (unsigned long long)cap) keys = (unsigned long long)cap;
+        const float4 a = params[2 * i], b = params[2 * i + 1];
+        float rq[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        QuantFacts f;
+        qat_fake_quant(rq, qa, &f);
+        float g[8];
+        float4 q0, q1;
+        quad_grad<COV>(params, i, q, count, off, part, keys, g, q0, q1, nullptr, rq + 2);
+        const double top = (double)((1 << qa.bits) - 1);
+        bool inside[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) inside[k] = f.x[k] >= 0.0 && f.x[k] <= top;
+        if (q == 0) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double dg = inside[k] ? f.code[k] - f.x[k] : (f.x[k] > top ? top : 0.0);
+                rows[gl][k] = (float)((double)g[2 + k] * dg);
+                rows[gl][3 + k] = inside[k] ? 0.f : g[2 + k];
+            }
+            // codebook terms: the residual before each stage and the chosen entry
+            double r0 = b.y, r1 = b.z, r2 = b.w;  // the float colour
+            double lc = 0.0;
+            const float *books = qa.quant + 6;
+            for (int m = 0; m < qa.stages; ++m) {
+                const float *e = books + ((int64_t)m * qa.size + f.idx[m]) * 3;
+                const double d0 = (double)e[0] - r0, d1 = (double)e[1] - r1;
+                const double d2 = (double)e[2] - r2;
+                rows[gl][7 + 3 * m] = (float)d0;
+                rows[gl][8 + 3 * m] = (float)d1;
+                rows[gl][9 + 3 * m] = (float)d2;
+                sidx[gl][m] = f.idx[m];
+                lc += (d0 * d0 + d1 * d1) + d2 * d2;
+                r0 -= (double)e[0];
+                r1 -= (double)e[1];
+                r2 -= (double)e[2];
+            }
+            rows[gl][6] = (float)lc;
+        }
+        // straight-through: covariance slots pass the gradient only inside the code range
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (!inside[k]) g[2 + k] = 0.f;
+        const float pv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        const float bc1 = s_bc[0], bc2 = s_bc[1];
+        const float2 mo = m2[4 * i + q], vo = v2[4 * i + q];
+        float p[2] = {pv[2 * q], pv[2 * q + 1]};
+        float m[2] = {mo.x, mo.y}, v[2] = {vo.x, vo.y};
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int k = 2 * q + e;
+            const float lr = k < 2 ? hp.lr_mu : (k < 5 ? hp.lr_l : hp.lr_c);
+            m[e] = hp.beta1 * m[e] + (1.f - hp.beta1) * g[k];
+            v[e] = hp.beta2 * v[e] + (1.f - hp.beta2) * g[k] * g[k];
+            p[e] -= lr * (m[e] / bc1) / (sqrtf(v[e] / bc2) + hp.eps);
+            const bool floor = COV == COV_ROTATION_SCALE ? (k == 2 || k == 3) : (k == 2 || k == 4);
+            if (floor && hp.l_min > 0.f && fabsf(p[e]) < hp.l_min)
+                p[e] = copysignf(hp.l_min, p[e]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        reinterpret_cast<float2 *>(params)[4 * i + q] = make_float2(p[0], p[1]);
+        m2[4 * i + q] = make_float2(m[0], m[1]);
+        v2[4 * i + q] = make_float2(v[0], v[1]);
+    }
+    __syncthreads();
+    // block sums in Gaussian order: LSQ terms, commitment, then codebook entries
+    const int nq = qat_nq(qa.stages, qa.size);
+    for (int t = threadIdx.x; t <= nq; t += UPD_T) {
+        float acc = 0.f;
+        if (t < 6) {
+            for (int j = 0; j < UPD_G; ++j) acc += rows[j][t];
+        } else if (t < nq) {
+            const int e = t - 6, m = e / (3 * qa.size), k = (e / 3) % qa.size, ch = e % 3;
+            for (int j = 0; j < UPD_G; ++j)
+                if (sidx[j][m] == k) acc += rows[j][7 + 3 * m + ch];
+        } else {
+            for (int j = 0; j < UPD_G; ++j) acc += rows[j][6];
+        }
+        qpart[(int64_t)blockIdx.x * (nq + 1) + t] = acc;
+    }
+}
+
+// The quantiser's step (one block): block sums added in block order (float64), codebook terms
+// scaled by 2 lambda / (N B), Adam with rate lr_q; the weighted commitment loss is added to the
+// image loss.
+__global__ __launch_bounds__(256) void k_qat_quant_adam(float *__restrict__ quant,
+                                                        float *__restrict__ qm,
+                                                        float *__restrict__ qv,
+                                                        const float *__restrict__ qpart,
+                                                        int64_t blocks, int64_t n, QatArgs qa,
+                                                        float lambda, float lr_q, AdamArgs hp,
+                                                        const int32_t *__restrict__ step,
+                                                        const DevState *__restrict__ st,
+                                                        float *__restrict__ loss_out) {
+    if (st->flags & FLAG_KEY_OVERFLOW) return;  // the Gaussians were not updated either
+    const int nq = qat_nq(qa.stages, qa.size);
+    const double t_step = (double)(*step - 1);
+    const double scale = 2.0 * (double)lambda / ((double)n * (double)qa.size);
+    for (int t = threadIdx.x; t <= nq; t += 256) {
+        double s = 0.0;
+        for (int64_t b = 0; b < blocks; ++b) s += (double)qpart[b * (nq + 1) + t];
+        if (t == nq) {
+            if (loss_out) loss_out[0] += (float)(lambda * s / ((double)n * (double)qa.size));
+            continue;
+        }
+        const float g = (float)(t < 6 ? s : s * scale);
+        const float bc1 = (float)(1.0 - pow((double)hp.beta1, t_step));
+        const float bc2 = (float)(1.0 - pow((double)hp.beta2, t_step));
+        const float m = hp.beta1 * qm[t] + (1.f - hp.beta1) * g;
+        const float v = hp.beta2 * qv[t] + (1.f - hp.beta2) * g * g;
+        quant[t] -= lr_q * (m / bc1) / (sqrtf(v / bc2) + hp.eps);
+        qm[t] = m;
+        qv[t] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_recipe_effective(const float4 *__restrict__ raw,
+                                                          int64_t n, ImgTable tab, int32_t cov,
+                                                          float4 *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float4 a = raw[2 * i], b = raw[2 * i + 1];
+    float q[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    int32_t H = tab.H, W = tab.W;
+    if (tab.B > 1) {
+        const int4 d = tab.dims[upper_index(tab.gauss_off, tab.B, (uint32_t)i)];
+        H = d.x;
+        W = d.y;
+    }
+    recipe_effective(q, H, W, cov == COV_ROTATION_SCALE);
+    out[2 * i] = make_float4(q[0], q[1], q[2], q[3]);
+    out[2 * i + 1] = make_float4(q[4], q[5], q[6], q[7]);
+}
+
 // Per-image mean of the squared residuals from the per-tile sums (float64 accumulation), and the
 // step counter advance.  One block per image.
 __global__ __launch_bounds__(256) void k_finish(const float *__restrict__ loss_part, ImgTable tab,
-                                                int64_t n_tiles, float *__restrict__ loss_out,
-                                                int32_t *__restrict__ step) {
+                                                int64_t n_tiles, float *__restrict__ loss_out) {
     __shared__ double red[4];
-    const int b = blockIdx.x;
-    if (loss_out) {
-        uint32_t t0 = 0, t1 = (uint32_t)n_tiles;
-        double npx;
-        if (tab.B == 1) {
-            npx = (double)tab.H * tab.W;
-        } else {
-            t0 = tab.tile_base[b];
-            t1 = tab.tile_base[b + 1];
-            npx = (double)tab.dims[b].x * tab.dims[b].y;
-        }
-        double s = 0.0;
-        for (uint32_t t = t0 + threadIdx.x; t < t1; t += 256) s += (double)loss_part[t];
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) loss_out[b] = (float)((red[0] + red[1] + red[2] + red[3]) / (3.0 * npx));
-    }
-    if (step && b == 0 && threadIdx.x == 0) *step += 1;
+    block_image_losses(loss_part, tab, n_tiles, loss_out, red);
 }
 
 }  // namespace
@@ -751,14 +1067,15 @@ hipError_t launch_raster_bwd(const RasterArgs &a, const float *dl, float *part, 
 }
 
 hipError_t launch_raster_fit(const RasterArgs &a, const float *target, float *part,
-                             float *image_out, float *loss_part, int px, hipStream_t s) {
+                             float *image_out, float *loss_part, int px, int32_t *step_inc,
+                             hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
     const float4 *rec = reinterpret_cast<const float4 *>(a.rec);
     float4 *p4 = reinterpret_cast<float4 *>(part);
     switch (px) {
-        case 1: hipLaunchKernelGGL(k_raster_fit<1>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part); break;
-        case 4: hipLaunchKernelGGL(k_raster_fit<4>, dim3((unsigned)a.n_tiles), dim3(64), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part); break;
-        default: hipLaunchKernelGGL(k_raster_fit<2>, dim3((unsigned)a.n_tiles), dim3(128), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part); break;
+        case 1: hipLaunchKernelGGL(k_raster_fit<1>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc); break;
+        case 4: hipLaunchKernelGGL(k_raster_fit<4>, dim3((unsigned)a.n_tiles), dim3(64), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc); break;
+        default: hipLaunchKernelGGL(k_raster_fit<2>, dim3((unsigned)a.n_tiles), dim3(128), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc); break;
     }
     return hipGetLastError();
 }
@@ -828,23 +1145,24 @@ hipError_t launch_adam(const UpdateArgs &u, float *params, float *m, float *v, i
         if (u.cov == COV_ROTATION_SCALE)
             hipLaunchKernelGGL((k_adam<COV_ROTATION_SCALE, BLEND_NONE>), grid, dim3(UPD_T), 0, s,
                                p4, u.n, u.count, u.off, part, u.state, u.cap, m2, v2, step, hp,
-                               nf, nf, nf);
+                               nf, nf, nf, loss_part, tab, n_tiles, loss_out);
         else
             hipLaunchKernelGGL((k_adam<COV_CHOLESKY, BLEND_NONE>), grid, dim3(UPD_T), 0, s, p4,
                                u.n, u.count, u.off, part, u.state, u.cap, m2, v2, step, hp, nf,
-                               nf, nf);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+                               nf, nf, loss_part, tab, n_tiles, loss_out);
+        return hipGetLastError();
     }
-    return launch_finish(loss_part, tab, n_tiles, loss_out, step, s);
+    return launch_finish(loss_part, tab, n_tiles, loss_out, s);
 }
 
 hipError_t launch_alpha_fit(const RasterArgs &a, const float *rec_o, const float *target,
-                            float *part12, float *image_out, float *loss_part, hipStream_t s) {
+                            float *part12, float *image_out, float *loss_part, int32_t *step_inc,
+                            hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_alpha_fit, dim3((unsigned)a.n_tiles), dim3(64), 0, s,
                        reinterpret_cast<const float4 *>(a.rec), rec_o, a.slot, a.ranges, a.tab,
-                       target, reinterpret_cast<float4 *>(part12), image_out, loss_part);
+                       target, reinterpret_cast<float4 *>(part12), image_out, loss_part,
+                       step_inc);
     return hipGetLastError();
 }
 
@@ -860,7 +1178,8 @@ hipError_t launch_adam_opacity(const UpdateArgs &u, float *params, float *opacit
         const bool rs = u.cov == COV_ROTATION_SCALE;
 #define GI_LAUNCH_AO(C, BL)                                                                     \
     hipLaunchKernelGGL((k_adam<C, BL>), grid, dim3(UPD_T), 0, s, p4, u.n, u.count, u.off, part, \
-                       u.state, u.cap, m2, v2, step, hp, opacity, mo, vo)
+                       u.state, u.cap, m2, v2, step, hp, opacity, mo, vo, loss_part, tab,       \
+                       n_tiles, loss_out)
         if (blend == BLEND_ALPHA) {
             if (rs) GI_LAUNCH_AO(COV_ROTATION_SCALE, BLEND_ALPHA);
             else GI_LAUNCH_AO(COV_CHOLESKY, BLEND_ALPHA);
@@ -869,16 +1188,77 @@ hipError_t launch_adam_opacity(const UpdateArgs &u, float *params, float *opacit
             else GI_LAUNCH_AO(COV_CHOLESKY, BLEND_SUM);
         }
 #undef GI_LAUNCH_AO
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        return hipGetLastError();
     }
-    return launch_finish(loss_part, tab, n_tiles, loss_out, step, s);
+    return launch_finish(loss_part, tab, n_tiles, loss_out, s);
+}
+
+hipError_t launch_adan(const UpdateArgs &u, float *raw, float *state, int32_t *step,
+                       const AdanArgs &hp, const ImgTable &tab, const float *loss_part,
+                       int64_t n_tiles, float *loss_out, hipStream_t s) {
+    if (u.n > 0) {
+        const dim3 grid((unsigned)((u.n + UPD_G - 1) / UPD_G));
+        float4 *r4 = reinterpret_cast<float4 *>(raw);
+        const float4 *part = reinterpret_cast<const float4 *>(u.part);
+        float2 *st2 = reinterpret_cast<float2 *>(state);
+        if (u.cov == COV_ROTATION_SCALE)
+            hipLaunchKernelGGL(k_adan<COV_ROTATION_SCALE>, grid, dim3(UPD_T), 0, s, r4, u.n,
+                               u.count, u.off, part, u.state, u.cap, st2, step, hp, tab,
+                               loss_part, n_tiles, loss_out);
+        else
+            hipLaunchKernelGGL(k_adan<COV_CHOLESKY>, grid, dim3(UPD_T), 0, s, r4, u.n, u.count,
+                               u.off, part, u.state, u.cap, st2, step, hp, tab, loss_part,
+                               n_tiles, loss_out);
+        return hipGetLastError();
+    }
+    return launch_finish(loss_part, tab, n_tiles, loss_out, s);
+}
+
+hipError_t launch_qat_update(const UpdateArgs &u, float *params, float *m, float *v,
+                             int32_t *step, const AdamArgs &hp, const QatArgs &qa, float lambda,
+                             float lr_q, float *quant_m, float *quant_v, float *qpart,
+                             const float *loss_part, const ImgTable &tab, int64_t n_tiles,
+                             float *loss_out, hipStream_t s) {
+    if (u.n <= 0) return launch_finish(loss_part, tab, n_tiles, loss_out, s);
+    const int64_t blocks = (u.n + UPD_G - 1) / UPD_G;
+    const dim3 grid((unsigned)blocks);
+    float4 *p4 = reinterpret_cast<float4 *>(params);
+    const float4 *part = reinterpret_cast<const float4 *>(u.part);
+    float2 *m2 = reinterpret_cast<float2 *>(m), *v2 = reinterpret_cast<float2 *>(v);
+    if (u.cov == COV_ROTATION_SCALE)
+        hipLaunchKernelGGL(k_qat_adam<COV_ROTATION_SCALE>, grid, dim3(UPD_T), 0, s, p4, u.n,
+                           u.count, u.off, part, u.state, u.cap, m2, v2, step, hp, qa, qpart,
+                           loss_part, tab, n_tiles, loss_out);
+    else
+        hipLaunchKernelGGL(k_qat_adam<COV_CHOLESKY>, grid, dim3(UPD_T), 0, s, p4, u.n, u.count,
+                           u.off, part, u.state, u.cap, m2, v2, step, hp, qa, qpart, loss_part,
+                           tab, n_tiles, loss_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_qat_quant_adam, dim3(1), dim3(256), 0, s, const_cast<float *>(qa.quant),
+                       quant_m, quant_v, qpart, blocks, u.n, qa, lambda, lr_q, hp, step, u.state,
+                       loss_out);
+    return hipGetLastError();
+}
+
+int64_t qat_part_floats(int64_t n, int stages, int size) {
+    return ((n + UPD_G - 1) / UPD_G) * (qat_nq(stages, size) + 1);
+}
+
+hipError_t launch_recipe_effective(const float *raw, int64_t n, const ImgTable &tab, int32_t cov,
+                                   float *params, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_recipe_effective, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<const float4 *>(raw), n, tab, cov,
+                       reinterpret_cast<float4 *>(params));
+    return hipGetLastError();
 }
 
 hipError_t launch_finish(const float *loss_part, const ImgTable &tab, int64_t n_tiles,
-                         float *loss_out, int32_t *step, hipStream_t s) {
+                         float *loss_out, hipStream_t s) {
+    if (!loss_out) return hipSuccess;
     hipLaunchKernelGGL(k_finish, dim3((unsigned)tab.B), dim3(256), 0, s, loss_part, tab, n_tiles,
-                       loss_out, step);
+                       loss_out);
     return hipGetLastError();
 }
 

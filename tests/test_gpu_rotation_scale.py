@@ -217,3 +217,28 @@ def test_rs_batched_equals_plain_and_graph_equals_eager(gi):
         graph.close()
     np.testing.assert_array_equal(host(pb), host(pa))
     assert math.isclose(float(host(sb)[0]), 4.0)
+
+
+def test_rs_kodak_size_sampled(gi):
+    # 768x512 / 70k rotation-scale records: binning bit-exact, sampled pixels against the oracle's
+    # per-pixel sum over the Gaussians of the pixel's tile list
+    h, w = 512, 768
+    p = synth.gaussians_rs(70_000, h, w, seed=2070, s_lo=1.0, s_hi=8.0, c_lo=0.0, c_hi=1.0)
+    b = gi.binning(dev(p), h, w)
+    ranges, ids = ref.tile_lists(p, h, w, cov="rs")
+    np.testing.assert_array_equal(host(b["ranges"]), ranges)
+    np.testing.assert_array_equal(host(b["ids"]), ids)
+    img = host(gi.render(dev(p), h, w))
+    inv = ref.inverse_covariance(p, cov="rs")
+    pf = p.astype(np.float64)
+    tw, _ = ref.grid_tiles(h, w)
+    rng = np.random.default_rng(2071)
+    for y, x in zip(rng.integers(0, h, 64), rng.integers(0, w, 64)):
+        a, e_ = ranges[(y // 16) * tw + x // 16]
+        sel = ids[a:e_]
+        dx, dy = x + 0.5 - pf[sel, 0], y + 0.5 - pf[sel, 1]
+        s = 0.5 * (inv[0][sel] * dx * dx + 2 * inv[1][sel] * dx * dy + inv[2][sel] * dy * dy)
+        e = np.exp(-s)
+        want = (e[:, None] * pf[sel, 5:8]).sum(0)
+        A = (e[:, None] * np.abs(pf[sel, 5:8])).sum(0)
+        assert np.all(np.abs(img[y, x] - want) <= FWD_RTOL * A + 1e-30), (y, x)
