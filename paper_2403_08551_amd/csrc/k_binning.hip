@@ -590,9 +590,8 @@ __global__ __launch_bounds__(BLK) void k_fill_u32(uint32_t *__restrict__ p, uint
 //     tile id in one pass, and the result equals that of the stable radix sort.
 
 constexpr int FB = 256;
-// waves that split a chunk's keys in the scatter: 8 where a workgroup may hold the 9 T words of
-// per-wave tile counters (more waves per CU hide the scatter's latency), else 4
-constexpr int SCATTER_WAVES_MAX = 8;
+// the scatter splits a chunk's keys over 4 or 8 waves (more waves per CU hide its latency;
+// each needs T words of LDS counters), see scatter_waves
 constexpr uint32_t OWN_CAP = 4096;
 constexpr int XCDS = 8;
 
@@ -1101,31 +1100,39 @@ hipError_t launch_fused_a(const FusedBuffers &f, const ImgTable &tab, hipStream_
     return hipGetLastError();
 }
 
-// Whether the 8-wave scatter fits this device's per-workgroup LDS at the largest tile count of
-// the one-pass path.  Decided once per device (at the first one-pass binning, which is never
-// inside a graph capture: captured steps are preceded by an eager sizing pass); the kernel's
-// dynamic LDS limit is raised then, once.
-static bool scatter_wide_fits() {
+// Waves of the scatter for this device: 8 where the per-workgroup LDS (static plus 9 words per
+// tile at the largest tile count of the one-pass path) fits, else 4.  (16 waves were measured
+// slower at 768x512: 29 us against 23 us.)  Decided
+// once per device at the first one-pass binning, which is never inside a graph capture
+// (captured steps are preceded by an eager sizing pass); the kernel's dynamic LDS limit is
+// raised then, once.
+template <int WV>
+static bool scatter_fits(int dev_lds) {
+    hipFuncAttributes fa;
+    const void *fn = reinterpret_cast<const void *>(&k_fused_scatter<WV>);
+    const size_t dyn = sizeof(uint32_t) * (WV + 1) * (size_t)FUSED_MAX_TILES;
+    if (hipFuncGetAttributes(&fa, fn) != hipSuccess || fa.sharedSizeBytes + dyn > (size_t)dev_lds)
+        return false;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) ==
+           hipSuccess;
+}
+
+static int scatter_waves() {
     static int dev_cached = -1;
-    static bool wide = false;
+    static int waves = 4;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipGetDevice(&dev) != hipSuccess) return 4;
     if (dev != dev_cached) {
         dev_cached = dev;
-        wide = false;
+        waves = 4;
         int v = 0;
-        hipFuncAttributes fa;
-        const void *fn = reinterpret_cast<const void *>(&k_fused_scatter<SCATTER_WAVES_MAX>);
-        const size_t dyn = sizeof(uint32_t) * (SCATTER_WAVES_MAX + 1) * (size_t)FUSED_MAX_TILES;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
-                hipSuccess &&
-            hipFuncGetAttributes(&fa, fn) == hipSuccess && fa.sharedSizeBytes + dyn <= (size_t)v &&
-            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) ==
-                hipSuccess)
-            wide = true;
+            hipSuccess) {
+            if (scatter_fits<8>(v)) waves = 8;
+        }
         (void)hipGetLastError();
     }
-    return wide;
+    return waves;
 }
 
 hipError_t launch_fused_c(const FusedBuffers &f, uint32_t *ids, hipStream_t s) {
@@ -1139,8 +1146,8 @@ hipError_t launch_fused_c(const FusedBuffers &f, uint32_t *ids, hipStream_t s) {
                        f.b.n, (int32_t)f.b.n_tiles, tbits, nchunk, f.b.cap,                     \
                        reinterpret_cast<float4 *>(f.b.rec), f.b.slot, ids, f.b.ranges,          \
                        f.b.opacity, f.b.rec_o, f.b.state)
-    if (scatter_wide_fits())
-        GI_LAUNCH_SCATTER(SCATTER_WAVES_MAX);
+    if (scatter_waves() == 8)
+        GI_LAUNCH_SCATTER(8);
     else
         GI_LAUNCH_SCATTER(4);
 #undef GI_LAUNCH_SCATTER

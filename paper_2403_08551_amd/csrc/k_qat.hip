@@ -97,7 +97,8 @@ __device__ inline int nearest(const double *cent, int k, double r0, double r1, d
     return best;
 }
 
-// assignment and per-block sums per centroid: part[block][k][4] = (sum x, sum y, sum z, count)
+// assignment and per-block sums per centroid: part[k][4][block] = (sum x, sum y, sum z, count)
+// (entry-major, so that the update reads each entry's block sums contiguously)
 __global__ __launch_bounds__(QB) void k_kmeans_assign(const double *__restrict__ resid,
                                                       int64_t n, int32_t k,
                                                       const double *__restrict__ cent,
@@ -123,17 +124,23 @@ __global__ __launch_bounds__(QB) void k_kmeans_assign(const double *__restrict__
         double acc = 0.0;
         for (int p = 0; p < QB; ++p)
             if (lab[p] == j) acc += c < 3 ? pts[p][c] : 1.0;
-        part[((int64_t)blockIdx.x * k + j) * 4 + c] = acc;
+        part[(int64_t)t * gridDim.x + blockIdx.x] = acc;
     }
 }
 
-__global__ void k_kmeans_update(const double *__restrict__ part, int64_t blocks, int32_t k,
-                                double *__restrict__ cent) {
+// one block of four waves: wave w adds the block sums of entries w, w + 4, ... (lanes in a
+// fixed strided order, then a fixed shuffle tree)
+__global__ __launch_bounds__(256) void k_kmeans_update(const double *__restrict__ part,
+                                                       int64_t blocks, int32_t k,
+                                                       double *__restrict__ cent) {
     __shared__ double tot[QAT_KMAX * 4];
-    for (int t = threadIdx.x; t < 4 * k; t += blockDim.x) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = wave; t < 4 * k; t += 4) {
         double acc = 0.0;
-        for (int64_t b = 0; b < blocks; ++b) acc += part[b * 4 * k + t];
-        tot[t] = acc;
+        for (int64_t b = lane; b < blocks; b += 64) acc += part[(int64_t)t * blocks + b];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+        if (lane == 0) tot[t] = acc;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < 3 * k; t += blockDim.x) {

@@ -866,7 +866,8 @@ __global__ __launch_bounds__(UPD_T) void k_adan(float4 *__restrict__ raw, int64_
 // terms for gamma, beta; for the codebooks, per entry, the sums of C[i] - r over the Gaussians
 // that chose it (scaled by 2 lambda / (N B) later); and the commitment sum |C[i] - r|^2.
 // Per-Gaussian terms go through LDS and are added in Gaussian order, so the sums do not
-// depend on scheduling.  qpart: [gridDim.x][qat_nq + 1].
+// depend on scheduling.  qpart: [qat_nq + 1][gridDim.x] (entry-major, so that the quantiser
+// kernel reads each entry's block sums contiguously).
 __host__ __device__ constexpr int qat_nq(int stages, int size) { return 6 + 3 * stages * size; }
 
 template <int COV>
@@ -981,13 +982,14 @@ __global__ __launch_bounds__(UPD_T) void k_qat_adam(float4 *__restrict__ params,
         } else {
             for (int j = 0; j < UPD_G; ++j) acc += rows[j][6];
         }
-        qpart[(int64_t)blockIdx.x * (nq + 1) + t] = acc;
+        qpart[(int64_t)t * gridDim.x + blockIdx.x] = acc;
     }
 }
 
-// The quantiser's step (one block): block sums added in block order (float64), codebook terms
-// scaled by 2 lambda / (N B), Adam with rate lr_q; the weighted commitment loss is added to the
-// image loss.
+// The quantiser's step: block t takes entry t (the last block the commitment loss); its threads
+// add the entry's block sums in a fixed strided order (float64) and a fixed tree joins them;
+// codebook terms are scaled by 2 lambda / (N B); Adam with rate lr_q; the weighted commitment
+// loss is added to the image loss.
 __global__ __launch_bounds__(256) void k_qat_quant_adam(float *__restrict__ quant,
                                                         float *__restrict__ qm,
                                                         float *__restrict__ qv,
@@ -1001,12 +1003,19 @@ __global__ __launch_bounds__(256) void k_qat_quant_adam(float *__restrict__ quan
     const int nq = qat_nq(qa.stages, qa.size);
     const double t_step = (double)(*step - 1);
     const double scale = 2.0 * (double)lambda / ((double)n * (double)qa.size);
-    for (int t = threadIdx.x; t <= nq; t += 256) {
-        double s = 0.0;
-        for (int64_t b = 0; b < blocks; ++b) s += (double)qpart[b * (nq + 1) + t];
+    __shared__ double red[4];
+    const int t = blockIdx.x;  // 0 .. nq
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < blocks; b += 256) s += (double)qpart[(int64_t)t * blocks + b];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s = (red[0] + red[1]) + (red[2] + red[3]);
         if (t == nq) {
             if (loss_out) loss_out[0] += (float)(lambda * s / ((double)n * (double)qa.size));
-            continue;
+            return;
         }
         const float g = (float)(t < 6 ? s : s * scale);
         const float bc1 = (float)(1.0 - pow((double)hp.beta1, t_step));
@@ -1235,7 +1244,8 @@ hipError_t launch_qat_update(const UpdateArgs &u, float *params, float *m, float
                            tab, n_tiles, loss_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_qat_quant_adam, dim3(1), dim3(256), 0, s, const_cast<float *>(qa.quant),
+    hipLaunchKernelGGL(k_qat_quant_adam, dim3((unsigned)(qat_nq(qa.stages, qa.size) + 1)),
+                       dim3(256), 0, s, const_cast<float *>(qa.quant),
                        quant_m, quant_v, qpart, blocks, u.n, qa, lambda, lr_q, hp, step, u.state,
                        loss_out);
     return hipGetLastError();
