@@ -541,10 +541,10 @@ def main():
                      "update": upd_ms / max(upd_n, 1)},
         "loss": {"after_warmup": loss_start, "after_timed": loss_end},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T FP32 op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(f"k_raster_fit<{tuned[0] or 2}>"),
+                     "unit": "T FP32 op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(f"k_raster_fit<{tuned[0] or 4}>"),
                      "peak_unpacked": VALU_PEAK_UNPACKED / 1e12,
                      "frac_unpacked": achieved / VALU_PEAK_UNPACKED,
-                     "kernel": f"k_raster_fit<{tuned[0] or 2}>", "ops_per_pair": OPS_PER_PAIR_FIT,
+                     "kernel": f"k_raster_fit<{tuned[0] or 4}>", "ops_per_pair": OPS_PER_PAIR_FIT,
                      "pairs_per_launch": P_prof, "avg_launch_ms": fit_ms / fit_n},
         "batched_vs_plain": bvp,
         "rotation_scale": rs,

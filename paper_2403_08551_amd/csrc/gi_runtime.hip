@@ -352,7 +352,7 @@ std::pair<int, int> size_class(int64_t n, int64_t n_pix) {
 int pick_px(gi_ctx *ctx, int64_t n, int64_t n_pix) {
     if (ctx->fwd_px) return ctx->fwd_px;
     auto it = ctx->tuned.find(size_class(n, n_pix));
-    return it != ctx->tuned.end() ? it->second.first : 2;
+    return it != ctx->tuned.end() ? it->second.first : 4;
 }
 
 int pick_digit(gi_ctx *ctx, int64_t n, int64_t n_pix, int key_bits, int64_t keys) {
@@ -919,7 +919,7 @@ int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n
     const int pxs[3] = {1, 2, 4};
     const int bits[5] = {0, 4, 6, 8, 11};
     float best = 1e30f;
-    int best_px = 2, best_bits = 0;
+    int best_px = 4, best_bits = 0;
     ctx->timing = 0;
     // one synchronous pass sizes the workspace, then steps do not wait on the host
     ctx->sync = 1;

@@ -9,10 +9,13 @@
 // A sum of squares does not cancel, unlike the quadratic form with the inverse covariance, so
 // float32 keeps sigma to a few ulp even for elongated, correlated Gaussians.
 //
-// Work mapping.  Forward: one workgroup per 16x16 tile, one pixel column segment per lane
-// (PX pixels of one column), the tile's records read in sorted order through the scalar unit
-// (every lane uses the same Gaussian at once), colour accumulated in float32 registers with a
-// two-level sum (partial sums per chunk of 32 Gaussians).  Adjoint: one Gaussian per lane, the
+// Work mapping.  Forward: one workgroup of 256 threads per 16x16 tile.  The tile's list is cut
+// into four equal parts; each part is summed by one group of 256 / PX threads, each lane owning
+// PX pixels of one column (so per-column terms are shared by PX pixels), the part's records read
+// in sorted order through the scalar unit (every lane uses the same Gaussian at once), colour
+// accumulated in float32 registers with a two-level sum (partial sums per chunk of 32
+// Gaussians).  The four part sums meet in LDS and are added in part order, so every PX gives
+// the same bits.  Adjoint: one Gaussian per lane, the
 // tile's 256 dL/dC values staged in LDS and read as broadcasts, so each lane reduces its own
 // Gaussian over the tile's pixels in registers: no cross-lane reduction and no atomics.  The
 // eight partial sums of each (tile, Gaussian) pair are stored at that pair's key position and
@@ -24,6 +27,7 @@ namespace gi {
 namespace {
 
 constexpr int CHUNK = 32;
+constexpr int PARTS = 4;  // parts of a tile's list summed separately in the forward
 constexpr int BWD_T = 256;
 
 // ---- begin: the fused fit kernel and the device functions it calls ----
@@ -36,18 +40,23 @@ __device__ inline float pair_add(float v) {
 }
 
 // One Gaussian's contribution to the PX pixels of this lane (A = mu_x, mu_y, a, b;
-// B = k, c0, c1, c2).
+// B = k, c0, c1, c2).  The lane's pixels lie in one column and in one group of four rows
+// starting at row centre py0; pixel j sits of[j] rows below it.  Every pixel's u2 is taken from
+// the group's first row as fl(o b + u2(py0)) (o b is exact in the FMA), whatever PX is, so the
+// forward gives the same bits for every PX; with PX = 4 the four rows share dx, u1, u1^2, k dx
+// and u2(py0).
 template <int PX>
-__device__ inline void fwd_eval(const float4 A, const float4 B, float px, const float (&py)[PX],
-                                float (&part)[PX][3]) {
+__device__ inline void fwd_eval(const float4 A, const float4 B, float px, float py0,
+                                const float (&of)[PX], float (&part)[PX][3]) {
     const float dx = px - A.x;
     const float u1 = A.z * dx;
     const float u1s = u1 * u1;
     const float t = B.x * dx;
+    const float u2b = fmaf(py0 - A.y, A.w, -t);
 #pragma unroll
     for (int j = 0; j < PX; ++j) {
-        const float dy = py[j] - A.y;
-        const float u2 = fmaf(dy, A.w, -t);
+        const float u2 = PX == 4 ? (j == 0 ? u2b : fmaf((float)j, A.w, u2b))
+                                 : fmaf(of[j], A.w, u2b);
         const float e = ex2(-fmaf(u2, u2, u1s));
         part[j][0] = fmaf(B.y, e, part[j][0]);
         part[j][1] = fmaf(B.z, e, part[j][1]);
@@ -55,15 +64,16 @@ __device__ inline void fwd_eval(const float4 A, const float4 B, float px, const 
     }
 }
 
-// Forward accumulation for the PX pixels (one column) of this thread.  Records are read in
+// Forward accumulation for the PX pixels (one column) of this thread over the list range r.  Records are read in
 // groups of four through the scalar unit into two register sets used in turn: the next group is
 // requested before the current one is evaluated, so its latency overlaps the arithmetic.
 // Scalar loads complete out of order and can only be awaited together, so each half-step first
 // waits for everything (only the group about to be used is outstanding then) and only then
 // issues the next request.  Partial sums are folded into the totals every 32 Gaussians.
 template <int PX>
-__device__ inline void fwd_tile(const float4 *__restrict__ rec, uint2 r, float px,
-                                const float (&py)[PX], float (&acc)[PX][3]) {
+__device__ __forceinline__ void fwd_tile(const float4 *__restrict__ rec, uint2 r, float px,
+                                         float py0, const float (&of)[PX],
+                                         float (&acc)[PX][3]) {
     float part[PX][3];
 #pragma unroll
     for (int j = 0; j < PX; ++j) {
@@ -95,7 +105,7 @@ __device__ inline void fwd_tile(const float4 *__restrict__ rec, uint2 r, float p
             for (int k = 0; k < 8; ++k) gb[k] = rec[2 * (int64_t)(i + 4) + k];
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) fwd_eval<PX>(ga[2 * k], ga[2 * k + 1], px, py, part);
+        for (int k = 0; k < 4; ++k) fwd_eval<PX>(ga[2 * k], ga[2 * k + 1], px, py0, of, part);
         i += 4;
         fold();
         if (++g >= ng) break;
@@ -105,12 +115,12 @@ __device__ inline void fwd_tile(const float4 *__restrict__ rec, uint2 r, float p
             for (int k = 0; k < 8; ++k) ga[k] = rec[2 * (int64_t)(i + 4) + k];
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) fwd_eval<PX>(gb[2 * k], gb[2 * k + 1], px, py, part);
+        for (int k = 0; k < 4; ++k) fwd_eval<PX>(gb[2 * k], gb[2 * k + 1], px, py0, of, part);
         i += 4;
         fold();
         ++g;
     }
-    for (; i < r.y; ++i) fwd_eval<PX>(rec[2 * (int64_t)i], rec[2 * (int64_t)i + 1], px, py, part);
+    for (; i < r.y; ++i) fwd_eval<PX>(rec[2 * (int64_t)i], rec[2 * (int64_t)i + 1], px, py0, of, part);
 #pragma unroll
     for (int j = 0; j < PX; ++j) {
         acc[j][0] += part[j][0];
@@ -189,30 +199,74 @@ __device__ inline void bwd_tile(const float4 *__restrict__ rec, const uint32_t *
     }
 }
 
+// Part q of a tile's list: [r.x + floor(q L / PARTS), r.x + floor((q + 1) L / PARTS)).
+__device__ inline uint2 list_part(uint2 r, int q) {
+    const uint64_t L = r.y - r.x;
+    return make_uint2(r.x + (uint32_t)(L * (uint64_t)q / PARTS),
+                      r.x + (uint32_t)(L * (uint64_t)(q + 1) / PARTS));
+}
+
+// Part sums of the tile's pixels into qs[PARTS][3][TILE_PX].  PX groups of 256 / PX threads
+// (whole waves) each take PARTS / PX parts in turn; lane l of a group owns the PX consecutive
+// rows from (l >> 4) PX on of column l & 15.
 template <int PX>
-__global__ __launch_bounds__(256 / PX) void k_raster_fwd(const float4 *__restrict__ rec,
+__device__ __forceinline__ void fwd_parts(const float4 *__restrict__ rec, uint2 r,
+                                          const TileInfo &ti, float *qs) {
+    constexpr int GROUP = 256 / PX, PER = PARTS / PX;
+    static_assert(GROUP % 64 == 0 && PARTS % PX == 0 && PX <= 4, "groups are whole waves");
+    const int grp = __builtin_amdgcn_readfirstlane((int)threadIdx.x / GROUP);
+    const int lt = (int)threadIdx.x % GROUP;
+    const int col = lt & 15, first = (lt >> 4) * PX;
+    const float px = (float)(ti.tx * TILE + col) + 0.5f;
+    const float py0 = (float)(ti.ty * TILE + (first & ~3)) + 0.5f;
+    float of[PX];
+#pragma unroll
+    for (int j = 0; j < PX; ++j) of[j] = (float)((first & 3) + j);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int q = grp * PER + k;
+        float acc[PX][3];
+        fwd_tile<PX>(rec, list_part(r, q), px, py0, of, acc);
+#pragma unroll
+        for (int j = 0; j < PX; ++j) {
+            const int p = (first + j) * TILE + col;
+            qs[(q * 3) * TILE_PX + p] = acc[j][0];
+            qs[(q * 3 + 1) * TILE_PX + p] = acc[j][1];
+            qs[(q * 3 + 2) * TILE_PX + p] = acc[j][2];
+        }
+    }
+}
+
+// Colour of pixel p from the part sums (after a barrier), added in part order.
+__device__ inline float3 fwd_colour(const float *qs, int p) {
+    float c[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float v = qs[ch * TILE_PX + p];
+#pragma unroll
+        for (int q = 1; q < PARTS; ++q) v += qs[(q * 3 + ch) * TILE_PX + p];
+        c[ch] = v;
+    }
+    return make_float3(c[0], c[1], c[2]);
+}
+
+template <int PX>
+__global__ __launch_bounds__(256) void k_raster_fwd(const float4 *__restrict__ rec,
                                                          const uint2 *__restrict__ ranges,
                                                          ImgTable tab, float *__restrict__ image) {
-    constexpr int ROWS = TILE / PX;
+    __shared__ float qs[PARTS * 3 * TILE_PX];
     const uint32_t tile = blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
-    const int col = threadIdx.x & 15, row = threadIdx.x >> 4;
-    const int x = ti.tx * TILE + col;
-    const float px = (float)x + 0.5f;
-    float py[PX];
-#pragma unroll
-    for (int j = 0; j < PX; ++j) py[j] = (float)(ti.ty * TILE + row + j * ROWS) + 0.5f;
-    float acc[PX][3];
-    fwd_tile<PX>(rec, ranges[tile], px, py, acc);
-#pragma unroll
-    for (int j = 0; j < PX; ++j) {
-        const int y = ti.ty * TILE + row + j * ROWS;
-        if (x < ti.W && y < ti.H) {
-            const unsigned long long idx = (ti.pix_base + (unsigned long long)y * ti.W + x) * 3ull;
-            image[idx] = acc[j][0];
-            image[idx + 1] = acc[j][1];
-            image[idx + 2] = acc[j][2];
-        }
+    fwd_parts<PX>(rec, ranges[tile], ti, qs);
+    __syncthreads();
+    const int p = threadIdx.x;
+    const int x = ti.tx * TILE + (p & 15), y = ti.ty * TILE + (p >> 4);
+    if (x < ti.W && y < ti.H) {
+        const float3 c = fwd_colour(qs, p);
+        const unsigned long long idx = (ti.pix_base + (unsigned long long)y * ti.W + x) * 3ull;
+        image[idx] = c.x;
+        image[idx + 1] = c.y;
+        image[idx + 2] = c.z;
     }
 }
 
@@ -240,7 +294,7 @@ __global__ __launch_bounds__(BWD_T) void k_raster_bwd(const float4 *__restrict__
 // Fit step for one tile: forward, residual and dL/dC = 2 (C - T) / (3 H W) into LDS, per-tile
 // sum of squared residuals, then the adjoint.
 template <int PX>
-__global__ __launch_bounds__(256 / PX) void k_raster_fit(const float4 *__restrict__ rec,
+__global__ __launch_bounds__(256) void k_raster_fit(const float4 *__restrict__ rec,
                                                          const uint32_t *__restrict__ slot,
                                                          const uint2 *__restrict__ ranges,
                                                          ImgTable tab,
@@ -249,41 +303,36 @@ __global__ __launch_bounds__(256 / PX) void k_raster_fit(const float4 *__restric
                                                          float *__restrict__ image_out,
                                                          float *__restrict__ loss_part,
                                                          int32_t *__restrict__ step_inc) {
-    constexpr int NT = 256 / PX;
-    constexpr int ROWS = TILE / PX;
+    constexpr int NT = 256;
+    __shared__ float qs[PARTS * 3 * TILE_PX];
     __shared__ float4 sg[TILE_PX];
     __shared__ float red[NT / 64];
     const uint32_t tile = blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     const uint2 r = ranges[tile];
-    const int col = threadIdx.x & 15, row = threadIdx.x >> 4;
-    const int x = ti.tx * TILE + col;
-    const float px = (float)x + 0.5f;
-    float py[PX];
-#pragma unroll
-    for (int j = 0; j < PX; ++j) py[j] = (float)(ti.ty * TILE + row + j * ROWS) + 0.5f;
-    float acc[PX][3];
-    fwd_tile<PX>(rec, r, px, py, acc);
+    fwd_parts<PX>(rec, r, ti, qs);
+    __syncthreads();
     const float scale = 2.0f / (3.0f * (float)ti.H * (float)ti.W);
     float sq = 0.f;
-#pragma unroll
-    for (int j = 0; j < PX; ++j) {
-        const int y = ti.ty * TILE + row + j * ROWS;
+    {
+        const int p = threadIdx.x;
+        const int x = ti.tx * TILE + (p & 15), y = ti.ty * TILE + (p >> 4);
         float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
         if (x < ti.W && y < ti.H) {
+            const float3 c = fwd_colour(qs, p);
             const unsigned long long idx = (ti.pix_base + (unsigned long long)y * ti.W + x) * 3ull;
-            const float r0 = acc[j][0] - target[idx];
-            const float r1 = acc[j][1] - target[idx + 1];
-            const float r2 = acc[j][2] - target[idx + 2];
+            const float r0 = c.x - target[idx];
+            const float r1 = c.y - target[idx + 1];
+            const float r2 = c.z - target[idx + 2];
             sq = fmaf(r0, r0, fmaf(r1, r1, fmaf(r2, r2, sq)));
             g = make_float4(scale * r0, scale * r1, scale * r2, 0.f);
             if (image_out) {
-                image_out[idx] = acc[j][0];
-                image_out[idx + 1] = acc[j][1];
-                image_out[idx + 2] = acc[j][2];
+                image_out[idx] = c.x;
+                image_out[idx + 1] = c.y;
+                image_out[idx + 2] = c.z;
             }
         }
-        sg[(row + j * ROWS) * TILE + col] = g;
+        sg[p] = g;
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) sq += __shfl_xor(sq, d, 64);
@@ -1061,8 +1110,8 @@ hipError_t launch_raster_fwd(const RasterArgs &a, float *image, int px, hipStrea
     const float4 *rec = reinterpret_cast<const float4 *>(a.rec);
     switch (px) {
         case 1: hipLaunchKernelGGL(k_raster_fwd<1>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image); break;
-        case 4: hipLaunchKernelGGL(k_raster_fwd<4>, dim3((unsigned)a.n_tiles), dim3(64), 0, s, rec, a.ranges, a.tab, image); break;
-        default: hipLaunchKernelGGL(k_raster_fwd<2>, dim3((unsigned)a.n_tiles), dim3(128), 0, s, rec, a.ranges, a.tab, image); break;
+        case 4: hipLaunchKernelGGL(k_raster_fwd<4>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image); break;
+        default: hipLaunchKernelGGL(k_raster_fwd<2>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image); break;
     }
     return hipGetLastError();
 }
@@ -1083,8 +1132,8 @@ hipError_t launch_raster_fit(const RasterArgs &a, const float *target, float *pa
     float4 *p4 = reinterpret_cast<float4 *>(part);
     switch (px) {
         case 1: hipLaunchKernelGGL(k_raster_fit<1>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc); break;
-        case 4: hipLaunchKernelGGL(k_raster_fit<4>, dim3((unsigned)a.n_tiles), dim3(64), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc); break;
-        default: hipLaunchKernelGGL(k_raster_fit<2>, dim3((unsigned)a.n_tiles), dim3(128), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc); break;
+        case 4: hipLaunchKernelGGL(k_raster_fit<4>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc); break;
+        default: hipLaunchKernelGGL(k_raster_fit<2>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc); break;
     }
     return hipGetLastError();
 }
