@@ -673,10 +673,22 @@ __global__ __launch_bounds__(CS_T) void k_chained_scan(uint32_t *__restrict__ da
     const uint32_t w = blockIdx.x;
     const unsigned long long tag = (unsigned long long)(state->scan_epoch & 0x1fffffffu) << CS_EPOCH_SHIFT;
     const int64_t base = (int64_t)w * CS_TILE;
+    {
+        // all loads first, then the LDS stores: a load per guarded step would be awaited before
+        // the next one is issued
+        uint32_t x[CS_IPT];
+        if (base + CS_TILE <= L) {
 #pragma unroll
-    for (int j = 0; j < CS_IPT; ++j) {
-        const int64_t idx = base + j * CS_T + threadIdx.x;
-        stage[spad(j * CS_T + threadIdx.x)] = idx < L ? data[idx] : 0u;
+            for (int j = 0; j < CS_IPT; ++j) x[j] = data[base + j * CS_T + threadIdx.x];
+        } else {
+#pragma unroll
+            for (int j = 0; j < CS_IPT; ++j) {
+                const int64_t idx = base + j * CS_T + threadIdx.x;
+                x[j] = idx < L ? data[idx] : 0u;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < CS_IPT; ++j) stage[spad(j * CS_T + threadIdx.x)] = x[j];
     }
     __syncthreads();
     uint32_t v[CS_IPT];
@@ -787,24 +799,45 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
     const uint32_t chunk = xcd_chunk(blockIdx.x, (uint32_t)nchunk);
     const bool own = threadIdx.x < FB;
     const int64_t i = (int64_t)chunk * FB + threadIdx.x;  // this thread's Gaussian when own
-    const uint32_t c = own && i < n ? count[i] : 0u;
+    const bool mine = own && i < n;
+    // Every global read of the set-up is issued before any of them is used (a read under a
+    // branch, or in a guarded loop, would be awaited before the next is issued): lanes without
+    // a Gaussian or a tile read a valid entry and drop it.
+    const int64_t ir = mine ? i : 0;
+    const uint32_t c_in = count[ir];
     const uint32_t K = scan[n];  // exclusive prefix after all Gaussian counts = key total
+    const int4 rc_in = rect[ir];
+    const uint2 inf_in = tinfo[ir];
+    const uint32_t off_in = scan[ir];
+    const float4 pa_in = proj[2 * ir], pb_in = proj[2 * ir + 1];
+    constexpr int TB_MAX = (int)((FUSED_MAX_TILES + NT - 1) / NT);
+    uint32_t tb_in[TB_MAX];
+#pragma unroll
+    for (int k = 0; k < TB_MAX; ++k) {
+        const int t = (int)threadIdx.x + k * NT;
+        tb_in[k] = scan[n + (int64_t)(t < T ? t : T - 1) * nchunk + chunk];
+    }
+    const uint32_t c = mine ? c_in : 0u;
     unsigned long long tot;
     const unsigned long long loc = block_exclusive_scan<unsigned long long, NT>(c, tmp, &tot);
     if (own) pre[threadIdx.x] = (uint32_t)loc;
     const bool table = tot <= OWN_CAP;  // same for the whole block
     if (table)
         for (uint32_t k = 0; k < c; ++k) owner[loc + k] = (uint8_t)threadIdx.x;
-    if (own && i < n) {
-        srect[threadIdx.x] = rect[i];
-        sinfo[threadIdx.x] = tinfo[i];
-        soff[threadIdx.x] = scan[i];
-        sproj[2 * threadIdx.x] = proj[2 * i];
-        sproj[2 * threadIdx.x + 1] = proj[2 * i + 1];
+    if (mine) {
+        srect[threadIdx.x] = rc_in;
+        sinfo[threadIdx.x] = inf_in;
+        soff[threadIdx.x] = off_in;
+        sproj[2 * threadIdx.x] = pa_in;
+        sproj[2 * threadIdx.x + 1] = pb_in;
     }
     for (int k = threadIdx.x; k < FUSED_WAVES * T; k += NT) wh[k] = 0u;
     // first position of this chunk's keys of each tile, in tile order
-    for (int t = threadIdx.x; t < T; t += NT) tbase[t] = scan[n + (int64_t)t * nchunk + chunk] - K;
+#pragma unroll
+    for (int k = 0; k < TB_MAX; ++k) {
+        const int t = (int)threadIdx.x + k * NT;
+        if (t < T) tbase[t] = tb_in[k] - K;
+    }
     // tile ranges: this chunk writes tiles chunk, chunk + nchunk, ...
     for (int64_t t = chunk + (int64_t)threadIdx.x * nchunk; t < T; t += (int64_t)NT * nchunk) {
         uint32_t a = scan[n + t * nchunk] - K;

@@ -652,11 +652,29 @@ __device__ inline void quad_grad(const float4 *__restrict__ params, int64_t i, i
 #pragma unroll
     for (int k = 0; k < NS; ++k) S[k] = 0.f;
     if (cnt && (unsigned long long)o + cnt <= keys) {
-        for (uint32_t j = o + (uint32_t)q; j < o + cnt; j += 4) {
+        // two keys per step, both read before either is added (same order of additions)
+        const uint32_t end = o + cnt;
+        for (uint32_t j = o + (uint32_t)q; j < end; j += 8) {
+            const bool two = j + 4 < end;
+            const int64_t j2 = two ? j + 4 : j;
             const float4 a = part[NV * (int64_t)j], b = part[NV * (int64_t)j + 1];
+            const float4 a2 = part[NV * j2], b2 = part[NV * j2 + 1];
+            float x = 0.f, x2 = 0.f;
+            if constexpr (NV == 3) {
+                x = part[NV * (int64_t)j + 2].x;
+                x2 = part[NV * j2 + 2].x;
+            }
             S[0] += a.x; S[1] += a.y; S[2] += a.z; S[3] += a.w;
             S[4] += b.x; S[5] += b.y; S[6] += b.z; S[7] += b.w;
-            if constexpr (NV == 3) S[8] += part[NV * (int64_t)j + 2].x;
+            if constexpr (NV == 3) S[8] += x;
+            // the second key by a multiply with 1 or 0 (exact either way), not a branch that the
+            // compiler would sink the reads into
+            const float w2 = two ? 1.f : 0.f;
+            S[0] = fmaf(a2.x, w2, S[0]); S[1] = fmaf(a2.y, w2, S[1]);
+            S[2] = fmaf(a2.z, w2, S[2]); S[3] = fmaf(a2.w, w2, S[3]);
+            S[4] = fmaf(b2.x, w2, S[4]); S[5] = fmaf(b2.y, w2, S[5]);
+            S[6] = fmaf(b2.z, w2, S[6]); S[7] = fmaf(b2.w, w2, S[7]);
+            if constexpr (NV == 3) S[8] = fmaf(x2, w2, S[8]);
         }
     }
 #pragma unroll
@@ -792,14 +810,18 @@ __global__ __launch_bounds__(UPD_T) void k_adam(float4 *__restrict__ params, int
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * UPD_G + (threadIdx.x >> 2);
     const int q = threadIdx.x & 3;
-    // gradients incomplete on key overflow: leave the state alone
-    if (i >= n || (st->flags & FLAG_KEY_OVERFLOW)) return;
+    if (i >= n) return;
+    // the moments and the overflow flag are read along with the sums (the reads stay within
+    // the key buffers either way); gradients incomplete on key overflow: the state is left alone
+    const bool overflow = (st->flags & FLAG_KEY_OVERFLOW) != 0;
+    const float2 mo = m2[4 * i + q], vo = v2[4 * i + q];
     unsigned long long keys = st->keys_total;
     if (keys > (unsigned long long)cap) keys = (unsigned long long)cap;
     float g[8], so = 0.f;
     float4 q0, q1;
     quad_grad<COV, BLEND == BLEND_ALPHA ? 3 : 2>(params, i, q, count, off, part, keys, g, q0, q1,
                                                  BLEND == BLEND_ALPHA ? &so : nullptr);
+    if (overflow) return;
     float op = 0.f;
     if (BLEND != BLEND_NONE) op = opacity[i];
     if (BLEND == BLEND_SUM) {
@@ -810,7 +832,6 @@ __global__ __launch_bounds__(UPD_T) void k_adam(float4 *__restrict__ params, int
     }
     const float pv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
     const float bc1 = s_bc[0], bc2 = s_bc[1];
-    const float2 mo = m2[4 * i + q], vo = v2[4 * i + q];
     float p[2] = {pv[2 * q], pv[2 * q + 1]};
     float m[2] = {mo.x, mo.y}, v[2] = {vo.x, vo.y};
 #pragma unroll
