@@ -160,22 +160,25 @@ __device__ inline void bwd_tile(const float4 *__restrict__ rec, const uint32_t *
             const float u1 = A.z * dx;
             const float u1s = u1 * u1;
             const float t = B.x * dx;
-            float Wc = 0.f, WU2 = 0.f, WU22 = 0.f;
+            float D0 = 0.f, D1 = 0.f, D2 = 0.f, WU2 = 0.f, WU22 = 0.f;
 #pragma unroll
             for (int rr = 0; rr < TILE; ++rr) {
                 const float4 g = sg[rr * TILE + cc];
                 const float u2 = fmaf(dy[rr], A.w, -t);
                 const float e = ex2(-fmaf(u2, u2, u1s));
-                C0 = fmaf(g.x, e, C0);
-                C1 = fmaf(g.y, e, C1);
-                C2 = fmaf(g.z, e, C2);
+                D0 = fmaf(g.x, e, D0);
+                D1 = fmaf(g.y, e, D1);
+                D2 = fmaf(g.z, e, D2);
                 const float gc = fmaf(g.z, B.w, fmaf(g.y, B.z, g.x * B.y));
-                const float w = e * gc;  // -dL/dsigma of this pixel
-                Wc += w;
-                const float wu2 = w * u2;
+                const float wu2 = (e * gc) * u2;  // -dL/dsigma of this pixel times u2
                 WU2 += wu2;
                 WU22 = fmaf(wu2, u2, WU22);
             }
+            // the column's sum of -dL/dsigma from its colour sums: sum_r e <g, c'> = <sum_r e g, c'>
+            const float Wc = fmaf(B.w, D2, fmaf(B.z, D1, B.y * D0));
+            C0 += D0;
+            C1 += D1;
+            C2 += D2;
             P1 = fmaf(u1, Wc, P1);
             Q11 = fmaf(u1s, Wc, Q11);
             Q12 = fmaf(u1, WU2, Q12);
