@@ -497,7 +497,8 @@ def main():
     fit_avg_s = fit_ms / fit_n / 1e3
     achieved = OPS_PER_PAIR_FIT * P_prof / fit_avg_s
 
-    # ---- render FPS: eager non-waiting renders of the initial parameters
+    # ---- render FPS: eager non-waiting renders of the initial parameters, no stage timing
+    ctx.set_option(P._lib.GI_OPT_TIMING, 0)
     img = torch.empty(H, W, 3, device=dev)
     for _ in range(10):
         ctx.render(params0, H, W, out=img)
@@ -508,7 +509,6 @@ def main():
         ctx.render(params0, H, W, out=img)
     torch.cuda.synchronize()
     fps = n_render / (time.perf_counter() - t0)
-    ctx.set_option(P._lib.GI_OPT_TIMING, 0)
     ctx.set_option(P._lib.GI_OPT_SYNC, 1)
     rs = None if args.no_rs else rotation_scale_leg(P, torch, w, min(max(args.steps, 100), 300),
                                                      tuned)
