@@ -810,21 +810,27 @@ __global__ __launch_bounds__(UPD_T) void k_adam(float4 *__restrict__ params, int
         s_bc[0] = (float)(1.0 - pow((double)hp.beta1, t));
         s_bc[1] = (float)(1.0 - pow((double)hp.beta2, t));
     }
-    __syncthreads();
+    // The sums do not need the bias corrections: they are read while thread 0 forms them, and
+    // the barrier comes only before the update.
     const int64_t i = (int64_t)blockIdx.x * UPD_G + (threadIdx.x >> 2);
     const int q = threadIdx.x & 3;
-    if (i >= n) return;
     // the moments and the overflow flag are read along with the sums (the reads stay within
     // the key buffers either way); gradients incomplete on key overflow: the state is left alone
-    const bool overflow = (st->flags & FLAG_KEY_OVERFLOW) != 0;
-    const float2 mo = m2[4 * i + q], vo = v2[4 * i + q];
-    unsigned long long keys = st->keys_total;
-    if (keys > (unsigned long long)cap) keys = (unsigned long long)cap;
+    bool overflow = true;
+    float2 mo, vo;
     float g[8], so = 0.f;
     float4 q0, q1;
-    quad_grad<COV, BLEND == BLEND_ALPHA ? 3 : 2>(params, i, q, count, off, part, keys, g, q0, q1,
-                                                 BLEND == BLEND_ALPHA ? &so : nullptr);
-    if (overflow) return;
+    if (i < n) {
+        overflow = (st->flags & FLAG_KEY_OVERFLOW) != 0;
+        mo = m2[4 * i + q];
+        vo = v2[4 * i + q];
+        unsigned long long keys = st->keys_total;
+        if (keys > (unsigned long long)cap) keys = (unsigned long long)cap;
+        quad_grad<COV, BLEND == BLEND_ALPHA ? 3 : 2>(params, i, q, count, off, part, keys, g, q0,
+                                                     q1, BLEND == BLEND_ALPHA ? &so : nullptr);
+    }
+    __syncthreads();  // s_bc
+    if (i >= n || overflow) return;
     float op = 0.f;
     if (BLEND != BLEND_NONE) op = opacity[i];
     if (BLEND == BLEND_SUM) {
@@ -889,15 +895,27 @@ __global__ __launch_bounds__(UPD_T) void k_adan(float4 *__restrict__ raw, int64_
         s_c[2] = (float)(1.0 - pow((double)hp.beta3, (double)k));
         s_c[3] = (float)lr;
     }
-    __syncthreads();
+    // the sums and the state are read while thread 0 forms the constants (as in k_adam)
     const int64_t i = (int64_t)blockIdx.x * UPD_G + (threadIdx.x >> 2);
     const int q = threadIdx.x & 3;
-    if (i >= n || (st->flags & FLAG_KEY_OVERFLOW)) return;
-    unsigned long long keys = st->keys_total;
-    if (keys > (unsigned long long)cap) keys = (unsigned long long)cap;
+    const int64_t stride = 4 * n;  // float2 entries per state array
+    float2 *m2 = state, *v2 = state + stride, *n2 = state + 2 * stride, *p2 = state + 3 * stride;
+    bool overflow = true;
     float g[8];
     float4 q0, q1;
-    quad_grad<COV, 2, true>(raw, i, q, count, off, part, keys, g, q0, q1);
+    float2 mo, vo, no, go;
+    if (i < n) {
+        overflow = (st->flags & FLAG_KEY_OVERFLOW) != 0;
+        mo = m2[4 * i + q];
+        vo = v2[4 * i + q];
+        no = n2[4 * i + q];
+        go = p2[4 * i + q];
+        unsigned long long keys = st->keys_total;
+        if (keys > (unsigned long long)cap) keys = (unsigned long long)cap;
+        quad_grad<COV, 2, true>(raw, i, q, count, off, part, keys, g, q0, q1);
+    }
+    __syncthreads();  // s_c
+    if (i >= n || overflow) return;
     int32_t H = tab.H, W = tab.W;
     if (tab.B > 1) {
         const int4 d = tab.dims[upper_index(tab.gauss_off, tab.B, (uint32_t)i)];
@@ -908,9 +926,6 @@ __global__ __launch_bounds__(UPD_T) void k_adan(float4 *__restrict__ raw, int64_
     g[0] *= 0.5f * (float)W * (1.f - tx * tx);
     g[1] *= 0.5f * (float)H * (1.f - ty * ty);
     const float pv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-    const int64_t stride = 4 * n;  // float2 entries per state array
-    float2 *m2 = state, *v2 = state + stride, *n2 = state + 2 * stride, *p2 = state + 3 * stride;
-    const float2 mo = m2[4 * i + q], vo = v2[4 * i + q], no = n2[4 * i + q], go = p2[4 * i + q];
     const float bc1 = s_c[0], bc2 = s_c[1], bc3 = s_c[2], lr = s_c[3];
     float p[2] = {pv[2 * q], pv[2 * q + 1]};
     float m[2] = {mo.x, mo.y}, v[2] = {vo.x, vo.y}, nn[2] = {no.x, no.y};
