@@ -766,6 +766,11 @@ __global__ __launch_bounds__(CS_T) void k_chained_scan(uint32_t *__restrict__ da
 }
 
 // Lanes of the wave whose tile equals this lane's, deciding `nbits` bits.
+// v of the neighbouring lane (lane ^ 1), by a DPP quad permutation [1, 0, 3, 2].
+__device__ inline int dpp_swap_pair(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0xb1, 0xf, 0xf, false);
+}
+
 __device__ inline unsigned long long match_bits(uint32_t d, bool valid, int nbits) {
     unsigned long long peers = __ballot(valid);
     for (int b = 0; b < nbits; ++b) {
@@ -919,17 +924,30 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
         const unsigned long long lt = (1ull << lane) - 1ull;
         const uint32_t old = valid ? my[t] : 0u;
         if (valid && lane == __ffsll((long long)peers) - 1) my[t] = old + __popcll(peers);
-        if (valid) {
-            const uint32_t pos = old + __popcll(peers & lt);
-            if (pos < cap) {
-                rec[2 * (int64_t)pos] = sproj[2 * g];
-                rec[2 * (int64_t)pos + 1] = sproj[2 * g + 1];
-                slot[pos] = soff[g] + li;
-                if (ids) ids[pos] = chunk * FB + (uint32_t)g;
-                if (rec_o) rec_o[pos] = opac[(int64_t)chunk * FB + g];
-            } else {
-                overflow = true;
-            }
+        const uint32_t pos = old + __popcll(peers & lt);
+        const bool ok = valid && pos < cap;
+        if (valid && !ok) overflow = true;
+        if (ok) {
+            slot[pos] = soff[g] + li;
+            if (ids) ids[pos] = chunk * FB + (uint32_t)g;
+            if (rec_o) rec_o[pos] = opac[(int64_t)chunk * FB + g];
+        }
+        // The 32-byte records go out two lanes per record: lanes 2m and 2m + 1 write the two
+        // halves of lane 2m's record, then of lane 2m + 1's, so each store touches 32 records
+        // instead of 64 (the partner's key comes over by a DPP swap of neighbouring lanes).
+        const bool odd = lane & 1;
+        const int pg = dpp_swap_pair(g);
+        const uint32_t ppos = (uint32_t)dpp_swap_pair((int)pos);
+        const bool pok = dpp_swap_pair(ok ? 1 : 0) != 0;
+        {
+            const int gg = odd ? pg : g;
+            const uint32_t pp = odd ? ppos : pos;
+            if (odd ? pok : ok) rec[2 * (int64_t)pp + odd] = sproj[2 * gg + odd];
+        }
+        {
+            const int gg = odd ? g : pg;
+            const uint32_t pp = odd ? pos : ppos;
+            if (odd ? ok : pok) rec[2 * (int64_t)pp + !odd] = sproj[2 * gg + !odd];
         }
     }
     if (__ballot(overflow) && lane == 0) atomicOr(&state->flags, FLAG_KEY_OVERFLOW);
