@@ -358,6 +358,40 @@ def test_graph_replay_matches_eager_steps(gi):
     assert int(host(sb)[0]) == 5
 
 
+def test_graph_launch_starts_from_the_parameters_as_they_are(gi):
+    # every launch of a captured step bins the parameters as they are then, so parameters
+    # changed between launches are the ones fitted
+    w = synth.plain_256()
+    p0, T = w.params(), dev(w.target())
+    pa, pb = dev(p0), dev(p0)
+    ma, va, mb, vb = (torch.zeros_like(pa) for _ in range(4))
+    sa = torch.ones(1, dtype=torch.int32, device="cuda")
+    sb = torch.ones(1, dtype=torch.int32, device="cuda")
+    import paper_2403_08551_amd as P
+    g = P.Context(0)
+    graph = g.fit_graph(pb, mb, vb, T, sb)
+    try:
+        graph.launch(2)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            gi.fit_step(pa, ma, va, T, sa)
+        torch.cuda.synchronize()
+        for p in (pa, pb):  # every Gaussian one pixel to the right, half a pixel up
+            p[:, 0] += 1.0
+            p[:, 1] -= 0.5
+        torch.cuda.synchronize()
+        graph.launch(3)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            gi.fit_step(pa, ma, va, T, sa)
+        assert graph.query()[1] == 0
+    finally:
+        graph.close()
+        g.close()
+    np.testing.assert_array_equal(host(pb), host(pa))
+    assert int(host(sb)[0]) == 6
+
+
 # ------------------------------------------------------------------ flags and edge cases
 
 def test_nonfinite_flag(gi):
