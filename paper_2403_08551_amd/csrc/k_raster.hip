@@ -13,10 +13,10 @@
 // into four equal parts; each part is summed by one group of 256 / PX threads, each lane owning
 // PX pixels of one column (so per-column terms are shared by PX pixels), the part's records read
 // in sorted order through the scalar unit (every lane uses the same Gaussian at once), colour
-// accumulated in float32 registers with a two-level sum (partial sums per chunk of 32
-// Gaussians).  The four part sums meet in LDS and are added in part order, so every PX gives
-// the same bits.  Adjoint: one Gaussian per lane, the
-// tile's 256 dL/dC values staged in LDS and read as broadcasts, so each lane reduces its own
+// accumulated in float32 registers with a two-level sum (partial sums of 8 Gaussians).  The
+// four part sums meet in LDS and are added in part order, so every PX gives the same bits.
+// Adjoint: one Gaussian per lane, the tile's 256 dL/dC values staged in LDS and read as
+// broadcasts, so each lane reduces its own
 // Gaussian over the tile's pixels in registers: no cross-lane reduction and no atomics.  The
 // eight partial sums of each (tile, Gaussian) pair are stored at that pair's key position and
 // the per-Gaussian kernel adds them in a fixed order, which keeps gradients deterministic.
@@ -26,7 +26,6 @@ namespace gi {
 
 namespace {
 
-constexpr int CHUNK = 32;
 constexpr int PARTS = 4;  // parts of a tile's list summed separately in the forward
 constexpr int BWD_T = 256;
 
@@ -45,7 +44,7 @@ __device__ inline float pair_add(float v) {
 // the group's first row as fl(o b + u2(py0)) (o b is exact in the FMA), whatever PX is, so the
 // forward gives the same bits for every PX; with PX = 4 the four rows share dx, u1, u1^2, k dx
 // and u2(py0).
-template <int PX>
+template <int PX, bool INIT = false>
 __device__ inline void fwd_eval(const float4 A, const float4 B, float px, float py0,
                                 const float (&of)[PX], float (&part)[PX][3]) {
     const float dx = px - A.x;
@@ -58,42 +57,44 @@ __device__ inline void fwd_eval(const float4 A, const float4 B, float px, float 
         const float u2 = PX == 4 ? (j == 0 ? u2b : fmaf((float)j, A.w, u2b))
                                  : fmaf(of[j], A.w, u2b);
         const float e = ex2(-fmaf(u2, u2, u1s));
-        part[j][0] = fmaf(B.y, e, part[j][0]);
-        part[j][1] = fmaf(B.z, e, part[j][1]);
-        part[j][2] = fmaf(B.w, e, part[j][2]);
+        if (INIT) {  // the first record of a partial sum sets it
+            part[j][0] = B.y * e;
+            part[j][1] = B.z * e;
+            part[j][2] = B.w * e;
+        } else {
+            part[j][0] = fmaf(B.y, e, part[j][0]);
+            part[j][1] = fmaf(B.z, e, part[j][1]);
+            part[j][2] = fmaf(B.w, e, part[j][2]);
+        }
     }
 }
 
-// Forward accumulation for the PX pixels (one column) of this thread over the list range r.  Records are read in
-// groups of four through the scalar unit into two register sets used in turn: the next group is
-// requested before the current one is evaluated, so its latency overlaps the arithmetic.
-// Scalar loads complete out of order and can only be awaited together, so each half-step first
-// waits for everything (only the group about to be used is outstanding then) and only then
-// issues the next request.  Partial sums are folded into the totals every 32 Gaussians.
+// Forward accumulation for the PX pixels (one column) of this thread over the list range r.
+// Records are read in groups of four through the scalar unit into two register sets used in
+// turn: the next group is requested before the current one is evaluated, so its latency
+// overlaps the arithmetic.  Scalar loads complete out of order and can only be awaited
+// together, so each half-step first waits for everything (only the group about to be used is
+// outstanding then) and only then issues the next request.  Two-level sum: each loop step's
+// eight records form a partial sum (set by its first record), added to the totals at the end
+// of the step; records after the last whole group form one more partial sum.
 template <int PX>
 __device__ __forceinline__ void fwd_tile(const float4 *__restrict__ rec, uint2 r, float px,
                                          float py0, const float (&of)[PX],
                                          float (&acc)[PX][3]) {
     float part[PX][3];
 #pragma unroll
-    for (int j = 0; j < PX; ++j) {
-        acc[j][0] = acc[j][1] = acc[j][2] = 0.f;
-        part[j][0] = part[j][1] = part[j][2] = 0.f;
-    }
+    for (int j = 0; j < PX; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.f;
+    auto fold = [&]() {
+#pragma unroll
+        for (int j = 0; j < PX; ++j) {
+            acc[j][0] += part[j][0];
+            acc[j][1] += part[j][1];
+            acc[j][2] += part[j][2];
+        }
+    };
     const uint32_t ng = (r.y - r.x) / 4;
     uint32_t i = r.x;
     float4 ga[8], gb[8];
-    auto fold = [&]() {
-        if (((i - r.x) & (CHUNK - 1)) == 0) {
-#pragma unroll
-            for (int j = 0; j < PX; ++j) {
-                acc[j][0] += part[j][0];
-                acc[j][1] += part[j][1];
-                acc[j][2] += part[j][2];
-                part[j][0] = part[j][1] = part[j][2] = 0.f;
-            }
-        }
-    };
     if (ng) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) ga[k] = rec[2 * (int64_t)i + k];
@@ -104,11 +105,14 @@ __device__ __forceinline__ void fwd_tile(const float4 *__restrict__ rec, uint2 r
 #pragma unroll
             for (int k = 0; k < 8; ++k) gb[k] = rec[2 * (int64_t)(i + 4) + k];
         }
+        fwd_eval<PX, true>(ga[0], ga[1], px, py0, of, part);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) fwd_eval<PX>(ga[2 * k], ga[2 * k + 1], px, py0, of, part);
+        for (int k = 1; k < 4; ++k) fwd_eval<PX>(ga[2 * k], ga[2 * k + 1], px, py0, of, part);
         i += 4;
-        fold();
-        if (++g >= ng) break;
+        if (++g >= ng) {
+            fold();
+            break;
+        }
         __builtin_amdgcn_s_waitcnt(0xc07f);  // group g is in gb
         if (g + 1 < ng) {
 #pragma unroll
@@ -117,15 +121,14 @@ __device__ __forceinline__ void fwd_tile(const float4 *__restrict__ rec, uint2 r
 #pragma unroll
         for (int k = 0; k < 4; ++k) fwd_eval<PX>(gb[2 * k], gb[2 * k + 1], px, py0, of, part);
         i += 4;
-        fold();
         ++g;
+        fold();
     }
-    for (; i < r.y; ++i) fwd_eval<PX>(rec[2 * (int64_t)i], rec[2 * (int64_t)i + 1], px, py0, of, part);
-#pragma unroll
-    for (int j = 0; j < PX; ++j) {
-        acc[j][0] += part[j][0];
-        acc[j][1] += part[j][1];
-        acc[j][2] += part[j][2];
+    if (i < r.y) {
+        fwd_eval<PX, true>(rec[2 * (int64_t)i], rec[2 * (int64_t)i + 1], px, py0, of, part);
+        for (++i; i < r.y; ++i)
+            fwd_eval<PX>(rec[2 * (int64_t)i], rec[2 * (int64_t)i + 1], px, py0, of, part);
+        fold();
     }
 }
 
