@@ -2,11 +2,14 @@
 //
 // Data layout in device memory (one context):
 //   params  [N][8]  f32   (mu_x, mu_y, l1, l2, l3, c0, c1, c2), caller owned
-//   proj    [N][8]  f32   (mu_x, mu_y, a, b, k, c0, c1, c2) with a = s/l1, b = s/l3,
-//                          k = s*l2/(l1*l3), s = sqrt(log2(e)/2): then u1 = a*dx and
-//                          u2 = b*dy - k*dx satisfy u1^2 + u2^2 = log2(e)*sigma, so that
-//                          exp(-sigma) = exp2(-(u1^2 + u2^2)) (Eq. rasterization2 through the
-//                          Cholesky factor: sigma = |L^{-1} d|^2 / 2)
+//   proj    [N][16] f32   one 64-byte line per Gaussian (radix path; the one-pass path packs
+//                          the 32-byte records at a stride of 8 floats): the record (mu_x, mu_y, a, b, k, c0,
+//                          c1, c2) with a = s/l1, b = s/l3, k = s*l2/(l1*l3), s =
+//                          sqrt(log2(e)/2): then u1 = a*dx and u2 = b*dy - k*dx satisfy
+//                          u1^2 + u2^2 = log2(e)*sigma, so that exp(-sigma) = exp2(-(u1^2 +
+//                          u2^2)) (Eq. rasterization2 through the Cholesky factor: sigma =
+//                          |L^{-1} d|^2 / 2); then u32 (key offset, image's first tile, tiles
+//                          across | rect width << 16, tx0 | ty0 << 16) and 4 unused words
 //   rect    [N]     int4  inclusive tile rectangle (tx0, ty0, tx1, ty1); (0, 0, -1, -1) if none
 //   tinfo   [N]     uint2 (first global tile id of the Gaussian's image, tiles across)
 //   count   [N]     u32   tiles covered;  off [N] u32 exclusive prefix sum of count
@@ -28,6 +31,10 @@ constexpr uint32_t FLAG_NONFINITE = 2u;
 constexpr uint32_t FLAG_SCAN_STALL = 4u;
 constexpr uint32_t FLAG_BAD_CODE = 8u;
 constexpr int64_t FUSED_MAX_TILES = 2048;
+// float4 words per projected Gaussian on the radix path: the rasteriser record (2), the slot
+// facts (1), padding to one 64-byte line (1), so that the gather after the sort reads one line
+// per key.  The one-pass path stores the record alone (2 words per Gaussian).
+constexpr int PROJ_F4 = 4;
 
 // sqrt(log2(e) / 2): scales L^{-1} d so that exp(-sigma) = exp2(-|u|^2)
 constexpr double U_SCALE = 0.84932180028801904272;
@@ -222,7 +229,6 @@ struct BinBuffers {
     unsigned long long *blocksum;  // [ceil(n/256)]
     uint32_t *keys[2];
     uint32_t *vals[2];
-    uint32_t *own;                  // [cap] Gaussian of each Gaussian-major key (radix path)
     uint32_t *ids_out;              // sorted Gaussian ids, when wanted (radix path), else null
     float *rec;
     uint32_t *slot;

@@ -48,7 +48,6 @@ struct gi_ctx {
     // per key
     uint32_t *keys[2] = {nullptr, nullptr};
     uint32_t *vals[2] = {nullptr, nullptr};
-    uint32_t *own = nullptr;            // [cap_k] Gaussian of each Gaussian-major key
     const uint32_t *ids_at = nullptr;   // sorted ids of the last gi_binning
     float *rec = nullptr;
     uint32_t *slot = nullptr;
@@ -191,7 +190,7 @@ int ensure_gauss(gi_ctx *ctx, int64_t n) {
     if (n <= ctx->cap_n) return GI_OK;
     const int64_t c = std::max<int64_t>(n, 1024);
     CK(hipDeviceSynchronize());
-    CK(grow(&ctx->proj, 8 * c));
+    CK(grow(&ctx->proj, 4 * PROJ_F4 * c));
     CK(grow(&ctx->rect, c));
     CK(grow(&ctx->tinfo, c));
     CK(grow(&ctx->count, c));
@@ -220,7 +219,6 @@ int ensure_keys(gi_ctx *ctx, int64_t k) {
         CK(grow(&ctx->keys[i], c));
         CK(grow(&ctx->vals[i], c));
     }
-    CK(grow(&ctx->own, c));
     CK(grow(&ctx->rec, 8 * c));
     CK(grow(&ctx->slot, c));
     CK(grow(&ctx->part, 8 * c));
@@ -387,7 +385,6 @@ BinBuffers bin_buffers(gi_ctx *ctx, const float *params, int64_t n, int64_t n_ti
     b.keys[1] = ctx->keys[1];
     b.vals[0] = ctx->vals[0];
     b.vals[1] = ctx->vals[1];
-    b.own = ctx->own;
     b.ids_out = nullptr;
     b.rec = ctx->rec;
     b.slot = ctx->slot;
@@ -780,7 +777,7 @@ int gi_destroy(gi_ctx *ctx) {
                     ctx->keys[0], ctx->keys[1], ctx->vals[0], ctx->vals[1], ctx->rec, ctx->slot,
                     ctx->part, ctx->hist, ctx->scan_bs, ctx->ranges, ctx->loss_part, ctx->state,
                     ctx->dims, ctx->tile_base, ctx->gauss_off, ctx->pix_off, ctx->tmp_k,
-                    ctx->tmp_v, ctx->fscan, ctx->fstatus, ctx->own, ctx->rec_o, ctx->part_a,
+                    ctx->tmp_v, ctx->fscan, ctx->fstatus, ctx->rec_o, ctx->part_a,
                     ctx->qpart, ctx->qscratch};
     for (void *p : bufs)
         if (p) (void)hipFree(p);

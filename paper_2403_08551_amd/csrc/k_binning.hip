@@ -124,7 +124,10 @@ __device__ inline bool load_record(const RecordSrc &src, int64_t i, float (&q)[8
 }
 
 // Projection and tile rectangle of Gaussian i (see the file header of k_raster.hip for the
-// stored record).  Writes proj, rect, tinfo and count; returns the count.
+// stored record).  Writes proj, rect, tinfo and count; returns the count.  FACTS (radix path):
+// one 64-byte line per Gaussian with the slot facts that the gather after the sort reads; else
+// (one-pass path) the 32-byte record alone, at a stride of 32 bytes.
+template <bool FACTS>
 __device__ inline uint32_t project_one(const RecordSrc &src, int64_t i,
                                        const ImgTable &tab, float4 *__restrict__ proj,
                                        int4 *__restrict__ rect, uint2 *__restrict__ tinfo,
@@ -213,8 +216,16 @@ __device__ inline uint32_t project_one(const RecordSrc &src, int64_t i,
         }
         p1 = make_float4((float)(U_SCALE * l2 / (l1 * l3)), q[5], q[6], q[7]);
     }
-    proj[2 * i] = p0;
-    proj[2 * i + 1] = p1;
+    constexpr int STRIDE = FACTS ? PROJ_F4 : 2;
+    proj[STRIDE * i] = p0;
+    proj[STRIDE * i + 1] = p1;
+    // the facts that turn a (tile, Gaussian) key into its slot: the key offset (written once the
+    // counts are scanned), the image's first tile and tiles per row, the rectangle's width and
+    // corner (all tile counts < 2^16)
+    if (FACTS)
+        proj[PROJ_F4 * i + 2] = __builtin_bit_cast(
+            float4, make_uint4(0u, tb, (uint32_t)TW | ((uint32_t)(rc.z - rc.x + 1) << 16),
+                               (uint32_t)rc.x | ((uint32_t)rc.y << 16)));
     rect[i] = rc;
     const uint2 inf = make_uint2(tb, (uint32_t)TW);
     tinfo[i] = inf;
@@ -238,7 +249,8 @@ __global__ __launch_bounds__(BLK) void k_project(const RecordSrc src, int64_t n,
     if (i < n) {
         int4 rc;
         uint2 inf;
-        cnt = project_one(src, i, tab, proj, rect, tinfo, count, &nonfinite, &bad, &rc, &inf);
+        cnt = project_one<true>(src, i, tab, proj, rect, tinfo, count, &nonfinite, &bad, &rc,
+                                &inf);
     }
     if (__ballot(nonfinite) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_NONFINITE);
     if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_BAD_CODE);
@@ -278,7 +290,7 @@ __global__ __launch_bounds__(BLK) void k_duplicate(const uint32_t *__restrict__ 
                                                    uint32_t *__restrict__ off,
                                                    uint32_t *__restrict__ keys,
                                                    uint32_t *__restrict__ vals,
-                                                   uint32_t *__restrict__ own,
+                                                   float4 *__restrict__ proj,
                                                    DevState *state) {
     __shared__ unsigned long long tmp[BLK / 64 + 1];
     __shared__ unsigned long long pre[BLK];
@@ -292,6 +304,7 @@ __global__ __launch_bounds__(BLK) void k_duplicate(const uint32_t *__restrict__ 
     pre[threadIdx.x] = loc;
     if (i < n) {
         off[i] = (uint32_t)(base + loc);
+        reinterpret_cast<uint32_t *>(proj)[4 * (PROJ_F4 * i + 2)] = (uint32_t)(base + loc);
         srect[threadIdx.x] = rect[i];
         sinfo[threadIdx.x] = tinfo[i];
     }
@@ -311,10 +324,10 @@ __global__ __launch_bounds__(BLK) void k_duplicate(const uint32_t *__restrict__ 
         const uint32_t li = (uint32_t)(j - pre[lo]);
         const uint32_t w = (uint32_t)(r.z - r.x + 1);
         const uint32_t tx = (uint32_t)r.x + li % w, ty = (uint32_t)r.y + li / w;
-        // the sort carries each key's own position (its slot); own[] maps it to the Gaussian
+        // the sort carries the Gaussian; its position in Gaussian-major order (the slot) is
+        // formed again after the sort from the projected record
         keys[base + j] = inf.x + ty * inf.y + tx;
-        vals[base + j] = (uint32_t)(base + j);
-        own[base + j] = (uint32_t)((int64_t)blockIdx.x * BLK + lo);
+        vals[base + j] = (uint32_t)((int64_t)blockIdx.x * BLK + lo);
     }
 }
 
@@ -546,7 +559,6 @@ __global__ __launch_bounds__(SORT_T) void k_radix_scatter(const uint32_t *__rest
 
 __global__ __launch_bounds__(BLK) void k_ranges_gather(const uint32_t *__restrict__ keys,
                                                        const uint32_t *__restrict__ vals,
-                                                       const uint32_t *__restrict__ own,
                                                        const unsigned long long *n_dev,
                                                        int64_t n_max,
                                                        const float4 *__restrict__ proj,
@@ -562,11 +574,16 @@ __global__ __launch_bounds__(BLK) void k_ranges_gather(const uint32_t *__restric
     const uint32_t key = keys[i];
     if (i == 0 || keys[i - 1] != key) ranges[key].x = (uint32_t)i;
     if (i == n - 1 || keys[i + 1] != key) ranges[key].y = (uint32_t)(i + 1);
-    const uint32_t sl = vals[i];  // the key's position in Gaussian-major order
-    const uint32_t g = own[sl];
-    rec[2 * i] = proj[2 * (int64_t)g];
-    rec[2 * i + 1] = proj[2 * (int64_t)g + 1];
-    slot[i] = sl;
+    const uint32_t g = vals[i];
+    // one 64-byte projected record per key: the rasteriser record and the slot facts
+    const float4 a = proj[PROJ_F4 * (int64_t)g], b = proj[PROJ_F4 * (int64_t)g + 1];
+    const uint4 f = __builtin_bit_cast(uint4, proj[PROJ_F4 * (int64_t)g + 2]);
+    const uint32_t tw = f.z & 0xffffu, w = f.z >> 16;
+    const uint32_t local = key - f.y;  // ty * TW + tx within the Gaussian's image
+    const uint32_t ty = local / tw, tx = local - ty * tw;
+    rec[2 * i] = a;
+    rec[2 * i + 1] = b;
+    slot[i] = f.x + (ty - (f.w >> 16)) * w + (tx - (f.w & 0xffffu));
     if (rec_o) rec_o[i] = opac[g];
     if (ids) ids[i] = g;
 }
@@ -635,8 +652,8 @@ __global__ __launch_bounds__(FB) void k_project_hist(const RecordSrc src, int64_
     if (i < n) {
         int4 rc;
         uint2 inf;
-        const uint32_t cnt = project_one(src, i, tab, proj, rect, tinfo, count, &nonfinite, &bad,
-                                         &rc, &inf);
+        const uint32_t cnt = project_one<false>(src, i, tab, proj, rect, tinfo, count, &nonfinite,
+                                                &bad, &rc, &inf);
         scan[i] = cnt;
         if (cnt) {
             for (int ty = rc.y; ty <= rc.w; ++ty)
@@ -814,7 +831,7 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
     const int4 rc_in = rect[ir];
     const uint2 inf_in = tinfo[ir];
     const uint32_t off_in = scan[ir];
-    const float4 pa_in = proj[2 * ir], pb_in = proj[2 * ir + 1];
+    const float4 pa_in = proj[2 * ir], pb_in = proj[2 * ir + 1];  // one-pass: 32-byte stride
     constexpr int TB_MAX = (int)((FUSED_MAX_TILES + NT - 1) / NT);
     uint32_t tb_in[TB_MAX];
 #pragma unroll
@@ -1029,8 +1046,8 @@ hipError_t launch_count_scan(const BinBuffers &b, hipStream_t s) {
 hipError_t launch_duplicate(const BinBuffers &b, hipStream_t s) {
     if (b.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_duplicate, dim3(grid_for(b.n, BLK)), dim3(BLK), 0, s, b.count, b.rect,
-                       b.tinfo, b.blocksum, b.n, b.cap, b.off, b.keys[0], b.vals[0], b.own,
-                       b.state);
+                       b.tinfo, b.blocksum, b.n, b.cap, b.off, b.keys[0], b.vals[0],
+                       reinterpret_cast<float4 *>(b.proj), b.state);
     return hipGetLastError();
 }
 
@@ -1211,7 +1228,7 @@ hipError_t launch_ranges_gather(const BinBuffers &b, int which, const ImgTable &
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(b.ranges), 0u, 2 * b.n_tiles, s);
     if (e != hipSuccess || n_max <= 0) return e;
     hipLaunchKernelGGL(k_ranges_gather, dim3(grid_for(n_max, BLK)), dim3(BLK), 0, s, b.keys[which],
-                       b.vals[which], b.own, &b.state->keys_total, n_max,
+                       b.vals[which], &b.state->keys_total, n_max,
                        reinterpret_cast<const float4 *>(b.proj), b.ranges,
                        reinterpret_cast<float4 *>(b.rec), b.slot, b.opacity, b.rec_o, b.ids_out);
     return hipGetLastError();
