@@ -443,10 +443,17 @@ __global__ __launch_bounds__(SORT_T) void k_radix_hist(const uint32_t *__restric
     for (int d = threadIdx.x; d < SORT_WAVES * BINS; d += SORT_T) (&h[0][0])[d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * SORT_TILE + (int64_t)wave * (SORT_TILE / SORT_WAVES);
-    for (int r = 0; r < SORT_TILE / SORT_WAVES / 64; ++r) {
-        const int64_t idx = base + r * 64 + lane;
-        const bool valid = idx < n;
-        const uint32_t d = valid ? (keys[idx] >> shift) & (BINS - 1) : 0u;
+    constexpr int ROUNDS = SORT_TILE / SORT_WAVES / 64;
+    // all reads first (lanes past the end read the last key and drop it): a read under the
+    // validity test would be awaited before the next one is issued
+    const int64_t last = n > 0 ? n - 1 : 0;
+    uint32_t kr[ROUNDS];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) kr[r] = keys[min(base + r * 64 + lane, last)];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const bool valid = base + r * 64 + lane < n;
+        const uint32_t d = valid ? (kr[r] >> shift) & (BINS - 1) : 0u;
         const unsigned long long peers = match_digit<BITS>(d, valid);
         if (valid && lane == __ffsll((long long)peers) - 1) h[wave][d] += __popcll(peers);
     }
@@ -474,6 +481,7 @@ __global__ __launch_bounds__(SORT_T) void k_radix_scatter(const uint32_t *__rest
     constexpr int ROUNDS = SORT_TILE / SORT_WAVES / 64;
     __shared__ uint32_t wh[SORT_WAVES][BINS];   // per-wave digit counts, then wave offsets
     __shared__ uint32_t dstart[BINS];            // first in-block position of each digit
+    __shared__ uint32_t gofs[BINS];              // output position minus in-block position
     __shared__ uint32_t sk[SORT_TILE];
     __shared__ uint32_t sv[SORT_TILE];
     __shared__ uint32_t tmp[SORT_T / 64 + 1];
@@ -481,16 +489,30 @@ __global__ __launch_bounds__(SORT_T) void k_radix_scatter(const uint32_t *__rest
     const int64_t blk_base = (int64_t)blockIdx.x * SORT_TILE;
     if (blk_base >= n) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // this block's output base of every digit: read now, used after the ranking
+    constexpr int DPT = (BINS + SORT_T - 1) / SORT_T;
+    uint32_t hb[DPT];
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+        const int d = (int)threadIdx.x + k * SORT_T;
+        hb[k] = hist[(int64_t)(d < BINS ? d : BINS - 1) * nblk + blockIdx.x];
+    }
     for (int d = threadIdx.x; d < SORT_WAVES * BINS; d += SORT_T) (&wh[0][0])[d] = 0;
     __syncthreads();
     const int64_t base = blk_base + (int64_t)wave * (SORT_TILE / SORT_WAVES);
     uint32_t key[ROUNDS], val[ROUNDS], rank[ROUNDS];
+    // all reads first (lanes past the end read the last pair and drop it), then the ranking
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int64_t idx = min(base + r * 64 + lane, n - 1);
+        key[r] = kin[idx];
+        val[r] = vin[idx];
+    }
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const int64_t idx = base + r * 64 + lane;
         const bool valid = idx < n;
-        key[r] = valid ? kin[idx] : 0u;
-        val[r] = valid ? vin[idx] : 0u;
+        if (!valid) key[r] = val[r] = 0u;
         const uint32_t d = (key[r] >> shift) & (BINS - 1);
         const unsigned long long peers = match_digit<BITS>(d, valid);
         const unsigned long long lt = (1ull << lane) - 1ull;
@@ -535,6 +557,11 @@ __global__ __launch_bounds__(SORT_T) void k_radix_scatter(const uint32_t *__rest
     }
     __syncthreads();
 #pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+        const int d = (int)threadIdx.x + k * SORT_T;
+        if (d < BINS) gofs[d] = hb[k] - dstart[d];
+    }
+#pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const int64_t idx = base + r * 64 + lane;
         if (idx < n) {
@@ -549,7 +576,7 @@ __global__ __launch_bounds__(SORT_T) void k_radix_scatter(const uint32_t *__rest
     for (int j = threadIdx.x; j < cnt; j += SORT_T) {
         const uint32_t k = sk[j];
         const uint32_t d = (k >> shift) & (BINS - 1);
-        const uint32_t dst = hist[(int64_t)d * nblk + blockIdx.x] + (uint32_t)j - dstart[d];
+        const uint32_t dst = gofs[d] + (uint32_t)j;
         kout[dst] = k;
         vout[dst] = sv[j];
     }
