@@ -30,6 +30,13 @@ __device__ inline int spad(int i) { return i + (i >> 5); }
 
 // ---- small block-level helpers --------------------------------------------------------------
 
+// in[idx] for idx < n, else 0, read without a branch (the index is clamped into [0, n) and the
+// value dropped): guarded reads in an unrolled loop are otherwise awaited one by one.
+__device__ inline uint32_t read_or_zero(const uint32_t *__restrict__ in, int64_t idx, int64_t n) {
+    const uint32_t v = in[idx < n ? idx : (n > 0 ? n - 1 : 0)];
+    return idx < n ? v : 0u;
+}
+
 template <typename T>
 __device__ inline T wave_inclusive_scan(T v) {
     const int lane = threadIdx.x & 63;
@@ -339,10 +346,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const uint32_t *__restri
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     unsigned long long s = 0;
 #pragma unroll
-    for (int j = 0; j < SCAN_IPT; ++j) {
-        int64_t idx = base + j * SCAN_T + threadIdx.x;
-        if (idx < n) s += in[idx];
-    }
+    for (int j = 0; j < SCAN_IPT; ++j) s += read_or_zero(in, base + j * SCAN_T + threadIdx.x, n);
     unsigned long long tot;
     block_exclusive_scan<unsigned long long, SCAN_T>(s, tmp, &tot);
     if (threadIdx.x == 0) bs[blockIdx.x] = tot;
@@ -355,10 +359,12 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_down(const uint32_t *__restrict
     __shared__ uint32_t stage[SCAN_TILE + SCAN_TILE / 32];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     // coalesced load into LDS, then each thread scans 16 consecutive values
+    {
+        uint32_t x[SCAN_IPT];
 #pragma unroll
-    for (int j = 0; j < SCAN_IPT; ++j) {
-        int64_t idx = base + j * SCAN_T + threadIdx.x;
-        stage[spad(j * SCAN_T + threadIdx.x)] = idx < n ? in[idx] : 0u;
+        for (int j = 0; j < SCAN_IPT; ++j) x[j] = read_or_zero(in, base + j * SCAN_T + threadIdx.x, n);
+#pragma unroll
+        for (int j = 0; j < SCAN_IPT; ++j) stage[spad(j * SCAN_T + threadIdx.x)] = x[j];
     }
     __syncthreads();
     uint32_t v[SCAN_IPT];
@@ -392,11 +398,9 @@ __global__ __launch_bounds__(1024) void k_scan_single(const uint32_t *__restrict
     uint32_t v[16];
     unsigned long long s = 0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        int64_t idx = (int64_t)threadIdx.x * 16 + j;
-        v[j] = idx < n ? in[idx] : 0u;
-        s += v[j];
-    }
+    for (int j = 0; j < 16; ++j) v[j] = read_or_zero(in, (int64_t)threadIdx.x * 16 + j, n);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) s += v[j];
     unsigned long long tot;
     unsigned long long run = block_exclusive_scan<unsigned long long, 1024>(s, tmp, &tot);
 #pragma unroll
@@ -598,13 +602,15 @@ __global__ __launch_bounds__(BLK) void k_ranges_gather(const uint32_t *__restric
     const int64_t n = sort_count(n_dev, n_max);
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     if (i >= n) return;
+    // the key, its neighbours and the Gaussian are read together (clamped, not guarded)
     const uint32_t key = keys[i];
-    if (i == 0 || keys[i - 1] != key) ranges[key].x = (uint32_t)i;
-    if (i == n - 1 || keys[i + 1] != key) ranges[key].y = (uint32_t)(i + 1);
+    const uint32_t kp = keys[i > 0 ? i - 1 : 0], kn = keys[i + 1 < n ? i + 1 : i];
     const uint32_t g = vals[i];
     // one 64-byte projected record per key: the rasteriser record and the slot facts
     const float4 a = proj[PROJ_F4 * (int64_t)g], b = proj[PROJ_F4 * (int64_t)g + 1];
     const uint4 f = __builtin_bit_cast(uint4, proj[PROJ_F4 * (int64_t)g + 2]);
+    if (i == 0 || kp != key) ranges[key].x = (uint32_t)i;
+    if (i == n - 1 || kn != key) ranges[key].y = (uint32_t)(i + 1);
     const uint32_t tw = f.z & 0xffffu, w = f.z >> 16;
     const uint32_t local = key - f.y;  // ty * TW + tx within the Gaussian's image
     const uint32_t ty = local / tw, tx = local - ty * tw;
