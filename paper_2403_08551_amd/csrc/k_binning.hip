@@ -16,6 +16,7 @@ namespace gi {
 namespace {
 
 constexpr int BLK = 256;           // threads per block for per-Gaussian and per-key kernels
+constexpr uint32_t DUP_OWN_CAP = 16384;  // keys of a duplication block held in its owner table
 constexpr int SORT_T = 256;        // threads per sort block
 constexpr int SORT_IPT = 16;       // keys per thread
 constexpr int SORT_TILE = SORT_T * SORT_IPT;
@@ -288,7 +289,9 @@ __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long *__restric
 // ---- K2: key duplication --------------------------------------------------------------------
 
 // Block b handles Gaussians [256 b, 256 b + 256): it rebuilds their offsets from the scanned
-// block totals, then its threads stride over the block's keys so that writes are coalesced.
+// block totals, then its threads stride over the block's keys so that writes are coalesced.  A
+// key finds its Gaussian in an LDS table (one byte per key) when the block's keys fit, else by
+// binary search over the offsets.
 __global__ __launch_bounds__(BLK) void k_duplicate(const uint32_t *__restrict__ count,
                                                    const int4 *__restrict__ rect,
                                                    const uint2 *__restrict__ tinfo,
@@ -303,10 +306,14 @@ __global__ __launch_bounds__(BLK) void k_duplicate(const uint32_t *__restrict__ 
     __shared__ unsigned long long pre[BLK];
     __shared__ int4 srect[BLK];
     __shared__ uint2 sinfo[BLK];
+    __shared__ uint8_t owner[DUP_OWN_CAP];  // block-local key -> its Gaussian, when the keys fit
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     const uint32_t c = i < n ? count[i] : 0u;
     unsigned long long tot;
     const unsigned long long loc = block_exclusive_scan<unsigned long long, BLK>(c, tmp, &tot);
+    const bool table = tot <= DUP_OWN_CAP;  // the same for the whole block
+    if (table)
+        for (uint32_t k = 0; k < c; ++k) owner[loc + k] = (uint8_t)threadIdx.x;
     const unsigned long long base = bs[blockIdx.x];
     pre[threadIdx.x] = loc;
     if (i < n) {
@@ -321,10 +328,15 @@ __global__ __launch_bounds__(BLK) void k_duplicate(const uint32_t *__restrict__ 
     else if (base + tot > (unsigned long long)cap) limit = (unsigned long long)cap - base;
     if (limit < tot && threadIdx.x == 0) atomicOr(&state->flags, FLAG_KEY_OVERFLOW);
     for (unsigned long long j = threadIdx.x; j < limit; j += BLK) {
-        int lo = 0, hi = BLK - 1;  // owner: largest g with pre[g] <= j
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+        int lo = 0;  // owner: largest g with pre[g] <= j
+        if (table) {
+            lo = owner[j];
+        } else {
+            int hi = BLK - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+            }
         }
         const int4 r = srect[lo];
         const uint2 inf = sinfo[lo];
