@@ -97,8 +97,10 @@ enum {
                                  capacity, never wait, report overflow through flags */
     GI_OPT_SORT_BITS = 2,     /* radix digit width 1..11, 0 = automatic */
     GI_OPT_FWD_PIXELS = 3,    /* pixels per lane in the forward kernels: 1, 2 or 4; 0 = auto */
-    GI_OPT_BINNING = 4,       /* 0 = auto (one pass when the tiles number at most 2048),
-                                 1 = key duplication + LSD radix sort, 2 = one pass if possible */
+    GI_OPT_BINNING = 4,       /* 0 = auto (one pass when the tiles number at most 2048, else
+                                 row binning when every image is at most 1024 tiles wide, else
+                                 radix), 1 = key duplication + LSD radix sort, 2 = one pass if
+                                 possible, else radix, 3 = row binning if possible, else radix */
     GI_OPT_TIMING = 5,        /* 1: bracket each stage of non-captured calls with HIP events on
                                  the call's stream (read with gi_timing); 0 (default): off */
     GI_OPT_COVARIANCE = 6     /* how params[2..4] describe Sigma (Sec. 3.1): GI_COV_CHOLESKY

@@ -31,9 +31,12 @@ constexpr uint32_t FLAG_NONFINITE = 2u;
 constexpr uint32_t FLAG_SCAN_STALL = 4u;
 constexpr uint32_t FLAG_BAD_CODE = 8u;
 constexpr int64_t FUSED_MAX_TILES = 2048;
-// float4 words per projected Gaussian on the radix path: the rasteriser record (2), the slot
-// facts (1), padding to one 64-byte line (1), so that the gather after the sort reads one line
-// per key.  The one-pass path stores the record alone (2 words per Gaussian).
+// Row binning (tile count above FUSED_MAX_TILES): images up to this many tiles per row.
+constexpr int32_t ROW_MAX_TW = 1024;
+// float4 words per projected Gaussian on the radix and row paths: the rasteriser record (2),
+// the slot facts (1), the first tile row and row count (1): one 64-byte line, so that the
+// kernels after the sort read one line per key.  The one-pass path stores the record alone (2
+// words per Gaussian).
 constexpr int PROJ_F4 = 4;
 
 // sqrt(log2(e) / 2): scales L^{-1} d so that exp(-sigma) = exp2(-|u|^2)
@@ -44,8 +47,10 @@ struct DevState {
     unsigned long long keys_total;  // keys of the last binning (may exceed capacity)
     uint32_t flags;                 // sticky FLAG_*
     uint32_t spare;
-    uint32_t scan_epoch;            // launch tag of the one-pass scan's status words
-    uint32_t pad;
+    uint32_t scan_epoch;            // launch tag of the chained scans' status words
+    uint32_t row_chunks;            // row binning: chunks of (row, Gaussian) pairs
+    unsigned long long rows_total;  // row binning: (row, Gaussian) pairs (may exceed capacity)
+    unsigned long long row_scan_len;  // row binning: length of the per-column count array
 };
 
 // Covariance factorisation read from params[2..4] (Sec. 3.1): (l1, l2, l3) of the Cholesky
@@ -62,6 +67,10 @@ struct ImgTable {
     const uint32_t *tile_base;        // [B+1] first global tile id of each image
     const uint32_t *gauss_off;        // [B+1]
     const unsigned long long *pix_off;  // [B+1] first pixel of each image
+    const uint32_t *row_base;         // [B+1] first global tile row of each image (B > 1)
+    const uint2 *row_tiles;           // [rows] first global tile, tiles per row (B > 1)
+    int32_t rows;                     // tile rows of all images
+    int32_t max_tw;                   // most tiles per row of any image
 };
 
 struct TileInfo {
@@ -235,6 +244,8 @@ struct BinBuffers {
     uint2 *ranges;
     int64_t n_tiles;
     int64_t cap;
+    unsigned long long *rblocksum;  // row binning: per-block sums of the tile rows per Gaussian
+    int64_t cap_p;                  // row binning: (row, Gaussian) pairs the sort is sized for
     DevState *state;
     // sort scratch
     uint32_t *hist;                 // [2^bits * max_sort_blocks]
@@ -269,6 +280,34 @@ int64_t fused_scan_entries(int64_t n, int64_t n_tiles);
 int64_t fused_scan_blocks(int64_t n, int64_t n_tiles);
 hipError_t launch_fused_a(const FusedBuffers &f, const ImgTable &tab, hipStream_t s);
 hipError_t launch_fused_c(const FusedBuffers &f, uint32_t *ids, hipStream_t s);
+
+// Row binning (n_tiles > FUSED_MAX_TILES, every image at most ROW_MAX_TW tiles wide), a
+// counting sort in two levels.  A: projection (64-byte lines) with per-block sums of the keys
+// and of the tile rows per Gaussian, scanned (state->keys_total, state->rows_total).  B: the
+// (global tile row, Gaussian) pairs, stably radix-sorted by row; each row's pairs cut into
+// chunks of ROW_CHUNK; per (row, column, chunk) key counts, one chained scan over them (row
+// major, then column, then chunk: exactly tile order), and the scatter of every chunk's keys in
+// Gaussian order into tile order with the records, slots and ranges.
+constexpr int ROW_CHUNK = 256;
+struct RowBuffers {
+    BinBuffers b;
+    uint2 *rrange;               // [rows] pair range of each row in the sorted pair list
+    uint4 *rinfo;                // [2 rows] {first pair, end pair, first chunk, scan offset},
+                                 // {first tile, tiles per row, chunks, 0}
+    uint32_t *chunk_row;         // [nch_max] the row of each chunk
+    uint32_t *scan;              // [scan_max] per-chunk column counts, then their scan
+    unsigned long long *status;  // [ceil(scan_max / 4096)] chained-scan status, epoch-tagged
+    int64_t nch_max, scan_max;
+};
+// Chunk and count-array bounds of row binning for a pair capacity.
+int64_t row_chunks_max(int64_t cap_p, int64_t rows);
+int64_t row_scan_max(int64_t cap_p, int64_t rows, int32_t max_tw);
+int64_t chained_scan_blocks(int64_t len);
+hipError_t launch_rows_a(const BinBuffers &b, const ImgTable &tab, hipStream_t s);
+// *which receives the buffer pair the sorted (row, Gaussian) pairs ended in; the sorted
+// Gaussian ids go to the other pair's values when wanted.
+hipError_t launch_rows_b(const RowBuffers &r, const ImgTable &tab, bool want_ids, int digit_bits,
+                         int *which, hipStream_t s);
 
 // generic pieces, also exported for testing
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n,

@@ -37,6 +37,7 @@ struct gi_ctx {
     int64_t cap_a = 0;
     int want_ids = 0;  // the one-pass binning writes sorted Gaussian ids only for gi_binning
     int64_t cap_n = 0, cap_t = 0, cap_k = 0;
+    int64_t cap_p = 0;  // (row, Gaussian) pairs the row binning is sized for
     int64_t last_keys = 0;
     // per Gaussian
     float *proj = nullptr;
@@ -45,6 +46,7 @@ struct gi_ctx {
     uint32_t *count = nullptr;
     uint32_t *off = nullptr;
     unsigned long long *blocksum = nullptr;
+    unsigned long long *rblocksum = nullptr;
     // per key
     uint32_t *keys[2] = {nullptr, nullptr};
     uint32_t *vals[2] = {nullptr, nullptr};
@@ -61,6 +63,14 @@ struct gi_ctx {
     int64_t fscan_cap = 0;
     unsigned long long *fstatus = nullptr;
     int64_t fstatus_cap = 0;
+    // row binning scratch
+    uint2 *rrange = nullptr;
+    uint4 *rinfo = nullptr;
+    int64_t rows_cap = 0;
+    uint32_t *chunk_row = nullptr;
+    int64_t chunk_cap = 0;
+    uint32_t *rscan = nullptr;
+    int64_t rscan_cap = 0;
     const uint32_t *off_cur = nullptr;  // key offsets of the last binning
     // per tile
     uint2 *ranges = nullptr;
@@ -72,6 +82,9 @@ struct gi_ctx {
     int32_t batch_cap = 0;
     int4 *dims = nullptr;
     uint32_t *tile_base = nullptr;
+    uint32_t *row_base = nullptr;
+    uint2 *row_tiles = nullptr;
+    int64_t row_tiles_cap = 0;
     uint32_t *gauss_off = nullptr;
     unsigned long long *pix_off = nullptr;
     std::vector<int64_t> batch_sig;  // host copy of the uploaded layout
@@ -196,6 +209,7 @@ int ensure_gauss(gi_ctx *ctx, int64_t n) {
     CK(grow(&ctx->count, c));
     CK(grow(&ctx->off, c));
     CK(grow(&ctx->blocksum, (c + 255) / 256 + 1));
+    CK(grow(&ctx->rblocksum, (c + 255) / 256 + 1));
     ctx->cap_n = c;
     return GI_OK;
 }
@@ -252,19 +266,26 @@ int upload_batch(gi_ctx *ctx, const gi_batch *b, ImgTable *tab, int64_t *n_tiles
                  int64_t *n_gauss, int64_t *n_pix) {
     const int32_t B = b->count;
     std::vector<int4> dims(B);
-    std::vector<uint32_t> tb(B + 1), go(B + 1);
+    std::vector<uint32_t> tb(B + 1), go(B + 1), rb(B + 1);
     std::vector<unsigned long long> po(B + 1);
+    std::vector<uint2> rt;
     int64_t t = 0, p = 0;
+    int32_t max_tw = 0;
     for (int32_t i = 0; i < B; ++i) {
         const int32_t H = b->height_host[i], W = b->width_host[i];
         const int32_t TW = (W + TILE - 1) / TILE, TH = (H + TILE - 1) / TILE;
         dims[i] = make_int4(H, W, TW, TH);
         tb[i] = (uint32_t)t;
+        rb[i] = (uint32_t)rt.size();
+        for (int32_t y = 0; y < TH; ++y)
+            rt.push_back(make_uint2((uint32_t)(t + (int64_t)y * TW), (uint32_t)TW));
+        max_tw = std::max(max_tw, TW);
         po[i] = (unsigned long long)p;
         go[i] = (uint32_t)b->gauss_off_host[i];
         t += (int64_t)TW * TH;
         p += (int64_t)H * W;
     }
+    rb[B] = (uint32_t)rt.size();
     tb[B] = (uint32_t)t;
     po[B] = (unsigned long long)p;
     go[B] = (uint32_t)b->gauss_off_host[B];
@@ -281,6 +302,7 @@ int upload_batch(gi_ctx *ctx, const gi_batch *b, ImgTable *tab, int64_t *n_tiles
             CK(hipDeviceSynchronize());
             CK(grow(&ctx->dims, B));
             CK(grow(&ctx->tile_base, B + 1));
+            CK(grow(&ctx->row_base, B + 1));
             CK(grow(&ctx->gauss_off, B + 1));
             CK(grow(&ctx->pix_off, B + 1));
             ctx->batch_cap = B;
@@ -288,6 +310,12 @@ int upload_batch(gi_ctx *ctx, const gi_batch *b, ImgTable *tab, int64_t *n_tiles
         CK(hipDeviceSynchronize());
         CK(hipMemcpy(ctx->dims, dims.data(), sizeof(int4) * B, hipMemcpyHostToDevice));
         CK(hipMemcpy(ctx->tile_base, tb.data(), sizeof(uint32_t) * (B + 1), hipMemcpyHostToDevice));
+        if ((int64_t)rt.size() > ctx->row_tiles_cap) {
+            CK(grow(&ctx->row_tiles, (int64_t)rt.size()));
+            ctx->row_tiles_cap = (int64_t)rt.size();
+        }
+        CK(hipMemcpy(ctx->row_base, rb.data(), sizeof(uint32_t) * (B + 1), hipMemcpyHostToDevice));
+        CK(hipMemcpy(ctx->row_tiles, rt.data(), sizeof(uint2) * rt.size(), hipMemcpyHostToDevice));
         CK(hipMemcpy(ctx->gauss_off, go.data(), sizeof(uint32_t) * (B + 1), hipMemcpyHostToDevice));
         CK(hipMemcpy(ctx->pix_off, po.data(), sizeof(unsigned long long) * (B + 1),
                      hipMemcpyHostToDevice));
@@ -301,6 +329,10 @@ int upload_batch(gi_ctx *ctx, const gi_batch *b, ImgTable *tab, int64_t *n_tiles
     tab->tile_base = ctx->tile_base;
     tab->gauss_off = ctx->gauss_off;
     tab->pix_off = ctx->pix_off;
+    tab->row_base = ctx->row_base;
+    tab->row_tiles = ctx->row_tiles;
+    tab->rows = (int32_t)rt.size();
+    tab->max_tw = max_tw;
     if (B == 1) {
         // single images read the scalar fields; the tables stay valid for B == 1 as well
     }
@@ -339,6 +371,8 @@ ImgTable single_table(int32_t H, int32_t W) {
     t.H = H;
     t.W = W;
     t.TW = (W + TILE - 1) / TILE;
+    t.rows = (H + TILE - 1) / TILE;
+    t.max_tw = t.TW;
     return t;
 }
 
@@ -391,6 +425,8 @@ BinBuffers bin_buffers(gi_ctx *ctx, const float *params, int64_t n, int64_t n_ti
     b.ranges = ctx->ranges;
     b.n_tiles = n_tiles;
     b.cap = ctx->cap_k;
+    b.rblocksum = ctx->rblocksum;
+    b.cap_p = ctx->cap_p;
     b.state = ctx->state;
     b.hist = ctx->hist;
     b.scan_blocksum = ctx->scan_bs;
@@ -452,6 +488,81 @@ int run_binning_fused(gi_ctx *ctx, const float *params, int64_t n, const ImgTabl
     return GI_OK;
 }
 
+int ensure_rows(gi_ctx *ctx, int64_t rows, int64_t nch_max, int64_t scan_max) {
+    if (rows > ctx->rows_cap) {
+        CK(hipDeviceSynchronize());
+        const int64_t c = std::max<int64_t>(rows, 256);
+        CK(grow(&ctx->rrange, c));
+        CK(grow(&ctx->rinfo, 2 * c));
+        ctx->rows_cap = c;
+    }
+    if (nch_max > ctx->chunk_cap) {
+        CK(hipDeviceSynchronize());
+        const int64_t c = nch_max + nch_max / 4;
+        CK(grow(&ctx->chunk_row, c));
+        ctx->chunk_cap = c;
+    }
+    if (scan_max > ctx->rscan_cap) {
+        CK(hipDeviceSynchronize());
+        const int64_t c = scan_max + scan_max / 4;
+        CK(grow(&ctx->rscan, c));
+        ctx->rscan_cap = c;
+    }
+    const int64_t blocks = chained_scan_blocks(scan_max);
+    if (blocks > ctx->fstatus_cap) {
+        CK(hipDeviceSynchronize());
+        const int64_t c = std::max<int64_t>(blocks + blocks / 4, 64);
+        CK(grow(&ctx->fstatus, c));
+        CK(hipMemset(ctx->fstatus, 0, sizeof(unsigned long long) * c));  // no flag: unpublished
+        ctx->fstatus_cap = c;
+    }
+    return GI_OK;
+}
+
+// Row binning (a counting sort in two levels, see launch_rows_b): n >= 1, every image at most
+// ROW_MAX_TW tiles wide.
+int run_binning_rows(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab,
+                     int64_t n_tiles, hipStream_t s, int64_t *bound, int *which) {
+    int rc;
+    ctx->off_cur = ctx->off;
+    BinBuffers b = bin_buffers(ctx, params, n, n_tiles);
+    StageTimer tm(ctx, s, GI_STAGE_BINNING);
+    CK(launch_rows_a(b, tab, s));
+    int64_t K = ctx->cap_k;
+    if (ctx->sync) {
+        CK(hipMemcpyAsync(ctx->pinned, ctx->state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        const DevState *st = reinterpret_cast<const DevState *>(ctx->pinned);
+        K = (int64_t)st->keys_total;
+        const int64_t P = (int64_t)st->rows_total;
+        ctx->last_keys = K;
+        if (K > MAX_KEYS) return GI_ERR_CAPACITY;
+        if (K > ctx->cap_k) {
+            if ((rc = ensure_keys(ctx, K + K / 4)) != GI_OK) return rc;
+        }
+        if (P > ctx->cap_p) ctx->cap_p = P + P / 4;
+    }
+    if (ctx->cap_p <= 0) ctx->cap_p = ctx->cap_k;
+    const int64_t pcap = std::min(ctx->cap_p, ctx->cap_k);
+    RowBuffers r;
+    const int64_t nch_max = row_chunks_max(pcap, tab.rows);
+    const int64_t scan_max = row_scan_max(pcap, tab.rows, tab.max_tw);
+    if ((rc = ensure_rows(ctx, tab.rows, nch_max, scan_max)) != GI_OK) return rc;
+    r.b = bin_buffers(ctx, params, n, n_tiles);
+    r.rrange = ctx->rrange;
+    r.rinfo = ctx->rinfo;
+    r.chunk_row = ctx->chunk_row;
+    r.scan = ctx->rscan;
+    r.status = ctx->fstatus;
+    r.nch_max = nch_max;
+    r.scan_max = scan_max;
+    CK(launch_rows_b(r, tab, ctx->want_ids != 0, ctx->sort_bits, which, s));
+    ctx->ids_at = ctx->vals[1 - *which];
+    tm.stop();
+    *bound = K;
+    return GI_OK;
+}
+
 // Projection, scan, duplication, sort, ranges and gather.  *bound receives the key bound the
 // later kernels are sized for; *which the ping-pong buffer holding the sorted pairs.
 int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab_in,
@@ -463,8 +574,13 @@ int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab
     if ((rc = ensure_tiles(ctx, n_tiles)) != GI_OK) return rc;
     if (ctx->cap_k == 0 && (rc = ensure_keys(ctx, 4096)) != GI_OK) return rc;
     if (ctx->blend_cur == BLEND_ALPHA && (rc = ensure_alpha(ctx)) != GI_OK) return rc;
-    if (ctx->binning != 1 && n > 0 && n_tiles <= FUSED_MAX_TILES)
+    // 0: one pass up to FUSED_MAX_TILES tiles, else rows; 1: radix; 2: one pass, else radix;
+    // 3: rows.  Rows need every image at most ROW_MAX_TW tiles wide, else radix.
+    const bool rows_ok = n > 0 && tab.max_tw >= 1 && tab.max_tw <= ROW_MAX_TW && tab.rows > 0;
+    if ((ctx->binning == 0 || ctx->binning == 2) && n > 0 && n_tiles <= FUSED_MAX_TILES)
         return run_binning_fused(ctx, params, n, tab, n_tiles, s, bound, which);
+    if ((ctx->binning == 0 || ctx->binning == 3) && rows_ok)
+        return run_binning_rows(ctx, params, n, tab, n_tiles, s, bound, which);
     ctx->off_cur = ctx->off;
     BinBuffers b = bin_buffers(ctx, params, n, n_tiles);
     StageTimer tm(ctx, s, GI_STAGE_BINNING);
@@ -759,7 +875,7 @@ int gi_create(gi_ctx **out, int device) {
     ctx->device = device;
     hipError_t e = hipMalloc((void **)&ctx->state, sizeof(DevState));
     if (e == hipSuccess) e = hipMemset(ctx->state, 0, sizeof(DevState));
-    if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->pinned, sizeof(unsigned long long) * 2);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->pinned, sizeof(DevState));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         gi_destroy(ctx);
@@ -778,7 +894,8 @@ int gi_destroy(gi_ctx *ctx) {
                     ctx->part, ctx->hist, ctx->scan_bs, ctx->ranges, ctx->loss_part, ctx->state,
                     ctx->dims, ctx->tile_base, ctx->gauss_off, ctx->pix_off, ctx->tmp_k,
                     ctx->tmp_v, ctx->fscan, ctx->fstatus, ctx->rec_o, ctx->part_a,
-                    ctx->qpart, ctx->qscratch};
+                    ctx->qpart, ctx->qscratch, ctx->rblocksum, ctx->rrange, ctx->rinfo,
+                    ctx->chunk_row, ctx->rscan, ctx->row_base, ctx->row_tiles};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -808,7 +925,7 @@ int gi_set_option(gi_ctx *ctx, int option, int64_t value) {
             ctx->fwd_px = (int)value;
             return GI_OK;
         case GI_OPT_BINNING:
-            if (value < 0 || value > 2) return GI_ERR_INVALID_ARG;
+            if (value < 0 || value > 3) return GI_ERR_INVALID_ARG;
             ctx->binning = (int)value;
             return GI_OK;
         case GI_OPT_TIMING:

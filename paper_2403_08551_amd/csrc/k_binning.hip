@@ -21,6 +21,16 @@ constexpr int SORT_T = 256;        // threads per sort block
 constexpr int SORT_IPT = 16;       // keys per thread
 constexpr int SORT_TILE = SORT_T * SORT_IPT;
 constexpr int SORT_WAVES = SORT_T / 64;
+constexpr int XCDS = 8;
+
+// Workgroup i runs on XCD i mod 8.  Give each XCD a contiguous range of chunks, so that the
+// chunks writing neighbouring positions of a tile's list share one L2 and their partial-line
+// writes combine there before reaching memory.
+__device__ inline uint32_t xcd_chunk(uint32_t i, uint32_t nchunk) {
+    const uint32_t q = nchunk / XCDS, rem = nchunk % XCDS;
+    const uint32_t x = i % XCDS, k = i / XCDS;
+    return x * q + (x < rem ? x : rem) + k;
+}
 constexpr int SCAN_T = 256;
 constexpr int SCAN_IPT = 16;
 constexpr int SCAN_TILE = SCAN_T * SCAN_IPT;
@@ -149,7 +159,7 @@ __device__ inline uint32_t project_one(const RecordSrc &src, int64_t i,
     float o = 1.f;
     if (src.opacity) o = src.opacity[i];
     int32_t TW, TH, IH, IW;
-    uint32_t tb;
+    uint32_t tb, rb = 0;
     if (tab.B == 1) {
         TW = tab.TW; TH = (tab.H + TILE - 1) / TILE; tb = 0;
         IH = tab.H; IW = tab.W;
@@ -157,6 +167,7 @@ __device__ inline uint32_t project_one(const RecordSrc &src, int64_t i,
         int32_t b = upper_index(tab.gauss_off, tab.B, (uint32_t)i);
         int4 d = tab.dims[b];
         TW = d.z; TH = d.w; tb = tab.tile_base[b];
+        if (FACTS) rb = tab.row_base[b];
         IH = d.x; IW = d.y;
     }
     if (src.recipe) recipe_effective(q, IH, IW, tab.cov == COV_ROTATION_SCALE);
@@ -229,11 +240,15 @@ __device__ inline uint32_t project_one(const RecordSrc &src, int64_t i,
     proj[STRIDE * i + 1] = p1;
     // the facts that turn a (tile, Gaussian) key into its slot: the key offset (written once the
     // counts are scanned), the image's first tile and tiles per row, the rectangle's width and
-    // corner (all tile counts < 2^16)
-    if (FACTS)
+    // corner (all tile counts < 2^16); then the global tile row of the rectangle's first row and
+    // its row count (row binning)
+    if (FACTS) {
         proj[PROJ_F4 * i + 2] = __builtin_bit_cast(
             float4, make_uint4(0u, tb, (uint32_t)TW | ((uint32_t)(rc.z - rc.x + 1) << 16),
                                (uint32_t)rc.x | ((uint32_t)rc.y << 16)));
+        proj[PROJ_F4 * i + 3] = __builtin_bit_cast(
+            float4, make_uint4(rb + (uint32_t)rc.y, cnt ? (uint32_t)(rc.w - rc.y + 1) : 0u, 0u, 0u));
+    }
     rect[i] = rc;
     const uint2 inf = make_uint2(tb, (uint32_t)TW);
     tinfo[i] = inf;
@@ -249,28 +264,41 @@ __global__ __launch_bounds__(BLK) void k_project(const RecordSrc src, int64_t n,
                                                  uint2 *__restrict__ tinfo,
                                                  uint32_t *__restrict__ count,
                                                  unsigned long long *__restrict__ blocksum,
+                                                 unsigned long long *__restrict__ rblocksum,
                                                  DevState *state) {
     __shared__ unsigned long long tmp[BLK / 64 + 1];
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, rows = 0;
     bool nonfinite = false, bad = false;
     if (i < n) {
         int4 rc;
         uint2 inf;
         cnt = project_one<true>(src, i, tab, proj, rect, tinfo, count, &nonfinite, &bad, &rc,
                                 &inf);
+        rows = cnt ? (uint32_t)(rc.w - rc.y + 1) : 0u;
     }
     if (__ballot(nonfinite) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_NONFINITE);
     if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_BAD_CODE);
     unsigned long long tot;
     block_exclusive_scan<unsigned long long, BLK>((unsigned long long)cnt, tmp, &tot);
     if (threadIdx.x == 0) blocksum[blockIdx.x] = tot;
+    if (rblocksum) {  // row binning: the tile rows per Gaussian as well
+        block_exclusive_scan<unsigned long long, BLK>((unsigned long long)rows, tmp, &tot);
+        if (threadIdx.x == 0) rblocksum[blockIdx.x] = tot;
+    }
 }
 
-// Exclusive scan of the per-block totals by one 1024-thread block; also the grand total.
+// Exclusive scan of the per-block totals by one 1024-thread block; also the grand total.  A
+// second block, when launched, does the same for bs2 / total2.
 __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long *__restrict__ bs, int64_t nb,
-                                                   unsigned long long *__restrict__ total) {
+                                                   unsigned long long *__restrict__ total,
+                                                   unsigned long long *__restrict__ bs2,
+                                                   unsigned long long *__restrict__ total2) {
     __shared__ unsigned long long tmp[1024 / 64 + 1];
+    if (blockIdx.x == 1) {
+        bs = bs2;
+        total = total2;
+    }
     const int64_t per = (nb + 1023) / 1024;
     const int64_t beg = threadIdx.x * per;
     const int64_t end = beg + per < nb ? beg + per : nb;
@@ -455,10 +483,12 @@ __global__ __launch_bounds__(SORT_T) void k_radix_hist(const uint32_t *__restric
     constexpr int BINS = 1 << BITS;
     __shared__ uint32_t h[SORT_WAVES][BINS];
     const int64_t n = sort_count(n_dev, n_max);
+    const uint32_t nbu = (uint32_t)((n + SORT_TILE - 1) / SORT_TILE);
+    const uint32_t blk = blockIdx.x < nbu ? xcd_chunk(blockIdx.x, nbu) : blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int d = threadIdx.x; d < SORT_WAVES * BINS; d += SORT_T) (&h[0][0])[d] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * SORT_TILE + (int64_t)wave * (SORT_TILE / SORT_WAVES);
+    const int64_t base = (int64_t)blk * SORT_TILE + (int64_t)wave * (SORT_TILE / SORT_WAVES);
     constexpr int ROUNDS = SORT_TILE / SORT_WAVES / 64;
     // all reads first (lanes past the end read the last key and drop it): a read under the
     // validity test would be awaited before the next one is issued
@@ -478,7 +508,7 @@ __global__ __launch_bounds__(SORT_T) void k_radix_hist(const uint32_t *__restric
         uint32_t s = 0;
 #pragma unroll
         for (int w = 0; w < SORT_WAVES; ++w) s += h[w][d];
-        hist[(int64_t)d * nblk + blockIdx.x] = s;
+        hist[(int64_t)d * nblk + blk] = s;
     }
 }
 
@@ -502,8 +532,10 @@ __global__ __launch_bounds__(SORT_T) void k_radix_scatter(const uint32_t *__rest
     __shared__ uint32_t sv[SORT_TILE];
     __shared__ uint32_t tmp[SORT_T / 64 + 1];
     const int64_t n = sort_count(n_dev, n_max);
-    const int64_t blk_base = (int64_t)blockIdx.x * SORT_TILE;
-    if (blk_base >= n) return;
+    const uint32_t nbu = (uint32_t)((n + SORT_TILE - 1) / SORT_TILE);
+    if (blockIdx.x >= nbu) return;
+    const uint32_t blk = xcd_chunk(blockIdx.x, nbu);
+    const int64_t blk_base = (int64_t)blk * SORT_TILE;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // this block's output base of every digit: read now, used after the ranking
     constexpr int DPT = (BINS + SORT_T - 1) / SORT_T;
@@ -511,7 +543,7 @@ __global__ __launch_bounds__(SORT_T) void k_radix_scatter(const uint32_t *__rest
 #pragma unroll
     for (int k = 0; k < DPT; ++k) {
         const int d = (int)threadIdx.x + k * SORT_T;
-        hb[k] = hist[(int64_t)(d < BINS ? d : BINS - 1) * nblk + blockIdx.x];
+        hb[k] = hist[(int64_t)(d < BINS ? d : BINS - 1) * nblk + blk];
     }
     for (int d = threadIdx.x; d < SORT_WAVES * BINS; d += SORT_T) (&wh[0][0])[d] = 0;
     __syncthreads();
@@ -612,7 +644,9 @@ __global__ __launch_bounds__(BLK) void k_ranges_gather(const uint32_t *__restric
                                                        float *__restrict__ rec_o,
                                                        uint32_t *__restrict__ ids) {
     const int64_t n = sort_count(n_dev, n_max);
-    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    const uint32_t nb = (uint32_t)((n + BLK - 1) / BLK);
+    if (blockIdx.x >= nb) return;
+    const int64_t i = (int64_t)xcd_chunk(blockIdx.x, nb) * BLK + threadIdx.x;
     if (i >= n) return;
     // the key, its neighbours and the Gaussian are read together (clamped, not guarded)
     const uint32_t key = keys[i];
@@ -655,16 +689,6 @@ constexpr int FB = 256;
 // the scatter splits a chunk's keys over 4 or 8 waves (more waves per CU hide its latency;
 // each needs T words of LDS counters), see scatter_waves
 constexpr uint32_t OWN_CAP = 4096;
-constexpr int XCDS = 8;
-
-// Workgroup i runs on XCD i mod 8.  Give each XCD a contiguous range of chunks, so that the
-// chunks writing neighbouring positions of a tile's list share one L2 and their partial-line
-// writes combine there before reaching memory.
-__device__ inline uint32_t xcd_chunk(uint32_t i, uint32_t nchunk) {
-    const uint32_t q = nchunk / XCDS, rem = nchunk % XCDS;
-    const uint32_t x = i % XCDS, k = i / XCDS;
-    return x * q + (x < rem ? x : rem) + k;
-}
 constexpr int CS_T = 256;
 constexpr int CS_IPT = 16;
 constexpr int CS_TILE = CS_T * CS_IPT;
@@ -723,16 +747,20 @@ __device__ inline unsigned long long load_status(const unsigned long long *p) {
 // launches read as "not yet published" and nothing needs clearing between launches.  Blocks are dispatched in
 // index order, so every predecessor a block waits for is already running; every wait is still
 // bounded (SPIN_LIMIT polls, then a stall flag), so the grid always drains.
-// *mark_out (if not null) receives the exclusive prefix at index `mark`.
+// *mark_out (if not null) receives the exclusive prefix at index `mark`.  L_dev (if not null)
+// holds the length, at most L; blocks past it leave at once (no block before them waits on them).
 __global__ __launch_bounds__(CS_T) void k_chained_scan(uint32_t *__restrict__ data, int64_t L,
                                                        unsigned long long *__restrict__ status,
                                                        int64_t mark,
                                                        unsigned long long *__restrict__ mark_out,
-                                                       DevState *state) {
+                                                       DevState *state,
+                                                       const unsigned long long *L_dev) {
     __shared__ unsigned long long s_prefix;
     __shared__ unsigned long long tmp[CS_T / 64 + 1];
     __shared__ uint32_t stage[CS_TILE + CS_TILE / 32];
+    if (L_dev && (int64_t)*L_dev < L) L = (int64_t)*L_dev;
     const uint32_t w = blockIdx.x;
+    if ((int64_t)w * CS_TILE >= L) return;
     const unsigned long long tag = (unsigned long long)(state->scan_epoch & 0x1fffffffu) << CS_EPOCH_SHIFT;
     const int64_t base = (int64_t)w * CS_TILE;
     {
@@ -990,7 +1018,11 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
         const bool ok = valid && pos < cap;
         if (valid && !ok) overflow = true;
         if (ok) {
-            slot[pos] = soff[g] + li;
+            // on key overflow a key below the capacity in tile order can lie above it in
+            // Gaussian order; its partial sums then go to the last slot (the update is skipped
+            // on overflow), never past the buffer
+            const uint32_t sl = soff[g] + li;
+            slot[pos] = sl < cap ? sl : (uint32_t)(cap - 1);
             if (ids) ids[pos] = chunk * FB + (uint32_t)g;
             if (rec_o) rec_o[pos] = opac[(int64_t)chunk * FB + g];
         }
@@ -1010,6 +1042,414 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
             const int gg = odd ? g : pg;
             const uint32_t pp = odd ? pos : ppos;
             if (odd ? ok : pok) rec[2 * (int64_t)pp + !odd] = sproj[2 * gg + !odd];
+        }
+    }
+    if (__ballot(overflow) && lane == 0) atomicOr(&state->flags, FLAG_KEY_OVERFLOW);
+}
+
+// ---- row binning: a counting sort in two levels, for many tiles ------------------------------
+//
+// Level one sorts the (global tile row, Gaussian) pairs by row (a Gaussian's rectangle spans a
+// few rows, so there are far fewer pairs than keys): k_dup_rows writes them in Gaussian order,
+// the stable radix sort orders them by row, k_row_bounds finds each row's pairs.  Level two
+// cuts every row's pairs (in Gaussian order) into chunks of ROW_CHUNK: k_row_table numbers the
+// chunks and lays out one count per (row, column, chunk), row-major, then column, then chunk;
+// k_row_hist fills the counts, one chained scan turns them into the first position of every
+// chunk's keys of every tile (that order is tile order), and k_row_scatter ranks each chunk's
+// keys per column in Gaussian order and writes records, slots and ranges there.  The result is
+// that of the stable sort of all keys by tile.
+
+// Block b handles Gaussians [256 b, 256 b + 256): their key offsets (slot bases), rebuilt from
+// the scanned block sums, and their (row, Gaussian) pairs at the scanned row offsets.  A pair
+// finds its Gaussian in an LDS table (one byte per pair) when the block's pairs fit, else by
+// binary search.
+__global__ __launch_bounds__(BLK) void k_dup_rows(const uint32_t *__restrict__ count,
+                                                  const unsigned long long *__restrict__ bs,
+                                                  const unsigned long long *__restrict__ rbs,
+                                                  int64_t n, int64_t cap,
+                                                  uint32_t *__restrict__ off,
+                                                  float4 *__restrict__ proj,
+                                                  uint32_t *__restrict__ rkeys,
+                                                  uint32_t *__restrict__ rvals,
+                                                  DevState *state) {
+    __shared__ unsigned long long tmp[BLK / 64 + 1];
+    __shared__ uint32_t pre[BLK];
+    __shared__ uint32_t srow[BLK];
+    __shared__ uint8_t owner[DUP_OWN_CAP];
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    const int64_t ir = i < n ? i : n - 1;
+    // reads issued together (clamped index), used after
+    const uint32_t c_in = count[ir];
+    const uint4 rl = __builtin_bit_cast(uint4, proj[PROJ_F4 * ir + 3]);  // first row, rows
+    const unsigned long long kbase = bs[blockIdx.x], rbase = rbs[blockIdx.x];
+    const uint32_t c = i < n ? c_in : 0u;
+    const uint32_t h = i < n ? rl.y : 0u;
+    unsigned long long ktot, rtot;
+    const unsigned long long kloc = block_exclusive_scan<unsigned long long, BLK>(c, tmp, &ktot);
+    const unsigned long long rloc = block_exclusive_scan<unsigned long long, BLK>(h, tmp, &rtot);
+    const bool table = rtot <= DUP_OWN_CAP;  // the same for the whole block
+    if (table)
+        for (uint32_t k = 0; k < h; ++k) owner[rloc + k] = (uint8_t)threadIdx.x;
+    pre[threadIdx.x] = (uint32_t)rloc;
+    srow[threadIdx.x] = rl.x;
+    if (i < n) {
+        off[i] = (uint32_t)(kbase + kloc);
+        reinterpret_cast<uint32_t *>(proj)[4 * (PROJ_F4 * i + 2)] = (uint32_t)(kbase + kloc);
+    }
+    __syncthreads();
+    unsigned long long limit = rtot;
+    if (rbase >= (unsigned long long)cap) limit = 0;
+    else if (rbase + rtot > (unsigned long long)cap) limit = (unsigned long long)cap - rbase;
+    if (limit < rtot && threadIdx.x == 0) atomicOr(&state->flags, FLAG_KEY_OVERFLOW);
+    for (uint32_t j = threadIdx.x; j < limit; j += BLK) {
+        int lo = 0;  // owner: largest g with pre[g] <= j
+        if (table) {
+            lo = owner[j];
+        } else {
+            int hi = BLK - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+            }
+        }
+        rkeys[rbase + j] = srow[lo] + (j - pre[lo]);
+        rvals[rbase + j] = (uint32_t)((int64_t)blockIdx.x * BLK + lo);
+    }
+}
+
+// First and end position of every row's pairs in the sorted pair list (rows without pairs keep
+// the zeros they were filled with).
+__global__ __launch_bounds__(BLK) void k_row_bounds(const uint32_t *__restrict__ rk,
+                                                    const unsigned long long *n_dev,
+                                                    int64_t n_max, uint2 *__restrict__ rrange) {
+    const int64_t n = sort_count(n_dev, n_max);
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t key = rk[i];
+    const uint32_t kp = rk[i > 0 ? i - 1 : 0], kn = rk[i + 1 < n ? i + 1 : i];
+    if (i == 0 || kp != key) rrange[key].x = (uint32_t)i;
+    if (i == n - 1 || kn != key) rrange[key].y = (uint32_t)(i + 1);
+}
+
+// First global tile and tiles per row of global tile row r.
+__device__ inline uint2 row_tiles(const ImgTable &t, uint32_t r) {
+    if (t.B == 1) return make_uint2(r * (uint32_t)t.TW, (uint32_t)t.TW);
+    return t.row_tiles[r];
+}
+
+constexpr int RT_T = 1024;  // threads of the row table
+constexpr int RT_PER = 8;   // rows per thread and round
+
+// One block.  Rows in rounds of RT_T * RT_PER (each thread RT_PER consecutive rows): chunk
+// counts and count-array sizes, scanned with the totals of earlier rounds carried; rinfo per
+// row; the row of every chunk (found by binary search over the round's chunk bases in LDS).
+// The count array gets one more entry, a zero, so that its scan ends with the total of the
+// keys written.  On overflow of the bounds the kernels after it see zero chunks and the
+// overflow flag is set.
+__global__ __launch_bounds__(RT_T) void k_row_table(const uint2 *__restrict__ rrange,
+                                                    ImgTable tab, int64_t rows, int64_t nch_max,
+                                                    int64_t scan_max, uint4 *__restrict__ rinfo,
+                                                    uint32_t *__restrict__ chunk_row,
+                                                    uint32_t *__restrict__ scan,
+                                                    DevState *state) {
+    __shared__ unsigned long long tmp[RT_T / 64 + 1];
+    __shared__ uint32_t lcb[RT_T * RT_PER];
+    unsigned long long cc = 0, cs = 0;  // chunks and counts of earlier rounds
+    for (int64_t r0 = 0; r0 < rows; r0 += RT_T * RT_PER) {
+        const int64_t nr = rows - r0 < RT_T * RT_PER ? rows - r0 : RT_T * RT_PER;
+        uint2 rr[RT_PER], rt[RT_PER];
+#pragma unroll
+        for (int j = 0; j < RT_PER; ++j) {
+            int64_t q = (int64_t)threadIdx.x * RT_PER + j;
+            q = r0 + (q < nr ? q : nr - 1);
+            rr[j] = rrange[q];
+            rt[j] = row_tiles(tab, (uint32_t)q);
+        }
+        uint32_t nch[RT_PER];
+        unsigned long long sc = 0, ss = 0;
+#pragma unroll
+        for (int j = 0; j < RT_PER; ++j) {
+            const bool ok = (int64_t)threadIdx.x * RT_PER + j < nr && rr[j].y > rr[j].x;
+            nch[j] = ok ? (rr[j].y - rr[j].x + ROW_CHUNK - 1) / ROW_CHUNK : 0u;
+            sc += nch[j];
+            ss += (unsigned long long)nch[j] * rt[j].y;
+        }
+        unsigned long long tc, ts;
+        unsigned long long cb = cc + block_exclusive_scan<unsigned long long, RT_T>(sc, tmp, &tc);
+        unsigned long long sb = cs + block_exclusive_scan<unsigned long long, RT_T>(ss, tmp, &ts);
+#pragma unroll
+        for (int j = 0; j < RT_PER; ++j) {
+            const int64_t q = (int64_t)threadIdx.x * RT_PER + j;
+            if (q < nr) {
+                rinfo[2 * (r0 + q)] = make_uint4(rr[j].x, rr[j].x + (nch[j] ? rr[j].y - rr[j].x : 0u),
+                                                 (uint32_t)cb, (uint32_t)sb);
+                rinfo[2 * (r0 + q) + 1] = make_uint4(rt[j].x, rt[j].y, nch[j], 0u);
+                lcb[q] = (uint32_t)(cb - cc);
+            }
+            cb += nch[j];
+            sb += (unsigned long long)nch[j] * rt[j].y;
+        }
+        __syncthreads();
+        // the row of each of this round's chunks: the last row whose first chunk is at most it
+        // (rows without chunks share the next row's first chunk and come before it)
+        for (unsigned long long k = threadIdx.x; k < tc; k += RT_T) {
+            int lo = 0, hi = (int)nr - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (lcb[mid] <= (uint32_t)k) lo = mid; else hi = mid - 1;
+            }
+            if (cc + k < (unsigned long long)nch_max) chunk_row[cc + k] = (uint32_t)(r0 + lo);
+        }
+        __syncthreads();
+        cc += tc;
+        cs += ts;
+    }
+    if (threadIdx.x == 0) {
+        const bool fits = cc <= (unsigned long long)nch_max && cs < (unsigned long long)scan_max;
+        if (fits) scan[cs] = 0u;
+        state->row_chunks = fits ? (uint32_t)cc : 0u;
+        state->row_scan_len = fits ? cs + 1 : 0ull;
+        if (!fits) atomicOr(&state->flags, FLAG_KEY_OVERFLOW);
+    }
+}
+
+// The chunk of workgroup blockIdx.x (contiguous ranges of chunks per XCD, so that a row's
+// chunks share an L2), its row and the row's table entries.
+struct RowChunk {
+    uint32_t k;      // chunk within the row
+    uint32_t first;  // first pair of the chunk
+    uint32_t pairs;  // pairs in the chunk (1 .. ROW_CHUNK)
+    uint32_t sofs;   // the row's first count
+    uint32_t nch;    // the row's chunks
+    uint32_t tile0;  // the row's first global tile
+    uint32_t tw;     // the row's tiles
+    uint32_t row;
+};
+
+__device__ inline RowChunk row_chunk(const uint4 *__restrict__ rinfo,
+                                     const uint32_t *__restrict__ chunk_row, uint32_t nc) {
+    RowChunk rc;
+    const uint32_t c = xcd_chunk(blockIdx.x, nc);
+    rc.row = chunk_row[c];
+    const uint4 a = rinfo[2 * rc.row], b = rinfo[2 * rc.row + 1];
+    rc.k = c - a.z;
+    rc.first = a.x + rc.k * ROW_CHUNK;
+    rc.pairs = a.y - rc.first < (uint32_t)ROW_CHUNK ? a.y - rc.first : (uint32_t)ROW_CHUNK;
+    rc.sofs = a.w;
+    rc.nch = b.z;
+    rc.tile0 = b.x;
+    rc.tw = b.y;
+    return rc;
+}
+
+// Per chunk: the number of its Gaussians covering each column of the row (a difference array:
+// +1 at the rectangle's first column, -1 after its last, then the prefix sums), stored at
+// scan[sofs + column * nch + k].
+__global__ __launch_bounds__(ROW_CHUNK) void k_row_hist(const uint32_t *__restrict__ rvals,
+                                                        const uint4 *__restrict__ rinfo,
+                                                        const uint32_t *__restrict__ chunk_row,
+                                                        const float4 *__restrict__ proj,
+                                                        uint32_t *__restrict__ scan,
+                                                        DevState *state) {
+    __shared__ uint32_t d[ROW_MAX_TW + 1];
+    __shared__ unsigned long long tmp[ROW_CHUNK / 64 + 1];
+    // a new epoch for the scan that follows (see k_chained_scan)
+    if (blockIdx.x == 0 && threadIdx.x == 0) state->scan_epoch += 1u;
+    const uint32_t nc = state->row_chunks;
+    if (blockIdx.x >= nc) return;
+    const RowChunk rc = row_chunk(rinfo, chunk_row, nc);
+    const uint32_t e = rc.first + (threadIdx.x < rc.pairs ? threadIdx.x : 0u);
+    const uint32_t g = rvals[e];
+    const uint4 f = __builtin_bit_cast(uint4, proj[PROJ_F4 * (int64_t)g + 2]);
+    for (uint32_t x = threadIdx.x; x <= rc.tw; x += ROW_CHUNK) d[x] = 0u;
+    __syncthreads();
+    if (threadIdx.x < rc.pairs) {
+        const uint32_t x0 = f.w & 0xffffu, w = f.z >> 16;
+        atomicAdd(&d[x0], 1u);
+        atomicSub(&d[x0 + w], 1u);
+    }
+    __syncthreads();
+    // prefix sums: thread t takes columns [t per, t per + per)
+    const uint32_t per = (rc.tw + ROW_CHUNK - 1) / ROW_CHUNK;
+    const uint32_t x0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (uint32_t x = x0; x < x0 + per && x < rc.tw; ++x) s += d[x];
+    unsigned long long tot;
+    uint32_t run = (uint32_t)block_exclusive_scan<unsigned long long, ROW_CHUNK>(s, tmp, &tot);
+    for (uint32_t x = x0; x < x0 + per && x < rc.tw; ++x) {
+        run += d[x];
+        scan[rc.sofs + (int64_t)x * rc.nch + rc.k] = run;
+    }
+}
+
+// Per chunk: its keys in Gaussian order (a pair's keys are its columns left to right), ranked
+// stably per column by the waves (each takes a contiguous share), written at the scanned
+// positions: the records, slots, Gaussian ids and opacities wanted; the first chunk of a row
+// also writes the row's tile ranges.
+template <int WV>
+__global__ __launch_bounds__(64 * WV) void k_row_scatter(
+    const uint32_t *__restrict__ rvals, const uint4 *__restrict__ rinfo,
+    const uint32_t *__restrict__ chunk_row, const float4 *__restrict__ proj,
+    const uint32_t *__restrict__ scan, int64_t cap, float4 *__restrict__ rec,
+    uint32_t *__restrict__ slot, uint32_t *__restrict__ ids, uint2 *__restrict__ ranges,
+    const float *__restrict__ opac, float *__restrict__ rec_o, DevState *state) {
+    extern __shared__ uint32_t dyn[];  // wh [WV][tw], then tbase [tw]
+    constexpr int NT = 64 * WV;
+    static_assert(NT >= ROW_CHUNK, "one thread per pair of a chunk");
+    __shared__ unsigned long long tmp[NT / 64 + 1];
+    __shared__ uint32_t pre[ROW_CHUNK];
+    __shared__ uint32_t sx0[ROW_CHUNK];    // first column
+    __shared__ uint32_t sbase[ROW_CHUNK];  // slot of the key in column 0 (modulo 2^32)
+    __shared__ uint32_t sg[ROW_CHUNK];
+    __shared__ float4 sproj[2 * ROW_CHUNK];
+    __shared__ uint8_t owner[OWN_CAP];
+    const uint32_t nc = state->row_chunks;
+    if (blockIdx.x >= nc) return;
+    const RowChunk rc = row_chunk(rinfo, chunk_row, nc);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t tw = rc.tw;
+    uint32_t *wh = dyn;
+    uint32_t *tbase = dyn + WV * tw;
+    // set-up reads issued together (clamped indices), used after
+    const bool mine = threadIdx.x < rc.pairs;
+    const uint32_t g = rvals[rc.first + (mine ? threadIdx.x : 0u)];
+    const float4 pa = proj[PROJ_F4 * (int64_t)g], pb = proj[PROJ_F4 * (int64_t)g + 1];
+    const uint4 f = __builtin_bit_cast(uint4, proj[PROJ_F4 * (int64_t)g + 2]);
+    const uint4 rl = __builtin_bit_cast(uint4, proj[PROJ_F4 * (int64_t)g + 3]);
+    constexpr int TB_MAX = (ROW_MAX_TW + NT - 1) / NT;
+    uint32_t tb_in[TB_MAX];
+#pragma unroll
+    for (int k = 0; k < TB_MAX; ++k) {
+        const uint32_t x = threadIdx.x + k * NT;
+        tb_in[k] = scan[rc.sofs + (int64_t)(x < tw ? x : tw - 1) * rc.nch + rc.k];
+    }
+    const uint32_t w = mine ? f.z >> 16 : 0u;
+    unsigned long long tot;
+    const unsigned long long loc = block_exclusive_scan<unsigned long long, NT>(w, tmp, &tot);
+    const bool table = tot <= OWN_CAP;  // the same for the whole block
+    if (table)
+        for (uint32_t k = 0; k < w; ++k) owner[loc + k] = (uint8_t)threadIdx.x;
+    if (mine) {
+        const uint32_t x0 = f.w & 0xffffu;
+        pre[threadIdx.x] = (uint32_t)loc;
+        sx0[threadIdx.x] = x0;
+        // slot = key offset + (row - first row) w + (column - first column)
+        sbase[threadIdx.x] = f.x + (rc.row - rl.x) * w - x0;
+        sg[threadIdx.x] = g;
+        sproj[2 * threadIdx.x] = pa;
+        sproj[2 * threadIdx.x + 1] = pb;
+    } else if (threadIdx.x < ROW_CHUNK) {
+        pre[threadIdx.x] = 0xffffffffu;  // never the owner of a key
+    }
+    for (uint32_t k = threadIdx.x; k < WV * tw; k += NT) wh[k] = 0u;
+#pragma unroll
+    for (int k = 0; k < TB_MAX; ++k) {
+        const uint32_t x = threadIdx.x + k * NT;
+        if (x < tw) tbase[x] = tb_in[k];
+    }
+    // the row's tile ranges, by its first chunk (a tile ends where the next count begins;
+    // after the last row that is the closing zero entry, i.e. the total)
+    if (rc.k == 0) {
+        for (uint32_t x = threadIdx.x; x < tw; x += NT) {
+            const int64_t ia = rc.sofs + (int64_t)x * rc.nch, ib = ia + rc.nch;
+            unsigned long long a = scan[ia];
+            unsigned long long b = scan[ib];
+            if (a > (unsigned long long)cap) a = (unsigned long long)cap;
+            if (b > (unsigned long long)cap) b = (unsigned long long)cap;
+            ranges[rc.tile0 + x] = make_uint2((uint32_t)a, (uint32_t)b);
+        }
+    }
+    __syncthreads();
+    int xbits = 1;
+    while ((1u << xbits) < tw) ++xbits;
+    const uint32_t total = (uint32_t)tot;
+    const uint32_t q = (total + WV - 1) / WV;
+    const uint32_t j0 = (uint32_t)wave * q < total ? (uint32_t)wave * q : total;
+    const uint32_t j1 = j0 + q < total ? j0 + q : total;
+    uint32_t *my = wh + wave * tw;
+    // pass 1: per-wave counts per column
+    for (uint32_t base = j0; base < j1; base += 64) {
+        const uint32_t j = base + lane;
+        const bool valid = j < j1;
+        uint32_t x = 0;
+        if (valid) {
+            int lo;
+            if (table) {
+                lo = owner[j];
+            } else {
+                lo = 0;
+                int hi = ROW_CHUNK - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+                }
+            }
+            x = sx0[lo] + (j - pre[lo]);
+        }
+        const unsigned long long peers = match_bits(x, valid, xbits);
+        if (valid && lane == __ffsll((long long)peers) - 1) my[x] += __popcll(peers);
+    }
+    __syncthreads();
+    // wave offsets per column, on top of the chunk's first position in the column's tile
+    for (uint32_t x = threadIdx.x; x < tw; x += NT) {
+        uint32_t run = tbase[x];
+#pragma unroll
+        for (int v = 0; v < WV; ++v) {
+            const uint32_t c = wh[v * tw + x];
+            wh[v * tw + x] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    // pass 2: stable ranks and the writes into tile order
+    bool overflow = false;
+    for (uint32_t base = j0; base < j1; base += 64) {
+        const uint32_t j = base + lane;
+        const bool valid = j < j1;
+        uint32_t x = 0;
+        int e = 0;
+        if (valid) {
+            int lo;
+            if (table) {
+                lo = owner[j];
+            } else {
+                lo = 0;
+                int hi = ROW_CHUNK - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+                }
+            }
+            e = lo;
+            x = sx0[lo] + (j - pre[lo]);
+        }
+        const unsigned long long peers = match_bits(x, valid, xbits);
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        const uint32_t old = valid ? my[x] : 0u;
+        if (valid && lane == __ffsll((long long)peers) - 1) my[x] = old + __popcll(peers);
+        const uint32_t pos = old + __popcll(peers & lt);
+        const bool ok = valid && pos < cap;
+        if (valid && !ok) overflow = true;
+        if (ok) {
+            const uint32_t sl = sbase[e] + x;  // kept below the capacity, as in k_fused_scatter
+            slot[pos] = sl < cap ? sl : (uint32_t)(cap - 1);
+            if (ids) ids[pos] = sg[e];
+            if (rec_o) rec_o[pos] = opac[sg[e]];
+        }
+        // records two lanes per record (see k_fused_scatter)
+        const bool odd = lane & 1;
+        const int pe = dpp_swap_pair(e);
+        const uint32_t ppos = (uint32_t)dpp_swap_pair((int)pos);
+        const bool pok = dpp_swap_pair(ok ? 1 : 0) != 0;
+        {
+            const int ee = odd ? pe : e;
+            const uint32_t pp = odd ? ppos : pos;
+            if (odd ? pok : ok) rec[2 * (int64_t)pp + odd] = sproj[2 * ee + odd];
+        }
+        {
+            const int ee = odd ? e : pe;
+            const uint32_t pp = odd ? pos : ppos;
+            if (odd ? ok : pok) rec[2 * (int64_t)pp + !odd] = sproj[2 * ee + !odd];
         }
     }
     if (__ballot(overflow) && lane == 0) atomicOr(&state->flags, FLAG_KEY_OVERFLOW);
@@ -1074,7 +1514,7 @@ hipError_t launch_project(const BinBuffers &b, const ImgTable &tab, hipStream_t 
     if (b.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_project, dim3(grid_for(b.n, BLK)), dim3(BLK), 0, s, record_src(b), b.n, tab,
                        reinterpret_cast<float4 *>(b.proj), b.rect, b.tinfo, b.count, b.blocksum,
-                       b.state);
+                       nullptr, b.state);
     return hipGetLastError();
 }
 
@@ -1084,7 +1524,7 @@ hipError_t launch_count_scan(const BinBuffers &b, hipStream_t s) {
         return launch_fill_u32(reinterpret_cast<uint32_t *>(&b.state->keys_total), 0u, 2, s);
     }
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, b.blocksum,
-                       (int64_t)grid_for(b.n, BLK), &b.state->keys_total);
+                       (int64_t)grid_for(b.n, BLK), &b.state->keys_total, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -1108,7 +1548,8 @@ hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n,
     }
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, blocksum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, blocksum, nb, total);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, blocksum, nb, total, nullptr,
+                       nullptr);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, blocksum);
     return hipGetLastError();
 }
@@ -1209,7 +1650,7 @@ hipError_t launch_fused_a(const FusedBuffers &f, const ImgTable &tab, hipStream_
     const int64_t L = fused_scan_entries(f.b.n, f.b.n_tiles);
     hipLaunchKernelGGL(k_chained_scan, dim3((unsigned)fused_scan_blocks(f.b.n, f.b.n_tiles)),
                        dim3(CS_T), 0, s, f.scan, L, f.status, f.b.n, &f.b.state->keys_total,
-                       f.b.state);
+                       f.b.state, nullptr);
     return hipGetLastError();
 }
 
@@ -1264,6 +1705,68 @@ hipError_t launch_fused_c(const FusedBuffers &f, uint32_t *ids, hipStream_t s) {
     else
         GI_LAUNCH_SCATTER(4);
 #undef GI_LAUNCH_SCATTER
+    return hipGetLastError();
+}
+
+int64_t row_chunks_max(int64_t cap_p, int64_t rows) {
+    return (cap_p + ROW_CHUNK - 1) / ROW_CHUNK + rows;
+}
+int64_t row_scan_max(int64_t cap_p, int64_t rows, int32_t max_tw) {
+    return row_chunks_max(cap_p, rows) * (int64_t)max_tw + 1;  // + the closing zero
+}
+int64_t chained_scan_blocks(int64_t len) { return (len + CS_TILE - 1) / CS_TILE; }
+
+hipError_t launch_rows_a(const BinBuffers &b, const ImgTable &tab, hipStream_t s) {
+    if (b.n <= 0) return hipErrorInvalidValue;
+    const int64_t nb = grid_for(b.n, BLK);
+    hipLaunchKernelGGL(k_project, dim3((unsigned)nb), dim3(BLK), 0, s, record_src(b), b.n, tab,
+                       reinterpret_cast<float4 *>(b.proj), b.rect, b.tinfo, b.count, b.blocksum,
+                       b.rblocksum, b.state);
+    hipLaunchKernelGGL(k_scan_top, dim3(2), dim3(1024), 0, s, b.blocksum, nb,
+                       &b.state->keys_total, b.rblocksum, &b.state->rows_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_b(const RowBuffers &r, const ImgTable &tab, bool want_ids, int digit_bits,
+                         int *which, hipStream_t s) {
+    const BinBuffers &b = r.b;
+    if (b.n <= 0 || tab.rows <= 0 || tab.max_tw < 1 || tab.max_tw > ROW_MAX_TW)
+        return hipErrorInvalidValue;
+    const int64_t pcap = b.cap_p < b.cap ? b.cap_p : b.cap;
+    float4 *proj = reinterpret_cast<float4 *>(b.proj);
+    hipLaunchKernelGGL(k_dup_rows, dim3(grid_for(b.n, BLK)), dim3(BLK), 0, s, b.count, b.blocksum,
+                       b.rblocksum, b.n, pcap, b.off, proj, b.keys[0], b.vals[0], b.state);
+    int kb = 1;
+    while (((int64_t)1 << kb) < (int64_t)tab.rows) ++kb;
+    int w = 0;
+    hipError_t e = launch_sort_pairs(b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0],
+                                     b.vals[0], pcap, &b.state->rows_total, kb, digit_bits,
+                                     b.hist, b.scan_blocksum, &w, s);
+    if (e != hipSuccess) return e;
+    const int at = w == 0 ? 1 : 0;  // keys[1] after an odd number of passes
+    *which = at;
+    const uint32_t *rk = b.keys[at], *rv = b.vals[at];
+    uint32_t *ids = want_ids ? b.vals[1 - at] : nullptr;
+    if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(r.rrange), 0u, 2 * (int64_t)tab.rows,
+                             s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_row_bounds, dim3(grid_for(pcap, BLK)), dim3(BLK), 0, s, rk,
+                       &b.state->rows_total, pcap, r.rrange);
+    hipLaunchKernelGGL(k_row_table, dim3(1), dim3(RT_T), 0, s, r.rrange, tab, (int64_t)tab.rows,
+                       r.nch_max, r.scan_max, r.rinfo, r.chunk_row, r.scan, b.state);
+    hipLaunchKernelGGL(k_row_hist, dim3((unsigned)r.nch_max), dim3(ROW_CHUNK), 0, s, rv, r.rinfo,
+                       r.chunk_row, proj, r.scan, b.state);
+    hipLaunchKernelGGL(k_chained_scan, dim3((unsigned)chained_scan_blocks(r.scan_max)), dim3(CS_T),
+                       0, s, r.scan, r.scan_max, r.status, (int64_t)-1, nullptr, b.state,
+                       &b.state->row_scan_len);
+    if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(b.ranges), 0u, 2 * b.n_tiles, s)) !=
+        hipSuccess)
+        return e;
+    constexpr int WV = 4;
+    hipLaunchKernelGGL(k_row_scatter<WV>, dim3((unsigned)r.nch_max), dim3(64 * WV),
+                       sizeof(uint32_t) * (WV + 1) * (size_t)tab.max_tw, s, rv, r.rinfo,
+                       r.chunk_row, proj, r.scan, b.cap, reinterpret_cast<float4 *>(b.rec), b.slot,
+                       ids, b.ranges, b.opacity, b.rec_o, b.state);
     return hipGetLastError();
 }
 

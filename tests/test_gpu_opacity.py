@@ -72,7 +72,7 @@ def gi():
     ctx.close()
 
 
-@pytest.fixture(params=[1, 2], ids=["radix", "one-pass"])
+@pytest.fixture(params=[1, 2, 3], ids=["radix", "one-pass", "rows"])
 def mode(request, gi):
     import paper_2403_08551_amd as P
     gi.set_option(P._lib.GI_OPT_BINNING, request.param)

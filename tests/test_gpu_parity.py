@@ -82,7 +82,7 @@ def assert_grads(g, o, A, what):
 
 # ------------------------------------------------------------------ binning (bit-exact)
 
-@pytest.fixture(params=[1, 2], ids=["radix", "one-pass"])
+@pytest.fixture(params=[1, 2, 3], ids=["radix", "one-pass", "rows"])
 def mode(request, gi):
     import paper_2403_08551_amd as P
     gi.set_option(P._lib.GI_OPT_BINNING, request.param)
@@ -122,14 +122,14 @@ def test_binning_independent_of_digit_width(gi, bits):
 
 
 def test_binning_paths_give_identical_results(gi):
-    # the one-pass counting sort and the radix sort produce the same tile order, so renders,
-    # gradients and fit steps agree bit for bit
+    # the one-pass counting sort, the row binning and the radix sort produce the same tile
+    # order, so renders, gradients and fit steps agree bit for bit
     import paper_2403_08551_amd as P
     w = synth.plain_256()
     p0, T = w.params(), dev(w.target())
     G = dev(synth.upstream_gradient(w.height, w.width, 9))
     out = {}
-    for m in (1, 2):
+    for m in (1, 2, 3):
         gi.set_option(P._lib.GI_OPT_BINNING, m)
         try:
             p = dev(p0)
@@ -142,8 +142,9 @@ def test_binning_paths_give_identical_results(gi):
             out[m] = (img, d, host(p))
         finally:
             gi.set_option(P._lib.GI_OPT_BINNING, 0)
-    for a, b in zip(out[1], out[2]):
-        np.testing.assert_array_equal(a, b)
+    for m in (2, 3):
+        for a, b in zip(out[1], out[m]):
+            np.testing.assert_array_equal(a, b)
 
 
 # ------------------------------------------------------------------ sort and scan primitives
@@ -336,7 +337,9 @@ def test_batched_fit_equals_plain_fit(gi):
 
 # ------------------------------------------------------------------ captured steps
 
-def test_graph_replay_matches_eager_steps(gi):
+@pytest.mark.parametrize("binning", [0, 3], ids=["auto", "rows"])
+def test_graph_replay_matches_eager_steps(gi, binning):
+    # the captured steps bin with the option given (eager steps: the default one-pass path)
     w = synth.plain_256()
     p0, T = w.params(), dev(w.target())
     pa, pb = dev(p0), dev(p0)
@@ -347,6 +350,7 @@ def test_graph_replay_matches_eager_steps(gi):
         gi.fit_step(pa, ma, va, T, sa)
     import paper_2403_08551_amd as P
     g = P.Context(0)
+    g.set_option(P._lib.GI_OPT_BINNING, binning)
     graph = g.fit_graph(pb, mb, vb, T, sb)
     for _ in range(2):  # eager work and synchronisation between replays
         graph.launch(2)
@@ -402,7 +406,7 @@ def test_nonfinite_flag(gi):
     assert flags & 2
 
 
-@pytest.mark.parametrize("binning", [1, 2])
+@pytest.mark.parametrize("binning", [1, 2, 3])
 def test_key_overflow_skips_the_update(binning):
     import paper_2403_08551_amd as P
     ctx = P.Context(0)
@@ -467,6 +471,42 @@ def test_div2k_size_sampled(gi, n):
     which = rng.choice(n, 64, replace=False)
     od, Ad = cref.grads_subset(p, h, wd, G, which, with_abs=True)
     assert_grads(d[which], od, Ad, f"div2k {n} sampled gradients")
+
+
+def binning_in_mode(gi, mode, pd, h, wd):
+    import paper_2403_08551_amd as P
+    gi.set_option(P._lib.GI_OPT_BINNING, mode)
+    try:
+        b = gi.binning(pd, h, wd)
+        return b["keys"], host(b["ranges"]), host(b["ids"]), host(b["offsets"])
+    finally:
+        gi.set_option(P._lib.GI_OPT_BINNING, 0)
+
+
+@pytest.mark.parametrize("n", [300_000])
+def test_row_binning_equals_radix_at_full_size(gi, n):
+    # 2040x1356, 10880 tiles: the row binning (the default at this size) against the radix
+    # sort, key for key; the radix path is itself checked against the oracle above
+    w = synth.div2k_full(n)
+    pd = dev(w.params())
+    rows = binning_in_mode(gi, 3, pd, w.height, w.width)
+    radix = binning_in_mode(gi, 1, pd, w.height, w.width)
+    assert rows[0] == radix[0]
+    for a, b in zip(rows[1:], radix[1:]):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_row_binning_matches_oracle_on_wide_rows(gi):
+    # one image 1024 tiles wide (the widest row binning takes) and one tile high, and a
+    # 1025-tile-wide one (radix then); tile lists against the oracle
+    for wd in (16 * 1024, 16 * 1024 + 5):
+        h = 20
+        p = synth.gaussians(3000, h, wd, seed=wd, l_lo=0.5, l_hi=40.0)
+        ranges, ids = cref.tile_lists(p, h, wd)
+        k, r, i, _ = binning_in_mode(gi, 3, dev(p), h, wd)
+        assert k == ids.size
+        np.testing.assert_array_equal(r, ranges)
+        np.testing.assert_array_equal(i, ids)
 
 
 # ------------------------------------------------------------------ autotuner
