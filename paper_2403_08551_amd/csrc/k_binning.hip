@@ -8,6 +8,7 @@
 // (tile id, Gaussian id) key per covered tile, in row-major order within its rectangle, and a
 // stable sort by tile id yields per-tile lists in ascending Gaussian order.
 #include <cstring>
+#include <type_traits>
 
 #include "gi_common.h"
 
@@ -1213,6 +1214,12 @@ __global__ __launch_bounds__(RT_T) void k_row_table(const uint2 *__restrict__ rr
     }
 }
 
+// Chunk-local key -> its pair (one byte while a chunk has at most 256 pairs), for chunks of up
+// to ROW_OWN_CAP keys (else binary search).
+using RowOwner = typename std::conditional<(ROW_CHUNK <= 256), uint8_t, uint16_t>::type;
+constexpr uint32_t ROW_OWN_CAP = 16 * ROW_CHUNK;
+constexpr int ROW_WAVES = ROW_CHUNK / 64;  // scatter waves: one thread per pair
+
 // The chunk of workgroup blockIdx.x (contiguous ranges of chunks per XCD, so that a row's
 // chunks share an L2), its row and the row's table entries.
 struct RowChunk {
@@ -1293,7 +1300,7 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
     const uint32_t *__restrict__ scan, int64_t cap, float4 *__restrict__ rec,
     uint32_t *__restrict__ slot, uint32_t *__restrict__ ids, uint2 *__restrict__ ranges,
     const float *__restrict__ opac, float *__restrict__ rec_o, DevState *state) {
-    extern __shared__ uint32_t dyn[];  // wh [WV][tw], then tbase [tw]
+    extern __shared__ uint32_t dyn[];  // wh [WV][tw], tbase [tw], lcs [tw]
     constexpr int NT = 64 * WV;
     static_assert(NT >= ROW_CHUNK, "one thread per pair of a chunk");
     __shared__ unsigned long long tmp[NT / 64 + 1];
@@ -1302,7 +1309,8 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
     __shared__ uint32_t sbase[ROW_CHUNK];  // slot of the key in column 0 (modulo 2^32)
     __shared__ uint32_t sg[ROW_CHUNK];
     __shared__ float4 sproj[2 * ROW_CHUNK];
-    __shared__ uint8_t owner[OWN_CAP];
+    __shared__ RowOwner owner[ROW_OWN_CAP];
+    __shared__ uint32_t inv[ROW_OWN_CAP];  // chunk-local position in tile order -> pair | column << 16
     const uint32_t nc = state->row_chunks;
     if (blockIdx.x >= nc) return;
     const RowChunk rc = row_chunk(rinfo, chunk_row, nc);
@@ -1310,6 +1318,7 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
     const uint32_t tw = rc.tw;
     uint32_t *wh = dyn;
     uint32_t *tbase = dyn + WV * tw;
+    uint32_t *lcs = tbase + tw;  // chunk-local first position of each column
     // set-up reads issued together (clamped indices), used after
     const bool mine = threadIdx.x < rc.pairs;
     const uint32_t g = rvals[rc.first + (mine ? threadIdx.x : 0u)];
@@ -1326,9 +1335,9 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
     const uint32_t w = mine ? f.z >> 16 : 0u;
     unsigned long long tot;
     const unsigned long long loc = block_exclusive_scan<unsigned long long, NT>(w, tmp, &tot);
-    const bool table = tot <= OWN_CAP;  // the same for the whole block
+    const bool table = tot <= ROW_OWN_CAP;  // the same for the whole block
     if (table)
-        for (uint32_t k = 0; k < w; ++k) owner[loc + k] = (uint8_t)threadIdx.x;
+        for (uint32_t k = 0; k < w; ++k) owner[loc + k] = (RowOwner)threadIdx.x;
     if (mine) {
         const uint32_t x0 = f.w & 0xffffu;
         pre[threadIdx.x] = (uint32_t)loc;
@@ -1390,6 +1399,83 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
         if (valid && lane == __ffsll((long long)peers) - 1) my[x] += __popcll(peers);
     }
     __syncthreads();
+    if (table) {
+        // Staged: the chunk's keys are ranked into chunk-local positions in tile order (LDS),
+        // then written out in that order, so that each column's keys go out as one contiguous
+        // run and the stores are coalesced.  Wave offsets within each column's run, the
+        // chunk's count per column, and the columns' chunk-local starts:
+        const uint32_t per = (tw + NT - 1) / NT, cx0 = threadIdx.x * per;
+        const uint32_t cx1 = cx0 + per < tw ? cx0 + per : tw;
+        uint32_t csum = 0;
+        for (uint32_t x = cx0; x < cx1; ++x) {
+            uint32_t run = 0;
+#pragma unroll
+            for (int v = 0; v < WV; ++v) {
+                const uint32_t c = wh[v * tw + x];
+                wh[v * tw + x] = run;
+                run += c;
+            }
+            lcs[x] = run;
+            csum += run;
+        }
+        unsigned long long ctot;
+        uint32_t run = (uint32_t)block_exclusive_scan<unsigned long long, NT>(csum, tmp, &ctot);
+        for (uint32_t x = cx0; x < cx1; ++x) {
+            const uint32_t c = lcs[x];
+            lcs[x] = run;
+            run += c;
+        }
+        __syncthreads();
+        // pass 2: stable ranks, as chunk-local positions
+        for (uint32_t base = j0; base < j1; base += 64) {
+            const uint32_t j = base + lane;
+            const bool valid = j < j1;
+            const int e = valid ? (int)owner[j] : 0;
+            const uint32_t x = valid ? sx0[e] + (j - pre[e]) : 0u;
+            const unsigned long long peers = match_bits(x, valid, xbits);
+            const unsigned long long lt = (1ull << lane) - 1ull;
+            const uint32_t old = valid ? my[x] : 0u;
+            if (valid && lane == __ffsll((long long)peers) - 1) my[x] = old + __popcll(peers);
+            if (valid) inv[lcs[x] + old + __popcll(peers & lt)] = (uint32_t)e | (x << 16);
+        }
+        __syncthreads();
+        // pass 3: the writes, in tile order
+        bool overflow = false;
+        for (uint32_t base = 0; base < total; base += NT) {
+            const uint32_t j = base + threadIdx.x;
+            const bool valid = j < total;
+            const uint32_t v = inv[valid ? j : 0u];
+            const int e = (int)(v & 0xffffu);
+            const uint32_t x = v >> 16;
+            const uint32_t pos = tbase[x] + (j - lcs[x]);
+            const bool ok = valid && pos < cap;
+            if (valid && !ok) overflow = true;
+            if (ok) {
+                const uint32_t sl = sbase[e] + x;  // kept below the capacity, as in k_fused_scatter
+                slot[pos] = sl < cap ? sl : (uint32_t)(cap - 1);
+                if (ids) ids[pos] = sg[e];
+                if (rec_o) rec_o[pos] = opac[sg[e]];
+            }
+            // records two lanes per record (see k_fused_scatter): consecutive lanes hold
+            // consecutive positions, so each store covers a contiguous stretch
+            const bool odd = lane & 1;
+            const int pe = dpp_swap_pair(e);
+            const uint32_t ppos = (uint32_t)dpp_swap_pair((int)pos);
+            const bool pok = dpp_swap_pair(ok ? 1 : 0) != 0;
+            {
+                const int ee = odd ? pe : e;
+                const uint32_t pp = odd ? ppos : pos;
+                if (odd ? pok : ok) rec[2 * (int64_t)pp + odd] = sproj[2 * ee + odd];
+            }
+            {
+                const int ee = odd ? e : pe;
+                const uint32_t pp = odd ? pos : ppos;
+                if (odd ? ok : pok) rec[2 * (int64_t)pp + !odd] = sproj[2 * ee + !odd];
+            }
+        }
+        if (__ballot(overflow) && lane == 0) atomicOr(&state->flags, FLAG_KEY_OVERFLOW);
+        return;
+    }
     // wave offsets per column, on top of the chunk's first position in the column's tile
     for (uint32_t x = threadIdx.x; x < tw; x += NT) {
         uint32_t run = tbase[x];
@@ -1762,9 +1848,9 @@ hipError_t launch_rows_b(const RowBuffers &r, const ImgTable &tab, bool want_ids
     if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(b.ranges), 0u, 2 * b.n_tiles, s)) !=
         hipSuccess)
         return e;
-    constexpr int WV = 4;
+    constexpr int WV = ROW_WAVES;
     hipLaunchKernelGGL(k_row_scatter<WV>, dim3((unsigned)r.nch_max), dim3(64 * WV),
-                       sizeof(uint32_t) * (WV + 1) * (size_t)tab.max_tw, s, rv, r.rinfo,
+                       sizeof(uint32_t) * (WV + 2) * (size_t)tab.max_tw, s, rv, r.rinfo,
                        r.chunk_row, proj, r.scan, b.cap, reinterpret_cast<float4 *>(b.rec), b.slot,
                        ids, b.ranges, b.opacity, b.rec_o, b.state);
     return hipGetLastError();
