@@ -1303,14 +1303,15 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
     extern __shared__ uint32_t dyn[];  // wh [WV][tw], tbase [tw], lcs [tw]
     constexpr int NT = 64 * WV;
     static_assert(NT >= ROW_CHUNK, "one thread per pair of a chunk");
+    static_assert(ROW_CHUNK <= 256, "staged positions hold the pair in 8 bits");
     __shared__ unsigned long long tmp[NT / 64 + 1];
     __shared__ uint32_t pre[ROW_CHUNK];
     __shared__ uint32_t sx0[ROW_CHUNK];    // first column
     __shared__ uint32_t sbase[ROW_CHUNK];  // slot of the key in column 0 (modulo 2^32)
-    __shared__ uint32_t sg[ROW_CHUNK];
     __shared__ float4 sproj[2 * ROW_CHUNK];
     __shared__ RowOwner owner[ROW_OWN_CAP];
-    __shared__ uint32_t inv[ROW_OWN_CAP];  // chunk-local position in tile order -> pair | column << 16
+    // chunk-local position in tile order -> pair | (column - first column) << 8
+    __shared__ uint16_t inv[ROW_OWN_CAP];
     const uint32_t nc = state->row_chunks;
     if (blockIdx.x >= nc) return;
     const RowChunk rc = row_chunk(rinfo, chunk_row, nc);
@@ -1335,7 +1336,9 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
     const uint32_t w = mine ? f.z >> 16 : 0u;
     unsigned long long tot;
     const unsigned long long loc = block_exclusive_scan<unsigned long long, NT>(w, tmp, &tot);
-    const bool table = tot <= ROW_OWN_CAP;  // the same for the whole block
+    // the staged path: the chunk's keys fit the tables and every rectangle is at most 256
+    // tiles wide (the same for the whole block)
+    const bool table = __syncthreads_and(tot <= ROW_OWN_CAP && w <= 256u) != 0;
     if (table)
         for (uint32_t k = 0; k < w; ++k) owner[loc + k] = (RowOwner)threadIdx.x;
     if (mine) {
@@ -1344,7 +1347,6 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
         sx0[threadIdx.x] = x0;
         // slot = key offset + (row - first row) w + (column - first column)
         sbase[threadIdx.x] = f.x + (rc.row - rl.x) * w - x0;
-        sg[threadIdx.x] = g;
         sproj[2 * threadIdx.x] = pa;
         sproj[2 * threadIdx.x + 1] = pb;
     } else if (threadIdx.x < ROW_CHUNK) {
@@ -1436,7 +1438,8 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
             const unsigned long long lt = (1ull << lane) - 1ull;
             const uint32_t old = valid ? my[x] : 0u;
             if (valid && lane == __ffsll((long long)peers) - 1) my[x] = old + __popcll(peers);
-            if (valid) inv[lcs[x] + old + __popcll(peers & lt)] = (uint32_t)e | (x << 16);
+            if (valid)
+                inv[lcs[x] + old + __popcll(peers & lt)] = (uint16_t)(e | ((x - sx0[e]) << 8));
         }
         __syncthreads();
         // pass 3: the writes, in tile order
@@ -1445,16 +1448,19 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
             const uint32_t j = base + threadIdx.x;
             const bool valid = j < total;
             const uint32_t v = inv[valid ? j : 0u];
-            const int e = (int)(v & 0xffffu);
-            const uint32_t x = v >> 16;
+            const int e = (int)(v & 0xffu);
+            const uint32_t x = sx0[e] + (v >> 8);
             const uint32_t pos = tbase[x] + (j - lcs[x]);
             const bool ok = valid && pos < cap;
             if (valid && !ok) overflow = true;
             if (ok) {
                 const uint32_t sl = sbase[e] + x;  // kept below the capacity, as in k_fused_scatter
                 slot[pos] = sl < cap ? sl : (uint32_t)(cap - 1);
-                if (ids) ids[pos] = sg[e];
-                if (rec_o) rec_o[pos] = opac[sg[e]];
+                if (ids || rec_o) {
+                    const uint32_t g = rvals[rc.first + e];
+                    if (ids) ids[pos] = g;
+                    if (rec_o) rec_o[pos] = opac[g];
+                }
             }
             // records two lanes per record (see k_fused_scatter): consecutive lanes hold
             // consecutive positions, so each store covers a contiguous stretch
@@ -1519,8 +1525,11 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
         if (ok) {
             const uint32_t sl = sbase[e] + x;  // kept below the capacity, as in k_fused_scatter
             slot[pos] = sl < cap ? sl : (uint32_t)(cap - 1);
-            if (ids) ids[pos] = sg[e];
-            if (rec_o) rec_o[pos] = opac[sg[e]];
+            if (ids || rec_o) {
+                const uint32_t g = rvals[rc.first + e];
+                if (ids) ids[pos] = g;
+                if (rec_o) rec_o[pos] = opac[g];
+            }
         }
         // records two lanes per record (see k_fused_scatter)
         const bool odd = lane & 1;
