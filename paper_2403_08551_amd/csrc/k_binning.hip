@@ -1060,8 +1060,9 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
 // keys per column in Gaussian order and writes records, slots and ranges there.  The result is
 // that of the stable sort of all keys by tile.
 
-// Block b handles Gaussians [256 b, 256 b + 256): their key offsets (slot bases), rebuilt from
-// the scanned block sums, and their (row, Gaussian) pairs at the scanned row offsets.  A pair
+// Block b handles Gaussians [256 b, 256 b + 256): their key offsets (slot bases, in `off`),
+// rebuilt from the scanned block sums, and their (row, Gaussian) pairs at the scanned row
+// offsets.  A pair
 // finds its Gaussian in an LDS table (one byte per pair) when the block's pairs fit, else by
 // binary search.
 __global__ __launch_bounds__(BLK) void k_dup_rows(const uint32_t *__restrict__ count,
@@ -1069,7 +1070,7 @@ __global__ __launch_bounds__(BLK) void k_dup_rows(const uint32_t *__restrict__ c
                                                   const unsigned long long *__restrict__ rbs,
                                                   int64_t n, int64_t cap,
                                                   uint32_t *__restrict__ off,
-                                                  float4 *__restrict__ proj,
+                                                  const float4 *__restrict__ proj,
                                                   uint32_t *__restrict__ rkeys,
                                                   uint32_t *__restrict__ rvals,
                                                   DevState *state) {
@@ -1093,10 +1094,7 @@ __global__ __launch_bounds__(BLK) void k_dup_rows(const uint32_t *__restrict__ c
         for (uint32_t k = 0; k < h; ++k) owner[rloc + k] = (uint8_t)threadIdx.x;
     pre[threadIdx.x] = (uint32_t)rloc;
     srow[threadIdx.x] = rl.x;
-    if (i < n) {
-        off[i] = (uint32_t)(kbase + kloc);
-        reinterpret_cast<uint32_t *>(proj)[4 * (PROJ_F4 * i + 2)] = (uint32_t)(kbase + kloc);
-    }
+    if (i < n) off[i] = (uint32_t)(kbase + kloc);
     __syncthreads();
     unsigned long long limit = rtot;
     if (rbase >= (unsigned long long)cap) limit = 0;
@@ -1297,7 +1295,8 @@ template <int WV>
 __global__ __launch_bounds__(64 * WV) void k_row_scatter(
     const uint32_t *__restrict__ rvals, const uint4 *__restrict__ rinfo,
     const uint32_t *__restrict__ chunk_row, const float4 *__restrict__ proj,
-    const uint32_t *__restrict__ scan, int64_t cap, float4 *__restrict__ rec,
+    const uint32_t *__restrict__ scan, const uint32_t *__restrict__ off, int64_t cap,
+    float4 *__restrict__ rec,
     uint32_t *__restrict__ slot, uint32_t *__restrict__ ids, uint2 *__restrict__ ranges,
     const float *__restrict__ opac, float *__restrict__ rec_o, DevState *state) {
     extern __shared__ uint32_t dyn[];  // wh [WV][tw], tbase [tw], lcs [tw]
@@ -1326,6 +1325,7 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
     const float4 pa = proj[PROJ_F4 * (int64_t)g], pb = proj[PROJ_F4 * (int64_t)g + 1];
     const uint4 f = __builtin_bit_cast(uint4, proj[PROJ_F4 * (int64_t)g + 2]);
     const uint4 rl = __builtin_bit_cast(uint4, proj[PROJ_F4 * (int64_t)g + 3]);
+    const uint32_t koff = off[g];  // the Gaussian's first slot
     constexpr int TB_MAX = (ROW_MAX_TW + NT - 1) / NT;
     uint32_t tb_in[TB_MAX];
 #pragma unroll
@@ -1346,7 +1346,7 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
         pre[threadIdx.x] = (uint32_t)loc;
         sx0[threadIdx.x] = x0;
         // slot = key offset + (row - first row) w + (column - first column)
-        sbase[threadIdx.x] = f.x + (rc.row - rl.x) * w - x0;
+        sbase[threadIdx.x] = koff + (rc.row - rl.x) * w - x0;
         sproj[2 * threadIdx.x] = pa;
         sproj[2 * threadIdx.x + 1] = pb;
     } else if (threadIdx.x < ROW_CHUNK) {
@@ -1860,8 +1860,9 @@ hipError_t launch_rows_b(const RowBuffers &r, const ImgTable &tab, bool want_ids
     constexpr int WV = ROW_WAVES;
     hipLaunchKernelGGL(k_row_scatter<WV>, dim3((unsigned)r.nch_max), dim3(64 * WV),
                        sizeof(uint32_t) * (WV + 2) * (size_t)tab.max_tw, s, rv, r.rinfo,
-                       r.chunk_row, proj, r.scan, b.cap, reinterpret_cast<float4 *>(b.rec), b.slot,
-                       ids, b.ranges, b.opacity, b.rec_o, b.state);
+                       r.chunk_row, proj, r.scan, b.off, b.cap,
+                       reinterpret_cast<float4 *>(b.rec), b.slot, ids, b.ranges, b.opacity,
+                       b.rec_o, b.state);
     return hipGetLastError();
 }
 

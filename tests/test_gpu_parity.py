@@ -165,7 +165,7 @@ def test_sort_pairs_is_a_stable_sort(gi, n, bits):
     np.testing.assert_array_equal(host(ko).view(np.uint32), keys[order])
 
 
-@pytest.mark.parametrize("n", [1, 17, 16384, 16385, 1 << 20])
+@pytest.mark.parametrize("n", [1, 17, 16384, 16385, 65536, 65537, 1 << 20])
 def test_scan_u32(gi, n):
     x = np.random.default_rng(n).integers(0, 1000, n).astype(np.int32)
     out, total = gi.scan_u32(dev(x, torch.int32))
