@@ -314,11 +314,18 @@ hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n,
                            unsigned long long *blocksum, unsigned long long *total,
                            hipStream_t s);
 int64_t scan_scratch_entries(int64_t n);
+// Resources for scanning the digit histograms with the one-pass chained scan (status words of
+// at least chained_scan_blocks(entries) and the context state whose epoch tags them); with a
+// null status the three-launch scan is used.
+struct ChainedScan {
+    unsigned long long *status = nullptr;
+    DevState *state = nullptr;
+};
 hipError_t launch_sort_pairs(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
                              uint32_t *vout, uint32_t *ktmp, uint32_t *vtmp, int64_t n,
                              const unsigned long long *n_dev, int key_bits, int digit_bits,
                              uint32_t *hist, unsigned long long *scan_bs, int *which_out,
-                             hipStream_t s);
+                             hipStream_t s, const ChainedScan &cs = ChainedScan{});
 int64_t sort_hist_entries(int64_t n, int digit_bits);
 int auto_digit_bits(int key_bits, int64_t n);
 

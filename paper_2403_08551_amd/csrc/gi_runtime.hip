@@ -488,7 +488,9 @@ int run_binning_fused(gi_ctx *ctx, const float *params, int64_t n, const ImgTabl
     return GI_OK;
 }
 
-int ensure_rows(gi_ctx *ctx, int64_t rows, int64_t nch_max, int64_t scan_max) {
+// Row binning scratch; the chained-scan status words serve the count scan and the pair sort's
+// digit histograms (at most 11-bit digits).
+int ensure_rows(gi_ctx *ctx, int64_t rows, int64_t nch_max, int64_t scan_max, int64_t pairs) {
     if (rows > ctx->rows_cap) {
         CK(hipDeviceSynchronize());
         const int64_t c = std::max<int64_t>(rows, 256);
@@ -508,7 +510,8 @@ int ensure_rows(gi_ctx *ctx, int64_t rows, int64_t nch_max, int64_t scan_max) {
         CK(grow(&ctx->rscan, c));
         ctx->rscan_cap = c;
     }
-    const int64_t blocks = chained_scan_blocks(scan_max);
+    const int64_t blocks = std::max(chained_scan_blocks(scan_max),
+                                    chained_scan_blocks(sort_hist_entries(pairs, 11)));
     if (blocks > ctx->fstatus_cap) {
         CK(hipDeviceSynchronize());
         const int64_t c = std::max<int64_t>(blocks + blocks / 4, 64);
@@ -547,7 +550,7 @@ int run_binning_rows(gi_ctx *ctx, const float *params, int64_t n, const ImgTable
     RowBuffers r;
     const int64_t nch_max = row_chunks_max(pcap, tab.rows);
     const int64_t scan_max = row_scan_max(pcap, tab.rows, tab.max_tw);
-    if ((rc = ensure_rows(ctx, tab.rows, nch_max, scan_max)) != GI_OK) return rc;
+    if ((rc = ensure_rows(ctx, tab.rows, nch_max, scan_max, pcap)) != GI_OK) return rc;
     r.b = bin_buffers(ctx, params, n, n_tiles);
     r.rrange = ctx->rrange;
     r.rinfo = ctx->rinfo;

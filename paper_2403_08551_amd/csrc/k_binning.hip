@@ -475,14 +475,16 @@ __device__ inline unsigned long long match_digit(uint32_t d, bool valid) {
 }
 
 // Per-block digit histogram, written digit-major: hist[d * nblk + block].
+// epoch (if not null): advanced for the chained scan of the histogram that follows.
 template <int BITS>
 __global__ __launch_bounds__(SORT_T) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                        const unsigned long long *n_dev,
                                                        int64_t n_max, int shift,
                                                        uint32_t *__restrict__ hist,
-                                                       int64_t nblk) {
+                                                       int64_t nblk, DevState *epoch) {
     constexpr int BINS = 1 << BITS;
     __shared__ uint32_t h[SORT_WAVES][BINS];
+    if (epoch && blockIdx.x == 0 && threadIdx.x == 0) epoch->scan_epoch += 1u;
     const int64_t n = sort_count(n_dev, n_max);
     const uint32_t nbu = (uint32_t)((n + SORT_TILE - 1) / SORT_TILE);
     const uint32_t blk = blockIdx.x < nbu ? xcd_chunk(blockIdx.x, nbu) : blockIdx.x;
@@ -1664,11 +1666,18 @@ int64_t sort_hist_entries(int64_t n, int digit_bits) {
 template <int BITS>
 static hipError_t sort_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
                       int64_t n, const unsigned long long *n_dev, int shift, uint32_t *hist,
-                      unsigned long long *scan_bs, hipStream_t s) {
+                      unsigned long long *scan_bs, const ChainedScan &cs, hipStream_t s) {
     const int64_t nblk = (n + SORT_TILE - 1) / SORT_TILE;
     hipLaunchKernelGGL(k_radix_hist<BITS>, dim3((unsigned)nblk), dim3(SORT_T), 0, s, kin, n_dev, n,
-                       shift, hist, nblk);
-    hipError_t e = launch_scan_u32(hist, hist, nblk << BITS, scan_bs, nullptr, s);
+                       shift, hist, nblk, cs.status ? cs.state : nullptr);
+    const int64_t L = nblk << BITS;
+    hipError_t e = hipSuccess;
+    if (cs.status) {  // one launch instead of three
+        hipLaunchKernelGGL(k_chained_scan, dim3((unsigned)chained_scan_blocks(L)), dim3(CS_T), 0,
+                           s, hist, L, cs.status, (int64_t)-1, nullptr, cs.state, nullptr);
+    } else {
+        e = launch_scan_u32(hist, hist, L, scan_bs, nullptr, s);
+    }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_radix_scatter<BITS>, dim3((unsigned)nblk), dim3(SORT_T), 0, s, kin, vin,
                        kout, vout, n_dev, n, shift, hist, nblk);
@@ -1679,7 +1688,7 @@ hipError_t launch_sort_pairs(const uint32_t *kin, const uint32_t *vin, uint32_t 
                              uint32_t *vout, uint32_t *ktmp, uint32_t *vtmp, int64_t n,
                              const unsigned long long *n_dev, int key_bits, int digit_bits,
                              uint32_t *hist, unsigned long long *scan_bs, int *which_out,
-                             hipStream_t s) {
+                             hipStream_t s, const ChainedScan &cs) {
     // Passes alternate out -> tmp -> out ...; the number of passes decides where the result
     // lands.  *which_out = 0: kout/vout, 1: ktmp/vtmp.
     if (n <= 0) {
@@ -1699,7 +1708,7 @@ hipError_t launch_sort_pairs(const uint32_t *kin, const uint32_t *vin, uint32_t 
         uint32_t *ov = (p % 2 == 0) ? vout : vtmp;
         switch (bits) {
 #define GI_SORT_CASE(B) \
-    case B: e = sort_pass<B>(ck, cv, ok, ov, n, n_dev, shift, hist, scan_bs, s); break;
+    case B: e = sort_pass<B>(ck, cv, ok, ov, n, n_dev, shift, hist, scan_bs, cs, s); break;
             GI_SORT_CASE(1) GI_SORT_CASE(2) GI_SORT_CASE(3) GI_SORT_CASE(4) GI_SORT_CASE(5)
             GI_SORT_CASE(6) GI_SORT_CASE(7) GI_SORT_CASE(8) GI_SORT_CASE(9) GI_SORT_CASE(10)
             GI_SORT_CASE(11)
@@ -1836,7 +1845,8 @@ hipError_t launch_rows_b(const RowBuffers &r, const ImgTable &tab, bool want_ids
     int w = 0;
     hipError_t e = launch_sort_pairs(b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0],
                                      b.vals[0], pcap, &b.state->rows_total, kb, digit_bits,
-                                     b.hist, b.scan_blocksum, &w, s);
+                                     b.hist, b.scan_blocksum, &w, s,
+                                     ChainedScan{r.status, b.state});
     if (e != hipSuccess) return e;
     const int at = w == 0 ? 1 : 0;  // keys[1] after an odd number of passes
     *which = at;
