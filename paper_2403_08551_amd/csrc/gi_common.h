@@ -31,8 +31,10 @@ constexpr uint32_t FLAG_NONFINITE = 2u;
 constexpr uint32_t FLAG_SCAN_STALL = 4u;
 constexpr uint32_t FLAG_BAD_CODE = 8u;
 constexpr int64_t FUSED_MAX_TILES = 2048;
-// Row binning (tile count above FUSED_MAX_TILES): images up to this many tiles per row.
+// Row binning (tile count above FUSED_MAX_TILES): images up to this many tiles per row, and
+// at most this many tile rows in the images that one block of 256 Gaussians spans.
 constexpr int32_t ROW_MAX_TW = 1024;
+constexpr int32_t ROW_WIN_MAX = 1024;
 // float4 words per projected Gaussian on the radix and row paths: the rasteriser record (2),
 // the slot facts (1), the first tile row and row count (1): one 64-byte line, so that the
 // kernels after the sort read one line per key.  The one-pass path stores the record alone (2
@@ -69,6 +71,13 @@ struct ImgTable {
     const unsigned long long *pix_off;  // [B+1] first pixel of each image
     const uint32_t *row_base;         // [B+1] first global tile row of each image (B > 1)
     const uint2 *row_tiles;           // [rows] first global tile, tiles per row (B > 1)
+    // row binning's per-block row counts, laid out image by image, then row, then the blocks
+    // of 256 Gaussians that overlap the image (B > 1; one image: row * blocks + block):
+    const unsigned long long *row_seg;  // [rows + 1] index of a row's first block's count
+    const uint32_t *row_fb;             // [rows] first block overlapping the row's image
+                                        // (0xffffffff: the image has no Gaussians)
+    int32_t row_win;                  // most tile rows that one block's images hold (B > 1)
+    int64_t row_len;                  // per-block row counts in all (B > 1)
     int32_t rows;                     // tile rows of all images
     int32_t max_tw;                   // most tiles per row of any image
 };
@@ -244,7 +253,6 @@ struct BinBuffers {
     uint2 *ranges;
     int64_t n_tiles;
     int64_t cap;
-    unsigned long long *rblocksum;  // row binning: per-block sums of the tile rows per Gaussian
     int64_t cap_p;                  // row binning: (row, Gaussian) pairs the sort is sized for
     DevState *state;
     // sort scratch
@@ -281,17 +289,21 @@ int64_t fused_scan_blocks(int64_t n, int64_t n_tiles);
 hipError_t launch_fused_a(const FusedBuffers &f, const ImgTable &tab, hipStream_t s);
 hipError_t launch_fused_c(const FusedBuffers &f, uint32_t *ids, hipStream_t s);
 
-// Row binning (n_tiles > FUSED_MAX_TILES, every image at most ROW_MAX_TW tiles wide), a
-// counting sort in two levels.  A: projection (64-byte lines) with per-block sums of the keys
-// and of the tile rows per Gaussian, scanned (state->keys_total, state->rows_total).  B: the
-// (global tile row, Gaussian) pairs, stably radix-sorted by row; each row's pairs cut into
-// chunks of ROW_CHUNK; per (row, column, chunk) key counts, one chained scan over them (row
-// major, then column, then chunk: exactly tile order), and the scatter of every chunk's keys in
-// Gaussian order into tile order with the records, slots and ranges.
+// Row binning (n_tiles > FUSED_MAX_TILES, every image at most ROW_MAX_TW tiles wide and the
+// images of any block of 256 Gaussians at most ROW_WIN_MAX tile rows), a counting sort in two
+// levels.  A: projection (64-byte lines) with per-block key sums (scanned: state->keys_total)
+// and per-block row counts (one chained scan: state->rows_total).  B: the (global tile row,
+// Gaussian) pairs scattered stably into row order; each row's pairs cut into chunks of
+// ROW_CHUNK; per (row, column, chunk) key counts, one chained scan over them (row major, then
+// column, then chunk: exactly tile order), and the scatter of every chunk's keys in Gaussian
+// order into tile order with the records, slots and ranges.
 constexpr int ROW_CHUNK = 256;
 struct RowBuffers {
     BinBuffers b;
-    uint2 *rrange;               // [rows] pair range of each row in the sorted pair list
+    uint32_t *rhist;             // [rhist_len + 1] per-block row counts (layout: ImgTable), a
+                                 // closing zero, then their scan
+    int64_t rhist_len;
+    uint4 *bwin;                 // [blocks] first global row and rows of each block's images
     uint4 *rinfo;                // [2 rows] {first pair, end pair, first chunk, scan offset},
                                  // {first tile, tiles per row, chunks, 0}
     uint32_t *chunk_row;         // [nch_max] the row of each chunk
@@ -303,11 +315,11 @@ struct RowBuffers {
 int64_t row_chunks_max(int64_t cap_p, int64_t rows);
 int64_t row_scan_max(int64_t cap_p, int64_t rows, int32_t max_tw);
 int64_t chained_scan_blocks(int64_t len);
-hipError_t launch_rows_a(const BinBuffers &b, const ImgTable &tab, hipStream_t s);
-// *which receives the buffer pair the sorted (row, Gaussian) pairs ended in; the sorted
-// Gaussian ids go to the other pair's values when wanted.
-hipError_t launch_rows_b(const RowBuffers &r, const ImgTable &tab, bool want_ids, int digit_bits,
-                         int *which, hipStream_t s);
+hipError_t launch_rows_a(const RowBuffers &r, const ImgTable &tab, hipStream_t s);
+// *which receives the buffer pair holding the (row, Gaussian) pairs (0); the sorted Gaussian
+// ids go to the other pair's values when wanted.
+hipError_t launch_rows_b(const RowBuffers &r, const ImgTable &tab, bool want_ids, int *which,
+                         hipStream_t s);
 
 // generic pieces, also exported for testing
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n,

@@ -46,7 +46,6 @@ struct gi_ctx {
     uint32_t *count = nullptr;
     uint32_t *off = nullptr;
     unsigned long long *blocksum = nullptr;
-    unsigned long long *rblocksum = nullptr;
     // per key
     uint32_t *keys[2] = {nullptr, nullptr};
     uint32_t *vals[2] = {nullptr, nullptr};
@@ -64,7 +63,10 @@ struct gi_ctx {
     unsigned long long *fstatus = nullptr;
     int64_t fstatus_cap = 0;
     // row binning scratch
-    uint2 *rrange = nullptr;
+    uint32_t *rhist = nullptr;
+    int64_t rhist_cap = 0;
+    uint4 *bwin = nullptr;
+    int64_t bwin_cap = 0;
     uint4 *rinfo = nullptr;
     int64_t rows_cap = 0;
     uint32_t *chunk_row = nullptr;
@@ -85,6 +87,8 @@ struct gi_ctx {
     uint32_t *row_base = nullptr;
     uint2 *row_tiles = nullptr;
     int64_t row_tiles_cap = 0;
+    unsigned long long *row_seg = nullptr;
+    uint32_t *row_fb = nullptr;
     uint32_t *gauss_off = nullptr;
     unsigned long long *pix_off = nullptr;
     std::vector<int64_t> batch_sig;  // host copy of the uploaded layout
@@ -209,7 +213,6 @@ int ensure_gauss(gi_ctx *ctx, int64_t n) {
     CK(grow(&ctx->count, c));
     CK(grow(&ctx->off, c));
     CK(grow(&ctx->blocksum, (c + 255) / 256 + 1));
-    CK(grow(&ctx->rblocksum, (c + 255) / 256 + 1));
     ctx->cap_n = c;
     return GI_OK;
 }
@@ -287,6 +290,33 @@ int upload_batch(gi_ctx *ctx, const gi_batch *b, ImgTable *tab, int64_t *n_tiles
     }
     rb[B] = (uint32_t)rt.size();
     tb[B] = (uint32_t)t;
+    // row binning's per-block row counts: image by image, row, then the blocks of 256
+    // Gaussians that overlap the image; and the most rows any block's images hold
+    std::vector<unsigned long long> rseg(rt.size() + 1);
+    std::vector<uint32_t> rfb(rt.size());
+    unsigned long long seg = 0;
+    int64_t win = 0;
+    for (int32_t i = 0; i < B; ++i) {
+        const int64_t g0 = b->gauss_off_host[i], g1 = b->gauss_off_host[i + 1];
+        const int64_t fb = g0 / 256, nbk = g1 > g0 ? (g1 - 1) / 256 - fb + 1 : 0;
+        for (uint32_t y = rb[i]; y < rb[i + 1]; ++y) {
+            rseg[y] = seg + (unsigned long long)(y - rb[i]) * (unsigned long long)nbk;
+            rfb[y] = nbk ? (uint32_t)fb : 0xffffffffu;  // an image without Gaussians: no counts
+        }
+        seg += (unsigned long long)(rb[i + 1] - rb[i]) * (unsigned long long)nbk;
+    }
+    rseg[rt.size()] = seg;
+    {
+        const int64_t n_all = b->gauss_off_host[B];
+        int32_t lo = 0;
+        for (int64_t blk = 0; blk * 256 < n_all; ++blk) {
+            const int64_t g0 = blk * 256, g1 = std::min<int64_t>(g0 + 256, n_all) - 1;
+            while (lo + 1 < B && b->gauss_off_host[lo + 1] <= g0) ++lo;
+            int32_t hi = lo;
+            while (hi + 1 < B && b->gauss_off_host[hi + 1] <= g1) ++hi;
+            win = std::max<int64_t>(win, (int64_t)rb[hi + 1] - rb[lo]);
+        }
+    }
     po[B] = (unsigned long long)p;
     go[B] = (uint32_t)b->gauss_off_host[B];
     std::vector<int64_t> sig;
@@ -312,8 +342,13 @@ int upload_batch(gi_ctx *ctx, const gi_batch *b, ImgTable *tab, int64_t *n_tiles
         CK(hipMemcpy(ctx->tile_base, tb.data(), sizeof(uint32_t) * (B + 1), hipMemcpyHostToDevice));
         if ((int64_t)rt.size() > ctx->row_tiles_cap) {
             CK(grow(&ctx->row_tiles, (int64_t)rt.size()));
+            CK(grow(&ctx->row_seg, (int64_t)rt.size() + 1));
+            CK(grow(&ctx->row_fb, (int64_t)rt.size()));
             ctx->row_tiles_cap = (int64_t)rt.size();
         }
+        CK(hipMemcpy(ctx->row_seg, rseg.data(), sizeof(unsigned long long) * rseg.size(),
+                     hipMemcpyHostToDevice));
+        CK(hipMemcpy(ctx->row_fb, rfb.data(), sizeof(uint32_t) * rfb.size(), hipMemcpyHostToDevice));
         CK(hipMemcpy(ctx->row_base, rb.data(), sizeof(uint32_t) * (B + 1), hipMemcpyHostToDevice));
         CK(hipMemcpy(ctx->row_tiles, rt.data(), sizeof(uint2) * rt.size(), hipMemcpyHostToDevice));
         CK(hipMemcpy(ctx->gauss_off, go.data(), sizeof(uint32_t) * (B + 1), hipMemcpyHostToDevice));
@@ -333,6 +368,10 @@ int upload_batch(gi_ctx *ctx, const gi_batch *b, ImgTable *tab, int64_t *n_tiles
     tab->row_tiles = ctx->row_tiles;
     tab->rows = (int32_t)rt.size();
     tab->max_tw = max_tw;
+    tab->row_seg = ctx->row_seg;
+    tab->row_fb = ctx->row_fb;
+    tab->row_win = (int32_t)std::min<int64_t>(win, 0x7fffffff);
+    tab->row_len = (int64_t)seg;
     if (B == 1) {
         // single images read the scalar fields; the tables stay valid for B == 1 as well
     }
@@ -425,7 +464,6 @@ BinBuffers bin_buffers(gi_ctx *ctx, const float *params, int64_t n, int64_t n_ti
     b.ranges = ctx->ranges;
     b.n_tiles = n_tiles;
     b.cap = ctx->cap_k;
-    b.rblocksum = ctx->rblocksum;
     b.cap_p = ctx->cap_p;
     b.state = ctx->state;
     b.hist = ctx->hist;
@@ -488,15 +526,26 @@ int run_binning_fused(gi_ctx *ctx, const float *params, int64_t n, const ImgTabl
     return GI_OK;
 }
 
-// Row binning scratch; the chained-scan status words serve the count scan and the pair sort's
-// digit histograms (at most 11-bit digits).
-int ensure_rows(gi_ctx *ctx, int64_t rows, int64_t nch_max, int64_t scan_max, int64_t pairs) {
+// Row binning scratch; the chained-scan status words serve both scans.
+int ensure_rows(gi_ctx *ctx, int64_t rows, int64_t blocks, int64_t rlen, int64_t nch_max,
+                int64_t scan_max) {
     if (rows > ctx->rows_cap) {
         CK(hipDeviceSynchronize());
         const int64_t c = std::max<int64_t>(rows, 256);
-        CK(grow(&ctx->rrange, c));
         CK(grow(&ctx->rinfo, 2 * c));
         ctx->rows_cap = c;
+    }
+    if (rlen + 1 > ctx->rhist_cap) {
+        CK(hipDeviceSynchronize());
+        const int64_t c = rlen + 1 + rlen / 4;
+        CK(grow(&ctx->rhist, c));
+        ctx->rhist_cap = c;
+    }
+    if (blocks > ctx->bwin_cap) {
+        CK(hipDeviceSynchronize());
+        const int64_t c = blocks + blocks / 4 + 16;
+        CK(grow(&ctx->bwin, c));
+        ctx->bwin_cap = c;
     }
     if (nch_max > ctx->chunk_cap) {
         CK(hipDeviceSynchronize());
@@ -510,11 +559,10 @@ int ensure_rows(gi_ctx *ctx, int64_t rows, int64_t nch_max, int64_t scan_max, in
         CK(grow(&ctx->rscan, c));
         ctx->rscan_cap = c;
     }
-    const int64_t blocks = std::max(chained_scan_blocks(scan_max),
-                                    chained_scan_blocks(sort_hist_entries(pairs, 11)));
-    if (blocks > ctx->fstatus_cap) {
+    const int64_t blocks_cs = std::max(chained_scan_blocks(scan_max), chained_scan_blocks(rlen + 1));
+    if (blocks_cs > ctx->fstatus_cap) {
         CK(hipDeviceSynchronize());
-        const int64_t c = std::max<int64_t>(blocks + blocks / 4, 64);
+        const int64_t c = std::max<int64_t>(blocks_cs + blocks_cs / 4, 64);
         CK(grow(&ctx->fstatus, c));
         CK(hipMemset(ctx->fstatus, 0, sizeof(unsigned long long) * c));  // no flag: unpublished
         ctx->fstatus_cap = c;
@@ -522,15 +570,39 @@ int ensure_rows(gi_ctx *ctx, int64_t rows, int64_t nch_max, int64_t scan_max, in
     return GI_OK;
 }
 
+// Per-block row counts of row binning for this table and Gaussian count.
+int64_t row_count_len(const ImgTable &tab, int64_t n) {
+    return tab.B == 1 ? (int64_t)tab.rows * ((n + 255) / 256) : tab.row_len;
+}
+
 // Row binning (a counting sort in two levels, see launch_rows_b): n >= 1, every image at most
-// ROW_MAX_TW tiles wide.
+// ROW_MAX_TW tiles wide, the images of any block of 256 Gaussians at most ROW_WIN_MAX rows.
 int run_binning_rows(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab,
                      int64_t n_tiles, hipStream_t s, int64_t *bound, int *which) {
     int rc;
     ctx->off_cur = ctx->off;
-    BinBuffers b = bin_buffers(ctx, params, n, n_tiles);
+    const int64_t blocks = (n + 255) / 256, rlen = row_count_len(tab, n);
+    if (ctx->cap_p <= 0) ctx->cap_p = ctx->cap_k;
+    int64_t pcap = std::min(ctx->cap_p, ctx->cap_k);
+    if ((rc = ensure_rows(ctx, tab.rows, blocks, rlen, row_chunks_max(pcap, tab.rows),
+                          row_scan_max(pcap, tab.rows, tab.max_tw))) != GI_OK)
+        return rc;
+    RowBuffers r;
+    auto fill = [&](int64_t pc) {
+        r.b = bin_buffers(ctx, params, n, n_tiles);
+        r.rhist = ctx->rhist;
+        r.rhist_len = rlen;
+        r.bwin = ctx->bwin;
+        r.rinfo = ctx->rinfo;
+        r.chunk_row = ctx->chunk_row;
+        r.scan = ctx->rscan;
+        r.status = ctx->fstatus;
+        r.nch_max = row_chunks_max(pc, tab.rows);
+        r.scan_max = row_scan_max(pc, tab.rows, tab.max_tw);
+    };
+    fill(pcap);
     StageTimer tm(ctx, s, GI_STAGE_BINNING);
-    CK(launch_rows_a(b, tab, s));
+    CK(launch_rows_a(r, tab, s));
     int64_t K = ctx->cap_k;
     if (ctx->sync) {
         CK(hipMemcpyAsync(ctx->pinned, ctx->state, sizeof(DevState), hipMemcpyDeviceToHost, s));
@@ -544,23 +616,14 @@ int run_binning_rows(gi_ctx *ctx, const float *params, int64_t n, const ImgTable
             if ((rc = ensure_keys(ctx, K + K / 4)) != GI_OK) return rc;
         }
         if (P > ctx->cap_p) ctx->cap_p = P + P / 4;
+        pcap = std::min(ctx->cap_p, ctx->cap_k);
+        if ((rc = ensure_rows(ctx, tab.rows, blocks, rlen, row_chunks_max(pcap, tab.rows),
+                              row_scan_max(pcap, tab.rows, tab.max_tw))) != GI_OK)
+            return rc;
+        fill(pcap);
     }
-    if (ctx->cap_p <= 0) ctx->cap_p = ctx->cap_k;
-    const int64_t pcap = std::min(ctx->cap_p, ctx->cap_k);
-    RowBuffers r;
-    const int64_t nch_max = row_chunks_max(pcap, tab.rows);
-    const int64_t scan_max = row_scan_max(pcap, tab.rows, tab.max_tw);
-    if ((rc = ensure_rows(ctx, tab.rows, nch_max, scan_max, pcap)) != GI_OK) return rc;
-    r.b = bin_buffers(ctx, params, n, n_tiles);
-    r.rrange = ctx->rrange;
-    r.rinfo = ctx->rinfo;
-    r.chunk_row = ctx->chunk_row;
-    r.scan = ctx->rscan;
-    r.status = ctx->fstatus;
-    r.nch_max = nch_max;
-    r.scan_max = scan_max;
-    CK(launch_rows_b(r, tab, ctx->want_ids != 0, ctx->sort_bits, which, s));
-    ctx->ids_at = ctx->vals[1 - *which];
+    CK(launch_rows_b(r, tab, ctx->want_ids != 0, which, s));
+    ctx->ids_at = ctx->vals[1];
     tm.stop();
     *bound = K;
     return GI_OK;
@@ -579,7 +642,8 @@ int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab
     if (ctx->blend_cur == BLEND_ALPHA && (rc = ensure_alpha(ctx)) != GI_OK) return rc;
     // 0: one pass up to FUSED_MAX_TILES tiles, else rows; 1: radix; 2: one pass, else radix;
     // 3: rows.  Rows need every image at most ROW_MAX_TW tiles wide, else radix.
-    const bool rows_ok = n > 0 && tab.max_tw >= 1 && tab.max_tw <= ROW_MAX_TW && tab.rows > 0;
+    const bool rows_ok = n > 0 && tab.max_tw >= 1 && tab.max_tw <= ROW_MAX_TW && tab.rows > 0 &&
+                         (tab.B == 1 ? tab.rows : tab.row_win) <= ROW_WIN_MAX;
     if ((ctx->binning == 0 || ctx->binning == 2) && n > 0 && n_tiles <= FUSED_MAX_TILES)
         return run_binning_fused(ctx, params, n, tab, n_tiles, s, bound, which);
     if ((ctx->binning == 0 || ctx->binning == 3) && rows_ok)
@@ -897,8 +961,9 @@ int gi_destroy(gi_ctx *ctx) {
                     ctx->part, ctx->hist, ctx->scan_bs, ctx->ranges, ctx->loss_part, ctx->state,
                     ctx->dims, ctx->tile_base, ctx->gauss_off, ctx->pix_off, ctx->tmp_k,
                     ctx->tmp_v, ctx->fscan, ctx->fstatus, ctx->rec_o, ctx->part_a,
-                    ctx->qpart, ctx->qscratch, ctx->rblocksum, ctx->rrange, ctx->rinfo,
-                    ctx->chunk_row, ctx->rscan, ctx->row_base, ctx->row_tiles};
+                    ctx->qpart, ctx->qscratch, ctx->rhist, ctx->bwin, ctx->rinfo,
+                    ctx->chunk_row, ctx->rscan, ctx->row_base, ctx->row_tiles, ctx->row_seg,
+                    ctx->row_fb};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);

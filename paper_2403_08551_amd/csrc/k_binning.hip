@@ -151,7 +151,8 @@ __device__ inline uint32_t project_one(const RecordSrc &src, int64_t i,
                                        const ImgTable &tab, float4 *__restrict__ proj,
                                        int4 *__restrict__ rect, uint2 *__restrict__ tinfo,
                                        uint32_t *__restrict__ count, bool *nonfinite,
-                                       bool *bad_code, int4 *rc_out, uint2 *inf_out) {
+                                       bool *bad_code, int4 *rc_out, uint2 *inf_out,
+                                       int32_t *img_out = nullptr) {
 #pragma clang fp contract(off)
     uint32_t cnt = 0;
     float q[8];
@@ -166,6 +167,7 @@ __device__ inline uint32_t project_one(const RecordSrc &src, int64_t i,
         IH = tab.H; IW = tab.W;
     } else {
         int32_t b = upper_index(tab.gauss_off, tab.B, (uint32_t)i);
+        if (img_out) *img_out = b;
         int4 d = tab.dims[b];
         TW = d.z; TH = d.w; tb = tab.tile_base[b];
         if (FACTS) rb = tab.row_base[b];
@@ -259,33 +261,80 @@ __device__ inline uint32_t project_one(const RecordSrc &src, int64_t i,
     return cnt;
 }
 
+// Row binning's per-block row counts (see ImgTable): scan == null when not wanted.
+struct RowHistArgs {
+    uint32_t *scan;  // [len + 1]
+    int64_t len;
+    uint4 *bwin;     // [blocks] (first global row, rows) of the images the block spans
+};
+
+__device__ inline unsigned long long row_seg_of(const ImgTable &t, uint32_t row, uint32_t blocks) {
+    return t.B == 1 ? (unsigned long long)row * blocks : t.row_seg[row];
+}
+__device__ inline uint32_t row_fb_of(const ImgTable &t, uint32_t row) {
+    return t.B == 1 ? 0u : t.row_fb[row];
+}
+
 __global__ __launch_bounds__(BLK) void k_project(const RecordSrc src, int64_t n,
                                                  ImgTable tab, float4 *__restrict__ proj,
                                                  int4 *__restrict__ rect,
                                                  uint2 *__restrict__ tinfo,
                                                  uint32_t *__restrict__ count,
                                                  unsigned long long *__restrict__ blocksum,
-                                                 unsigned long long *__restrict__ rblocksum,
-                                                 DevState *state) {
+                                                 RowHistArgs rh, DevState *state) {
     __shared__ unsigned long long tmp[BLK / 64 + 1];
+    __shared__ uint32_t rhc[ROW_WIN_MAX];
+    __shared__ int32_t img_lo, img_hi;
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    uint32_t cnt = 0, rows = 0;
+    uint32_t cnt = 0, rows = 0, row0 = 0;
+    int32_t img = 0;
     bool nonfinite = false, bad = false;
+    if (rh.scan && threadIdx.x == 0) {
+        img_lo = 0x7fffffff;
+        img_hi = -1;
+        // a new epoch for the chained scan of the row counts that follows
+        if (blockIdx.x == 0) state->scan_epoch += 1u;
+    }
     if (i < n) {
         int4 rc;
         uint2 inf;
         cnt = project_one<true>(src, i, tab, proj, rect, tinfo, count, &nonfinite, &bad, &rc,
-                                &inf);
+                                &inf, &img);
         rows = cnt ? (uint32_t)(rc.w - rc.y + 1) : 0u;
+        if (rh.scan) row0 = (tab.B == 1 ? 0u : tab.row_base[img]) + (uint32_t)rc.y;
     }
     if (__ballot(nonfinite) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_NONFINITE);
     if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&state->flags, FLAG_BAD_CODE);
     unsigned long long tot;
     block_exclusive_scan<unsigned long long, BLK>((unsigned long long)cnt, tmp, &tot);
     if (threadIdx.x == 0) blocksum[blockIdx.x] = tot;
-    if (rblocksum) {  // row binning: the tile rows per Gaussian as well
-        block_exclusive_scan<unsigned long long, BLK>((unsigned long long)rows, tmp, &tot);
-        if (threadIdx.x == 0) rblocksum[blockIdx.x] = tot;
+    if (!rh.scan) return;
+    // row binning: this block's count of (row, Gaussian) pairs per tile row of the images its
+    // Gaussians belong to (a window of consecutive global rows)
+    if (i < n) {
+        atomicMin(&img_lo, img);
+        atomicMax(&img_hi, img);
+    }
+    for (int r = threadIdx.x; r < ROW_WIN_MAX; r += BLK) rhc[r] = 0u;
+    __syncthreads();
+    uint32_t w0, W;
+    if (tab.B == 1) {
+        w0 = 0;
+        W = (uint32_t)tab.rows;
+    } else {
+        w0 = tab.row_base[img_lo];
+        W = tab.row_base[img_hi + 1] - w0;
+    }
+    for (uint32_t k = 0; k < rows; ++k) atomicAdd(&rhc[row0 - w0 + k], 1u);
+    __syncthreads();
+    const uint32_t blocks = (uint32_t)gridDim.x;
+    for (uint32_t r = threadIdx.x; r < W; r += BLK) {
+        const uint32_t row = w0 + r, fb = row_fb_of(tab, row);
+        if (fb != 0xffffffffu) rh.scan[row_seg_of(tab, row, blocks) + (blockIdx.x - fb)] = rhc[r];
+    }
+    if (threadIdx.x == 0) {
+        rh.bwin[blockIdx.x] = make_uint4(w0, W, 0u, 0u);
+        if (blockIdx.x == 0) rh.scan[rh.len] = 0u;  // the closing zero: its prefix is the total
     }
 }
 
@@ -1052,9 +1101,10 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
 
 // ---- row binning: a counting sort in two levels, for many tiles ------------------------------
 //
-// Level one sorts the (global tile row, Gaussian) pairs by row (a Gaussian's rectangle spans a
-// few rows, so there are far fewer pairs than keys): k_dup_rows writes them in Gaussian order,
-// the stable radix sort orders them by row, k_row_bounds finds each row's pairs.  Level two
+// Level one puts the (global tile row, Gaussian) pairs into row order (a Gaussian's rectangle
+// spans a few rows, so there are far fewer pairs than keys): k_project counts each block's pairs
+// per row, one chained scan gives each block's first position in every row, and k_rows_scatter
+// writes the pairs there, in Gaussian order within a row.  Level two
 // cuts every row's pairs (in Gaussian order) into chunks of ROW_CHUNK: k_row_table numbers the
 // chunks and lays out one count per (row, column, chunk), row-major, then column, then chunk;
 // k_row_hist fills the counts, one chained scan turns them into the first position of every
@@ -1062,74 +1112,137 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
 // keys per column in Gaussian order and writes records, slots and ranges there.  The result is
 // that of the stable sort of all keys by tile.
 
-// Block b handles Gaussians [256 b, 256 b + 256): their key offsets (slot bases, in `off`),
-// rebuilt from the scanned block sums, and their (row, Gaussian) pairs at the scanned row
-// offsets.  A pair
-// finds its Gaussian in an LDS table (one byte per pair) when the block's pairs fit, else by
-// binary search.
-__global__ __launch_bounds__(BLK) void k_dup_rows(const uint32_t *__restrict__ count,
-                                                  const unsigned long long *__restrict__ bs,
-                                                  const unsigned long long *__restrict__ rbs,
-                                                  int64_t n, int64_t cap,
-                                                  uint32_t *__restrict__ off,
-                                                  const float4 *__restrict__ proj,
-                                                  uint32_t *__restrict__ rkeys,
-                                                  uint32_t *__restrict__ rvals,
-                                                  DevState *state) {
+// Level one.  Block b handles Gaussians [256 b, 256 b + 256): their key offsets (slot bases, in
+// `off`), rebuilt from the scanned block sums, and their (row, Gaussian) pairs, enumerated in
+// Gaussian order (a pair finds its Gaussian in an LDS table, one byte per pair, when the block's
+// pairs fit, else by binary search), ranked stably per row by the waves (ballots on the row bits,
+// per-wave counters, two passes) and written at the block's scanned first position in each row:
+// the pairs in row order, and in Gaussian order within a row.
+constexpr uint32_t PAIR_OWN_CAP = 8192;
+__global__ __launch_bounds__(BLK) void k_rows_scatter(const uint32_t *__restrict__ count,
+                                                      const float4 *__restrict__ proj,
+                                                      const unsigned long long *__restrict__ bs,
+                                                      const uint32_t *__restrict__ rscan,
+                                                      const uint4 *__restrict__ bwin,
+                                                      ImgTable tab, int64_t n, int64_t cap,
+                                                      uint32_t *__restrict__ off,
+                                                      uint32_t *__restrict__ rvals,
+                                                      DevState *state) {
+    constexpr int WV = BLK / 64;
     __shared__ unsigned long long tmp[BLK / 64 + 1];
     __shared__ uint32_t pre[BLK];
-    __shared__ uint32_t srow[BLK];
-    __shared__ uint8_t owner[DUP_OWN_CAP];
+    __shared__ uint32_t srow[BLK];                 // first window row of each Gaussian
+    __shared__ uint8_t owner[PAIR_OWN_CAP];
+    __shared__ uint32_t wh[WV][ROW_WIN_MAX];       // per-wave counts, then wave offsets
+    __shared__ uint32_t rbase[ROW_WIN_MAX];        // the block's first position in each row
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
     const int64_t ir = i < n ? i : n - 1;
     // reads issued together (clamped index), used after
     const uint32_t c_in = count[ir];
     const uint4 rl = __builtin_bit_cast(uint4, proj[PROJ_F4 * ir + 3]);  // first row, rows
-    const unsigned long long kbase = bs[blockIdx.x], rbase = rbs[blockIdx.x];
+    const unsigned long long kbase = bs[blockIdx.x];
+    const uint4 win = bwin[blockIdx.x];
+    const uint32_t w0 = win.x, W = win.y;
+    const uint32_t blocks = (uint32_t)gridDim.x;
+    constexpr int RB_MAX = ROW_WIN_MAX / BLK;
+    uint32_t rb_in[RB_MAX];
+#pragma unroll
+    for (int k = 0; k < RB_MAX; ++k) {
+        const uint32_t r = threadIdx.x + k * BLK;
+        const uint32_t row = w0 + (r < W ? r : W - 1), fb = row_fb_of(tab, row);
+        // (rows of an image without Gaussians hold no pairs and have no counts: index 0, dropped)
+        const bool has = fb != 0xffffffffu;
+        const uint32_t v = rscan[has ? row_seg_of(tab, row, blocks) + (blockIdx.x - fb) : 0ull];
+        rb_in[k] = has ? v : 0u;
+    }
     const uint32_t c = i < n ? c_in : 0u;
     const uint32_t h = i < n ? rl.y : 0u;
     unsigned long long ktot, rtot;
     const unsigned long long kloc = block_exclusive_scan<unsigned long long, BLK>(c, tmp, &ktot);
     const unsigned long long rloc = block_exclusive_scan<unsigned long long, BLK>(h, tmp, &rtot);
-    const bool table = rtot <= DUP_OWN_CAP;  // the same for the whole block
+    const bool table = rtot <= PAIR_OWN_CAP;  // the same for the whole block
     if (table)
         for (uint32_t k = 0; k < h; ++k) owner[rloc + k] = (uint8_t)threadIdx.x;
     pre[threadIdx.x] = (uint32_t)rloc;
-    srow[threadIdx.x] = rl.x;
+    srow[threadIdx.x] = rl.x - w0;
     if (i < n) off[i] = (uint32_t)(kbase + kloc);
-    __syncthreads();
-    unsigned long long limit = rtot;
-    if (rbase >= (unsigned long long)cap) limit = 0;
-    else if (rbase + rtot > (unsigned long long)cap) limit = (unsigned long long)cap - rbase;
-    if (limit < rtot && threadIdx.x == 0) atomicOr(&state->flags, FLAG_KEY_OVERFLOW);
-    for (uint32_t j = threadIdx.x; j < limit; j += BLK) {
-        int lo = 0;  // owner: largest g with pre[g] <= j
-        if (table) {
-            lo = owner[j];
-        } else {
-            int hi = BLK - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pre[mid] <= j) lo = mid; else hi = mid - 1;
-            }
-        }
-        rkeys[rbase + j] = srow[lo] + (j - pre[lo]);
-        rvals[rbase + j] = (uint32_t)((int64_t)blockIdx.x * BLK + lo);
+#pragma unroll
+    for (int k = 0; k < RB_MAX; ++k) {
+        const uint32_t r = threadIdx.x + k * BLK;
+        if (r < W) rbase[r] = rb_in[k];
     }
-}
-
-// First and end position of every row's pairs in the sorted pair list (rows without pairs keep
-// the zeros they were filled with).
-__global__ __launch_bounds__(BLK) void k_row_bounds(const uint32_t *__restrict__ rk,
-                                                    const unsigned long long *n_dev,
-                                                    int64_t n_max, uint2 *__restrict__ rrange) {
-    const int64_t n = sort_count(n_dev, n_max);
-    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t key = rk[i];
-    const uint32_t kp = rk[i > 0 ? i - 1 : 0], kn = rk[i + 1 < n ? i + 1 : i];
-    if (i == 0 || kp != key) rrange[key].x = (uint32_t)i;
-    if (i == n - 1 || kn != key) rrange[key].y = (uint32_t)(i + 1);
+    for (int k = threadIdx.x; k < WV * ROW_WIN_MAX; k += BLK) (&wh[0][0])[k] = 0u;
+    __syncthreads();
+    int rbits = 1;
+    while ((1u << rbits) < W) ++rbits;
+    const uint32_t total = (uint32_t)rtot;
+    const uint32_t q = (total + WV - 1) / WV;
+    const uint32_t j0 = (uint32_t)wave * q < total ? (uint32_t)wave * q : total;
+    const uint32_t j1 = j0 + q < total ? j0 + q : total;
+    uint32_t *my = wh[wave];
+    // pass 1: per-wave counts per row
+    for (uint32_t base = j0; base < j1; base += 64) {
+        const uint32_t j = base + lane;
+        const bool valid = j < j1;
+        uint32_t r = 0;
+        if (valid) {
+            int lo = 0;
+            if (table) {
+                lo = owner[j];
+            } else {
+                int hi = BLK - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+                }
+            }
+            r = srow[lo] + (j - pre[lo]);
+        }
+        const unsigned long long peers = match_bits(r, valid, rbits);
+        if (valid && lane == __ffsll((long long)peers) - 1) my[r] += __popcll(peers);
+    }
+    __syncthreads();
+    for (uint32_t r = threadIdx.x; r < W; r += BLK) {
+        uint32_t run = rbase[r];
+#pragma unroll
+        for (int v = 0; v < WV; ++v) {
+            const uint32_t x = wh[v][r];
+            wh[v][r] = run;
+            run += x;
+        }
+    }
+    __syncthreads();
+    // pass 2: stable ranks and the writes
+    bool overflow = false;
+    for (uint32_t base = j0; base < j1; base += 64) {
+        const uint32_t j = base + lane;
+        const bool valid = j < j1;
+        uint32_t r = 0;
+        int lo = 0;
+        if (valid) {
+            if (table) {
+                lo = owner[j];
+            } else {
+                int hi = BLK - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+                }
+            }
+            r = srow[lo] + (j - pre[lo]);
+        }
+        const unsigned long long peers = match_bits(r, valid, rbits);
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        const uint32_t old = valid ? my[r] : 0u;
+        if (valid && lane == __ffsll((long long)peers) - 1) my[r] = old + __popcll(peers);
+        const uint32_t pos = old + __popcll(peers & lt);
+        if (valid) {
+            if (pos < cap) rvals[pos] = (uint32_t)((int64_t)blockIdx.x * BLK + lo);
+            else overflow = true;
+        }
+    }
+    if (__ballot(overflow) && lane == 0) atomicOr(&state->flags, FLAG_KEY_OVERFLOW);
 }
 
 // First global tile and tiles per row of global tile row r.
@@ -1147,8 +1260,9 @@ constexpr int RT_PER = 8;   // rows per thread and round
 // The count array gets one more entry, a zero, so that its scan ends with the total of the
 // keys written.  On overflow of the bounds the kernels after it see zero chunks and the
 // overflow flag is set.
-__global__ __launch_bounds__(RT_T) void k_row_table(const uint2 *__restrict__ rrange,
-                                                    ImgTable tab, int64_t rows, int64_t nch_max,
+__global__ __launch_bounds__(RT_T) void k_row_table(const uint32_t *__restrict__ rscan,
+                                                    uint32_t blocks, ImgTable tab, int64_t rows,
+                                                    int64_t nch_max,
                                                     int64_t scan_max, uint4 *__restrict__ rinfo,
                                                     uint32_t *__restrict__ chunk_row,
                                                     uint32_t *__restrict__ scan,
@@ -1163,7 +1277,9 @@ __global__ __launch_bounds__(RT_T) void k_row_table(const uint2 *__restrict__ rr
         for (int j = 0; j < RT_PER; ++j) {
             int64_t q = (int64_t)threadIdx.x * RT_PER + j;
             q = r0 + (q < nr ? q : nr - 1);
-            rr[j] = rrange[q];
+            // the row's pairs: from its first block's scanned position to the next row's
+            rr[j] = make_uint2(rscan[row_seg_of(tab, (uint32_t)q, blocks)],
+                               rscan[row_seg_of(tab, (uint32_t)q + 1, blocks)]);
             rt[j] = row_tiles(tab, (uint32_t)q);
         }
         uint32_t nch[RT_PER];
@@ -1611,7 +1727,7 @@ hipError_t launch_project(const BinBuffers &b, const ImgTable &tab, hipStream_t 
     if (b.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_project, dim3(grid_for(b.n, BLK)), dim3(BLK), 0, s, record_src(b), b.n, tab,
                        reinterpret_cast<float4 *>(b.proj), b.rect, b.tinfo, b.count, b.blocksum,
-                       nullptr, b.state);
+                       RowHistArgs{nullptr, 0, nullptr}, b.state);
     return hipGetLastError();
 }
 
@@ -1820,50 +1936,45 @@ int64_t row_scan_max(int64_t cap_p, int64_t rows, int32_t max_tw) {
 }
 int64_t chained_scan_blocks(int64_t len) { return (len + CS_TILE - 1) / CS_TILE; }
 
-hipError_t launch_rows_a(const BinBuffers &b, const ImgTable &tab, hipStream_t s) {
+hipError_t launch_rows_a(const RowBuffers &r, const ImgTable &tab, hipStream_t s) {
+    const BinBuffers &b = r.b;
     if (b.n <= 0) return hipErrorInvalidValue;
     const int64_t nb = grid_for(b.n, BLK);
     hipLaunchKernelGGL(k_project, dim3((unsigned)nb), dim3(BLK), 0, s, record_src(b), b.n, tab,
                        reinterpret_cast<float4 *>(b.proj), b.rect, b.tinfo, b.count, b.blocksum,
-                       b.rblocksum, b.state);
-    hipLaunchKernelGGL(k_scan_top, dim3(2), dim3(1024), 0, s, b.blocksum, nb,
-                       &b.state->keys_total, b.rblocksum, &b.state->rows_total);
+                       RowHistArgs{r.rhist, r.rhist_len, r.bwin}, b.state);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, b.blocksum, nb,
+                       &b.state->keys_total, nullptr, nullptr);
+    // the row counts and their closing zero; the prefix at the zero is the pair total
+    const int64_t L = r.rhist_len + 1;
+    hipLaunchKernelGGL(k_chained_scan, dim3((unsigned)chained_scan_blocks(L)), dim3(CS_T), 0, s,
+                       r.rhist, L, r.status, r.rhist_len, &b.state->rows_total, b.state, nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_rows_b(const RowBuffers &r, const ImgTable &tab, bool want_ids, int digit_bits,
-                         int *which, hipStream_t s) {
+hipError_t launch_rows_b(const RowBuffers &r, const ImgTable &tab, bool want_ids, int *which,
+                         hipStream_t s) {
     const BinBuffers &b = r.b;
     if (b.n <= 0 || tab.rows <= 0 || tab.max_tw < 1 || tab.max_tw > ROW_MAX_TW)
         return hipErrorInvalidValue;
     const int64_t pcap = b.cap_p < b.cap ? b.cap_p : b.cap;
+    const int64_t nb = grid_for(b.n, BLK);
     float4 *proj = reinterpret_cast<float4 *>(b.proj);
-    hipLaunchKernelGGL(k_dup_rows, dim3(grid_for(b.n, BLK)), dim3(BLK), 0, s, b.count, b.blocksum,
-                       b.rblocksum, b.n, pcap, b.off, proj, b.keys[0], b.vals[0], b.state);
-    int kb = 1;
-    while (((int64_t)1 << kb) < (int64_t)tab.rows) ++kb;
-    int w = 0;
-    hipError_t e = launch_sort_pairs(b.keys[0], b.vals[0], b.keys[1], b.vals[1], b.keys[0],
-                                     b.vals[0], pcap, &b.state->rows_total, kb, digit_bits,
-                                     b.hist, b.scan_blocksum, &w, s,
-                                     ChainedScan{r.status, b.state});
-    if (e != hipSuccess) return e;
-    const int at = w == 0 ? 1 : 0;  // keys[1] after an odd number of passes
-    *which = at;
-    const uint32_t *rk = b.keys[at], *rv = b.vals[at];
-    uint32_t *ids = want_ids ? b.vals[1 - at] : nullptr;
-    if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(r.rrange), 0u, 2 * (int64_t)tab.rows,
-                             s)) != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_row_bounds, dim3(grid_for(pcap, BLK)), dim3(BLK), 0, s, rk,
-                       &b.state->rows_total, pcap, r.rrange);
-    hipLaunchKernelGGL(k_row_table, dim3(1), dim3(RT_T), 0, s, r.rrange, tab, (int64_t)tab.rows,
-                       r.nch_max, r.scan_max, r.rinfo, r.chunk_row, r.scan, b.state);
+    // the pairs go to vals[0]; the sorted Gaussian ids, when wanted, to vals[1]
+    *which = 0;
+    uint32_t *rv = b.vals[0];
+    uint32_t *ids = want_ids ? b.vals[1] : nullptr;
+    hipLaunchKernelGGL(k_rows_scatter, dim3((unsigned)nb), dim3(BLK), 0, s, b.count, proj,
+                       b.blocksum, r.rhist, r.bwin, tab, b.n, pcap, b.off, rv, b.state);
+    hipLaunchKernelGGL(k_row_table, dim3(1), dim3(RT_T), 0, s, r.rhist, (uint32_t)nb, tab,
+                       (int64_t)tab.rows, r.nch_max, r.scan_max, r.rinfo, r.chunk_row, r.scan,
+                       b.state);
     hipLaunchKernelGGL(k_row_hist, dim3((unsigned)r.nch_max), dim3(ROW_CHUNK), 0, s, rv, r.rinfo,
                        r.chunk_row, proj, r.scan, b.state);
     hipLaunchKernelGGL(k_chained_scan, dim3((unsigned)chained_scan_blocks(r.scan_max)), dim3(CS_T),
                        0, s, r.scan, r.scan_max, r.status, (int64_t)-1, nullptr, b.state,
                        &b.state->row_scan_len);
+    hipError_t e;
     if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(b.ranges), 0u, 2 * b.n_tiles, s)) !=
         hipSuccess)
         return e;
