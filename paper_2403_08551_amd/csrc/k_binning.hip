@@ -1021,8 +1021,8 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
             const uint32_t li = j - pre[lo], wd = (uint32_t)(r.z - r.x + 1);
             t = inf.x + ((uint32_t)r.y + li / wd) * inf.y + (uint32_t)r.x + li % wd;
         }
-        const unsigned long long peers = match_bits(t, valid, tbits);
-        if (valid && lane == __ffsll((long long)peers) - 1) my[t] += __popcll(peers);
+        // counts only (order does not matter here): one LDS atomic per key
+        if (valid) atomicAdd(&my[t], 1u);
     }
     __syncthreads();
     // wave offsets within the chunk, per tile, on top of the chunk's base in tile order
@@ -1199,8 +1199,8 @@ __global__ __launch_bounds__(BLK) void k_rows_scatter(const uint32_t *__restrict
             }
             r = srow[lo] + (j - pre[lo]);
         }
-        const unsigned long long peers = match_bits(r, valid, rbits);
-        if (valid && lane == __ffsll((long long)peers) - 1) my[r] += __popcll(peers);
+        // counts only (order does not matter here): one LDS atomic per key
+        if (valid) atomicAdd(&my[r], 1u);
     }
     __syncthreads();
     for (uint32_t r = threadIdx.x; r < W; r += BLK) {
@@ -1515,8 +1515,8 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
             }
             x = sx0[lo] + (j - pre[lo]);
         }
-        const unsigned long long peers = match_bits(x, valid, xbits);
-        if (valid && lane == __ffsll((long long)peers) - 1) my[x] += __popcll(peers);
+        // counts only (order does not matter here): one LDS atomic per key
+        if (valid) atomicAdd(&my[x], 1u);
     }
     __syncthreads();
     if (table) {
