@@ -311,6 +311,36 @@ def test_batched_render_and_grad_equal_plain(gi):
         np.testing.assert_array_equal(dall[off[b]:off[b + 1]], ds)
 
 
+@pytest.mark.parametrize("binning", [1, 3], ids=["radix", "rows"])
+def test_batched_with_empty_images_and_blocks_spanning_images(gi, binning):
+    # eight small images, two without Gaussians, so that one block of 256 Gaussians spans
+    # several images and an empty one between them; batched render and gradient against each
+    # image alone (default binning), bit for bit
+    import paper_2403_08551_amd as P
+    hs = [40, 33, 57, 20, 64, 18, 45, 30]
+    ws = [36, 70, 25, 44, 50, 90, 31, 27]
+    ns = [120, 0, 90, 60, 0, 150, 75, 40]
+    ps = [synth.gaussians(n, h, w, seed=300 + i) for i, (n, h, w) in enumerate(zip(ns, hs, ws))]
+    off = np.concatenate([[0], np.cumsum(ns)])
+    batch = P.Batch(hs, ws, off)
+    allp = dev(np.concatenate(ps))
+    Gs = [synth.upstream_gradient(h, w, 60 + i) for i, (h, w) in enumerate(zip(hs, ws))]
+    Gall = dev(np.concatenate([g.reshape(-1, 3) for g in Gs]))
+    gi.set_option(P._lib.GI_OPT_BINNING, binning)
+    try:
+        imgs = gi.render_batched(allp, batch)
+        dall = host(gi.grad_batched(allp, batch, Gall))
+    finally:
+        gi.set_option(P._lib.GI_OPT_BINNING, 0)
+    for b in range(len(hs)):
+        pb = dev(ps[b]) if ns[b] else dev(np.zeros((0, 8), np.float32))
+        single = host(gi.render(pb, hs[b], ws[b]))
+        np.testing.assert_array_equal(host(batch.image(imgs, b)), single)
+        if ns[b]:
+            ds = host(gi.grad(pb, hs[b], ws[b], dev(Gs[b])))
+            np.testing.assert_array_equal(dall[off[b]:off[b + 1]], ds)
+
+
 def test_batched_fit_equals_plain_fit(gi):
     import paper_2403_08551_amd as P
     hs, ws, ps, ts = small_batch()
