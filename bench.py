@@ -351,8 +351,9 @@ def ablation_leg(P, torch, steps):
 
 def recipe_leg(P, torch, w, steps):
     """Fit it/s of the paper's recipe (raw records, App. C parametrisation, Adan) and of the
-    quantisation-aware fine-tuning (b = 6, M = 2, B = 8), eager non-waiting steps on the
-    workload's size; also the quantiser set-up and encoding times."""
+    quantisation-aware fine-tuning (b = 6, M = 2, B = 8) on the workload's size, graph-replayed
+    steps (and eager non-waiting steps beside them); also the quantiser set-up and encoding
+    times."""
     import numpy as np
     dev = torch.device("cuda", 0)
     H, W = w.height, w.width
@@ -378,7 +379,15 @@ def recipe_leg(P, torch, w, steps):
     for _ in range(steps):
         ctx.fit_step_recipe(rd, state, target, step)
     torch.cuda.synchronize()
+    out["recipe_fit_its_eager"] = steps / (time.perf_counter() - t0)
+    g = ctx.fit_graph_recipe(rd, state, target, step)
+    g.launch(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.launch(steps)
+    torch.cuda.synchronize()
     out["recipe_fit_its"] = steps / (time.perf_counter() - t0)
+    g.close()
     ctx.set_option(P._lib.GI_OPT_SYNC, 1)
     params = ctx.recipe_params(rd, H, W)
     q = P.Quantiser.zeros(dev)
@@ -398,7 +407,15 @@ def recipe_leg(P, torch, w, steps):
     for _ in range(steps):
         ctx.fit_step_qat(params, m, v, target, step, q)
     torch.cuda.synchronize()
+    out["qat_fit_its_eager"] = steps / (time.perf_counter() - t0)
+    g = ctx.fit_graph_qat(params, m, v, target, step, q)
+    g.launch(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.launch(steps)
+    torch.cuda.synchronize()
     out["qat_fit_its"] = steps / (time.perf_counter() - t0)
+    g.close()
     t0 = time.perf_counter()
     codec = ctx.qat_encode(params, q)
     torch.cuda.synchronize()

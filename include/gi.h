@@ -350,6 +350,19 @@ int gi_fit_graph_create(gi_ctx *ctx, float *params_dev, float *m_dev, float *v_d
                         const gi_batch *batch, const gi_adam *hp, int32_t *step_dev,
                         float *image_out_dev, float *loss_out_dev, void *stream,
                         gi_graph **out);
+/* The same for one step of the paper's fitting recipe (gi_fit_step_recipe: raw records, Adan;
+ * Sec. 4.1, App. C) and one quantisation-aware fine-tuning step (gi_fit_step_qat; Sec. 3.3) on a
+ * single image; the sizing pass bins the records as those steps project them (the recipe's
+ * parametrisation, the fake-quantised records).  The quantiser's buffers in q are baked in. */
+int gi_fit_graph_create_recipe(gi_ctx *ctx, float *raw_dev, float *state_dev,
+                               const float *target_dev, int64_t n, int32_t height, int32_t width,
+                               const gi_adan *hp, int32_t *step_dev, float *image_out_dev,
+                               float *loss_out_dev, void *stream, gi_graph **out);
+int gi_fit_graph_create_qat(gi_ctx *ctx, float *params_dev, float *m_dev, float *v_dev,
+                            const float *target_dev, int64_t n, int32_t height, int32_t width,
+                            const gi_adam *hp, const gi_qat *q, int32_t *step_dev,
+                            float *image_out_dev, float *loss_out_dev, void *stream,
+                            gi_graph **out);
 /* Replay the captured step `steps` times on `stream`. */
 int gi_fit_graph_launch(gi_graph *graph, int32_t steps, void *stream);
 /* gi_query on the graph's private workspace (waits for the device). */

@@ -531,6 +531,42 @@ class Context:
             "gi_fit_graph_create")
         return FitGraph(self, g, (params, m, v, target, step, image_out, loss_out))
 
+    def fit_graph_recipe(self, raw, state, target, step, hp: AdanConfig | None = None,
+                         image_out=None, loss_out=None) -> "FitGraph":
+        """Capture one step of the fitting recipe (see fit_step_recipe) into a HIP graph."""
+        n = raw.shape[0]
+        h, w = target.shape[0], target.shape[1]
+        _check(raw, "raw", self.device, (n, 8))
+        _check(state, "state", self.device, (4, n, 8))
+        _check(target, "target", self.device, (h, w, 3))
+        _check(step, "step", self.device, (1,), torch.int32)
+        hpc = (hp or AdanConfig()).c()
+        g = ctypes.c_void_p()
+        self._raise(_lib.lib().gi_fit_graph_create_recipe(
+            self._h, _ptr(raw), _ptr(state), _ptr(target), n, h, w, ctypes.byref(hpc),
+            _ptr(step), _ptr(image_out), _ptr(loss_out), _stream(self.device), ctypes.byref(g)),
+            "gi_fit_graph_create_recipe")
+        return FitGraph(self, g, (raw, state, target, step, image_out, loss_out))
+
+    def fit_graph_qat(self, params, m, v, target, step, quant: "Quantiser",
+                      hp: AdamConfig | None = None, image_out=None,
+                      loss_out=None) -> "FitGraph":
+        """Capture one fine-tuning step (see fit_step_qat) into a HIP graph."""
+        n = params.shape[0]
+        h, w = target.shape[0], target.shape[1]
+        for t, name in ((params, "params"), (m, "m"), (v, "v")):
+            _check(t, name, self.device, (n, 8))
+        _check(target, "target", self.device, (h, w, 3))
+        _check(step, "step", self.device, (1,), torch.int32)
+        hpc = (hp or AdamConfig()).c()
+        q = quant.c(self.device)
+        g = ctypes.c_void_p()
+        self._raise(_lib.lib().gi_fit_graph_create_qat(
+            self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(target), n, h, w, ctypes.byref(hpc),
+            ctypes.byref(q), _ptr(step), _ptr(image_out), _ptr(loss_out), _stream(self.device),
+            ctypes.byref(g)), "gi_fit_graph_create_qat")
+        return FitGraph(self, g, (params, m, v, target, step, quant, image_out, loss_out))
+
     # -- inspection of the binning stages
     def binning(self, params, height: int, width: int):
         """Run the binning stages and return rects, counts, offsets, ranges and sorted ids."""

@@ -51,6 +51,7 @@ EXPORTS = (
     "gi_get_option", "gi_autotune", "gi_fit_graph_query", "gi_codec_decode", "gi_render_codec",
     "gi_render_opacity", "gi_grad_opacity", "gi_fit_step_opacity", "gi_fit_step_recipe",
     "gi_recipe_params", "gi_qat_init", "gi_fit_step_qat", "gi_qat_encode",
+    "gi_fit_graph_create_recipe", "gi_fit_graph_create_qat",
 )
 
 
@@ -152,6 +153,11 @@ def lib():
             "gi_fit_step_qat": ([P, P, P, P, P, I64, I32, I32, ctypes.POINTER(gi_adam),
                                  ctypes.POINTER(gi_qat), P, P, P, P], ctypes.c_int),
             "gi_qat_encode": ([P, P, I64, ctypes.POINTER(gi_qat), P, P, P, P], ctypes.c_int),
+            "gi_fit_graph_create_recipe": ([P, P, P, P, I64, I32, I32, ctypes.POINTER(gi_adan),
+                                            P, P, P, P, ctypes.POINTER(P)], ctypes.c_int),
+            "gi_fit_graph_create_qat": ([P, P, P, P, P, I64, I32, I32, ctypes.POINTER(gi_adam),
+                                         ctypes.POINTER(gi_qat), P, P, P, P, ctypes.POINTER(P)],
+                                        ctypes.c_int),
             "gi_render_opacity": ([P, P, P, I64, I32, I32, I32, P, P], ctypes.c_int),
             "gi_grad_opacity": ([P, P, P, I64, I32, I32, I32, P, P, P, P], ctypes.c_int),
             "gi_codec_decode": ([P, ctypes.POINTER(gi_codec), I64, P, P], ctypes.c_int),

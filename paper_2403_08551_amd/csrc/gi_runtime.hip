@@ -1423,23 +1423,16 @@ int gi_fit_step_batched(gi_ctx *ctx, float *params, float *m, float *v, const fl
                   (hipStream_t)stream);
 }
 
-int gi_fit_graph_create(gi_ctx *user, float *params, float *m, float *v, const float *target,
-                        int64_t n, int32_t H, int32_t W, const gi_batch *batch,
-                        const gi_adam *hp, int32_t *step, float *image_out, float *loss_out,
-                        void *stream, gi_graph **out) {
-    if (!out) return GI_ERR_INVALID_ARG;
-    *out = nullptr;
-    if (!user || !target || !step || check_adam(hp) != GI_OK) return GI_ERR_INVALID_ARG;
-    if (batch) {
-        if (check_batch(batch) != GI_OK) return GI_ERR_INVALID_ARG;
-        n = batch->gauss_off_host[batch->count];
-    } else if (check_single(n, H, W) != GI_OK) {
-        return GI_ERR_INVALID_ARG;
-    }
-    if (n > 0 && (!params || !m || !v || !aligned16(params) || !aligned16(m) || !aligned16(v)))
-        return GI_ERR_INVALID_ARG;
-    // The graph bakes in workspace addresses, so it gets a workspace of its own that no later
-    // call can reallocate: a private context with the caller's settings.
+// Capture one step into a graph on a private context (the graph bakes in workspace addresses,
+// so it gets a workspace of its own that no later call can reallocate), with the caller's
+// settings.  `prepare(ctx, on)` sets (on) and clears (!on) what the step's binning reads and
+// sizes the step's own buffers; one synchronous binning pass of params then sizes the keys with
+// a 25% margin; `step(ctx, tab, T, stream)` is captured.
+extern "C++" {
+template <typename Prepare, typename Step>
+int capture_step(gi_ctx *user, const float *params, int64_t n, int32_t H, int32_t W,
+                 const gi_batch *batch, void *stream, Prepare prepare, Step step,
+                 gi_graph **out) {
     gi_ctx *ctx = nullptr;
     int rc = gi_create(&ctx, user->device);
     if (rc != GI_OK) return rc;
@@ -1469,12 +1462,13 @@ int gi_fit_graph_create(gi_ctx *user, float *params, float *m, float *v, const f
         tab = single_table(H, W);
         T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
     }
-    // one synchronous binning pass sizes the workspace: keys with a 25% margin
     hipStream_t s = (hipStream_t)stream;
     ctx->sync = 1;
     int64_t bound;
     int which;
-    rc = run_binning(ctx, params, n, tab, T, s, &bound, &which);
+    rc = prepare(ctx, true);
+    if (rc == GI_OK) rc = run_binning(ctx, params, n, tab, T, s, &bound, &which);
+    (void)prepare(ctx, false);
     if (rc == GI_OK) rc = ensure_keys(ctx, bound + bound / 4 + 4096);
     if (rc != GI_OK) return fail(rc);
     hipError_t e = hipStreamSynchronize(s);
@@ -1483,7 +1477,7 @@ int gi_fit_graph_create(gi_ctx *user, float *params, float *m, float *v, const f
     hipStream_t cs = ctx->capture_stream;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamBeginCapture"));
-    rc = do_fit(ctx, params, m, v, target, n, tab, T, hp, step, image_out, loss_out, cs);
+    rc = step(ctx, tab, T, cs);
     e = hipStreamEndCapture(cs, &gr->graph);
     if (rc != GI_OK) return fail(rc);
     if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamEndCapture"));
@@ -1491,6 +1485,91 @@ int gi_fit_graph_create(gi_ctx *user, float *params, float *m, float *v, const f
     if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipGraphInstantiate"));
     *out = gr;
     return GI_OK;
+}
+}  // extern "C++"
+
+int gi_fit_graph_create(gi_ctx *user, float *params, float *m, float *v, const float *target,
+                        int64_t n, int32_t H, int32_t W, const gi_batch *batch,
+                        const gi_adam *hp, int32_t *step, float *image_out, float *loss_out,
+                        void *stream, gi_graph **out) {
+    if (!out) return GI_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!user || !target || !step || check_adam(hp) != GI_OK) return GI_ERR_INVALID_ARG;
+    if (batch) {
+        if (check_batch(batch) != GI_OK) return GI_ERR_INVALID_ARG;
+        n = batch->gauss_off_host[batch->count];
+    } else if (check_single(n, H, W) != GI_OK) {
+        return GI_ERR_INVALID_ARG;
+    }
+    if (n > 0 && (!params || !m || !v || !aligned16(params) || !aligned16(m) || !aligned16(v)))
+        return GI_ERR_INVALID_ARG;
+    return capture_step(
+        user, params, n, H, W, batch, stream, [](gi_ctx *, bool) { return (int)GI_OK; },
+        [&](gi_ctx *ctx, const ImgTable &tab, int64_t T, hipStream_t cs) {
+            return do_fit(ctx, params, m, v, target, n, tab, T, hp, step, image_out, loss_out,
+                          cs);
+        },
+        out);
+}
+
+int gi_fit_graph_create_recipe(gi_ctx *user, float *raw, float *state, const float *target,
+                               int64_t n, int32_t H, int32_t W, const gi_adan *hp, int32_t *step,
+                               float *image_out, float *loss_out, void *stream, gi_graph **out) {
+    if (!out) return GI_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!user || !target || !step || check_adan(hp) != GI_OK) return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!raw || !state || !aligned16(raw) || !aligned16(state)))
+        return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    return capture_step(
+        user, raw, n, H, W, nullptr, stream,
+        [](gi_ctx *ctx, bool on) {
+            ctx->recipe_cur = on ? 1 : 0;  // the binning projects the raw records
+            return (int)GI_OK;
+        },
+        [&](gi_ctx *ctx, const ImgTable &tab, int64_t T, hipStream_t cs) {
+            return do_fit_recipe(ctx, raw, state, target, n, tab, T, hp, step, image_out,
+                                 loss_out, cs);
+        },
+        out);
+}
+
+int gi_fit_graph_create_qat(gi_ctx *user, float *params, float *m, float *v, const float *target,
+                            int64_t n, int32_t H, int32_t W, const gi_adam *hp, const gi_qat *q,
+                            int32_t *step, float *image_out, float *loss_out, void *stream,
+                            gi_graph **out) {
+    QatArgs qa;
+    if (!out) return GI_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!user || !target || !step || check_adam(hp) != GI_OK || qat_args(q, &qa) != GI_OK)
+        return GI_ERR_INVALID_ARG;
+    if (!q->quant_m_dev || !q->quant_v_dev || !(q->lambda >= 0.f) || !(q->lr_q >= 0.f))
+        return GI_ERR_INVALID_ARG;
+    if (n > 0 && (!params || !m || !v || !aligned16(params) || !aligned16(m) || !aligned16(v)))
+        return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    return capture_step(
+        user, params, n, H, W, nullptr, stream,
+        [&](gi_ctx *ctx, bool on) {
+            if (!on) {
+                ctx->qat_cur = QatArgs{nullptr, 0, 0, 0};
+                return (int)GI_OK;
+            }
+            // the quantiser's block sums, sized now (the captured step must not allocate)
+            const int64_t need = qat_part_floats(n, qa.stages, qa.size);
+            if (need > ctx->qpart_cap) {
+                CK(hipDeviceSynchronize());
+                CK(grow(&ctx->qpart, need));
+                ctx->qpart_cap = need;
+            }
+            ctx->qat_cur = qa;  // the binning projects the fake-quantised records
+            return (int)GI_OK;
+        },
+        [&](gi_ctx *ctx, const ImgTable &tab, int64_t T, hipStream_t cs) {
+            return do_fit_qat(ctx, params, m, v, target, n, tab, T, hp, q, qa, step, image_out,
+                              loss_out, cs);
+        },
+        out);
 }
 
 int gi_fit_graph_launch(gi_graph *gr, int32_t steps, void *stream) {

@@ -77,3 +77,36 @@ def test_recipe_steps_match_oracle(cov):
         assert int(host(step)[0]) == 5
     finally:
         ctx.close()
+
+
+def test_recipe_graph_replay_equals_eager_steps():
+    # a captured recipe step replayed (with eager work and synchronisation between replays)
+    # gives the eager steps' records and Adan state bit for bit
+    import paper_2403_08551_amd as P
+    h, w = 80, 112
+    raw0 = raw_set(500, 73, "chol")
+    T = dev(synth.target_noise_rects(h, w, seed=74))
+    hp = P.AdanConfig(**dict(recipe.DEFAULT_ADAN, lr=0.01, halve_every=2))
+    ea, gr = P.Context(0), P.Context(0)
+    try:
+        ra, rb = dev(raw0), dev(raw0)
+        sa, sb = torch.zeros(4, 500, 8, device="cuda"), torch.zeros(4, 500, 8, device="cuda")
+        ka = torch.ones(1, dtype=torch.int32, device="cuda")
+        kb = torch.ones(1, dtype=torch.int32, device="cuda")
+        for _ in range(4):
+            ea.fit_step_recipe(ra, sa, T, ka, hp)
+        graph = gr.fit_graph_recipe(rb, sb, T, kb, hp)
+        try:
+            for _ in range(2):
+                graph.launch(2)
+                torch.cuda.synchronize()
+                _ = torch.zeros(10, device="cuda").sum().item()
+            assert graph.query()[1] == 0
+        finally:
+            graph.close()
+        np.testing.assert_array_equal(host(rb), host(ra))
+        np.testing.assert_array_equal(host(sb), host(sa))
+        assert int(host(kb)[0]) == 5
+    finally:
+        ea.close()
+        gr.close()
