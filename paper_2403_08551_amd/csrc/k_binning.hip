@@ -940,6 +940,9 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
     __shared__ int4 srect[FB];
     __shared__ uint2 sinfo[FB];
     __shared__ uint32_t soff[FB];
+    // m = ceil(2^32 / w) for each rectangle's width w: a key's row within its rectangle is
+    // (i m) >> 32, exact while i < 2^32 / w (here i < w h <= 2048 and w <= 2048)
+    __shared__ unsigned long long smag[FB];
     __shared__ float4 sproj[2 * FB];
     __shared__ uint8_t owner[OWN_CAP];  // chunk-local key -> its Gaussian, when the keys fit
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -972,6 +975,8 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
     if (table)
         for (uint32_t k = 0; k < c; ++k) owner[loc + k] = (uint8_t)threadIdx.x;
     if (mine) {
+        const uint32_t wd = rc_in.z >= rc_in.x ? (uint32_t)(rc_in.z - rc_in.x + 1) : 1u;
+        smag[threadIdx.x] = (unsigned long long)(0xffffffffu / wd) + 1ull;  // = ceil(2^32 / w)
         srect[threadIdx.x] = rc_in;
         sinfo[threadIdx.x] = inf_in;
         soff[threadIdx.x] = off_in;
@@ -1019,7 +1024,8 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
             const int4 r = srect[lo];
             const uint2 inf = sinfo[lo];
             const uint32_t li = j - pre[lo], wd = (uint32_t)(r.z - r.x + 1);
-            t = inf.x + ((uint32_t)r.y + li / wd) * inf.y + (uint32_t)r.x + li % wd;
+            const uint32_t q = (uint32_t)(((unsigned long long)li * smag[lo]) >> 32);
+            t = inf.x + ((uint32_t)r.y + q) * inf.y + (uint32_t)r.x + (li - q * wd);
         }
         // counts only (order does not matter here): one LDS atomic per key
         if (valid) atomicAdd(&my[t], 1u);
@@ -1060,7 +1066,8 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
             const uint2 inf = sinfo[lo];
             li = j - pre[lo];
             const uint32_t wd = (uint32_t)(r.z - r.x + 1);
-            t = inf.x + ((uint32_t)r.y + li / wd) * inf.y + (uint32_t)r.x + li % wd;
+            const uint32_t q = (uint32_t)(((unsigned long long)li * smag[lo]) >> 32);
+            t = inf.x + ((uint32_t)r.y + q) * inf.y + (uint32_t)r.x + (li - q * wd);
         }
         const unsigned long long peers = match_bits(t, valid, tbits);
         const unsigned long long lt = (1ull << lane) - 1ull;
