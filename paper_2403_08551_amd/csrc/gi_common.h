@@ -2,19 +2,21 @@
 //
 // Data layout in device memory (one context):
 //   params  [N][8]  f32   (mu_x, mu_y, l1, l2, l3, c0, c1, c2), caller owned
-//   proj    [N][16] f32   one 64-byte line per Gaussian (radix path; the one-pass path packs
-//                          the 32-byte records at a stride of 8 floats): the record (mu_x, mu_y, a, b, k, c0,
+//   proj    [N][16] f32   one 64-byte line per Gaussian (radix and row paths; the one-pass path
+//                          packs the 32-byte records at a stride of 8 floats): the record (mu_x, mu_y, a, b, k, c0,
 //                          c1, c2) with a = s/l1, b = s/l3, k = s*l2/(l1*l3), s =
 //                          sqrt(log2(e)/2): then u1 = a*dx and u2 = b*dy - k*dx satisfy
 //                          u1^2 + u2^2 = log2(e)*sigma, so that exp(-sigma) = exp2(-(u1^2 +
 //                          u2^2)) (Eq. rasterization2 through the Cholesky factor: sigma =
 //                          |L^{-1} d|^2 / 2); then u32 (key offset, image's first tile, tiles
-//                          across | rect width << 16, tx0 | ty0 << 16) and 4 unused words
+//                          across | rect width << 16, tx0 | ty0 << 16), then u32 (global tile
+//                          row of the rectangle's first row, its rows) and 2 unused words
 //   rect    [N]     int4  inclusive tile rectangle (tx0, ty0, tx1, ty1); (0, 0, -1, -1) if none
 //   tinfo   [N]     uint2 (first global tile id of the Gaussian's image, tiles across)
 //   count   [N]     u32   tiles covered;  off [N] u32 exclusive prefix sum of count
 //   keys/vals [cap] u32   (global tile id, Gaussian id), two ping-pong pairs for the sort
-//   rec     [cap][8] f32  proj records gathered into tile-sorted order
+//                          (row binning keeps its (row, Gaussian) pairs in vals[0])
+//   rec     [cap][8] f32  proj records in tile-sorted order
 //   slot    [cap]   u32   position of each sorted key in the unsorted (Gaussian-major) order
 //   part    [cap][8] f32  per (tile, Gaussian) partial gradient sums, indexed by slot
 //   ranges  [T]     uint2 [start, end) of each tile in the sorted order

@@ -1,6 +1,8 @@
-// Binning kernels for gfx950: projection and 3-sigma tile culling, prefix scans, key
-// duplication, the stable LSD radix sort by tile id, and tile-range extraction with the gather
-// of records into tile order.
+// Binning kernels for gfx950: projection and 3-sigma tile culling, prefix scans, and three
+// ways to put every (tile, Gaussian) key into tile order with its record, slot and the tile
+// ranges: a one-pass counting sort (up to 2048 tiles), row binning (a counting sort in two
+// levels, for more tiles), and key duplication with a stable LSD radix sort and a gather (any
+// size).  All three give the same order.
 //
 // The paper renders tile by tile (Sec. 4.1 builds on the tile-based rasteriser of 3D-GS) and
 // removes the depth sort because the accumulated sum does not depend on order (Sec. 3.2, after

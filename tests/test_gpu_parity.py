@@ -341,6 +341,45 @@ def test_batched_with_empty_images_and_blocks_spanning_images(gi, binning):
             np.testing.assert_array_equal(dall[off[b]:off[b + 1]], ds)
 
 
+def test_row_binning_equals_radix_on_the_64_image_batch(gi):
+    # the batch of uneven images (95k tiles, 1.1M Gaussians) rendered and differentiated with
+    # row binning and with the radix sort of all keys: the same images and gradients, bit for bit
+    import paper_2403_08551_amd as P
+    ws = synth.batch_small(64)
+    ps = [w.params() for w in ws]
+    off = np.concatenate([[0], np.cumsum([p.shape[0] for p in ps])])
+    batch = P.Batch([w.height for w in ws], [w.width for w in ws], off)
+    allp = dev(np.concatenate(ps))
+    G = dev(np.concatenate([synth.upstream_gradient(w.height, w.width, 500 + i).reshape(-1, 3)
+                            for i, w in enumerate(ws)]))
+    out = {}
+    for mode in (1, 3):
+        gi.set_option(P._lib.GI_OPT_BINNING, mode)
+        try:
+            img = host(gi.render_batched(allp, batch))
+            d = host(gi.grad_batched(allp, batch, G))
+        finally:
+            gi.set_option(P._lib.GI_OPT_BINNING, 0)
+        out[mode] = (img, d)
+    np.testing.assert_array_equal(out[1][0], out[3][0])
+    np.testing.assert_array_equal(out[1][1], out[3][1])
+
+
+def test_batch_with_blocks_over_too_many_tile_rows_falls_back_to_the_radix_sort(gi):
+    # three tall images (1024 tile rows each, 6144 tiles in all) whose 300 Gaussians share one
+    # block of 256: its images hold 3072 tile rows, more than row binning takes, so the radix
+    # path bins them; the batched render equals each image rendered alone
+    import paper_2403_08551_amd as P
+    hs, ws, ns = [16384] * 3, [32] * 3, [100] * 3
+    ps = [synth.gaussians(n, h, w, seed=600 + i) for i, (n, h, w) in enumerate(zip(ns, hs, ws))]
+    off = np.concatenate([[0], np.cumsum(ns)])
+    batch = P.Batch(hs, ws, off)
+    imgs = gi.render_batched(dev(np.concatenate(ps)), batch)
+    for b in range(3):
+        np.testing.assert_array_equal(host(batch.image(imgs, b)),
+                                      host(gi.render(dev(ps[b]), hs[b], ws[b])))
+
+
 def test_batched_fit_equals_plain_fit(gi):
     import paper_2403_08551_amd as P
     hs, ws, ps, ts = small_batch()
