@@ -451,62 +451,89 @@ __device__ inline float wave_sum(float v) {
 }
 
 // Adjoint walk of one tile (one wave, four pixels per lane): D holds the final colours on entry,
-// g the pixels' dL/dC.
+// g the pixels' dL/dC.  Each Gaussian's nine sums are reduced over the wave in groups of
+// ALPHA_GRP Gaussians: the lanes store their partial sums as rows of LDS (`red`, ALPHA_GRP * 9
+// rows of ALPHA_STR floats), then each lane adds up one row in lane order and stores it.
+constexpr int ALPHA_GRP = 4;
+constexpr int ALPHA_NV = 9;
+constexpr int ALPHA_STR = 68;  // row stride: 16-byte aligned rows; lanes l, l+16, .. share banks
+constexpr int ALPHA_RED = ALPHA_GRP * ALPHA_NV * ALPHA_STR;
 __device__ inline void alpha_adjoint(const float4 *__restrict__ rec,
                                      const float *__restrict__ rec_o,
                                      const uint32_t *__restrict__ slot, uint2 r, float px,
                                      const float (&py)[4], float (&D)[4][3],
-                                     const float (&g)[4][3], float4 *__restrict__ part) {
+                                     const float (&g)[4][3], float4 *__restrict__ part,
+                                     float *red) {
     constexpr int PX = 4;
+    const int lane = threadIdx.x & 63;
     float T[PX];
 #pragma unroll
     for (int j = 0; j < PX; ++j) T[j] = 1.f;
-    for (uint32_t i = r.x; i < r.y; ++i) {
-        const float4 A = rec[2 * (int64_t)i], B = rec[2 * (int64_t)i + 1];
-        const float o = rec_o[i];
-        const float dx = px - A.x;
-        const float u1 = A.z * dx;
-        const float u1s = u1 * u1;
-        const float t = B.x * dx;
-        float C0 = 0.f, C1 = 0.f, C2 = 0.f, SO = 0.f, W = 0.f, WU2 = 0.f, WU22 = 0.f;
+    for (uint32_t i0 = r.x; i0 < r.y; i0 += ALPHA_GRP) {
+        const uint32_t ng = r.y - i0 < (uint32_t)ALPHA_GRP ? r.y - i0 : (uint32_t)ALPHA_GRP;
+        for (uint32_t k = 0; k < ng; ++k) {
+            const uint32_t i = i0 + k;
+            const float4 A = rec[2 * (int64_t)i], B = rec[2 * (int64_t)i + 1];
+            const float o = rec_o[i];
+            const float dx = px - A.x;
+            const float u1 = A.z * dx;
+            const float u1s = u1 * u1;
+            const float t = B.x * dx;
+            float C0 = 0.f, C1 = 0.f, C2 = 0.f, SO = 0.f, W = 0.f, WU2 = 0.f, WU22 = 0.f;
 #pragma unroll
-        for (int j = 0; j < PX; ++j) {
-            const float u2 = fmaf(py[j] - A.y, A.w, -t);
-            const float e = ex2(-fmaf(u2, u2, u1s));
-            const float oe = o * e;
-            const float a = fminf(oe, ALPHA_MAX);
-            const float w = a * T[j];
-            D[j][0] = fmaf(-B.y, w, D[j][0]);
-            D[j][1] = fmaf(-B.z, w, D[j][1]);
-            D[j][2] = fmaf(-B.w, w, D[j][2]);
-            C0 = fmaf(g[j][0], w, C0);
-            C1 = fmaf(g[j][1], w, C1);
-            C2 = fmaf(g[j][2], w, C2);
-            const float gc = fmaf(g[j][2], B.w, fmaf(g[j][1], B.z, g[j][0] * B.y));
-            const float gd = fmaf(g[j][2], D[j][2], fmaf(g[j][1], D[j][1], g[j][0] * D[j][0]));
-            const float ga = fmaf(T[j], gc, -gd * __builtin_amdgcn_rcpf(1.f - a));  // dL/dalpha
-            const float gae = oe < ALPHA_MAX ? ga * e : 0.f;  // clamped: no dependence on o, sigma
-            SO += gae;
-            const float ws = o * gae;  // -dL/dsigma
-            W += ws;
-            const float wu2 = ws * u2;
-            WU2 += wu2;
-            WU22 = fmaf(wu2, u2, WU22);
-            T[j] *= 1.f - a;
+            for (int j = 0; j < PX; ++j) {
+                const float u2 = fmaf(py[j] - A.y, A.w, -t);
+                const float e = ex2(-fmaf(u2, u2, u1s));
+                const float oe = o * e;
+                const float a = fminf(oe, ALPHA_MAX);
+                const float w = a * T[j];
+                D[j][0] = fmaf(-B.y, w, D[j][0]);
+                D[j][1] = fmaf(-B.z, w, D[j][1]);
+                D[j][2] = fmaf(-B.w, w, D[j][2]);
+                C0 = fmaf(g[j][0], w, C0);
+                C1 = fmaf(g[j][1], w, C1);
+                C2 = fmaf(g[j][2], w, C2);
+                const float gc = fmaf(g[j][2], B.w, fmaf(g[j][1], B.z, g[j][0] * B.y));
+                const float gd = fmaf(g[j][2], D[j][2], fmaf(g[j][1], D[j][1], g[j][0] * D[j][0]));
+                const float ga = fmaf(T[j], gc, -gd * __builtin_amdgcn_rcpf(1.f - a));  // dL/dalpha
+                const float gae = oe < ALPHA_MAX ? ga * e : 0.f;  // clamped: no dependence on o, sigma
+                SO += gae;
+                const float ws = o * gae;  // -dL/dsigma
+                W += ws;
+                const float wu2 = ws * u2;
+                WU2 += wu2;
+                WU22 = fmaf(wu2, u2, WU22);
+                T[j] *= 1.f - a;
+            }
+            // rows in the order of the stored sums: C0 C1 C2 P1 | P2 Q11 Q12 Q22 | SO
+            float *row = red + (int)k * ALPHA_NV * ALPHA_STR + lane;
+            row[0 * ALPHA_STR] = C0;
+            row[1 * ALPHA_STR] = C1;
+            row[2 * ALPHA_STR] = C2;
+            row[3 * ALPHA_STR] = u1 * W;
+            row[4 * ALPHA_STR] = WU2;
+            row[5 * ALPHA_STR] = u1s * W;
+            row[6 * ALPHA_STR] = u1 * WU2;
+            row[7 * ALPHA_STR] = WU22;
+            row[8 * ALPHA_STR] = SO;
         }
-        const float P1 = wave_sum_to_last(u1 * W), Q11 = wave_sum_to_last(u1s * W);
-        const float Q12 = wave_sum_to_last(u1 * WU2), P2 = wave_sum_to_last(WU2);
-        const float Q22 = wave_sum_to_last(WU22);
-        C0 = wave_sum_to_last(C0);
-        C1 = wave_sum_to_last(C1);
-        C2 = wave_sum_to_last(C2);
-        SO = wave_sum_to_last(SO);
-        if (threadIdx.x == 63) {
-            const int64_t sl = slot[i];
-            part[3 * sl] = make_float4(C0, C1, C2, P1);
-            part[3 * sl + 1] = make_float4(P2, Q11, Q12, Q22);
-            part[3 * sl + 2] = make_float4(SO, 0.f, 0.f, 0.f);
+        __syncthreads();  // one wave: the rows are in LDS
+        for (uint32_t rw = lane; rw < ng * ALPHA_NV; rw += 64) {
+            const float4 *q = reinterpret_cast<const float4 *>(red + rw * ALPHA_STR);
+            float acc = 0.f;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const float4 v = q[c];
+                acc += v.x;
+                acc += v.y;
+                acc += v.z;
+                acc += v.w;
+            }
+            const uint32_t k = rw / ALPHA_NV, v = rw - k * ALPHA_NV;
+            const int64_t sl = slot[i0 + k];
+            reinterpret_cast<float *>(part)[12 * sl + v] = acc;
         }
+        __syncthreads();  // the rows are read before the next group writes them
     }
 }
 
@@ -517,6 +544,7 @@ __global__ __launch_bounds__(64) void k_alpha_bwd(const float4 *__restrict__ rec
                                                   const uint2 *__restrict__ ranges, ImgTable tab,
                                                   const float *__restrict__ G,
                                                   float4 *__restrict__ part) {
+    __shared__ __align__(16) float red[ALPHA_RED];
     constexpr int PX = 4, ROWS = TILE / PX;
     const uint32_t tile = blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
@@ -538,7 +566,7 @@ __global__ __launch_bounds__(64) void k_alpha_bwd(const float4 *__restrict__ rec
         }
     }
     alpha_forward<PX>(rec, rec_o, r, px, py, D, T);
-    alpha_adjoint(rec, rec_o, slot, r, px, py, D, g, part);
+    alpha_adjoint(rec, rec_o, slot, r, px, py, D, g, part, red);
 }
 
 // Fit step of one tile with alpha blending: forward, residual, dL/dC = 2 (C - T) / (3 H W) in
@@ -552,6 +580,7 @@ __global__ __launch_bounds__(64) void k_alpha_fit(const float4 *__restrict__ rec
                                                   float *__restrict__ image_out,
                                                   float *__restrict__ loss_part,
                                                   int32_t *__restrict__ step_inc) {
+    __shared__ __align__(16) float red[ALPHA_RED];
     constexpr int PX = 4, ROWS = TILE / PX;
     const uint32_t tile = blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
@@ -590,7 +619,7 @@ __global__ __launch_bounds__(64) void k_alpha_fit(const float4 *__restrict__ rec
         loss_part[tile] = sq;
         if (step_inc && tile == 0) *step_inc += 1;
     }
-    alpha_adjoint(rec, rec_o, slot, r, px, py, D, g, part);
+    alpha_adjoint(rec, rec_o, slot, r, px, py, D, g, part, red);
 }
 
 // Per-image mean of the squared residuals from the per-tile sums (float64 accumulation): blocks
