@@ -399,29 +399,71 @@ __device__ inline void alpha_forward(const float4 *__restrict__ rec,
     }
 }
 
-template <int PX>
-__global__ __launch_bounds__(256 / PX) void k_alpha_fwd(const float4 *__restrict__ rec,
-                                                        const float *__restrict__ rec_o,
-                                                        const uint2 *__restrict__ ranges,
-                                                        ImgTable tab, float *__restrict__ image) {
-    constexpr int ROWS = TILE / PX;
+// Four parts per tile, one wave each (four pixels per lane: column lane & 15, rows
+// (lane >> 4) + 4 j): each part composites its share of the list alone, from T = 1, into
+// (colour, transmittance), and the parts compose in order:
+// C = C_0 + T_0 (C_1 + T_1 (C_2 + T_2 C_3)).
+constexpr int ALPHA_PARTS = 4;
+
+__device__ inline int alpha_pix(int lane, int j) { return ((lane >> 4) + 4 * j) * TILE + (lane & 15); }
+
+// Transmittance and colour in front of part q (Tb, Cb) and the total colour C of one pixel, from
+// the parts' (colour, transmittance) in xs[part * TILE_PX + pixel].
+__device__ inline void alpha_compose(const float4 *xs, int q, int pix, float &Tb, float (&Cb)[3],
+                                     float (&C)[3]) {
+    float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    Tb = 1.f;
+    Cb[0] = Cb[1] = Cb[2] = 0.f;
+#pragma unroll
+    for (int p = 0; p < ALPHA_PARTS; ++p) {
+        if (p == q) {
+            Tb = T;
+            Cb[0] = c0;
+            Cb[1] = c1;
+            Cb[2] = c2;
+        }
+        const float4 v = xs[p * TILE_PX + pix];
+        c0 = fmaf(T, v.x, c0);
+        c1 = fmaf(T, v.y, c1);
+        c2 = fmaf(T, v.z, c2);
+        T *= v.w;
+    }
+    C[0] = c0;
+    C[1] = c1;
+    C[2] = c2;
+}
+
+__global__ __launch_bounds__(256) void k_alpha_fwd(const float4 *__restrict__ rec,
+                                                   const float *__restrict__ rec_o,
+                                                   const uint2 *__restrict__ ranges, ImgTable tab,
+                                                   float *__restrict__ image) {
+    constexpr int PX = 4;
+    __shared__ float4 xs[ALPHA_PARTS * TILE_PX];
     const uint32_t tile = blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
-    const int col = threadIdx.x & 15, row = threadIdx.x >> 4;
-    const int x = ti.tx * TILE + col;
-    const float px = (float)x + 0.5f;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int col = lane & 15, row = lane >> 4;
+    const float px = (float)(ti.tx * TILE + col) + 0.5f;
     float py[PX], T[PX], acc[PX][3];
 #pragma unroll
-    for (int j = 0; j < PX; ++j) py[j] = (float)(ti.ty * TILE + row + j * ROWS) + 0.5f;
-    alpha_forward<PX>(rec, rec_o, ranges[tile], px, py, acc, T);
+    for (int j = 0; j < PX; ++j) py[j] = (float)(ti.ty * TILE + row + 4 * j) + 0.5f;
+    alpha_forward<PX>(rec, rec_o, list_part(ranges[tile], q), px, py, acc, T);
+#pragma unroll
+    for (int j = 0; j < PX; ++j)
+        xs[q * TILE_PX + alpha_pix(lane, j)] = make_float4(acc[j][0], acc[j][1], acc[j][2], T[j]);
+    __syncthreads();
+    if (q != 0) return;
+    const int x = ti.tx * TILE + col;
 #pragma unroll
     for (int j = 0; j < PX; ++j) {
-        const int y = ti.ty * TILE + row + j * ROWS;
+        const int y = ti.ty * TILE + row + 4 * j;
+        float Tb, Cb[3], C[3];
+        alpha_compose(xs, 0, alpha_pix(lane, j), Tb, Cb, C);
         if (x < ti.W && y < ti.H) {
             const unsigned long long idx = (ti.pix_base + (unsigned long long)y * ti.W + x) * 3ull;
-            image[idx] = acc[j][0];
-            image[idx + 1] = acc[j][1];
-            image[idx + 2] = acc[j][2];
+            image[idx] = C[0];
+            image[idx + 1] = C[1];
+            image[idx + 2] = C[2];
         }
     }
 }
@@ -450,27 +492,32 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
-// Adjoint walk of one tile (one wave, four pixels per lane): D holds the final colours on entry,
-// g the pixels' dL/dC.  Each Gaussian's nine sums are reduced over the wave in groups of
-// ALPHA_GRP Gaussians: the lanes store their partial sums as rows of LDS (`red`, ALPHA_GRP * 9
-// rows of ALPHA_STR floats), then each lane adds up one row in lane order and stores it.
+// Adjoint walk of one part of a tile's list (one wave, four pixels per lane): T0 holds the
+// transmittance and D the colour behind the part's first Gaussian on entry, g the pixels' dL/dC.
+// Each Gaussian's nine sums are reduced over the wave in groups of ALPHA_GRP Gaussians: the
+// lanes store their partial sums as rows of LDS (`red`, this wave's ALPHA_GRP * 9 rows of
+// ALPHA_STR floats), then each lane adds up one row in lane order and stores it.  Every wave of
+// the workgroup runs maxlen / ALPHA_GRP rounds (maxlen: the longest part), so the barriers are
+// reached by all.
 constexpr int ALPHA_GRP = 4;
 constexpr int ALPHA_NV = 9;
 constexpr int ALPHA_STR = 68;  // row stride: 16-byte aligned rows; lanes l, l+16, .. share banks
 constexpr int ALPHA_RED = ALPHA_GRP * ALPHA_NV * ALPHA_STR;
 __device__ inline void alpha_adjoint(const float4 *__restrict__ rec,
                                      const float *__restrict__ rec_o,
-                                     const uint32_t *__restrict__ slot, uint2 r, float px,
-                                     const float (&py)[4], float (&D)[4][3],
-                                     const float (&g)[4][3], float4 *__restrict__ part,
-                                     float *red) {
+                                     const uint32_t *__restrict__ slot, uint2 r, uint32_t maxlen,
+                                     float px, const float (&py)[4], const float (&T0)[4],
+                                     float (&D)[4][3], const float (&g)[4][3],
+                                     float4 *__restrict__ part, float *red) {
     constexpr int PX = 4;
     const int lane = threadIdx.x & 63;
     float T[PX];
 #pragma unroll
-    for (int j = 0; j < PX; ++j) T[j] = 1.f;
-    for (uint32_t i0 = r.x; i0 < r.y; i0 += ALPHA_GRP) {
-        const uint32_t ng = r.y - i0 < (uint32_t)ALPHA_GRP ? r.y - i0 : (uint32_t)ALPHA_GRP;
+    for (int j = 0; j < PX; ++j) T[j] = T0[j];
+    const uint32_t len = r.y - r.x;
+    for (uint32_t o = 0; o < maxlen; o += ALPHA_GRP) {
+        const uint32_t i0 = r.x + o;
+        const uint32_t ng = o >= len ? 0u : (len - o < (uint32_t)ALPHA_GRP ? len - o : (uint32_t)ALPHA_GRP);
         for (uint32_t k = 0; k < ng; ++k) {
             const uint32_t i = i0 + k;
             const float4 A = rec[2 * (int64_t)i], B = rec[2 * (int64_t)i + 1];
@@ -537,25 +584,30 @@ __device__ inline void alpha_adjoint(const float4 *__restrict__ rec,
     }
 }
 
-// One wave per tile, 4 pixels per lane.
-__global__ __launch_bounds__(64) void k_alpha_bwd(const float4 *__restrict__ rec,
-                                                  const float *__restrict__ rec_o,
-                                                  const uint32_t *__restrict__ slot,
-                                                  const uint2 *__restrict__ ranges, ImgTable tab,
-                                                  const float *__restrict__ G,
-                                                  float4 *__restrict__ part) {
-    __shared__ __align__(16) float red[ALPHA_RED];
-    constexpr int PX = 4, ROWS = TILE / PX;
+// Four waves per tile (parts of the list), 4 pixels per lane.  The parts' (colour,
+// transmittance) meet in LDS (`red` holds them first, then each wave's reduction rows).
+__global__ __launch_bounds__(256) void k_alpha_bwd(const float4 *__restrict__ rec,
+                                                   const float *__restrict__ rec_o,
+                                                   const uint32_t *__restrict__ slot,
+                                                   const uint2 *__restrict__ ranges, ImgTable tab,
+                                                   const float *__restrict__ G,
+                                                   float4 *__restrict__ part) {
+    constexpr int PX = 4;
+    __shared__ __align__(16) float red[ALPHA_PARTS * ALPHA_RED];
+    static_assert(ALPHA_PARTS * ALPHA_RED >= 4 * ALPHA_PARTS * TILE_PX, "the part sums fit");
+    float4 *xs = reinterpret_cast<float4 *>(red);
     const uint32_t tile = blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     const uint2 r = ranges[tile];
-    const int col = threadIdx.x & 15, row = threadIdx.x >> 4;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int col = lane & 15, row = lane >> 4;
     const int x = ti.tx * TILE + col;
     const float px = (float)x + 0.5f;
+    const uint2 rq = list_part(r, q);
     float py[PX], T[PX], D[PX][3], g[PX][3];
 #pragma unroll
     for (int j = 0; j < PX; ++j) {
-        const int y = ti.ty * TILE + row + j * ROWS;
+        const int y = ti.ty * TILE + row + 4 * j;
         py[j] = (float)y + 0.5f;
         g[j][0] = g[j][1] = g[j][2] = 0.f;
         if (x < ti.W && y < ti.H) {
@@ -565,61 +617,92 @@ __global__ __launch_bounds__(64) void k_alpha_bwd(const float4 *__restrict__ rec
             g[j][2] = G[idx + 2];
         }
     }
-    alpha_forward<PX>(rec, rec_o, r, px, py, D, T);
-    alpha_adjoint(rec, rec_o, slot, r, px, py, D, g, part, red);
+    alpha_forward<PX>(rec, rec_o, rq, px, py, D, T);
+#pragma unroll
+    for (int j = 0; j < PX; ++j)
+        xs[q * TILE_PX + alpha_pix(lane, j)] = make_float4(D[j][0], D[j][1], D[j][2], T[j]);
+    __syncthreads();
+    float Tb[PX];
+#pragma unroll
+    for (int j = 0; j < PX; ++j) {
+        float Cb[3], C[3];
+        alpha_compose(xs, q, alpha_pix(lane, j), Tb[j], Cb, C);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) D[j][c] = C[c] - Cb[c];  // colour behind the part's start
+    }
+    __syncthreads();  // xs is read before the reduction rows overwrite it
+    alpha_adjoint(rec, rec_o, slot, rq, (r.y - r.x + ALPHA_PARTS - 1) / ALPHA_PARTS, px, py, Tb,
+                  D, g, part, red + q * ALPHA_RED);
 }
 
-// Fit step of one tile with alpha blending: forward, residual, dL/dC = 2 (C - T) / (3 H W) in
-// registers, per-tile sum of squared residuals, then the adjoint walk.
-__global__ __launch_bounds__(64) void k_alpha_fit(const float4 *__restrict__ rec,
-                                                  const float *__restrict__ rec_o,
-                                                  const uint32_t *__restrict__ slot,
-                                                  const uint2 *__restrict__ ranges, ImgTable tab,
-                                                  const float *__restrict__ target,
-                                                  float4 *__restrict__ part,
-                                                  float *__restrict__ image_out,
-                                                  float *__restrict__ loss_part,
-                                                  int32_t *__restrict__ step_inc) {
-    __shared__ __align__(16) float red[ALPHA_RED];
-    constexpr int PX = 4, ROWS = TILE / PX;
+// Fit step of one tile with alpha blending: the parts' forward, their composition, residual,
+// dL/dC = 2 (C - T) / (3 H W) in registers, per-tile sum of squared residuals (first wave), then
+// each part's adjoint walk.
+__global__ __launch_bounds__(256) void k_alpha_fit(const float4 *__restrict__ rec,
+                                                   const float *__restrict__ rec_o,
+                                                   const uint32_t *__restrict__ slot,
+                                                   const uint2 *__restrict__ ranges, ImgTable tab,
+                                                   const float *__restrict__ target,
+                                                   float4 *__restrict__ part,
+                                                   float *__restrict__ image_out,
+                                                   float *__restrict__ loss_part,
+                                                   int32_t *__restrict__ step_inc) {
+    constexpr int PX = 4;
+    __shared__ __align__(16) float red[ALPHA_PARTS * ALPHA_RED];
+    static_assert(ALPHA_PARTS * ALPHA_RED >= 4 * ALPHA_PARTS * TILE_PX, "the part sums fit");
+    float4 *xs = reinterpret_cast<float4 *>(red);
     const uint32_t tile = blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     const uint2 r = ranges[tile];
-    const int col = threadIdx.x & 15, row = threadIdx.x >> 4;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int col = lane & 15, row = lane >> 4;
     const int x = ti.tx * TILE + col;
     const float px = (float)x + 0.5f;
+    const uint2 rq = list_part(r, q);
     float py[PX], T[PX], D[PX][3], g[PX][3];
 #pragma unroll
-    for (int j = 0; j < PX; ++j) py[j] = (float)(ti.ty * TILE + row + j * ROWS) + 0.5f;
-    alpha_forward<PX>(rec, rec_o, r, px, py, D, T);
+    for (int j = 0; j < PX; ++j) py[j] = (float)(ti.ty * TILE + row + 4 * j) + 0.5f;
+    alpha_forward<PX>(rec, rec_o, rq, px, py, D, T);
+#pragma unroll
+    for (int j = 0; j < PX; ++j)
+        xs[q * TILE_PX + alpha_pix(lane, j)] = make_float4(D[j][0], D[j][1], D[j][2], T[j]);
+    __syncthreads();
     const float scale = 2.0f / (3.0f * (float)ti.H * (float)ti.W);
-    float sq = 0.f;
+    float sq = 0.f, Tb[PX];
 #pragma unroll
     for (int j = 0; j < PX; ++j) {
-        const int y = ti.ty * TILE + row + j * ROWS;
+        float Cb[3], C[3];
+        alpha_compose(xs, q, alpha_pix(lane, j), Tb[j], Cb, C);
+        const int y = ti.ty * TILE + row + 4 * j;
         g[j][0] = g[j][1] = g[j][2] = 0.f;
         if (x < ti.W && y < ti.H) {
             const unsigned long long idx = (ti.pix_base + (unsigned long long)y * ti.W + x) * 3ull;
-            const float r0 = D[j][0] - target[idx];
-            const float r1 = D[j][1] - target[idx + 1];
-            const float r2 = D[j][2] - target[idx + 2];
+            const float r0 = C[0] - target[idx];
+            const float r1 = C[1] - target[idx + 1];
+            const float r2 = C[2] - target[idx + 2];
             sq = fmaf(r0, r0, fmaf(r1, r1, fmaf(r2, r2, sq)));
             g[j][0] = scale * r0;
             g[j][1] = scale * r1;
             g[j][2] = scale * r2;
-            if (image_out) {
-                image_out[idx] = D[j][0];
-                image_out[idx + 1] = D[j][1];
-                image_out[idx + 2] = D[j][2];
+            if (image_out && q == 0) {
+                image_out[idx] = C[0];
+                image_out[idx + 1] = C[1];
+                image_out[idx + 2] = C[2];
             }
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) D[j][c] = C[c] - Cb[c];  // colour behind the part's start
     }
-    sq = wave_sum(sq);
-    if (threadIdx.x == 0) {
-        loss_part[tile] = sq;
-        if (step_inc && tile == 0) *step_inc += 1;
+    if (q == 0) {
+        sq = wave_sum(sq);
+        if (lane == 0) {
+            loss_part[tile] = sq;
+            if (step_inc && tile == 0) *step_inc += 1;
+        }
     }
-    alpha_adjoint(rec, rec_o, slot, r, px, py, D, g, part, red);
+    __syncthreads();  // xs is read before the reduction rows overwrite it
+    alpha_adjoint(rec, rec_o, slot, rq, (r.y - r.x + ALPHA_PARTS - 1) / ALPHA_PARTS, px, py, Tb,
+                  D, g, part, red + q * ALPHA_RED);
 }
 
 // Per-image mean of the squared residuals from the per-tile sums (float64 accumulation): blocks
@@ -1213,7 +1296,7 @@ hipError_t launch_raster_fit(const RasterArgs &a, const float *target, float *pa
 
 hipError_t launch_alpha_fwd(const RasterArgs &a, const float *rec_o, float *image, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_alpha_fwd<2>, dim3((unsigned)a.n_tiles), dim3(128), 0, s,
+    hipLaunchKernelGGL(k_alpha_fwd, dim3((unsigned)a.n_tiles), dim3(256), 0, s,
                        reinterpret_cast<const float4 *>(a.rec), rec_o, a.ranges, a.tab, image);
     return hipGetLastError();
 }
@@ -1221,7 +1304,7 @@ hipError_t launch_alpha_fwd(const RasterArgs &a, const float *rec_o, float *imag
 hipError_t launch_alpha_bwd(const RasterArgs &a, const float *rec_o, const float *dl,
                             float *part12, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_alpha_bwd, dim3((unsigned)a.n_tiles), dim3(64), 0, s,
+    hipLaunchKernelGGL(k_alpha_bwd, dim3((unsigned)a.n_tiles), dim3(256), 0, s,
                        reinterpret_cast<const float4 *>(a.rec), rec_o, a.slot, a.ranges, a.tab,
                        dl, reinterpret_cast<float4 *>(part12));
     return hipGetLastError();
@@ -1290,7 +1373,7 @@ hipError_t launch_alpha_fit(const RasterArgs &a, const float *rec_o, const float
                             float *part12, float *image_out, float *loss_part, int32_t *step_inc,
                             hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_alpha_fit, dim3((unsigned)a.n_tiles), dim3(64), 0, s,
+    hipLaunchKernelGGL(k_alpha_fit, dim3((unsigned)a.n_tiles), dim3(256), 0, s,
                        reinterpret_cast<const float4 *>(a.rec), rec_o, a.slot, a.ranges, a.tab,
                        target, reinterpret_cast<float4 *>(part12), image_out, loss_part,
                        step_inc);
