@@ -1270,8 +1270,8 @@ constexpr int RT_PER = 8;   // rows per thread and round
 // keys written.  On overflow of the bounds the kernels after it see zero chunks and the
 // overflow flag is set.
 __global__ __launch_bounds__(RT_T) void k_row_table(const uint32_t *__restrict__ rscan,
-                                                    uint32_t blocks, ImgTable tab, int64_t rows,
-                                                    int64_t nch_max,
+                                                    uint32_t blocks, int64_t pcap, ImgTable tab,
+                                                    int64_t rows, int64_t nch_max,
                                                     int64_t scan_max, uint4 *__restrict__ rinfo,
                                                     uint32_t *__restrict__ chunk_row,
                                                     uint32_t *__restrict__ scan,
@@ -1286,9 +1286,12 @@ __global__ __launch_bounds__(RT_T) void k_row_table(const uint32_t *__restrict__
         for (int j = 0; j < RT_PER; ++j) {
             int64_t q = (int64_t)threadIdx.x * RT_PER + j;
             q = r0 + (q < nr ? q : nr - 1);
-            // the row's pairs: from its first block's scanned position to the next row's
-            rr[j] = make_uint2(rscan[row_seg_of(tab, (uint32_t)q, blocks)],
-                               rscan[row_seg_of(tab, (uint32_t)q + 1, blocks)]);
+            // the row's pairs: from its first block's scanned position to the next row's, cut at
+            // the pair capacity (pairs beyond it were not written; the overflow flag is set)
+            const unsigned long long a = rscan[row_seg_of(tab, (uint32_t)q, blocks)];
+            const unsigned long long b = rscan[row_seg_of(tab, (uint32_t)q + 1, blocks)];
+            rr[j] = make_uint2((uint32_t)(a < (unsigned long long)pcap ? a : pcap),
+                               (uint32_t)(b < (unsigned long long)pcap ? b : pcap));
             rt[j] = row_tiles(tab, (uint32_t)q);
         }
         uint32_t nch[RT_PER];
@@ -1975,7 +1978,7 @@ hipError_t launch_rows_b(const RowBuffers &r, const ImgTable &tab, bool want_ids
     uint32_t *ids = want_ids ? b.vals[1] : nullptr;
     hipLaunchKernelGGL(k_rows_scatter, dim3((unsigned)nb), dim3(BLK), 0, s, b.count, proj,
                        b.blocksum, r.rhist, r.bwin, tab, b.n, pcap, b.off, rv, b.state);
-    hipLaunchKernelGGL(k_row_table, dim3(1), dim3(RT_T), 0, s, r.rhist, (uint32_t)nb, tab,
+    hipLaunchKernelGGL(k_row_table, dim3(1), dim3(RT_T), 0, s, r.rhist, (uint32_t)nb, pcap, tab,
                        (int64_t)tab.rows, r.nch_max, r.scan_max, r.rinfo, r.chunk_row, r.scan,
                        b.state);
     hipLaunchKernelGGL(k_row_hist, dim3((unsigned)r.nch_max), dim3(ROW_CHUNK), 0, s, rv, r.rinfo,
