@@ -36,6 +36,7 @@ struct gi_ctx {
     float *part_a = nullptr;           // [cap_a][12] alpha-blending partial sums
     int64_t cap_a = 0;
     int want_ids = 0;  // the one-pass binning writes sorted Gaussian ids only for gi_binning
+    int render_only = 0;  // set for the duration of a render's binning: no adjoint reads slots
     int64_t cap_n = 0, cap_t = 0, cap_k = 0;
     int64_t cap_p = 0;  // (row, Gaussian) pairs the row binning is sized for
     int64_t last_keys = 0;
@@ -460,7 +461,7 @@ BinBuffers bin_buffers(gi_ctx *ctx, const float *params, int64_t n, int64_t n_ti
     b.vals[1] = ctx->vals[1];
     b.ids_out = nullptr;
     b.rec = ctx->rec;
-    b.slot = ctx->slot;
+    b.slot = ctx->render_only ? nullptr : ctx->slot;  // a null slot array is not written
     b.ranges = ctx->ranges;
     b.n_tiles = n_tiles;
     b.cap = ctx->cap_k;
@@ -680,11 +681,23 @@ int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab
 }
 
 
+// Marks a render for the duration of its binning: the scatters then skip the key slots, which
+// only the adjoint reads.
+struct RenderScope {
+    gi_ctx *c;
+    explicit RenderScope(gi_ctx *ctx) : c(ctx) { ctx->render_only = 1; }
+    ~RenderScope() { c->render_only = 0; }
+};
+
 int do_render(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab, int64_t n_tiles,
               float *image, hipStream_t s) {
     int64_t bound;
     int which;
-    int rc = run_binning(ctx, params, n, tab, n_tiles, s, &bound, &which);
+    int rc;
+    {
+        RenderScope rs(ctx);
+        rc = run_binning(ctx, params, n, tab, n_tiles, s, &bound, &which);
+    }
     if (rc != GI_OK) return rc;
     RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FWD);
@@ -752,7 +765,11 @@ int do_render_opacity(gi_ctx *ctx, const float *params, const float *opacity, in
     OpacityScope scope(ctx, opacity, blend);
     int64_t bound;
     int which;
-    int rc = run_binning(ctx, params, n, tab, n_tiles, s, &bound, &which);
+    int rc;
+    {
+        RenderScope rs(ctx);
+        rc = run_binning(ctx, params, n, tab, n_tiles, s, &bound, &which);
+    }
     if (rc != GI_OK) return rc;
     RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FWD);

@@ -716,7 +716,7 @@ __global__ __launch_bounds__(BLK) void k_ranges_gather(const uint32_t *__restric
     const uint32_t ty = local / tw, tx = local - ty * tw;
     rec[2 * i] = a;
     rec[2 * i + 1] = b;
-    slot[i] = f.x + (ty - (f.w >> 16)) * w + (tx - (f.w & 0xffffu));
+    if (slot) slot[i] = f.x + (ty - (f.w >> 16)) * w + (tx - (f.w & 0xffffu));
     if (rec_o) rec_o[i] = opac[g];
     if (ids) ids[i] = g;
 }
@@ -1083,7 +1083,7 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
             // Gaussian order; its partial sums then go to the last slot (the update is skipped
             // on overflow), never past the buffer
             const uint32_t sl = soff[g] + li;
-            slot[pos] = sl < cap ? sl : (uint32_t)(cap - 1);
+            if (slot) slot[pos] = sl < cap ? sl : (uint32_t)(cap - 1);
             if (ids) ids[pos] = chunk * FB + (uint32_t)g;
             if (rec_o) rec_o[pos] = opac[(int64_t)chunk * FB + g];
         }
@@ -1585,7 +1585,7 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
             if (valid && !ok) overflow = true;
             if (ok) {
                 const uint32_t sl = sbase[e] + x;  // kept below the capacity, as in k_fused_scatter
-                slot[pos] = sl < cap ? sl : (uint32_t)(cap - 1);
+                if (slot) slot[pos] = sl < cap ? sl : (uint32_t)(cap - 1);
                 if (ids || rec_o) {
                     const uint32_t g = rvals[rc.first + e];
                     if (ids) ids[pos] = g;
@@ -1654,7 +1654,7 @@ __global__ __launch_bounds__(64 * WV) void k_row_scatter(
         if (valid && !ok) overflow = true;
         if (ok) {
             const uint32_t sl = sbase[e] + x;  // kept below the capacity, as in k_fused_scatter
-            slot[pos] = sl < cap ? sl : (uint32_t)(cap - 1);
+            if (slot) slot[pos] = sl < cap ? sl : (uint32_t)(cap - 1);
             if (ids || rec_o) {
                 const uint32_t g = rvals[rc.first + e];
                 if (ids) ids[pos] = g;
