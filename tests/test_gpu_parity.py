@@ -465,6 +465,51 @@ def test_graph_launch_starts_from_the_parameters_as_they_are(gi):
     assert int(host(sb)[0]) == 6
 
 
+@pytest.mark.parametrize("binning", [1, 2, 3], ids=["radix", "one-pass", "rows"])
+def test_renders_between_steps_leave_fit_and_grad_unchanged(binning):
+    # a render's binning skips the key slots (only the adjoint reads them): steps, gradients and
+    # captured steps after renders on the same context bin again and give the same bits
+    import paper_2403_08551_amd as P
+    w = synth.plain_256()
+    h, wd = w.height, w.width
+    p0, T = w.params(), dev(w.target())
+    o = dev(np.random.default_rng(5).uniform(0.2, 1.0, p0.shape[0]))
+    dl = dev(np.random.default_rng(6).normal(size=(h, wd, 3)))
+    pa, pb = dev(p0), dev(p0)
+    ma, va, mb, vb = (torch.zeros_like(pa) for _ in range(4))
+    sa = torch.ones(1, dtype=torch.int32, device="cuda")
+    sb = torch.ones(1, dtype=torch.int32, device="cuda")
+    ca, cb = P.Context(0), P.Context(0)
+    graph = None
+    try:
+        for c in (ca, cb):
+            c.set_option(P._lib.GI_OPT_BINNING, binning)
+        for _ in range(3):
+            ca.fit_step(pa, ma, va, T, sa)
+        ga = host(ca.grad(pa, h, wd, dl))
+        for _ in range(3):
+            cb.render(pb, h, wd)
+            cb.fit_step(pb, mb, vb, T, sb)
+            cb.render_opacity(pb, o, h, wd, blend="alpha")
+        cb.render(pb, h, wd)
+        np.testing.assert_array_equal(host(pb), host(pa))
+        np.testing.assert_array_equal(host(cb.grad(pb, h, wd, dl)), ga)
+        for _ in range(2):
+            ca.fit_step(pa, ma, va, T, sa)
+        graph = cb.fit_graph(pb, mb, vb, T, sb)
+        for _ in range(2):  # a render between the launches of the captured step
+            graph.launch(1)
+            cb.render(pb, h, wd)
+            torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(pb), host(pa))
+        assert int(host(sb)[0]) == int(host(sa)[0]) == 6
+    finally:
+        if graph is not None:
+            graph.close()
+        ca.close()
+        cb.close()
+
+
 # ------------------------------------------------------------------ flags and edge cases
 
 def test_nonfinite_flag(gi):
