@@ -437,8 +437,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (one image or one "
-              "batch per GPU; sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (work shards as "
+              "one image, or one batch of images, per GPU)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
 
