@@ -55,7 +55,7 @@ enum {
     GI_ERR_CAPACITY = -2,     /* keys exceed the reserved capacity in a non-growing call */
     GI_ERR_HIP = -3,          /* a HIP runtime call failed (gi_last_error has the text) */
     GI_ERR_NONFINITE = -4,    /* a parameter was not finite (reported by gi_query) */
-    GI_ERR_UNSUPPORTED = -5,  /* valid request this build does not handle */
+    GI_ERR_UNSUPPORTED = -5,  /* valid request the library does not handle */
     GI_ERR_NO_DEVICE = -6     /* no usable gfx950 device */
 };
 
@@ -372,8 +372,8 @@ int gi_fit_graph_destroy(gi_graph *graph);
 
 /* ---- the binning stages, for inspection and testing ---------------------------------------- */
 
-/* Run projection, key duplication, the stable radix sort and tile-range extraction (north star
- * stages a-b; Sec. 3.2 drops the depth key, so the sort key is the tile id alone), then copy out:
+/* Run projection, key duplication, the stable radix sort and tile-range extraction (the
+ * binning stages; Sec. 3.2 drops the depth key, so the sort key is the tile id alone), then copy out:
  * rects_dev [N][4] int32 (tx0, ty0, tx1, ty1; (0, 0, -1, -1) when the Gaussian covers nothing),
  * counts_dev [N] uint32, offsets_dev [N] uint32 (exclusive prefix sum of counts),
  * ranges_dev [T][2] uint32 ([start, end) into the sorted list, T = ceil(H/16) ceil(W/16)),
