@@ -106,3 +106,50 @@ def test_recipe_fit_step_lowers_the_loss():
         r = r.astype(np.float32)
         losses.append(loss)
     assert losses[-1] < 0.5 * losses[0], losses[::6]
+
+
+def test_adan_with_equal_first_two_rates_is_adam_on_the_nesterov_gradient():
+    # Adan's reformulation: with b1 = b2 = b the numerator m_k + b v_k is an exponential average
+    # of g_k + b (g_k - g_{k-1}), and n_k one of its square; so Adan equals Adam (the pinned
+    # oracle) fed that gradient, with Adam's second rate b3, under a gradient that changes
+    rng = np.random.default_rng(11)
+    b, b3 = 0.9, 0.99
+    hp = dict(recipe.DEFAULT_ADAN, beta1=b, beta2=b, beta3=b3, halve_every=0, lr=0.02)
+    adam = dict(ref.DEFAULT_ADAM, lr_mu=0.02, lr_l=0.02, lr_c=0.02, beta1=b, beta2=b3,
+                eps=hp["eps"], l_min=0.0)
+    th = rng.normal(size=(5, 8))
+    a = th.copy()
+    st = (np.zeros((5, 8)),) * 4
+    am, av = np.zeros((5, 8)), np.zeros((5, 8))
+    g_prev = None
+    for k in range(1, 9):
+        g = rng.normal(size=(5, 8)) * (1.0 + k)
+        nesterov = g if g_prev is None else g + b * (g - g_prev)
+        th, *st = recipe.adan_step(th, *st, g, k, hp)
+        a, am, av = ref.adam_step(a, am, av, nesterov, k, adam)
+        np.testing.assert_allclose(th, a, rtol=1e-12, atol=1e-14)
+        g_prev = g
+
+
+def test_adan_moments_are_explicit_weighted_sums():
+    # with the default rates (all different) the three moments after k steps are the unrolled
+    # sums sum_j (1 - b) b^(k - j) x_j of their inputs (x = g, g - g_prev (0 at j = 1), and
+    # (g + b2 (g - g_prev))^2), and the update divides the bias-corrected ones
+    rng = np.random.default_rng(12)
+    hp = dict(recipe.DEFAULT_ADAN, halve_every=0, lr=0.01)
+    b1, b2, b3, eps = hp["beta1"], hp["beta2"], hp["beta3"], hp["eps"]
+    gs = [rng.normal(size=6) for _ in range(7)]
+    th = np.zeros(6)
+    st = (np.zeros(6),) * 4
+    for k in range(1, 8):
+        before = th.copy()
+        th, *st = recipe.adan_step(th, *st, gs[k - 1], k, hp)
+        d = [np.zeros(6)] + [gs[j] - gs[j - 1] for j in range(1, k)]
+        m = sum((1 - b1) * b1 ** (k - 1 - j) * gs[j] for j in range(k))
+        v = sum((1 - b2) * b2 ** (k - 1 - j) * d[j] for j in range(k))
+        n = sum((1 - b3) * b3 ** (k - 1 - j) * (gs[j] + b2 * d[j]) ** 2 for j in range(k))
+        np.testing.assert_allclose(st[0], m, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(st[1], v, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(st[2], n, rtol=1e-12, atol=1e-15)
+        step = (m / (1 - b1 ** k) + b2 * v / (1 - b2 ** k)) / (np.sqrt(n / (1 - b3 ** k)) + eps)
+        np.testing.assert_allclose(before - th, 0.01 * step, rtol=1e-10, atol=1e-15)
