@@ -268,30 +268,41 @@ int gi_recipe_params(gi_ctx *ctx, const float *raw_dev, int64_t n, int32_t heigh
 /* The quantiser being fine-tuned, on the device (caller owned, float32):
  *   quant_dev   [6 + 3 M B]: gamma[3], beta[3] of the b-bit covariance codes (LSQ+), then the
  *               residual-VQ codebooks [M][B][3]
- *   quant_m_dev, quant_v_dev: Adam moments of quant_dev (same size, caller-initialised, zeros)
- * 1 <= bits <= 8, 1 <= stages <= 8, 1 <= codebook_size <= 64, stages * codebook_size <= 64.
- * lambda weights the commitment loss; lr_q is the quantiser's Adam rate. */
+ *   quant_m_dev, quant_v_dev [6]: Adam moments of gamma and beta (caller-initialised, zeros)
+ *   ema_dev     [M][B][4]: each codebook entry's running count and running residual sum (3)
+ *               of the moving-average update (set by gi_qat_init; not read by gi_qat_encode)
+ * 1 <= bits <= 8, 1 <= stages <= 8, 1 <= codebook_size <= 64, stages * codebook_size <= 64;
+ * 0 <= decay <= 1.  lambda weights the commitment loss in the reported loss; lr_q is the Adam
+ * rate of gamma and beta; decay is the codebooks' moving-average decay (Sec. 3.4). */
 typedef struct gi_qat {
     float *quant_dev;
     float *quant_m_dev, *quant_v_dev;
     int32_t bits, stages, codebook_size;
     float lambda, lr_q;
+    float *ema_dev;
+    float decay;
 } gi_qat;
 
-/* Initialise quant_dev from float records params_dev [N][8] (N >= 1): beta_i = min of slot i,
- * gamma_i = the least float32 >= (max - min) / (2^b - 1); codebooks by kmeans_iters Lloyd
- * iterations per stage on the residual colours (float64), seeded with the points
- * floor(j N / B), an emptied centroid staying put.  Allocates scratch on first use. */
+/* Initialise quant_dev and ema_dev from float records params_dev [N][8] (N >= 1): beta_i = min
+ * of slot i, gamma_i = the least float32 >= (max - min) / (2^b - 1); codebooks by kmeans_iters
+ * Lloyd iterations per stage on the residual colours (float64), seeded with the points
+ * floor(j N / B), an emptied centroid staying put; each entry's running count = the number of
+ * residuals nearest its final centroid, running sum = count x the float32 entry.  Allocates
+ * scratch on first use. */
 int gi_qat_init(gi_ctx *ctx, const float *params_dev, int64_t n, const gi_qat *q,
                 int32_t kmeans_iters, void *stream);
-/* One fine-tuning step (as gi_fit_step, on float records): render the fake-quantised records
- * (binary16 positions; covariance slot i as code * gamma_i + beta_i, code =
- * round-half-even(clamp((l - beta_i) / gamma_i, 0, 2^b - 1)); colours by greedy residual VQ,
- * nearest entry by squared distance, lowest index on ties; all in float64, rounded once), loss
- * = mean (C - target)^2 + lambda L_c with L_c = 1/(N B) sum over stages and Gaussians of
- * |C^m[i^m] - r^{m-1}|^2 (r the residual before stage m); straight-through gradients to the
- * records (covariance slots only inside the code range), LSQ+ gradients to gamma and beta,
- * commitment-loss gradients to the codebooks; Adam on records (hp) and quantiser (lr_q). */
+/* One fine-tuning step (as gi_fit_step, on float records; Sec. 3.3 and Sec. 3.4): render the
+ * fake-quantised records (binary16 positions; covariance slot i as code * gamma_i + beta_i,
+ * code = round-half-even(clamp((l - beta_i) / gamma_i, 0, 2^b - 1)); colours by greedy residual
+ * VQ, nearest entry by squared distance, lowest index on ties; all in float64, rounded once);
+ * reported loss = mean (C - target)^2 + lambda L_c, L_c = 1/(N B) sum over stages and Gaussians
+ * of |C^m[i^m] - r^{m-1}|^2 (r the residual before stage m); straight-through gradients to the
+ * records (covariance slots only inside the code range) and LSQ+ gradients to gamma and beta,
+ * each taking an Adam step (records with hp, gamma and beta with lr_q and hp's moments); the
+ * codebooks by the moving average: per stage m and entry j, with n_j the Gaussians that chose
+ * it and s_j the sum of their residuals r^{m-1}, count <- decay count + (1 - decay) n_j,
+ * sum <- decay sum + (1 - decay) s_j, entry = sum / count (kept while the count is 0); float64
+ * arithmetic, float32 state.  A step whose keys overflow updates nothing (flag raised). */
 int gi_fit_step_qat(gi_ctx *ctx, float *params_dev, float *m_dev, float *v_dev,
                     const float *target_dev, int64_t n, int32_t height, int32_t width,
                     const gi_adam *hp, const gi_qat *q, int32_t *step_dev, float *image_out_dev,

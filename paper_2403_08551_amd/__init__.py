@@ -118,22 +118,28 @@ class AdanConfig:
 
 @dataclass
 class Quantiser:
-    """The quantiser of the fine-tuning (Sec. 3.3) on the device: ``quant`` holds gamma[3],
-    beta[3] and the codebooks [stages, size, 3]; ``quant_m``, ``quant_v`` its Adam moments."""
+    """The quantiser of the fine-tuning (Sec. 3.3, Sec. 3.4) on the device: ``quant`` holds
+    gamma[3], beta[3] and the codebooks [stages, size, 3]; ``quant_m``, ``quant_v`` [6] the Adam
+    moments of gamma and beta; ``ema`` [stages, size, 4] each codebook entry's running count
+    and residual sum of the moving-average update with ``decay``."""
     quant: torch.Tensor
     quant_m: torch.Tensor
     quant_v: torch.Tensor
+    ema: torch.Tensor
     bits: int = 6
     stages: int = 2
     size: int = 8
     lam: float = 1.0
     lr_q: float = 1e-3
+    decay: float = 0.99
 
     @staticmethod
-    def zeros(device, bits=6, stages=2, size=8, lam=1.0, lr_q=1e-3) -> "Quantiser":
+    def zeros(device, bits=6, stages=2, size=8, lam=1.0, lr_q=1e-3, decay=0.99) -> "Quantiser":
         nq = 6 + 3 * stages * size
-        z = [torch.zeros(nq, device=device, dtype=torch.float32) for _ in range(3)]
-        return Quantiser(*z, bits=bits, stages=stages, size=size, lam=lam, lr_q=lr_q)
+        f = dict(device=device, dtype=torch.float32)
+        return Quantiser(torch.zeros(nq, **f), torch.zeros(6, **f), torch.zeros(6, **f),
+                         torch.zeros(stages, size, 4, **f), bits=bits, stages=stages, size=size,
+                         lam=lam, lr_q=lr_q, decay=decay)
 
     @property
     def gamma(self):
@@ -149,12 +155,14 @@ class Quantiser:
 
     def c(self, device) -> _lib.gi_qat:
         nq = 6 + 3 * self.stages * self.size
-        for t, name in ((self.quant, "quant"), (self.quant_m, "quant_m"),
-                        (self.quant_v, "quant_v")):
-            _check(t, name, device, (nq,))
+        _check(self.quant, "quant", device, (nq,))
+        _check(self.quant_m, "quant_m", device, (6,))
+        _check(self.quant_v, "quant_v", device, (6,))
+        _check(self.ema, "ema", device, (self.stages, self.size, 4))
         return _lib.gi_qat(self.quant.data_ptr(), self.quant_m.data_ptr(),
                            self.quant_v.data_ptr(), int(self.bits), int(self.stages),
-                           int(self.size), float(self.lam), float(self.lr_q))
+                           int(self.size), float(self.lam), float(self.lr_q),
+                           self.ema.data_ptr(), float(self.decay))
 
     def codec(self, mu, codes, index) -> "Codec":
         """The codec record set of an encoding (gamma and beta copied to the host)."""

@@ -78,7 +78,8 @@ class gi_qat(ctypes.Structure):
     _fields_ = [("quant_dev", ctypes.c_void_p), ("quant_m_dev", ctypes.c_void_p),
                 ("quant_v_dev", ctypes.c_void_p), ("bits", ctypes.c_int32),
                 ("stages", ctypes.c_int32), ("codebook_size", ctypes.c_int32),
-                ("lambda_", ctypes.c_float), ("lr_q", ctypes.c_float)]
+                ("lambda_", ctypes.c_float), ("lr_q", ctypes.c_float),
+                ("ema_dev", ctypes.c_void_p), ("decay", ctypes.c_float)]
 
 
 class gi_codec(ctypes.Structure):

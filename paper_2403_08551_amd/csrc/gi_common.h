@@ -409,19 +409,20 @@ hipError_t launch_adan(const UpdateArgs &u, float *raw, float *state, int32_t *s
                        const AdanArgs &hp, const ImgTable &tab, const float *loss_part,
                        int64_t n_tiles, float *loss_out, hipStream_t s);
 // Quantisation-aware fine-tuning update: the Gaussians' Adam step (straight-through gradients
-// of the fake-quantised records), then the quantiser's Adam step (LSQ+ and commitment-loss
-// gradients); qpart holds qat_part_floats(n, stages, size) floats of block sums.
+// of the fake-quantised records), then the quantiser's step (Adam on gamma and beta from their
+// LSQ+ gradients, the moving average of the codebooks); qpart holds qat_part_floats(n, stages,
+// size) floats of block sums (its start 8-byte aligned).
 hipError_t launch_qat_update(const UpdateArgs &u, float *params, float *m, float *v,
                              int32_t *step, const AdamArgs &hp, const QatArgs &qa, float lambda,
-                             float lr_q, float *quant_m, float *quant_v, float *qpart,
-                             const float *loss_part, const ImgTable &tab, int64_t n_tiles,
-                             float *loss_out, hipStream_t s);
+                             float lr_q, float *quant_m, float *quant_v, float *ema, float decay,
+                             float *qpart, const float *loss_part, const ImgTable &tab,
+                             int64_t n_tiles, float *loss_out, hipStream_t s);
 int64_t qat_part_floats(int64_t n, int stages, int size);
 // Quantiser initialisation and encoding (k_qat.hip): gamma, beta from the covariance range,
 // codebooks by K-means per stage; scratch: at least qat_init_scratch_bytes(n, size) bytes.
 size_t qat_init_scratch_bytes(int64_t n, int size);
 hipError_t launch_qat_init(const float *params, int64_t n, const QatArgs &qa, int kmeans_iters,
-                           void *scratch, hipStream_t s);
+                           float *ema, void *scratch, hipStream_t s);
 hipError_t launch_qat_encode(const float *params, int64_t n, const QatArgs &qa, uint16_t *mu,
                              uint8_t *codes, uint8_t *index, hipStream_t s);
 // Effective records of raw recipe records.

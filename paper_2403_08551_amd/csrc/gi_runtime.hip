@@ -873,6 +873,13 @@ int qat_args(const gi_qat *q, QatArgs *out) {
     return GI_OK;
 }
 
+// what a fine-tuning step needs beyond qat_args: the moments of gamma and beta, the running
+// state of the codebooks (4-byte aligned), lambda, lr_q >= 0 and 0 <= decay <= 1
+bool qat_train_args_ok(const gi_qat *q) {
+    return q->quant_m_dev && q->quant_v_dev && q->ema_dev && !((uintptr_t)q->ema_dev & 3u) &&
+           q->lambda >= 0.f && q->lr_q >= 0.f && q->decay >= 0.f && q->decay <= 1.f;
+}
+
 int do_fit_qat(gi_ctx *ctx, float *params, float *m, float *v, const float *target, int64_t n,
                const ImgTable &tab, int64_t n_tiles, const gi_adam *hp, const gi_qat *q,
                const QatArgs &qa, int32_t *step, float *image_out, float *loss_out,
@@ -902,7 +909,8 @@ int do_fit_qat(gi_ctx *ctx, float *params, float *m, float *v, const float *targ
     AdamArgs h{hp->lr_mu, hp->lr_l, hp->lr_c, hp->beta1, hp->beta2, hp->eps, hp->l_min};
     StageTimer tu(ctx, s, GI_STAGE_UPDATE);
     CK(launch_qat_update(u, params, m, v, step, h, qa, q->lambda, q->lr_q, q->quant_m_dev,
-                         q->quant_v_dev, ctx->qpart, ctx->loss_part, tab, n_tiles, loss_out, s));
+                         q->quant_v_dev, q->ema_dev, q->decay, ctx->qpart, ctx->loss_part, tab,
+                         n_tiles, loss_out, s));
     tu.stop();
     return GI_OK;
 }
@@ -1303,7 +1311,8 @@ int gi_qat_init(gi_ctx *ctx, const float *params, int64_t n, const gi_qat *q,
                 int32_t kmeans_iters, void *stream) {
     QatArgs qa;
     if (!ctx || n < 1 || n >= ((int64_t)1 << 31) || !params || !aligned16(params) ||
-        kmeans_iters < 0 || kmeans_iters > 1000 || qat_args(q, &qa) != GI_OK)
+        kmeans_iters < 0 || kmeans_iters > 1000 || qat_args(q, &qa) != GI_OK || !q->ema_dev ||
+        ((uintptr_t)q->ema_dev & 3u))
         return GI_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
     const size_t need = qat_init_scratch_bytes(n, qa.size);
@@ -1315,7 +1324,8 @@ int gi_qat_init(gi_ctx *ctx, const float *params, int64_t n, const gi_qat *q,
         CK(hipMalloc(&ctx->qscratch, need));
         ctx->qscratch_cap = need;
     }
-    CK(launch_qat_init(params, n, qa, kmeans_iters, ctx->qscratch, (hipStream_t)stream));
+    CK(launch_qat_init(params, n, qa, kmeans_iters, q->ema_dev, ctx->qscratch,
+                       (hipStream_t)stream));
     return GI_OK;
 }
 
@@ -1325,8 +1335,7 @@ int gi_fit_step_qat(gi_ctx *ctx, float *params, float *m, float *v, const float 
     QatArgs qa;
     if (!ctx || !target || !step || check_adam(hp) != GI_OK || qat_args(q, &qa) != GI_OK)
         return GI_ERR_INVALID_ARG;
-    if (!q->quant_m_dev || !q->quant_v_dev || !(q->lambda >= 0.f) || !(q->lr_q >= 0.f))
-        return GI_ERR_INVALID_ARG;
+    if (!qat_train_args_ok(q)) return GI_ERR_INVALID_ARG;
     if (n > 0 && (!params || !m || !v || !aligned16(params) || !aligned16(m) || !aligned16(v)))
         return GI_ERR_INVALID_ARG;
     if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
@@ -1560,8 +1569,7 @@ int gi_fit_graph_create_qat(gi_ctx *user, float *params, float *m, float *v, con
     *out = nullptr;
     if (!user || !target || !step || check_adam(hp) != GI_OK || qat_args(q, &qa) != GI_OK)
         return GI_ERR_INVALID_ARG;
-    if (!q->quant_m_dev || !q->quant_v_dev || !(q->lambda >= 0.f) || !(q->lr_q >= 0.f))
-        return GI_ERR_INVALID_ARG;
+    if (!qat_train_args_ok(q)) return GI_ERR_INVALID_ARG;
     if (n > 0 && (!params || !m || !v || !aligned16(params) || !aligned16(m) || !aligned16(v)))
         return GI_ERR_INVALID_ARG;
     if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;

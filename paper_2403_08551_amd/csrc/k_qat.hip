@@ -4,7 +4,8 @@
 //   * the residual-VQ codebooks by K-means (Lloyd iterations, Sec. 4.1 uses 5) per stage on the
 //     residual colours, seeded with the points at indices floor(j N / B), a centroid whose
 //     cluster empties staying put; distances and means in float64, partial sums per block added
-//     in block order (deterministic);
+//     in block order (deterministic); the moving average's running state (Sec. 3.4) starts at
+//     each final centroid's count of nearest residuals and that count times the entry;
 //   * encoding of float records into the codec layout of include/gi.h with the same fake
 //     quantiser the fine-tuning renders with.
 #include <hip/hip_runtime.h>
@@ -150,6 +151,32 @@ __global__ __launch_bounds__(256) void k_kmeans_update(const double *__restrict_
     }
 }
 
+// running state of the codebooks' moving average at stage m: the number of residuals nearest
+// each final centroid (the assignment sums of k_kmeans_assign, added in the fixed order of
+// k_kmeans_update) and that count times the float32 entry
+__global__ __launch_bounds__(256) void k_ema_init(const double *__restrict__ part, int64_t blocks,
+                                                  int32_t k, const double *__restrict__ cent,
+                                                  float *__restrict__ ema) {
+#pragma clang fp contract(off)
+    __shared__ double cnt[QAT_KMAX];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j < k; j += 4) {
+        const int64_t t = 4 * (int64_t)j + 3;
+        double acc = 0.0;
+        for (int64_t b = lane; b < blocks; b += 64) acc += part[t * blocks + b];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+        if (lane == 0) cnt[j] = acc;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        const double c = cnt[j];
+        ema[4 * j] = (float)c;
+        for (int ch = 0; ch < 3; ++ch)
+            ema[4 * j + 1 + ch] = (float)(c * (double)(float)cent[3 * j + ch]);
+    }
+}
+
 // codebook stage m (float32) from the centroids, and the residuals for the next stage
 __global__ __launch_bounds__(QB) void k_kmeans_finish(double *__restrict__ resid, int64_t n,
                                                       int32_t k, const double *__restrict__ cent,
@@ -195,7 +222,7 @@ size_t qat_init_scratch_bytes(int64_t n, int size) {
 }
 
 hipError_t launch_qat_init(const float *params, int64_t n, const QatArgs &qa, int kmeans_iters,
-                           void *scratch, hipStream_t s) {
+                           float *ema, void *scratch, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + QB - 1) / QB;
     const float4 *p4 = reinterpret_cast<const float4 *>(params);
@@ -215,6 +242,10 @@ hipError_t launch_qat_init(const float *params, int64_t n, const QatArgs &qa, in
             hipLaunchKernelGGL(k_kmeans_update, dim3(1), dim3(256), 0, s, part, blocks, qa.size,
                                cent);
         }
+        hipLaunchKernelGGL(k_kmeans_assign, dim3(blocks_for(n)), dim3(QB), 0, s, resid, n, qa.size,
+                           cent, part);
+        hipLaunchKernelGGL(k_ema_init, dim3(1), dim3(256), 0, s, part, blocks, qa.size, cent,
+                           ema + (int64_t)m * qa.size * 4);
         hipLaunchKernelGGL(k_kmeans_finish, dim3(blocks_for(n)), dim3(QB), 0, s, resid, n,
                            qa.size, cent, quant + 6 + (int64_t)m * qa.size * 3);
     }

@@ -1066,14 +1066,19 @@ __global__ __launch_bounds__(UPD_T) void k_adan(float4 *__restrict__ raw, int64_
     p2[4 * i + q] = make_float2(gk[0], gk[1]);
 }
 
-// Quantisation-aware fine-tuning (Sec. 3.3): the Gaussians' Adam step with straight-through
-// gradients of the fake-quantised record, and per-block sums of the quantiser's gradient: LSQ+
-// terms for gamma, beta; for the codebooks, per entry, the sums of C[i] - r over the Gaussians
-// that chose it (scaled by 2 lambda / (N B) later); and the commitment sum |C[i] - r|^2.
-// Per-Gaussian terms go through LDS and are added in Gaussian order, so the sums do not
-// depend on scheduling.  qpart: [qat_nq + 1][gridDim.x] (entry-major, so that the quantiser
-// kernel reads each entry's block sums contiguously).
-__host__ __device__ constexpr int qat_nq(int stages, int size) { return 6 + 3 * stages * size; }
+// Quantisation-aware fine-tuning (Sec. 3.3, Sec. 3.4): the Gaussians' Adam step with
+// straight-through gradients of the fake-quantised record, and per-block sums for the
+// quantiser: the LSQ+ terms of gamma and beta and the commitment sum |C[i] - r|^2 (float), and
+// per codebook entry the number of Gaussians that chose it and the sum of their residuals
+// before its stage (float64), for the moving average.  Per-Gaussian terms go through LDS and
+// are added in Gaussian order, so the sums do not depend on scheduling.  qpart: float sums
+// [QAT_FSUMS][gridDim.x], then (8-byte aligned) float64 sums [4 M B][gridDim.x], entry-major
+// so that the quantiser kernel reads each entry's block sums contiguously.
+constexpr int QAT_FSUMS = 7;  // 6 LSQ terms, the commitment sum
+
+__host__ __device__ constexpr int64_t qat_dsum_offset(int64_t blocks) {
+    return (QAT_FSUMS * blocks + 1) & ~(int64_t)1;  // in floats, rounded up to a double
+}
 
 template <int COV>
 __global__ __launch_bounds__(UPD_T) void k_qat_adam(float4 *__restrict__ params, int64_t n,
@@ -1088,10 +1093,11 @@ __global__ __launch_bounds__(UPD_T) void k_qat_adam(float4 *__restrict__ params,
                                                     const float *__restrict__ loss_part,
                                                     ImgTable tab, int64_t n_tiles,
                                                     float *__restrict__ loss_out) {
-    constexpr int W = 7 + 3 * QAT_MAX_STAGES;  // 6 LSQ terms, commitment, 3 per stage
+#pragma clang fp contract(off)
     __shared__ float s_bc[2];
     __shared__ double red[4];
-    __shared__ float rows[UPD_G][W];
+    __shared__ float rows[UPD_G][QAT_FSUMS];
+    __shared__ double res[UPD_G][QAT_MAX_STAGES][3];
     __shared__ int32_t sidx[UPD_G][QAT_MAX_STAGES];
     if (loss_out) block_image_losses(loss_part, tab, n_tiles, loss_out, red);
     if (threadIdx.x == 0) {
@@ -1104,7 +1110,7 @@ __global__ __launch_bounds__(UPD_T) void k_qat_adam(float4 *__restrict__ params,
     const int q = threadIdx.x & 3;
     const bool live = i < n && !(st->flags & FLAG_KEY_OVERFLOW);
     if (q == 0) {
-        for (int k = 0; k < W; ++k) rows[gl][k] = 0.f;
+        for (int k = 0; k < QAT_FSUMS; ++k) rows[gl][k] = 0.f;
         for (int m = 0; m < QAT_MAX_STAGES; ++m) sidx[gl][m] = -1;
     }
     __syncthreads();
@@ -1129,18 +1135,18 @@ __global__ __launch_bounds__(UPD_T) void k_qat_adam(float4 *__restrict__ params,
                 rows[gl][k] = (float)((double)g[2 + k] * dg);
                 rows[gl][3 + k] = inside[k] ? 0.f : g[2 + k];
             }
-            // codebook terms: the residual before each stage and the chosen entry
+            // the residual before each stage and the chosen entry
             double r0 = b.y, r1 = b.z, r2 = b.w;  // the float colour
             double lc = 0.0;
             const float *books = qa.quant + 6;
             for (int m = 0; m < qa.stages; ++m) {
                 const float *e = books + ((int64_t)m * qa.size + f.idx[m]) * 3;
+                res[gl][m][0] = r0;
+                res[gl][m][1] = r1;
+                res[gl][m][2] = r2;
+                sidx[gl][m] = f.idx[m];
                 const double d0 = (double)e[0] - r0, d1 = (double)e[1] - r1;
                 const double d2 = (double)e[2] - r2;
-                rows[gl][7 + 3 * m] = (float)d0;
-                rows[gl][8 + 3 * m] = (float)d1;
-                rows[gl][9 + 3 * m] = (float)d2;
-                sidx[gl][m] = f.idx[m];
                 lc += (d0 * d0 + d1 * d1) + d2 * d2;
                 r0 -= (double)e[0];
                 r1 -= (double)e[1];
@@ -1174,55 +1180,71 @@ __global__ __launch_bounds__(UPD_T) void k_qat_adam(float4 *__restrict__ params,
         v2[4 * i + q] = make_float2(v[0], v[1]);
     }
     __syncthreads();
-    // block sums in Gaussian order: LSQ terms, commitment, then codebook entries
-    const int nq = qat_nq(qa.stages, qa.size);
-    for (int t = threadIdx.x; t <= nq; t += UPD_T) {
-        float acc = 0.f;
-        if (t < 6) {
+    // block sums in Gaussian order: LSQ terms and the commitment sum (float), then per codebook
+    // entry the count and the residual sum (float64)
+    const int64_t blocks = gridDim.x;
+    double *dpart = reinterpret_cast<double *>(qpart + qat_dsum_offset(blocks));
+    const int nd = 4 * qa.stages * qa.size;
+    for (int t = threadIdx.x; t < QAT_FSUMS + nd; t += UPD_T) {
+        if (t < QAT_FSUMS) {
+            float acc = 0.f;
             for (int j = 0; j < UPD_G; ++j) acc += rows[j][t];
-        } else if (t < nq) {
-            const int e = t - 6, m = e / (3 * qa.size), k = (e / 3) % qa.size, ch = e % 3;
-            for (int j = 0; j < UPD_G; ++j)
-                if (sidx[j][m] == k) acc += rows[j][7 + 3 * m + ch];
+            qpart[(int64_t)t * blocks + blockIdx.x] = acc;
         } else {
-            for (int j = 0; j < UPD_G; ++j) acc += rows[j][6];
+            const int e = (t - QAT_FSUMS) >> 2, ch = (t - QAT_FSUMS) & 3;
+            const int m = e / qa.size, k = e % qa.size;
+            double acc = 0.0;
+            for (int j = 0; j < UPD_G; ++j)
+                if (sidx[j][m] == k) acc += ch < 3 ? res[j][m][ch] : 1.0;
+            dpart[(int64_t)(t - QAT_FSUMS) * blocks + blockIdx.x] = acc;
         }
-        qpart[(int64_t)t * gridDim.x + blockIdx.x] = acc;
     }
 }
 
-// The quantiser's step: block t takes entry t (the last block the commitment loss); its threads
-// add the entry's block sums in a fixed strided order (float64) and a fixed tree joins them;
-// codebook terms are scaled by 2 lambda / (N B); Adam with rate lr_q; the weighted commitment
-// loss is added to the image loss.
-__global__ __launch_bounds__(256) void k_qat_quant_adam(float *__restrict__ quant,
-                                                        float *__restrict__ qm,
-                                                        float *__restrict__ qv,
-                                                        const float *__restrict__ qpart,
-                                                        int64_t blocks, int64_t n, QatArgs qa,
-                                                        float lambda, float lr_q, AdamArgs hp,
-                                                        const int32_t *__restrict__ step,
-                                                        const DevState *__restrict__ st,
-                                                        float *__restrict__ loss_out) {
+// The quantiser's step.  Block t < 6 takes gamma or beta (t) and its Adam step with rate lr_q;
+// block 6 + e takes codebook entry e = m B + j and its moving average: count <- d count +
+// (1 - d) n_j, sum <- d sum + (1 - d) s_j, entry = sum / count while the count is positive
+// (float64 arithmetic, each result rounded once to float32); the last block adds lambda L_c
+// to the loss.  Threads add the block sums in a fixed strided order (float64) and a fixed tree
+// joins them, so the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_qat_quant_update(float *__restrict__ quant,
+                                                          float *__restrict__ qm,
+                                                          float *__restrict__ qv,
+                                                          float *__restrict__ ema, float decay,
+                                                          const float *__restrict__ qpart,
+                                                          int64_t blocks, int64_t n, QatArgs qa,
+                                                          float lambda, float lr_q, AdamArgs hp,
+                                                          const int32_t *__restrict__ step,
+                                                          const DevState *__restrict__ st,
+                                                          float *__restrict__ loss_out) {
+#pragma clang fp contract(off)
     if (st->flags & FLAG_KEY_OVERFLOW) return;  // the Gaussians were not updated either
-    const int nq = qat_nq(qa.stages, qa.size);
-    const double t_step = (double)(*step - 1);
-    const double scale = 2.0 * (double)lambda / ((double)n * (double)qa.size);
-    __shared__ double red[4];
-    const int t = blockIdx.x;  // 0 .. nq
-    double s = 0.0;
-    for (int64_t b = threadIdx.x; b < blocks; b += 256) s += (double)qpart[(int64_t)t * blocks + b];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        s = (red[0] + red[1]) + (red[2] + red[3]);
-        if (t == nq) {
-            if (loss_out) loss_out[0] += (float)(lambda * s / ((double)n * (double)qa.size));
-            return;
+    const int entries = qa.stages * qa.size;
+    const int t = blockIdx.x;  // 0 .. 6 + entries
+    const double *dpart = reinterpret_cast<const double *>(qpart + qat_dsum_offset(blocks));
+    __shared__ double red[4][4];
+    const int nv = (t >= 6 && t < 6 + entries) ? 4 : 1;
+    for (int c = 0; c < nv; ++c) {
+        double s = 0.0;
+        if (nv == 4) {
+            const double *src = dpart + (int64_t)(4 * (t - 6) + c) * blocks;
+            for (int64_t b = threadIdx.x; b < blocks; b += 256) s += src[b];
+        } else {
+            const int row = t < 6 ? t : 6;  // the commitment sum after the six LSQ terms
+            const float *src = qpart + (int64_t)row * blocks;
+            for (int64_t b = threadIdx.x; b < blocks; b += 256) s += (double)src[b];
         }
-        const float g = (float)(t < 6 ? s : s * scale);
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+        if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double tot[4];
+    for (int c = 0; c < nv; ++c) tot[c] = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
+    if (t < 6) {
+        const double t_step = (double)(*step - 1);
+        const float g = (float)tot[0];
         const float bc1 = (float)(1.0 - pow((double)hp.beta1, t_step));
         const float bc2 = (float)(1.0 - pow((double)hp.beta2, t_step));
         const float m = hp.beta1 * qm[t] + (1.f - hp.beta1) * g;
@@ -1230,6 +1252,20 @@ __global__ __launch_bounds__(256) void k_qat_quant_adam(float *__restrict__ quan
         quant[t] -= lr_q * (m / bc1) / (sqrtf(v / bc2) + hp.eps);
         qm[t] = m;
         qv[t] = v;
+    } else if (t < 6 + entries) {
+        const int e = t - 6;
+        const double d = (double)decay;
+        float *es = ema + 4 * (int64_t)e;
+        const float cnt = (float)(d * (double)es[0] + (1.0 - d) * tot[3]);
+        float sum[3];
+        for (int c = 0; c < 3; ++c) sum[c] = (float)(d * (double)es[1 + c] + (1.0 - d) * tot[c]);
+        es[0] = cnt;
+        for (int c = 0; c < 3; ++c) es[1 + c] = sum[c];
+        if (cnt > 0.f)
+            for (int c = 0; c < 3; ++c)
+                quant[6 + 3 * (int64_t)e + c] = (float)((double)sum[c] / (double)cnt);
+    } else if (loss_out) {
+        loss_out[0] += (float)(lambda * tot[0] / ((double)n * (double)qa.size));
     }
 }
 
@@ -1430,9 +1466,9 @@ hipError_t launch_adan(const UpdateArgs &u, float *raw, float *state, int32_t *s
 
 hipError_t launch_qat_update(const UpdateArgs &u, float *params, float *m, float *v,
                              int32_t *step, const AdamArgs &hp, const QatArgs &qa, float lambda,
-                             float lr_q, float *quant_m, float *quant_v, float *qpart,
-                             const float *loss_part, const ImgTable &tab, int64_t n_tiles,
-                             float *loss_out, hipStream_t s) {
+                             float lr_q, float *quant_m, float *quant_v, float *ema, float decay,
+                             float *qpart, const float *loss_part, const ImgTable &tab,
+                             int64_t n_tiles, float *loss_out, hipStream_t s) {
     if (u.n <= 0) return launch_finish(loss_part, tab, n_tiles, loss_out, s);
     const int64_t blocks = (u.n + UPD_G - 1) / UPD_G;
     const dim3 grid((unsigned)blocks);
@@ -1449,15 +1485,15 @@ hipError_t launch_qat_update(const UpdateArgs &u, float *params, float *m, float
                            tab, n_tiles, loss_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_qat_quant_adam, dim3((unsigned)(qat_nq(qa.stages, qa.size) + 1)),
-                       dim3(256), 0, s, const_cast<float *>(qa.quant),
-                       quant_m, quant_v, qpart, blocks, u.n, qa, lambda, lr_q, hp, step, u.state,
-                       loss_out);
+    hipLaunchKernelGGL(k_qat_quant_update, dim3((unsigned)(6 + qa.stages * qa.size + 1)),
+                       dim3(256), 0, s, const_cast<float *>(qa.quant), quant_m, quant_v, ema,
+                       decay, qpart, blocks, u.n, qa, lambda, lr_q, hp, step, u.state, loss_out);
     return hipGetLastError();
 }
 
 int64_t qat_part_floats(int64_t n, int stages, int size) {
-    return ((n + UPD_G - 1) / UPD_G) * (qat_nq(stages, size) + 1);
+    const int64_t blocks = (n + UPD_G - 1) / UPD_G;
+    return qat_dsum_offset(blocks) + 2 * 4 * (int64_t)stages * size * blocks;
 }
 
 hipError_t launch_recipe_effective(const float *raw, int64_t n, const ImgTable &tab, int32_t cov,

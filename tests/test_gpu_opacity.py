@@ -6,6 +6,7 @@ absolute per-pixel contributions, as for the merged-colour path.
 import numpy as np
 import pytest
 
+import parity_util as pu
 import synth
 from oracle import blend, ref
 
@@ -212,3 +213,36 @@ def test_fit_steps_match_oracle(gi, blend_mode):
         assert np.all(np.abs(got_o - oo) <= 2.0 * hp32["lr_c"] + 1e-6)
         assert firm.mean() > 0.9 and firm_o.mean() > 0.9
     assert int(host(step)[0]) == 4
+
+
+@pytest.mark.parametrize("blend_mode", ["sum", "alpha"])
+def test_fit_step_gradients_element_by_element(gi, blend_mode):
+    # Adam with beta1 = beta2 = 0, eps = 1: the first moments of records and opacities are the
+    # fused kernel's gradients, compared element by element with the oracle's at the gradient
+    # bar (plus what the forward bar allows through dL/dC)
+    import paper_2403_08551_amd as P
+    h, w = 96, 128
+    p0 = synth.gaussians(700, h, w, seed=97, l_lo=0.6, l_hi=6.0)
+    o0 = opac(700, 98, 0.2, 0.9)
+    T = synth.target_noise_rects(h, w, seed=99)
+    want, A = blend.render_blend(p0, o0, h, w, blend_mode, with_abs=True)
+    G = ref.mse_grad(want, T)
+    gp, go, ap, ao = blend.grads_blend(p0, o0, h, w, G, blend_mode, with_abs=True)
+    Gp = (2.0 * pu.FWD_RTOL / (3.0 * h * w)) * A
+    _, _, app, aop = blend.grads_blend(p0, o0, h, w, Gp, blend_mode, with_abs=True)
+    bp = pu.GRAD_RTOL * ap + app + 1e-30
+    bo = pu.GRAD_RTOL * ao + aop + 1e-30
+    hp = pu.linear_hp(pu.lr_for(p0, bp, [0, 1]), pu.lr_for(p0, bp, [2, 3, 4]),
+                      pu.lr_for(p0, bp, [5, 6, 7]))
+    pd, od = dev(p0), dev(o0)
+    md, vd = torch.zeros_like(pd), torch.zeros_like(pd)
+    mo, vo = torch.zeros_like(od), torch.zeros_like(od)
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    img = torch.empty(h, w, 3, device="cuda")
+    gi.fit_step_opacity(pd, od, md, vd, mo, vo, dev(T), step, blend_mode, P.AdamConfig(**hp),
+                        image_out=img)
+    check(host(img), want, A, FWD_RTOL, "image")
+    pu.assert_gradient(host(md), gp, bp, f"{blend_mode} record gradients")
+    pu.assert_gradient(host(mo), go, bo, f"{blend_mode} opacity gradients")
+    lr = np.array([hp["lr_mu"]] * 2 + [hp["lr_l"]] * 3 + [hp["lr_c"]] * 3)
+    pu.assert_linear_step(p0, host(pd), gp, bp, lr, f"{blend_mode} linear step")

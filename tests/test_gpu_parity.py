@@ -10,6 +10,7 @@ import math
 import numpy as np
 import pytest
 
+import parity_util as pu
 import synth
 from oracle import cref, ref
 
@@ -282,6 +283,35 @@ def test_fit_steps_match_oracle(gi):
         assert int(host(step)[0]) == t + 1
 
 
+@pytest.mark.parametrize("which", ["plain-256x256-2k", "kodak-768x512-70k"])
+def test_fit_step_gradients_element_by_element(gi, which):
+    # Adam with beta1 = beta2 = 0 and eps = 1: the first moment the fused fit kernel's update
+    # writes is its gradient (L2 loss scale 2 / (3 H W) included), compared element by element
+    # with the oracle's at the gradient bar; the step is then lr g / (|g| + 1), checked too
+    import paper_2403_08551_amd as P
+    w = synth.plain_256() if which.startswith("plain") else synth.kodak_like(70_000)
+    orc = ref if which.startswith("plain") else cref
+    h, wd = w.height, w.width
+    p0, T = w.params(), w.target()
+    o, A = orc.render_culled(p0, h, wd, with_abs=True)
+    g, bound = pu.grad_bound(orc.grads, p0, h, wd, ref.mse_grad(o, T), A)
+    hp = pu.linear_hp(pu.lr_for(p0, bound, [0, 1]), pu.lr_for(p0, bound, [2, 3, 4]),
+                      pu.lr_for(p0, bound, [5, 6, 7]))
+    pd = dev(p0)
+    md, vd = torch.zeros_like(pd), torch.zeros_like(pd)
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    img = torch.empty(h, wd, 3, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    gi.query(clear=True)  # flags other tests left on the shared context
+    gi.fit_step(pd, md, vd, dev(T), step, P.AdamConfig(**hp), image_out=img, loss_out=loss)
+    assert_forward(host(img), o, A, f"{which} fit image")
+    np.testing.assert_allclose(host(loss)[0], ref.mse(o, T), rtol=1e-5)
+    pu.assert_gradient(host(md), g, bound, f"{which} fused gradient")
+    lr = np.array([hp["lr_mu"]] * 2 + [hp["lr_l"]] * 3 + [hp["lr_c"]] * 3)
+    pu.assert_linear_step(p0, host(pd), g, bound, lr, f"{which} linear step")
+    assert gi.query(clear=True)[1] == 0
+
+
 # ------------------------------------------------------------------ batched == plain
 
 def small_batch():
@@ -545,7 +575,9 @@ def test_key_overflow_skips_the_update(binning):
 # ------------------------------------------------------------------ full-size workloads, sampled
 
 @pytest.mark.parametrize("n", [70_000])
-def test_kodak_size_full_run_sampled(gi, n):
+def test_kodak_size_full_images_and_gradients(gi, n):
+    # the metric's workload whole: tile lists key for key, every pixel of the render and every
+    # gradient element (gi_grad with a seeded dL/dC) against the C oracle
     w = synth.kodak_like(n)
     p, h, wd = w.params(), w.height, w.width
     pd = dev(p)
@@ -555,19 +587,18 @@ def test_kodak_size_full_run_sampled(gi, n):
     np.testing.assert_array_equal(host(b["ranges"]), ranges)
     np.testing.assert_array_equal(host(b["ids"]), ids)
     img = host(gi.render(pd, h, wd))
-    rng = np.random.default_rng(1)
-    pix = rng.choice(h * wd, 3000, replace=False)
-    o, A = cref.render_pixels(p, h, wd, pix, with_abs=True)
-    assert_forward(img.reshape(-1, 3)[pix], o, A, "kodak sampled pixels")
+    o, A = cref.render_culled(p, h, wd, with_abs=True)
+    assert_forward(img, o, A, "kodak full image")
     G = synth.upstream_gradient(h, wd, 3)
     d = host(gi.grad(pd, h, wd, dev(G)))
-    which = rng.choice(n, 200, replace=False)
-    od, Ad = cref.grads_subset(p, h, wd, G, which, with_abs=True)
-    assert_grads(d[which], od, Ad, "kodak sampled gradients")
+    od, Ad = cref.grads(p, h, wd, G, with_abs=True)
+    assert_grads(d, od, Ad, "kodak full gradients")
 
 
 @pytest.mark.parametrize("n", [100_000, 300_000])
-def test_div2k_size_sampled(gi, n):
+def test_div2k_size_full_images(gi, n):
+    # 2040x1356 (row binning): counts exactly, every pixel of the render against the C oracle;
+    # gradients whole at 100k, on a seeded sample of Gaussians at 300k
     w = synth.div2k_full(n)
     p, h, wd = w.params(), w.height, w.width
     pd = dev(p)
@@ -576,15 +607,17 @@ def test_div2k_size_sampled(gi, n):
     assert b["keys"] == int(count.sum())
     np.testing.assert_array_equal(host(b["counts"]), count)
     img = host(gi.render(pd, h, wd))
-    rng = np.random.default_rng(2)
-    pix = rng.choice(h * wd, 1500, replace=False)
-    o, A = cref.render_pixels(p, h, wd, pix, with_abs=True)
-    assert_forward(img.reshape(-1, 3)[pix], o, A, f"div2k {n} sampled pixels")
+    o, A = cref.render_culled(p, h, wd, with_abs=True)
+    assert_forward(img, o, A, f"div2k {n} full image")
     G = synth.upstream_gradient(h, wd, 4)
     d = host(gi.grad(pd, h, wd, dev(G)))
-    which = rng.choice(n, 64, replace=False)
-    od, Ad = cref.grads_subset(p, h, wd, G, which, with_abs=True)
-    assert_grads(d[which], od, Ad, f"div2k {n} sampled gradients")
+    if n <= 100_000:
+        od, Ad = cref.grads(p, h, wd, G, with_abs=True)
+        assert_grads(d, od, Ad, f"div2k {n} full gradients")
+    else:
+        which = np.random.default_rng(2).choice(n, 2000, replace=False)
+        od, Ad = cref.grads_subset(p, h, wd, G, which, with_abs=True)
+        assert_grads(d[which], od, Ad, f"div2k {n} sampled gradients")
 
 
 def binning_in_mode(gi, mode, pd, h, wd):

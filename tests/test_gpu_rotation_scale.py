@@ -10,6 +10,7 @@ import math
 import numpy as np
 import pytest
 
+import parity_util as pu
 import synth
 from oracle import ref
 
@@ -179,6 +180,30 @@ def test_rs_fit_steps_match_oracle(gi):
         assert firm.mean() > 0.9
         assert np.all(np.abs(got[:, 2:4]) >= np.float32(hp32["l_min"]))
     assert int(host(step)[0]) == 4
+
+
+def test_rs_fit_step_gradients_element_by_element(gi):
+    # Adam with beta1 = beta2 = 0, eps = 1: the first moment is the fused kernel's gradient in
+    # (mu, s1, s2, theta, c'), compared element by element with the oracle's at the gradient bar
+    import paper_2403_08551_amd as P
+    h, w = 96, 128
+    p0 = synth.gaussians_rs(600, h, w, seed=35, s_lo=0.6, s_hi=6.0, c_lo=0.0, c_hi=0.3)
+    T = synth.target_noise_rects(h, w, seed=36)
+    o, A = ref.render_culled(p0, h, w, with_abs=True, cov="rs")
+
+    def grads_rs(p, hh, ww, G, with_abs):
+        return ref.grads(p, hh, ww, G, with_abs=with_abs, cov="rs")
+
+    g, bound = pu.grad_bound(grads_rs, p0, h, w, ref.mse_grad(o, T), A)
+    hp = pu.linear_hp(pu.lr_for(p0, bound, [0, 1]), pu.lr_for(p0, bound, [2, 3, 4]),
+                      pu.lr_for(p0, bound, [5, 6, 7]))
+    pd = dev(p0)
+    md, vd = torch.zeros_like(pd), torch.zeros_like(pd)
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    gi.fit_step(pd, md, vd, dev(T), step, P.AdamConfig(**hp))
+    pu.assert_gradient(host(md), g, bound, "rotation-scale fused gradient")
+    lr = np.array([hp["lr_mu"]] * 2 + [hp["lr_l"]] * 3 + [hp["lr_c"]] * 3)
+    pu.assert_linear_step(p0, host(pd), g, bound, lr, "rotation-scale linear step")
 
 
 def test_rs_batched_equals_plain_and_graph_equals_eager(gi):
