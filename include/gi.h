@@ -381,6 +381,35 @@ int gi_fit_graph_query(gi_graph *graph, int64_t *last_keys, uint32_t *flags, int
 /* Wait for the device, then release the graph and its workspace. */
 int gi_fit_graph_destroy(gi_graph *graph);
 
+/* ---- render without allocation --------------------------------------------------------------- */
+
+/* Limits of gi_render_noalloc: the bytes of its static device array (held by every device the
+ * library runs on, from the library's first use there until the process ends), and the largest
+ * Gaussian and tile counts it accepts. */
+#define GI_NOALLOC_SCRATCH_BYTES (64ll << 20)
+#define GI_NOALLOC_MAX_GAUSSIANS (1ll << 18)
+#define GI_NOALLOC_MAX_TILES 2048ll
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gi_render without a context and without any
+ * allocation.  It renders params_dev [N][8] (Cholesky records, as gi_render) into image_dev
+ * [H][W][3] on the current HIP device with the same kernels as gi_render's one-pass binning and
+ * gives the same bits.  Every intermediate buffer lives in one static device array of
+ * GI_NOALLOC_SCRATCH_BYTES per device; the call allocates nothing, never waits and enqueues only
+ * kernels (no memset or copy nodes), so it can be captured.
+ * Limits: N <= GI_NOALLOC_MAX_GAUSSIANS and ceil(H/16) ceil(W/16) <= GI_NOALLOC_MAX_TILES, else
+ * GI_ERR_CAPACITY and nothing is enqueued; (tile, Gaussian) keys beyond what the array holds
+ * after the per-Gaussian buffers (about 1.0 million at the largest N, 1.8 million at
+ * N = 70 000)
+ * raise GI_FLAG_KEY_OVERFLOW and leave the image undefined.
+ * flags_dev (one uint32 on the device, may be NULL) receives the call's GI_FLAG_* bits when the
+ * call's work has run.  GI_ERR_NO_DEVICE when the current device is not gfx950.
+ * All calls on one device share its array: calls whose work overlaps in time on one device (on
+ * different streams, or from different host threads without ordering) race and give undefined
+ * results; calls ordered on one stream are safe. */
+int gi_render_noalloc(const float *params_dev, int64_t n, int32_t height, int32_t width,
+                      float *image_dev, uint32_t *flags_dev, void *stream);
+
 /* ---- the binning stages, for inspection and testing ---------------------------------------- */
 
 /* Run projection, key duplication, the stable radix sort and tile-range extraction (the

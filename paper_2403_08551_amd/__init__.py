@@ -21,7 +21,7 @@ import torch
 from . import _lib
 from ._lib import GiError
 
-__all__ = ["Context", "Batch", "AdamConfig", "AdanConfig", "Codec", "Quantiser", "GaussianRender", "render", "default_context",
+__all__ = ["Context", "Batch", "AdamConfig", "AdanConfig", "Codec", "Quantiser", "GaussianRender", "render", "render_noalloc", "default_context",
            "GiError"]
 
 
@@ -685,3 +685,22 @@ class GaussianRender(torch.autograd.Function):
 def render(params: torch.Tensor, height: int, width: int, context: Context | None = None):
     """Differentiable render of [N, 8] Gaussians to an [H, W, 3] image."""
     return GaussianRender.apply(params, height, width, context)
+
+
+def render_noalloc(params: torch.Tensor, height: int, width: int, out: torch.Tensor,
+                   flags: torch.Tensor | None = None) -> torch.Tensor:
+    """gi_render_noalloc: render [N, 8] Cholesky records into the caller's [H, W, 3] image on the
+    current stream of the tensors' device, with no device allocation (every buffer lives in the
+    library's static device array).  `flags` (one int32 on the device, may be None) receives the
+    call's GI_FLAG_* bits once the work has run."""
+    dev = params.device
+    _check(params, "params", dev, (params.shape[0], 8))
+    _check(out, "out", dev, (height, width, 3))
+    if flags is not None:
+        _check(flags, "flags", dev, (1,), torch.int32)
+    with torch.cuda.device(dev):
+        st = _lib.lib().gi_render_noalloc(_ptr(params), params.shape[0], height, width, _ptr(out),
+                                          _ptr(flags), _stream(dev))
+    if st != _lib.GI_OK:
+        raise _lib.GiError(st, "gi_render_noalloc")
+    return out

@@ -42,6 +42,11 @@ GI_STAGE_RASTER_BWD = 2
 GI_STAGE_RASTER_FIT = 3
 GI_STAGE_UPDATE = 4
 
+# limits of gi_render_noalloc (include/gi.h)
+GI_NOALLOC_SCRATCH_BYTES = 64 << 20
+GI_NOALLOC_MAX_GAUSSIANS = 1 << 18
+GI_NOALLOC_MAX_TILES = 2048
+
 # every symbol that include/gi.h declares
 EXPORTS = (
     "gi_create", "gi_destroy", "gi_set_option", "gi_reserve", "gi_query", "gi_status_string",
@@ -51,7 +56,7 @@ EXPORTS = (
     "gi_get_option", "gi_autotune", "gi_fit_graph_query", "gi_codec_decode", "gi_render_codec",
     "gi_render_opacity", "gi_grad_opacity", "gi_fit_step_opacity", "gi_fit_step_recipe",
     "gi_recipe_params", "gi_qat_init", "gi_fit_step_qat", "gi_qat_encode",
-    "gi_fit_graph_create_recipe", "gi_fit_graph_create_qat",
+    "gi_fit_graph_create_recipe", "gi_fit_graph_create_qat", "gi_render_noalloc",
 )
 
 
@@ -124,6 +129,7 @@ def lib():
             "gi_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "gi_last_error": ([P], ctypes.c_char_p),
             "gi_render": ([P, P, I64, I32, I32, P, P], ctypes.c_int),
+            "gi_render_noalloc": ([P, I64, I32, I32, P, P, P], ctypes.c_int),
             "gi_grad": ([P, P, I64, I32, I32, P, P, P], ctypes.c_int),
             "gi_fit_step": ([P, P, P, P, P, I64, I32, I32, ctypes.POINTER(gi_adam), P, P, P, P],
                             ctypes.c_int),

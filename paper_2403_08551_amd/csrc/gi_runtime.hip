@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <mutex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -1711,6 +1712,137 @@ int gi_sort_pairs(gi_ctx *ctx, const uint32_t *kin, const uint32_t *vin, uint32_
         CK(hipMemcpyAsync(vout, ctx->tmp_v, 4 * n, hipMemcpyDeviceToDevice, s));
     }
     return GI_OK;
+}
+
+}  // extern "C"
+
+// ---- render without allocation: every buffer in one static device array -------------------
+//
+// gi_render_noalloc runs gi_render's one-pass path (projection with per-chunk tile counts, one
+// chained scan, the stable scatter into tile order, the forward kernel) on buffers carved out of
+// `scratch`, a file-scope device array of GI_NOALLOC_SCRATCH_BYTES that the code object holds on
+// every device the library runs on.  In host code `scratch` names a host-side stand-in, not the
+// device array: its device address is taken once per device with hipGetSymbolAddress and only
+// that address is ever passed to kernels.
+//
+// Layout: the device state (flags, key total, scan epoch) and the chained scan's status words
+// sit at fixed offsets at the front, so nothing else is ever written there; the status words
+// carry the epoch of the launch that wrote them, which the projection advances on every call,
+// so words left by earlier calls read as unpublished.  Both start at zero (static storage is
+// zero-initialised), and every call ends by clearing the flags.  The per-call buffers follow:
+// projections, rectangles, tile facts, counts, the scan array, tile ranges, then the records
+// in tile order, which take the rest (32 bytes per key).
+
+namespace {
+
+constexpr size_t NA_ALIGN = 256;
+constexpr size_t NA_STATE_BYTES = 256;
+constexpr int64_t NA_STATUS_WORDS = 1024;  // >= the scan blocks of the largest accepted call
+constexpr size_t NA_FIXED_BYTES = NA_STATE_BYTES + 8 * NA_STATUS_WORDS;
+
+static __device__ __align__(256) unsigned char scratch[GI_NOALLOC_SCRATCH_BYTES];
+
+// one thread: hand the call's flags to the caller (if asked) and clear them for the next call
+__global__ void k_noalloc_flags(DevState *state, uint32_t *flags_out) {
+    const uint32_t f = state->flags;
+    if (flags_out) *flags_out = f;
+    state->flags = 0u;
+}
+
+struct NoallocDevice {
+    int ready = 0;      // 1: set up, 2: not a gfx950 device or set-up failed
+    unsigned char *ptr = nullptr;  // device address of `scratch` on this device
+};
+
+std::mutex na_mutex;
+std::map<int, NoallocDevice> na_devices;
+
+size_t na_up(size_t b) { return (b + NA_ALIGN - 1) / NA_ALIGN * NA_ALIGN; }
+
+// Device address of `scratch` on the current device (nullptr if the device is not usable),
+// found once per device.
+unsigned char *noalloc_scratch(int dev) {
+    std::lock_guard<std::mutex> lock(na_mutex);
+    NoallocDevice &d = na_devices[dev];
+    if (d.ready == 0) {
+        d.ready = 2;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+            strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return nullptr;
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        if (fused_scan_blocks(GI_NOALLOC_MAX_GAUSSIANS, FUSED_MAX_TILES) > NA_STATUS_WORDS)
+            return nullptr;  // the fixed status area would be too small (a build error)
+        d.ptr = static_cast<unsigned char *>(p);
+        d.ready = 1;
+    }
+    return d.ready == 1 ? d.ptr : nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gi_render_noalloc(const float *params, int64_t n, int32_t H, int32_t W, float *image,
+                      uint32_t *flags_out, void *stream) {
+    if (!image || (n > 0 && !params)) return GI_ERR_INVALID_ARG;
+    if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
+    if (n > 0 && !aligned16(params)) return GI_ERR_INVALID_ARG;
+    const ImgTable tab = single_table(H, W);
+    const int64_t T = (int64_t)tab.TW * tab.rows;
+    if (n > GI_NOALLOC_MAX_GAUSSIANS || T > GI_NOALLOC_MAX_TILES) return GI_ERR_CAPACITY;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GI_ERR_NO_DEVICE;
+    unsigned char *base = noalloc_scratch(dev);
+    if (!base) return GI_ERR_NO_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    DevState *state = reinterpret_cast<DevState *>(base);
+    if (n == 0) {
+        if (launch_fill_u32(reinterpret_cast<uint32_t *>(image), 0u, (int64_t)H * W * 3, s) !=
+            hipSuccess)
+            return GI_ERR_HIP;
+        hipLaunchKernelGGL(k_noalloc_flags, dim3(1), dim3(1), 0, s, state, flags_out);
+        return hipGetLastError() == hipSuccess ? GI_OK : GI_ERR_HIP;
+    }
+    // per-call layout after the fixed area
+    size_t o = NA_FIXED_BYTES;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = na_up(o + bytes);
+        return base + at;
+    };
+    FusedBuffers f;
+    memset(&f, 0, sizeof(f));
+    BinBuffers &b = f.b;
+    b.params = params;
+    b.blend = BLEND_NONE;
+    b.n = n;
+    b.proj = reinterpret_cast<float *>(take(sizeof(float) * 4 * PROJ_F4 * (size_t)n));
+    b.rect = reinterpret_cast<int4 *>(take(sizeof(int4) * (size_t)n));
+    b.tinfo = reinterpret_cast<uint2 *>(take(sizeof(uint2) * (size_t)n));
+    b.count = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * (size_t)n));
+    f.scan = reinterpret_cast<uint32_t *>(
+        take(sizeof(uint32_t) * (size_t)fused_scan_entries(n, T)));
+    b.ranges = reinterpret_cast<uint2 *>(take(sizeof(uint2) * (size_t)T));
+    if (o + 32 > (size_t)GI_NOALLOC_SCRATCH_BYTES) return GI_ERR_CAPACITY;  // not reached
+    b.rec = reinterpret_cast<float *>(base + o);
+    b.cap = (int64_t)(((size_t)GI_NOALLOC_SCRATCH_BYTES - o) / 32);
+    b.slot = nullptr;  // a render: no adjoint reads the key slots
+    b.n_tiles = T;
+    b.state = state;
+    f.status = reinterpret_cast<unsigned long long *>(base + NA_STATE_BYTES);
+    ImgTable tb = tab;
+    tb.cov = COV_CHOLESKY;
+    if (launch_fused_a(f, tb, s) != hipSuccess) return GI_ERR_HIP;
+    if (launch_fused_c(f, nullptr, s) != hipSuccess) return GI_ERR_HIP;
+    RasterArgs a{b.rec, nullptr, b.ranges, T, tb};
+    if (launch_raster_fwd(a, image, 4, s) != hipSuccess) return GI_ERR_HIP;
+    hipLaunchKernelGGL(k_noalloc_flags, dim3(1), dim3(1), 0, s, state, flags_out);
+    return hipGetLastError() == hipSuccess ? GI_OK : GI_ERR_HIP;
 }
 
 }  // extern "C"

@@ -81,3 +81,17 @@ def test_header_constants_match_the_binding():
     for name in ("GI_OPT_COVARIANCE", "GI_COV_CHOLESKY", "GI_COV_ROTATION_SCALE",
                  "GI_FLAG_SCAN_STALL", "GI_STAGE_UPDATE"):
         assert name in found and hasattr(_lib, name), name
+
+
+def test_noalloc_render_rejects_bad_sizes_without_a_device():
+    L = _lib.lib()
+    nul = ctypes.c_void_p(0)
+    buf = (ctypes.c_float * 64)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.gi_render_noalloc(p, 1, 16, 16, nul, nul, nul) == _lib.GI_ERR_INVALID_ARG
+    assert L.gi_render_noalloc(nul, 1, 16, 16, p, nul, nul) == _lib.GI_ERR_INVALID_ARG
+    assert L.gi_render_noalloc(p, 1, 0, 16, p, nul, nul) == _lib.GI_ERR_INVALID_ARG
+    big = _lib.GI_NOALLOC_MAX_GAUSSIANS + 1
+    assert L.gi_render_noalloc(p, big, 16, 16, p, nul, nul) == _lib.GI_ERR_CAPACITY
+    # 2 x 1025 tiles is two tiles over the limit
+    assert L.gi_render_noalloc(p, 1, 32, 16 * 1025, p, nul, nul) == _lib.GI_ERR_CAPACITY
