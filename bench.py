@@ -22,17 +22,22 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP32 vector peak of the chip in operations per second (an FMA counted once): 157.3 TFLOP/s /
-# 2 = 256 CUs x 4 SIMDs x 16 lanes x 2 (packed dual FP32) x 2.4 GHz.  These kernels do not emit
-# packed FP32 instructions (kept out for correctness), so their own ceiling is half of it:
-# 39.3 T lane-operations per second.
-VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9
-VALU_PEAK_UNPACKED = VALU_PEAK / 2
-# Algorithmic work per pixel-Gaussian pair (the unit), in FP32 operations: forward 10 VALU
-# operations + 1 exp2, adjoint 26 VALU operations + 1 exp2 (plain per-pair forms, before any
-# sharing of per-column terms); each exp2 is counted as one operation.
-OPS_PER_PAIR_FIT = 10 + 26 + 2
-OPS_PER_PAIR_FWD = 10 + 1
+# Derived FP32 issue ceiling of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane
+# operations per second, one FP32 operation (an FMA counted once) per lane per clock.  The
+# published 157.3 TFLOP/s counts an FMA as two flops and packed dual FP32 as two lanes; these
+# kernels are built without packed FP32, so 39.3 T lane-op/s is their ceiling.
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
+PUBLISHED_FP32_TFLOPS = 157.3
+# Algorithmic work per pixel-Gaussian pair (the unit) of the fused fit kernel, counting each
+# pair's own arithmetic and sharing what a pixel column or a Gaussian shares:
+#   forward (Eq. rasterization4): u2 (1 FMA), the exponent |u|^2 (1 FMA), exp2, colour (3 FMA)
+#   adjoint (App. A): u2, |u|^2, exp2, dL/dc sums (3 FMA), <dL/dC, c'> (3), its product with
+#   exp (1), the sums weighted by u2 and u2^2 (2)
+# = 16 FP32 VALU operations and 2 exp2 per pair.  exp2 costs what the measured exp2 rate says.
+VALU_PER_PAIR_FIT = 5 + 11
+EXP_PER_PAIR_FIT = 2
+VALU_PER_PAIR_FWD = 5
+EXP_PER_PAIR_FWD = 1
 
 
 def parse():
@@ -51,7 +56,7 @@ def parse():
     ap.add_argument("--batch-set", default="small", choices=["small", "large"],
                     help="small: sides 128-1024, 1k-50k Gaussians; large: sides 512-2048, "
                          "20k-200k Gaussians")
-    ap.add_argument("--batch-steps", type=int, default=50)
+    ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--no-codec", action="store_true",
                     help="skip the codec decode leg (Sec. 3.3, Table 2)")
@@ -66,6 +71,10 @@ def parse():
                          "and WRITE_SIZE to bytes)")
     ap.add_argument("--binning", type=int, default=0,
                     help="0 auto, 1 duplication + radix sort, 2 one-pass counting sort")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only run the roofline microbenchmarks and print their rates")
+    ap.add_argument("--long-steps", type=int, default=1000,
+                    help="fit steps of the long-fit leg (keys at step 0 and at its end; 0 skips)")
     return ap.parse_args()
 
 
@@ -101,6 +110,116 @@ def cpu_baseline(w, steps):
                       f"same {w.width}x{w.height} / {n} Gaussian workload, after one untimed step"}
 
 
+def peaks():
+    """Roofline denominators measured on this GPU (libgi_peaks.so): FP32 FMA lane rate, exp2
+    lane rate alone and with four FMAs issued beside each exp2, and device copy bandwidth."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2403_08551_amd", "libgi_peaks.so"))
+    lib.peaks_run.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double)]
+    out = {}
+    for kind, name, size in ((0, "fma", 4000), (1, "exp2", 1000), (2, "mixed", 1000),
+                             (3, "copy", 1 << 30)):
+        r, r2 = ctypes.c_double(), ctypes.c_double()
+        st = lib.peaks_run(kind, size, ctypes.byref(r), ctypes.byref(r2))
+        if st != 0:
+            raise RuntimeError(f"peaks_run({kind}) failed: {st}")
+        out[name] = r.value
+        if kind == 2:
+            out["mixed_fma"] = r2.value
+    fma, ex = out["fma"], out["exp2"]
+    # time of one exp2 + 4 FMAs if the two share the issue slots (sum) or overlap (max)
+    t_mixed = 1.0 / out["mixed"]
+    t_sum = 1.0 / ex + 4.0 / fma
+    model = "sum" if t_mixed > 0.9 * t_sum else "max"
+    return {"fma_lane_ops_per_s": fma, "exp2_per_s": ex, "exp2_cost_in_fma": fma / ex,
+            "mixed_exp2_per_s": out["mixed"], "mixed_fma_per_s": out["mixed_fma"],
+            "exp2_model": model, "copy_bytes_per_s": out["copy"],
+            "derived_valu_peak": VALU_PEAK, "fma_frac_of_derived": fma / VALU_PEAK}
+
+
+def valu_roofline(pairs, seconds, valu_per_pair, exp_per_pair, pk):
+    """Roofline object of an ALU-bound kernel: pairs x (VALU + exp2 weighted by its measured
+    cost) lane operations per launch over the launch time, against the derived 39.3 T ceiling."""
+    w = pk["exp2_cost_in_fma"]
+    if pk["exp2_model"] == "sum":
+        ops = pairs * (valu_per_pair + w * exp_per_pair)
+    else:
+        ops = pairs * max(valu_per_pair, w * exp_per_pair)
+    achieved = ops / seconds
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+            "unit": "T FP32 lane-op/s", "frac": achieved / VALU_PEAK,
+            "valu_per_pair": valu_per_pair, "exp2_per_pair": exp_per_pair,
+            "exp2_cost_in_fma": w, "exp2_model": pk["exp2_model"],
+            "frac_of_measured_fma_rate": achieved / pk["fma_lane_ops_per_s"],
+            "flops_per_s_fma_as_2": 2 * achieved / 1e12,
+            "frac_of_published_fp32": 2 * achieved / 1e12 / PUBLISHED_FP32_TFLOPS}
+
+
+def render_graph_leg(P, torch, params, H, W, replays):
+    """Render FPS from a captured graph: the no-allocation render (gi_render_noalloc) recorded
+    once into a HIP graph on a side stream, replayed; every replay's image equals the eager
+    one (checked on the last)."""
+    dev = params.device
+    img = torch.empty(H, W, 3, device=dev)
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    P.render_noalloc(params, H, W, img, flags)  # eager: sets up the device's scratch
+    torch.cuda.synchronize()
+    eager = img.clone()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            P.render_noalloc(params, H, W, img, flags)
+    torch.cuda.current_stream(dev).wait_stream(side)
+    for _ in range(10):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        g.replay()
+    torch.cuda.synchronize()
+    fps = replays / (time.perf_counter() - t0)
+    if int(flags.item()) != 0 or not torch.equal(img, eager):
+        raise RuntimeError("graph-replayed render differs from the eager one")
+    del g
+    return fps
+
+
+def long_fit_leg(P, torch, w, steps):
+    """The cfg2 run: `steps` graph-replayed fit steps from the initial parameters; keys, loss
+    and pairs at step 0 and at the end, and the it/s over the whole run."""
+    dev = torch.device("cuda", 0)
+    ctx = P.Context(0)
+    params = torch.tensor(w.params(), device=dev)
+    target = torch.tensor(w.target(), device=dev)
+    b0 = ctx.binning(params, w.height, w.width)
+    pairs0 = pairs_from_ranges(b0["ranges"].cpu().numpy(), w.height, w.width)
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    step = torch.ones(1, dtype=torch.int32, device=dev)
+    loss = torch.empty(1, device=dev)
+    graph = ctx.fit_graph(params, m, v, target, step, loss_out=loss)
+    graph.launch(1)
+    torch.cuda.synchronize()
+    loss0 = float(loss.item())
+    t0 = time.perf_counter()
+    graph.launch(steps - 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    loss_end = float(loss.item())
+    _, flags = graph.query(clear=True)
+    graph.close()
+    if flags & (P._lib.GI_FLAG_KEY_OVERFLOW | P._lib.GI_FLAG_SCAN_STALL):
+        raise RuntimeError(f"flags {flags} raised during the long fit")
+    b1 = ctx.binning(params, w.height, w.width)
+    pairs1 = pairs_from_ranges(b1["ranges"].cpu().numpy(), w.height, w.width)
+    ctx.close()
+    return {"steps": steps, "fit_its": (steps - 1) / dt, "keys_step0": b0["keys"],
+            "keys_end": b1["keys"], "pairs_step0": pairs0, "pairs_end": pairs1,
+            "loss_step0": loss0, "loss_end": loss_end}
+
+
 def batch_inputs(images, which):
     """Workloads, parameters and targets of the batch (targets made in worker processes; call
     this before the process touches the GPU)."""
@@ -113,11 +232,12 @@ def batch_inputs(images, which):
 
 def batched_vs_plain(ctx, inputs, steps, P, torch, np):
     """Fit uneven images for `steps` steps as one batch (one launch per stage) and as sequential
-    single-image fits; both graph-replayed.  The batched fit is bit-identical to the plain one,
-    so the final losses are equal."""
+    single-image fits; both graph-replayed after one untimed replay each.  The batched fit is
+    bit-identical to the plain one, so every image's final loss is equal."""
     ws, ps, ts = inputs
     images = len(ws)
     dev = ctx.device
+    bad = P._lib.GI_FLAG_KEY_OVERFLOW | P._lib.GI_FLAG_SCAN_STALL
     off = np.concatenate([[0], np.cumsum([p.shape[0] for p in ps])])
     batch = P.Batch([w.height for w in ws], [w.width for w in ws], off)
     allp = torch.tensor(np.concatenate(ps), device=dev)
@@ -126,12 +246,16 @@ def batched_vs_plain(ctx, inputs, steps, P, torch, np):
     step = torch.ones(1, dtype=torch.int32, device=dev)
     loss_b = torch.empty(images, device=dev)
     g = ctx.fit_graph(allp, m, v, allt, step, batch=batch, loss_out=loss_b)
+    g.launch(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g.launch(steps)
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
+    _, flags = g.query(clear=True)
     g.close()
+    if flags & bad:
+        raise RuntimeError(f"flags {flags} raised during the batched fit")
     # plain: one graph per image, replayed in turn
     singles = []
     for w, p, t in zip(ws, ps, ts):
@@ -140,7 +264,9 @@ def batched_vs_plain(ctx, inputs, steps, P, torch, np):
         md, vd = torch.zeros_like(pd), torch.zeros_like(pd)
         sd = torch.ones(1, dtype=torch.int32, device=dev)
         ld = torch.empty(1, device=dev)
-        singles.append((ctx.fit_graph(pd, md, vd, td, sd, loss_out=ld), pd, ld))
+        gr = ctx.fit_graph(pd, md, vd, td, sd, loss_out=ld)
+        gr.launch(1)
+        singles.append((gr, pd, ld))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for gr, _, _ in singles:
@@ -152,12 +278,17 @@ def batched_vs_plain(ctx, inputs, steps, P, torch, np):
     same_params = all(torch.equal(allp[off[i]:off[i + 1]], pd) for i, (_, pd, _) in
                       enumerate(singles))
     for gr, _, _ in singles:
+        _, f = gr.query(clear=True)
         gr.close()
+        if f & bad:
+            raise RuntimeError(f"flags {f} raised during a plain fit")
+    rel = np.abs(lb - lp) / np.abs(lp)
     return {"images": images, "steps": steps, "gaussians": int(off[-1]),
             "pixels": int(batch.n_pix), "batched_s": t_batched, "plain_s": t_plain,
             "speedup": t_plain / t_batched,
             "batched_image_steps_per_s": images * steps / t_batched,
-            "final_mse_max_rel_diff": float(np.max(np.abs(lb - lp) / np.abs(lp))),
+            "final_mse_max_rel_diff": float(rel.max()),
+            "images_within_1e-3": int((rel <= 1e-3).sum()),
             "params_bit_identical": bool(same_params)}
 
 
@@ -436,6 +567,9 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.peaks:
+        print(json.dumps(peaks()), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (work shards as "
               "one image, or one batch of images, per GPU)", file=sys.stderr)
@@ -456,6 +590,7 @@ def main():
     n_gauss = w.n
     H, W = w.height, w.width
     dev = torch.device("cuda", 0)
+    pk = peaks()
     params0 = torch.tensor(w.params(), device=dev)
     target = torch.tensor(w.target(), device=dev)
     ctx = P.Context(0)
@@ -478,10 +613,18 @@ def main():
     graph.launch(args.warmup)
     torch.cuda.synchronize()
     loss_start = float(loss.item())
+    # the K timed replays, each also bracketed by HIP events on the launch stream so that a
+    # one-off cost shows up as an outlier
+    st = torch.cuda.current_stream(dev)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    graph.launch(args.steps)
+    evs[0].record(st)
+    for i in range(args.steps):
+        graph.launch(1)
+        evs[i + 1].record(st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    rep = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
     its = args.steps / dt
     loss_end = float(loss.item())
     keys_now, flags = graph.query(clear=True)
@@ -512,7 +655,7 @@ def main():
     P_prof = pairs_from_ranges(b2["ranges"].cpu().numpy(), H, W)
     ctx.set_option(P._lib.GI_OPT_SYNC, 0)
     fit_avg_s = fit_ms / fit_n / 1e3
-    achieved = OPS_PER_PAIR_FIT * P_prof / fit_avg_s
+    roof = valu_roofline(P_prof, fit_avg_s, VALU_PER_PAIR_FIT, EXP_PER_PAIR_FIT, pk)
 
     # ---- render FPS: eager non-waiting renders of the initial parameters, no stage timing
     ctx.set_option(P._lib.GI_OPT_TIMING, 0)
@@ -526,12 +669,24 @@ def main():
         ctx.render(params0, H, W, out=img)
     torch.cuda.synchronize()
     fps = n_render / (time.perf_counter() - t0)
+    ctx.set_option(P._lib.GI_OPT_TIMING, 1)
+    ctx.timing(0, reset=True)
+    for _ in range(100):
+        ctx.render(params0, H, W, out=img)
+    torch.cuda.synchronize()
+    fwd_ms, fwd_n = ctx.timing(P._lib.GI_STAGE_RASTER_FWD)
+    rbin_ms, rbin_n = ctx.timing(P._lib.GI_STAGE_BINNING, reset=True)
+    ctx.set_option(P._lib.GI_OPT_TIMING, 0)
+    fwd_roof = valu_roofline(P_pairs, fwd_ms / fwd_n / 1e3, VALU_PER_PAIR_FWD, EXP_PER_PAIR_FWD,
+                             pk)
+    fps_graph = render_graph_leg(P, torch, params0, H, W, n_render)
     ctx.set_option(P._lib.GI_OPT_SYNC, 1)
     rs = None if args.no_rs else rotation_scale_leg(P, torch, w, min(max(args.steps, 100), 300),
                                                      tuned)
     cod = None if args.no_codec else codec_leg(P, torch, w, max(args.steps, 100))
     abl = None if args.no_ablation else ablation_leg(P, torch, 100)
     rcp = None if args.no_recipe else recipe_leg(P, torch, w, 100)
+    lng = long_fit_leg(P, torch, w, args.long_steps) if args.long_steps > 1 else None
     bvp = None
     if args.batch_images > 0:
         bvp = batched_vs_plain(ctx, binputs, args.batch_steps, P, torch, np)
@@ -553,16 +708,22 @@ def main():
         "config": {"workload": w.name, "height": H, "width": W, "gaussians": n_gauss,
                    "keys": K, "pairs": P_pairs, "fit_steps": "hip graph replay"},
         "render_fps": fps,
+        "render_fps_graph": fps_graph,
+        "replay_ms": {"first": float(rep[0]), "min": float(rep.min()),
+                      "median": float(np.median(rep)), "max": float(rep.max())},
         "tuned": {"fwd_pixels_per_lane": tuned[0], "radix_digit_bits": tuned[1]},
         "stage_ms": {"binning": bin_ms / max(bin_n, 1), "raster_fit": fit_ms / max(fit_n, 1),
-                     "update": upd_ms / max(upd_n, 1)},
+                     "update": upd_ms / max(upd_n, 1),
+                     "render_binning": rbin_ms / max(rbin_n, 1),
+                     "raster_fwd": fwd_ms / max(fwd_n, 1)},
         "loss": {"after_warmup": loss_start, "after_timed": loss_end},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T FP32 op/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(f"k_raster_fit<{tuned[0] or 4}>"),
-                     "peak_unpacked": VALU_PEAK_UNPACKED / 1e12,
-                     "frac_unpacked": achieved / VALU_PEAK_UNPACKED,
-                     "kernel": f"k_raster_fit<{tuned[0] or 4}>", "ops_per_pair": OPS_PER_PAIR_FIT,
-                     "pairs_per_launch": P_prof, "avg_launch_ms": fit_ms / fit_n},
+        "roofline": dict(roof, traffic=measured_traffic(f"k_raster_fit<{tuned[0] or 4}>"),
+                         kernel=f"k_raster_fit<{tuned[0] or 4}>", pairs_per_launch=P_prof,
+                         avg_launch_ms=fit_ms / fit_n),
+        "render_roofline": dict(fwd_roof, kernel="k_raster_fwd<4>", pairs_per_launch=P_pairs,
+                                avg_launch_ms=fwd_ms / fwd_n),
+        "peaks": pk,
+        "long_fit": lng,
         "batched_vs_plain": bvp,
         "rotation_scale": rs,
         "codec": cod,

@@ -13,15 +13,24 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libgi.so")
 SOURCES = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
+# the roofline microbenchmarks: a library of their own, loaded only by the benchmark
+PEAKS_LIB = os.path.join(HERE, "libgi_peaks.so")
+PEAKS_SOURCES = [os.path.join(HERE, "peaks", "k_peaks.hip")]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
 
 
 def build(verbose: bool = False) -> str:
+    _build_one(SOURCES, LIB, verbose)
+    _build_one(PEAKS_SOURCES, PEAKS_LIB, verbose)
+    return LIB
+
+
+def _build_one(sources, lib, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc, *FLAGS, *SOURCES, "-o", tmp]
+    tmp = lib + f".tmp{os.getpid()}"
+    cmd = [hipcc, *FLAGS, *sources, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -29,11 +38,10 @@ def build(verbose: bool = False) -> str:
             if "packed-fp32-ops' is not a recognized feature" not in ln]
     if res.returncode != 0:
         sys.stderr.write("\n".join(errs) + "\n")
-        raise RuntimeError("hipcc failed building libgi.so")
+        raise RuntimeError(f"hipcc failed building {os.path.basename(lib)}")
     if verbose and errs:
         sys.stderr.write("\n".join(errs) + "\n")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
 
 
 if __name__ == "__main__":

@@ -1510,6 +1510,10 @@ int capture_step(gi_ctx *user, const float *params, int64_t n, int32_t H, int32_
     if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamEndCapture"));
     e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipGraphInstantiate"));
+    // move the executable graph to the device now, not at its first launch (no work runs)
+    e = hipGraphUpload(gr->exec, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipGraphUpload"));
     *out = gr;
     return GI_OK;
 }

@@ -111,3 +111,41 @@ def test_noalloc_empty_set_and_nonfinite_flag():
         assert torch.equal(got, ctx.render(pd, 40, 40))
     finally:
         ctx.close()
+
+
+def test_noalloc_render_replays_from_a_captured_graph():
+    # the call recorded into a HIP graph (kernel nodes only) and replayed four times, with other
+    # renders (through gi_render, and no-allocation renders of another size that overwrite the
+    # shared array) and host waits between the replays: every replay equals the eager image
+    import paper_2403_08551_amd as P
+    w = synth.kodak_like(30_000)
+    h, wd = w.height, w.width
+    pd = dev(w.params())
+    want, flags = run_noalloc(P, pd, h, wd)
+    assert flags == 0
+    other = synth.plain_256()
+    po = dev(other.params())
+    img = torch.full((h, wd, 3), float("nan"), device="cuda")
+    fl = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            P.render_noalloc(pd, h, wd, img, fl)
+    torch.cuda.current_stream().wait_stream(side)
+    ctx = P.Context(0)
+    try:
+        for i in range(4):
+            img.fill_(float("nan"))
+            fl.fill_(-1)
+            g.replay()
+            torch.cuda.synchronize()
+            assert int(fl.item()) == 0, f"replay {i}: flags {int(fl.item())}"
+            assert torch.equal(img, want), f"replay {i} differs from the eager image"
+            ctx.render(po, other.height, other.width)
+            small, f2 = run_noalloc(P, po, other.height, other.width)
+            assert f2 == 0
+    finally:
+        ctx.close()
+        del g
