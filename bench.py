@@ -22,22 +22,22 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Derived FP32 issue ceiling of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane
-# operations per second, one FP32 operation (an FMA counted once) per lane per clock.  The
-# published 157.3 TFLOP/s counts an FMA as two flops and packed dual FP32 as two lanes; these
-# kernels are built without packed FP32, so 39.3 T lane-op/s is their ceiling.
-VALU_PEAK = 256 * 4 * 16 * 2.4e9
-PUBLISHED_FP32_TFLOPS = 157.3
 # Algorithmic work per pixel-Gaussian pair (the unit) of the fused fit kernel, counting each
 # pair's own arithmetic and sharing what a pixel column or a Gaussian shares:
 #   forward (Eq. rasterization4): u2 (1 FMA), the exponent |u|^2 (1 FMA), exp2, colour (3 FMA)
-#   adjoint (App. A): u2, |u|^2, exp2, dL/dc sums (3 FMA), <dL/dC, c'> (3), its product with
-#   exp (1), the sums weighted by u2 and u2^2 (2)
-# = 16 FP32 VALU operations and 2 exp2 per pair.  exp2 costs what the measured exp2 rate says.
+#   adjoint (App. A): u2, |u|^2, exp2, dL/dc sums (3 FMA), <dL/dC, c'> (a multiply and 2 FMA),
+#   its product with exp and u2 (2 multiplies), the sums of w u2 and w u2^2 (an add and an FMA)
+# = 16 FP32 VALU operations (30 flops, an FMA counted as two) and 2 exp2 per pair.
 VALU_PER_PAIR_FIT = 5 + 11
 EXP_PER_PAIR_FIT = 2
+FLOPS_PER_PAIR_FIT = 10 + 20
 VALU_PER_PAIR_FWD = 5
 EXP_PER_PAIR_FWD = 1
+FLOPS_PER_PAIR_FWD = 10
+# MI355X published dense FP32 vector rate (an FMA as two flops), and the same as FP32 lane
+# operations per second from unit counts and clock: 256 CUs x 128 FP32 lanes x 2.4 GHz.
+PUBLISHED_FP32_TFLOPS = 157.3
+DERIVED_FP32_LANE_OPS = 256 * 128 * 2.4e9
 
 
 def parse():
@@ -73,6 +73,10 @@ def parse():
                     help="0 auto, 1 duplication + radix sort, 2 one-pass counting sort")
     ap.add_argument("--peaks", action="store_true",
                     help="only run the roofline microbenchmarks and print their rates")
+    ap.add_argument("--profile", type=int, default=0, metavar="K",
+                    help="only run K eager fit steps with zero learning rates (every step the "
+                         "same work: the initial parameters) and K renders of the workload, for "
+                         "kernel traces and counters")
     ap.add_argument("--long-steps", type=int, default=1000,
                     help="fit steps of the long-fit leg (keys at step 0 and at its end; 0 skips)")
     return ap.parse_args()
@@ -111,56 +115,70 @@ def cpu_baseline(w, steps):
 
 
 def peaks():
-    """Roofline denominators measured on this GPU (libgi_peaks.so): FP32 FMA lane rate, exp2
-    lane rate alone and with four FMAs issued beside each exp2, and device copy bandwidth."""
+    """Roofline denominators measured on this GPU (libgi_peaks.so): the FP32 FMA lane rate of the
+    v_fmac_f32 form, the exp2 rate alone and its marginal rate among other VALU work, the device
+    copy bandwidth, and the pixel-Gaussian pair rates of the kernels' smallest per-pair
+    instruction sequences."""
     import ctypes
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2403_08551_amd", "libgi_peaks.so"))
     lib.peaks_run.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double)]
     out = {}
-    for kind, name, size in ((0, "fma", 4000), (1, "exp2", 1000), (2, "mixed", 1000),
-                             (3, "copy", 1 << 30)):
+    # about 20 ms of FMAs first, so that the clocks have risen before anything is timed
+    r, r2 = ctypes.c_double(), ctypes.c_double()
+    if lib.peaks_run(0, 20000, ctypes.byref(r), ctypes.byref(r2)) != 0:
+        raise RuntimeError("peaks_run warm-up failed")
+    for kind, name, size in ((0, "fma", 20000), (1, "exp2", 5000), (2, "exp2_marginal", 4000),
+                             (3, "copy", 1 << 30), (4, "fwd_pairs", 4000),
+                             (5, "bwd_pairs", 2000)):
         r, r2 = ctypes.c_double(), ctypes.c_double()
         st = lib.peaks_run(kind, size, ctypes.byref(r), ctypes.byref(r2))
-        if st != 0:
+        if st != 0 or r.value <= 0:
             raise RuntimeError(f"peaks_run({kind}) failed: {st}")
         out[name] = r.value
         if kind == 2:
-            out["mixed_fma"] = r2.value
-    fma, ex = out["fma"], out["exp2"]
-    # time of one exp2 + 4 FMAs if the two share the issue slots (sum) or overlap (max)
-    t_mixed = 1.0 / out["mixed"]
-    t_sum = 1.0 / ex + 4.0 / fma
-    model = "sum" if t_mixed > 0.9 * t_sum else "max"
-    return {"fma_lane_ops_per_s": fma, "exp2_per_s": ex, "exp2_cost_in_fma": fma / ex,
-            "mixed_exp2_per_s": out["mixed"], "mixed_fma_per_s": out["mixed_fma"],
-            "exp2_model": model, "copy_bytes_per_s": out["copy"],
-            "derived_valu_peak": VALU_PEAK, "fma_frac_of_derived": fma / VALU_PEAK}
+            out["add_steps"] = r2.value
+    return {"fp32_fma_per_s": out["fma"], "exp2_alone_per_s": out["exp2"],
+            "exp2_marginal_per_s": out["exp2_marginal"],
+            "exp2_cost_in_fma": out["fma"] / out["exp2_marginal"],
+            "fp32_add_per_s": 2.0 * out["add_steps"],
+            "copy_bytes_per_s": out["copy"],
+            "fwd_pairs_per_s": out["fwd_pairs"], "bwd_pairs_per_s": out["bwd_pairs"],
+            "derived_fp32_lane_ops_per_s": DERIVED_FP32_LANE_OPS,
+            "fma_frac_of_derived": out["fma"] / DERIVED_FP32_LANE_OPS}
 
 
-def valu_roofline(pairs, seconds, valu_per_pair, exp_per_pair, pk):
-    """Roofline object of an ALU-bound kernel: pairs x (VALU + exp2 weighted by its measured
-    cost) lane operations per launch over the launch time, against the derived 39.3 T ceiling."""
-    w = pk["exp2_cost_in_fma"]
-    if pk["exp2_model"] == "sum":
-        ops = pairs * (valu_per_pair + w * exp_per_pair)
+def valu_roofline(pairs, seconds, valu_per_pair, exp_per_pair, flops_per_pair, pk):
+    """Roofline object of the ALU-bound raster kernel: pairs x (FP32 VALU operations + exp2)
+    per launch over the launch time, against the rate the measured FP32 FMA and (marginal) exp2
+    rates give that mix, t = pairs (VALU / R_fma + exp2 / R_exp2); beside it the fraction of the
+    pair rate of the kernels' smallest per-pair sequences and the flop rate against the
+    published FP32 peak."""
+    r_fma, r_exp = pk["fp32_fma_per_s"], pk["exp2_marginal_per_s"]
+    t_floor = pairs * (valu_per_pair / r_fma + exp_per_pair / r_exp)
+    ops = pairs * (valu_per_pair + exp_per_pair)
+    if exp_per_pair == EXP_PER_PAIR_FIT:
+        t_pairs = pairs * (1.0 / pk["fwd_pairs_per_s"] + 1.0 / pk["bwd_pairs_per_s"])
     else:
-        ops = pairs * max(valu_per_pair, w * exp_per_pair)
-    achieved = ops / seconds
-    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-            "unit": "T FP32 lane-op/s", "frac": achieved / VALU_PEAK,
+        t_pairs = pairs / pk["fwd_pairs_per_s"]
+    tflops = pairs * flops_per_pair / seconds / 1e12
+    return {"bound": "alu", "achieved": ops / seconds / 1e12, "peak": ops / t_floor / 1e12,
+            "unit": "T op/s (FP32 VALU + exp2)", "frac": t_floor / seconds,
             "valu_per_pair": valu_per_pair, "exp2_per_pair": exp_per_pair,
-            "exp2_cost_in_fma": w, "exp2_model": pk["exp2_model"],
-            "frac_of_measured_fma_rate": achieved / pk["fma_lane_ops_per_s"],
-            "flops_per_s_fma_as_2": 2 * achieved / 1e12,
-            "frac_of_published_fp32": 2 * achieved / 1e12 / PUBLISHED_FP32_TFLOPS}
+            "frac_of_pair_sequences": t_pairs / seconds,
+            "tflops": tflops, "frac_of_published_fp32": tflops / PUBLISHED_FP32_TFLOPS}
 
 
-def render_graph_leg(P, torch, params, H, W, replays):
-    """Render FPS from a captured graph: the no-allocation render (gi_render_noalloc) recorded
-    once into a HIP graph on a side stream, replayed; every replay's image equals the eager
-    one (checked on the last)."""
+def render_graph_leg(P, torch, params, H, W, renders):
+    """Render FPS from a captured graph: 16 no-allocation renders (gi_render_noalloc) recorded
+    into one HIP graph on a side stream (a graph launch leaves the device idle for a few
+    microseconds at its boundary, so one render per launch would time that gap), replayed;
+    the last replay's image equals the eager one."""
     dev = params.device
+    tiles = ((H + 15) // 16) * ((W + 15) // 16)
+    if tiles > P._lib.GI_NOALLOC_MAX_TILES or params.shape[0] > P._lib.GI_NOALLOC_MAX_GAUSSIANS:
+        return None  # beyond the no-allocation render's limits
+    per = 16
     img = torch.empty(H, W, 3, device=dev)
     flags = torch.zeros(1, dtype=torch.int32, device=dev)
     P.render_noalloc(params, H, W, img, flags)  # eager: sets up the device's scratch
@@ -171,16 +189,18 @@ def render_graph_leg(P, torch, params, H, W, replays):
     side.wait_stream(torch.cuda.current_stream(dev))
     with torch.cuda.stream(side):
         with torch.cuda.graph(g, stream=side):
-            P.render_noalloc(params, H, W, img, flags)
+            for _ in range(per):
+                P.render_noalloc(params, H, W, img, flags)
     torch.cuda.current_stream(dev).wait_stream(side)
-    for _ in range(10):
+    for _ in range(2):
         g.replay()
     torch.cuda.synchronize()
+    replays = max(1, renders // per)
     t0 = time.perf_counter()
     for _ in range(replays):
         g.replay()
     torch.cuda.synchronize()
-    fps = replays / (time.perf_counter() - t0)
+    fps = replays * per / (time.perf_counter() - t0)
     if int(flags.item()) != 0 or not torch.equal(img, eager):
         raise RuntimeError("graph-replayed render differs from the eager one")
     del g
@@ -218,6 +238,35 @@ def long_fit_leg(P, torch, w, steps):
     return {"steps": steps, "fit_its": (steps - 1) / dt, "keys_step0": b0["keys"],
             "keys_end": b1["keys"], "pairs_step0": pairs0, "pairs_end": pairs1,
             "loss_step0": loss0, "loss_end": loss_end}
+
+
+def profile_run(P, torch, ctx, params0, target, H, W, k):
+    """k eager fit steps at zero learning rates (the parameters stay the initial ones, so every
+    step does the same work) and k renders; prints the stage times."""
+    hp = P.AdamConfig(lr_mu=0.0, lr_l=0.0, lr_c=0.0)
+    params = params0.clone()
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    step = torch.ones(1, dtype=torch.int32, device=params.device)
+    img = torch.empty(H, W, 3, device=params.device)
+    ctx.fit_step(params, m, v, target, step, hp)  # sizes the buffers
+    ctx.render(params, H, W, out=img)
+    ctx.set_option(P._lib.GI_OPT_SYNC, 0)
+    ctx.set_option(P._lib.GI_OPT_TIMING, 1)
+    ctx.timing(0, reset=True)
+    for _ in range(k):
+        ctx.fit_step(params, m, v, target, step, hp)
+    for _ in range(k):
+        ctx.render(params, H, W, out=img)
+    torch.cuda.synchronize()
+    out = {name: ctx.timing(st)[0] / max(ctx.timing(st)[1], 1) for name, st in
+           (("binning", P._lib.GI_STAGE_BINNING), ("raster_fit", P._lib.GI_STAGE_RASTER_FIT),
+            ("update", P._lib.GI_STAGE_UPDATE), ("raster_fwd", P._lib.GI_STAGE_RASTER_FWD))}
+    _, flags = ctx.query(clear=True)
+    if flags:
+        raise RuntimeError(f"flags {flags} raised during the profiled steps")
+    if not torch.equal(params, params0):
+        raise RuntimeError("zero learning rates changed the parameters")
+    print(json.dumps({"profile_steps": k, "stage_ms": out}), flush=True)
 
 
 def batch_inputs(images, which):
@@ -305,14 +354,14 @@ def raster_fit_digest():
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of the fused raster kernel instance `kernel` from the committed
-    counter record, if it was taken on the current source of the kernel (else None)."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of the fused raster kernel instance `kernel` on `workload` from the
+    committed counter record, if it was taken on the current source of the kernel (else None)."""
     try:
         rec = json.load(open(TRAFFIC_RECORD))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel") != kernel:
+    if rec.get("kernel") != kernel or rec.get("workload") != workload:
         return None
     return _traffic_if_current(rec)
 
@@ -334,16 +383,23 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 10}), flush=True)
 
 
+def apply_schedule(P, ctx, sched):
+    """Set a tuned schedule's knobs as explicit options of another context."""
+    if not sched:
+        return
+    ctx.set_option(P._lib.GI_OPT_BINNING, sched["binning"])
+    ctx.set_option(P._lib.GI_OPT_FWD_PIXELS, sched["fwd_pixels"])
+    ctx.set_option(P._lib.GI_OPT_SORT_BITS, sched["sort_bits"])
+    ctx.set_option(P._lib.GI_OPT_TILE_ORDER, sched["tile_order"])
+
+
 def rotation_scale_leg(P, torch, w, steps, tuned):
     """Fit it/s (graph replay) and render FPS of the same workload with rotation-scale records
     (s1, s2 with the Cholesky diagonals' distribution, theta uniform)."""
     import synth
     dev = torch.device("cuda", 0)
     ctx = P.Context(0, covariance="rotation_scale")
-    if tuned[0]:
-        ctx.set_option(P._lib.GI_OPT_FWD_PIXELS, tuned[0])
-    if tuned[1]:
-        ctx.set_option(P._lib.GI_OPT_SORT_BITS, tuned[1])
+    apply_schedule(P, ctx, tuned)
     p0 = torch.tensor(synth.gaussians_rs(w.n, w.height, w.width, w.param_seed, s_lo=w.l_lo,
                                          s_hi=w.l_hi, c_lo=0.0, c_hi=1.0), device=dev)
     target = torch.tensor(w.target(), device=dev)
@@ -576,7 +632,8 @@ def main():
         sys.exit(2)
     import numpy as np
 
-    binputs = batch_inputs(args.batch_images, args.batch_set) if args.batch_images > 0 else None
+    binputs = (batch_inputs(args.batch_images, args.batch_set)
+               if args.batch_images > 0 and not args.profile else None)
 
     import torch
 
@@ -590,11 +647,15 @@ def main():
     n_gauss = w.n
     H, W = w.height, w.width
     dev = torch.device("cuda", 0)
-    pk = peaks()
     params0 = torch.tensor(w.params(), device=dev)
     target = torch.tensor(w.target(), device=dev)
     ctx = P.Context(0)
     ctx.set_option(P._lib.GI_OPT_BINNING, args.binning)
+    if args.profile > 0:
+        profile_run(P, torch, ctx, params0, target, H, W, args.profile)
+        ctx.close()
+        return
+    pk = peaks()
 
     # exact work of this workload
     b = ctx.binning(params0, H, W)
@@ -603,7 +664,8 @@ def main():
     K = b["keys"]
 
     # ---- tune the kernel settings for this size class, then capture and replay fit steps
-    tuned = ctx.autotune(params0, target, reps=5) if not args.no_tune else (0, 0)
+    tuned = ctx.autotune(params0, target, reps=5) if not args.no_tune else None
+    px_used = (tuned or {}).get("fwd_pixels") or 4
     params = params0.clone()
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
@@ -613,18 +675,20 @@ def main():
     graph.launch(args.warmup)
     torch.cuda.synchronize()
     loss_start = float(loss.item())
-    # the K timed replays, each also bracketed by HIP events on the launch stream so that a
-    # one-off cost shows up as an outlier
+    # the K timed steps in launches of up to 16 (the library replays runs of 16 steps as one
+    # graph launch), each launch bracketed by HIP events on the launch stream so that a one-off
+    # cost shows up as an outlier (per-step times of each launch)
     st = torch.cuda.current_stream(dev)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    runs = [16] * (args.steps // 16) + ([args.steps % 16] if args.steps % 16 else [])
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(runs) + 1)]
     t0 = time.perf_counter()
     evs[0].record(st)
-    for i in range(args.steps):
-        graph.launch(1)
+    for i, k in enumerate(runs):
+        graph.launch(k)
         evs[i + 1].record(st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    rep = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    rep = np.array([evs[i].elapsed_time(evs[i + 1]) / k for i, k in enumerate(runs)])
     its = args.steps / dt
     loss_end = float(loss.item())
     keys_now, flags = graph.query(clear=True)
@@ -632,18 +696,23 @@ def main():
         raise RuntimeError(f"flags {flags} raised during the timed steps")
     graph.close()
 
-    # ---- dominant kernel: the fused raster kernel, timed with events on its stream (eager
-    # steps without host waits, same parameters as the timed region's end state)
-    n_prof = min(args.steps, 100)
-    for _ in range(5):  # waiting calls: the key buffers grow to this state's count (+25%)
-        ctx.fit_step(params, m, v, target, step)
+    # ---- dominant kernel: the fused raster kernel, timed with events on its stream over eager
+    # steps without host waits at zero learning rates on the initial parameters (every step the
+    # same work, the state `--profile` runs and the committed counters were taken on)
+    n_prof = min(max(args.steps, 20), 100)
+    hp0 = P.AdamConfig(lr_mu=0.0, lr_l=0.0, lr_c=0.0)
+    pz = params0.clone()
+    mz, vz = torch.zeros_like(pz), torch.zeros_like(pz)
+    sz = torch.ones(1, dtype=torch.int32, device=dev)
+    for _ in range(3):  # waiting calls: the key buffers fit this state
+        ctx.fit_step(pz, mz, vz, target, sz, hp0)
     torch.cuda.synchronize()
     ctx.query(clear=True)
     ctx.set_option(P._lib.GI_OPT_SYNC, 0)
     ctx.set_option(P._lib.GI_OPT_TIMING, 1)
     ctx.timing(0, reset=True)
     for _ in range(n_prof):
-        ctx.fit_step(params, m, v, target, step)
+        ctx.fit_step(pz, mz, vz, target, sz, hp0)
     torch.cuda.synchronize()
     fit_ms, fit_n = ctx.timing(P._lib.GI_STAGE_RASTER_FIT)
     bin_ms, bin_n = ctx.timing(P._lib.GI_STAGE_BINNING)
@@ -651,11 +720,13 @@ def main():
     _, flags = ctx.query(clear=True)
     if flags & (P._lib.GI_FLAG_KEY_OVERFLOW | P._lib.GI_FLAG_SCAN_STALL):
         raise RuntimeError(f"flags {flags} raised during the profiled steps")
-    b2 = ctx.binning(params, H, W)  # pairs of the state that was profiled
-    P_prof = pairs_from_ranges(b2["ranges"].cpu().numpy(), H, W)
+    if not torch.equal(pz, params0):
+        raise RuntimeError("zero learning rates changed the parameters")
+    P_prof = P_pairs  # the initial parameters' pairs
     ctx.set_option(P._lib.GI_OPT_SYNC, 0)
     fit_avg_s = fit_ms / fit_n / 1e3
-    roof = valu_roofline(P_prof, fit_avg_s, VALU_PER_PAIR_FIT, EXP_PER_PAIR_FIT, pk)
+    roof = valu_roofline(P_prof, fit_avg_s, VALU_PER_PAIR_FIT, EXP_PER_PAIR_FIT,
+                         FLOPS_PER_PAIR_FIT, pk)
 
     # ---- render FPS: eager non-waiting renders of the initial parameters, no stage timing
     ctx.set_option(P._lib.GI_OPT_TIMING, 0)
@@ -678,7 +749,7 @@ def main():
     rbin_ms, rbin_n = ctx.timing(P._lib.GI_STAGE_BINNING, reset=True)
     ctx.set_option(P._lib.GI_OPT_TIMING, 0)
     fwd_roof = valu_roofline(P_pairs, fwd_ms / fwd_n / 1e3, VALU_PER_PAIR_FWD, EXP_PER_PAIR_FWD,
-                             pk)
+                             FLOPS_PER_PAIR_FWD, pk)
     fps_graph = render_graph_leg(P, torch, params0, H, W, n_render)
     ctx.set_option(P._lib.GI_OPT_SYNC, 1)
     rs = None if args.no_rs else rotation_scale_leg(P, torch, w, min(max(args.steps, 100), 300),
@@ -709,18 +780,19 @@ def main():
                    "keys": K, "pairs": P_pairs, "fit_steps": "hip graph replay"},
         "render_fps": fps,
         "render_fps_graph": fps_graph,
-        "replay_ms": {"first": float(rep[0]), "min": float(rep.min()),
+        "replay_ms_per_step": {"first": float(rep[0]), "min": float(rep.min()),
                       "median": float(np.median(rep)), "max": float(rep.max())},
-        "tuned": {"fwd_pixels_per_lane": tuned[0], "radix_digit_bits": tuned[1]},
+        "tuned": tuned,
         "stage_ms": {"binning": bin_ms / max(bin_n, 1), "raster_fit": fit_ms / max(fit_n, 1),
                      "update": upd_ms / max(upd_n, 1),
                      "render_binning": rbin_ms / max(rbin_n, 1),
                      "raster_fwd": fwd_ms / max(fwd_n, 1)},
         "loss": {"after_warmup": loss_start, "after_timed": loss_end},
-        "roofline": dict(roof, traffic=measured_traffic(f"k_raster_fit<{tuned[0] or 4}>"),
-                         kernel=f"k_raster_fit<{tuned[0] or 4}>", pairs_per_launch=P_prof,
+        "roofline": dict(roof, traffic=measured_traffic(f"k_raster_fit<{px_used}>", w.name),
+                         kernel=f"k_raster_fit<{px_used}>", pairs_per_launch=P_prof,
                          avg_launch_ms=fit_ms / fit_n),
-        "render_roofline": dict(fwd_roof, kernel="k_raster_fwd<4>", pairs_per_launch=P_pairs,
+        "render_roofline": dict(fwd_roof, kernel=f"k_raster_fwd<{px_used}>",
+                                pairs_per_launch=P_pairs,
                                 avg_launch_ms=fwd_ms / fwd_n),
         "peaks": pk,
         "long_fit": lng,

@@ -103,9 +103,13 @@ enum {
                                  possible, else radix, 3 = row binning if possible, else radix */
     GI_OPT_TIMING = 5,        /* 1: bracket each stage of non-captured calls with HIP events on
                                  the call's stream (read with gi_timing); 0 (default): off */
-    GI_OPT_COVARIANCE = 6     /* how params[2..4] describe Sigma (Sec. 3.1): GI_COV_CHOLESKY
+    GI_OPT_COVARIANCE = 6,    /* how params[2..4] describe Sigma (Sec. 3.1): GI_COV_CHOLESKY
                                  (default) or GI_COV_ROTATION_SCALE; read by every later call,
                                  and fixed into a captured step when it is created */
+    GI_OPT_TILE_ORDER = 7     /* order in which the raster workgroups take the tiles: 0 = auto
+                                 (tuned, else 1), 1 = tile index, 2 = longest list first (one
+                                 small sorting kernel after the binning).  Never changes a
+                                 result: each tile's arithmetic is the same in any order */
 };
 
 /* Values of GI_OPT_COVARIANCE. */
@@ -142,17 +146,43 @@ int gi_query(gi_ctx *ctx, int64_t *last_keys, uint32_t *flags, int clear);
 /* Read an option (GI_OPT_*); for the tunable options 0 means "automatic". */
 int gi_get_option(gi_ctx *ctx, int option, int64_t *value);
 
+/* A schedule of the tunable knobs (0 = the knob's automatic rule): binning path (GI_OPT_BINNING
+ * values 1..3), forward pixels per lane (1, 2, 4), radix digit width (radix path only), tile
+ * order (GI_OPT_TILE_ORDER values 1, 2); ms_per_step is the fit step time it was chosen with. */
+typedef struct gi_schedule {
+    int32_t binning;
+    int32_t fwd_pixels;
+    int32_t sort_bits;
+    int32_t tile_order;
+    float ms_per_step;
+} gi_schedule;
+
 /* Autotuner: time fit steps of this workload (batch == NULL: the single image n x height x
- * width; else the batch) for each setting of the tunable knobs -- forward pixels per lane
- * (1, 2, 4) and radix digit width (automatic, 4, 6, 8, 11) -- on scratch copies of the
- * parameters (the caller's buffers are read, never written), `reps` timed steps per setting.
- * The fastest setting is kept in the context for the workload's size class (Gaussian count and
+ * width; else the batch) under the tunable knobs, one knob at a time in this order, each
+ * starting from the best of the knobs before it: the binning path (one pass when the tiles
+ * number at most 2048, row binning when the images allow it, radix always), the radix digit
+ * width (automatic, 4, 6, 8, 11; radix path only), forward pixels per lane (1, 2, 4) and the
+ * tile order (index, longest list first).  Runs on scratch copies of the parameters (the
+ * caller's buffers are read, never written) with zero learning rates, so every timed step does
+ * the same work: one untimed step, then `reps` timed steps per trial.  After three untimed
+ * trials of the default schedule (clocks and caches warm up), each candidate is timed in turn
+ * with the best schedule so far (candidate, best, candidate, best; the faster trial of each
+ * counts) and replaces it only when faster by more than 1.5%.  The fastest schedule is kept in the context for the workload's size class (covariance form, Gaussian count and
  * pixel count, each rounded to a power of sqrt(2)) and used by later calls whose options are
- * automatic.  Allocates scratch memory and synchronises; never call it during graph capture.
- * Writes the chosen settings to *fwd_pixels and *sort_bits (either may be NULL). */
+ * automatic; every schedule gives the same results bit for bit.  Allocates scratch memory and
+ * synchronises; never call it during graph capture.  *chosen (may be NULL) receives it. */
 int gi_autotune(gi_ctx *ctx, const float *params_dev, const float *target_dev, int64_t n,
                 int32_t height, int32_t width, const gi_batch *batch, int32_t reps,
-                void *stream, int32_t *fwd_pixels, int32_t *sort_bits);
+                void *stream, gi_schedule *chosen);
+
+/* Write the context's tuned schedules to a text file (one JSON object per line, with the
+ * device's architecture name), replacing it; GI_ERR_INVALID_ARG if it cannot be written. */
+int gi_autotune_save(gi_ctx *ctx, const char *path);
+/* Read schedules written by gi_autotune_save for this device's architecture into the context
+ * (entries for other architectures are skipped; an entry replaces the context's schedule of
+ * its size class).  *loaded (may be NULL) receives the number of entries taken.
+ * GI_ERR_INVALID_ARG if the file cannot be read or a line for this architecture is malformed. */
+int gi_autotune_load(gi_ctx *ctx, const char *path, int32_t *loaded);
 
 /* Wait for the timed events, then report the summed milliseconds and the number of timed
  * launches of `stage` (GI_STAGE_*) since the last reset; reset = 1 clears the totals. */
@@ -374,7 +404,9 @@ int gi_fit_graph_create_qat(gi_ctx *ctx, float *params_dev, float *m_dev, float 
                             const gi_adam *hp, const gi_qat *q, int32_t *step_dev,
                             float *image_out_dev, float *loss_out_dev, void *stream,
                             gi_graph **out);
-/* Replay the captured step `steps` times on `stream`. */
+/* Replay the captured step `steps` times on `stream`.  Runs of 16 steps go out as one launch of
+ * a graph that holds the step 16 times (a graph launch leaves the device idle for a few
+ * microseconds at its boundary); the work done is the same. */
 int gi_fit_graph_launch(gi_graph *graph, int32_t steps, void *stream);
 /* gi_query on the graph's private workspace (waits for the device). */
 int gi_fit_graph_query(gi_graph *graph, int64_t *last_keys, uint32_t *flags, int clear);

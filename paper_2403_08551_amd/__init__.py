@@ -13,6 +13,7 @@ module only passes device pointers, sizes and the current torch stream.  There i
 from __future__ import annotations
 
 import ctypes
+import os
 import threading
 from dataclasses import dataclass
 
@@ -266,9 +267,10 @@ class Context:
         self._raise(_lib.lib().gi_get_option(self._h, option, ctypes.byref(v)), "gi_get_option")
         return v.value
 
-    def autotune(self, params, target, batch: Batch | None = None, reps: int = 5):
-        """Time the tunable settings on fit steps of this workload (scratch copies) and keep the
-        fastest for its size class; returns (pixels per lane, radix digit width, 0 = auto)."""
+    def autotune(self, params, target, batch: Batch | None = None, reps: int = 5) -> dict:
+        """Time the tunable knobs on fit steps of this workload (scratch copies, see
+        gi_autotune) and keep the fastest schedule for its size class; returns it as a dict
+        (binning, fwd_pixels, sort_bits, tile_order, ms_per_step)."""
         if batch is None:
             h, w = target.shape[0], target.shape[1]
             n = params.shape[0]
@@ -277,13 +279,23 @@ class Context:
             n = batch.n_gauss
         _check(params, "params", self.device, (n, 8))
         _check(target, "target", self.device)
-        px = ctypes.c_int32()
-        bits = ctypes.c_int32()
+        sc = _lib.gi_schedule()
         self._raise(_lib.lib().gi_autotune(
             self._h, _ptr(params), _ptr(target), n, h, w,
             ctypes.byref(batch.c) if batch is not None else None, reps, _stream(self.device),
-            ctypes.byref(px), ctypes.byref(bits)), "gi_autotune")
-        return px.value, bits.value
+            ctypes.byref(sc)), "gi_autotune")
+        return {name: getattr(sc, name) for name, _ in sc._fields_}
+
+    def autotune_save(self, path: str):
+        """Write the tuned schedules to `path` (gi_autotune_save)."""
+        self._raise(_lib.lib().gi_autotune_save(self._h, os.fsencode(path)), "gi_autotune_save")
+
+    def autotune_load(self, path: str) -> int:
+        """Read tuned schedules of this device's architecture from `path`; returns how many."""
+        k = ctypes.c_int32()
+        self._raise(_lib.lib().gi_autotune_load(self._h, os.fsencode(path), ctypes.byref(k)),
+                    "gi_autotune_load")
+        return k.value
 
     def timing(self, stage: int, reset: bool = False):
         """(total milliseconds, launches) of a stage timed with GI_OPT_TIMING."""

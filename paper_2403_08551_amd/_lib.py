@@ -28,6 +28,7 @@ GI_OPT_SORT_BITS = 2
 GI_OPT_FWD_PIXELS = 3
 GI_OPT_BINNING = 4
 GI_OPT_TIMING = 5
+GI_OPT_TILE_ORDER = 7
 GI_OPT_COVARIANCE = 6
 
 GI_BLEND_SUM = 1
@@ -57,6 +58,7 @@ EXPORTS = (
     "gi_render_opacity", "gi_grad_opacity", "gi_fit_step_opacity", "gi_fit_step_recipe",
     "gi_recipe_params", "gi_qat_init", "gi_fit_step_qat", "gi_qat_encode",
     "gi_fit_graph_create_recipe", "gi_fit_graph_create_qat", "gi_render_noalloc",
+    "gi_autotune_save", "gi_autotune_load",
 )
 
 
@@ -64,6 +66,12 @@ class gi_adam(ctypes.Structure):
     _fields_ = [("lr_mu", ctypes.c_float), ("lr_l", ctypes.c_float), ("lr_c", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("l_min", ctypes.c_float)]
+
+
+class gi_schedule(ctypes.Structure):
+    _fields_ = [("binning", ctypes.c_int32), ("fwd_pixels", ctypes.c_int32),
+                ("sort_bits", ctypes.c_int32), ("tile_order", ctypes.c_int32),
+                ("ms_per_step", ctypes.c_float)]
 
 
 class gi_batch(ctypes.Structure):
@@ -150,7 +158,9 @@ def lib():
             "gi_sort_pairs": ([P, P, P, P, P, I64, I32, P], ctypes.c_int),
             "gi_get_option": ([P, ctypes.c_int, ctypes.POINTER(I64)], ctypes.c_int),
             "gi_autotune": ([P, P, P, I64, I32, I32, ctypes.POINTER(gi_batch), I32, P,
-                             ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
+                             ctypes.POINTER(gi_schedule)], ctypes.c_int),
+            "gi_autotune_save": ([P, ctypes.c_char_p], ctypes.c_int),
+            "gi_autotune_load": ([P, ctypes.c_char_p, ctypes.POINTER(I32)], ctypes.c_int),
             "gi_fit_step_opacity": ([P, P, P, P, P, P, P, P, I64, I32, I32, I32,
                                      ctypes.POINTER(gi_adam), P, P, P, P], ctypes.c_int),
             "gi_fit_step_recipe": ([P, P, P, P, I64, I32, I32, ctypes.POINTER(gi_adan), P, P, P,

@@ -349,7 +349,15 @@ struct RasterArgs {
     const uint2 *ranges;
     int64_t n_tiles;
     ImgTable tab;
+    const uint32_t *order = nullptr;  // workgroup w rasterises tile order[w]; null: tile w
 };
+
+// Tile order for the raster kernels, longest list first (a counting sort by list length, one
+// workgroup; lengths over TILE_ORDER_BINS - 1 share the first bin).  The order only changes
+// which workgroup takes which tile, never a tile's arithmetic, so results are the same bits.
+constexpr int TILE_ORDER_BINS = 4096;
+hipError_t launch_tile_order(const uint2 *ranges, int64_t n_tiles, uint32_t *order,
+                             hipStream_t s);
 
 hipError_t launch_raster_fwd(const RasterArgs &a, float *image, int px_per_lane, hipStream_t s);
 hipError_t launch_raster_bwd(const RasterArgs &a, const float *dl_dimage, float *part,

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/gi.h"
@@ -17,12 +18,22 @@
 
 using namespace gi;
 
+// One schedule of the tunable knobs (0 = the automatic rule for that knob).
+struct Schedule {
+    int binning = 0;  // GI_OPT_BINNING value: 1 radix, 2 one pass, 3 rows
+    int px = 0;       // forward pixels per lane
+    int digit = 0;    // radix digit width
+    int order = 0;    // 1 tile index, 2 longest list first
+    float ms = 0.f;   // measured time per fit step
+};
+
 struct gi_ctx {
     int device = 0;
     int sync = 1;
     int sort_bits = 0;
     int fwd_px = 0;
     int binning = 0;
+    int order = 0;           // GI_OPT_TILE_ORDER: 0 auto, 1 tile index, 2 longest list first
     int cov = COV_CHOLESKY;  // GI_OPT_COVARIANCE
     const CodecArgs *codec = nullptr;  // set for the duration of a codec render
     const float *opac_cur = nullptr;   // set for the duration of an opacity render / grad
@@ -79,6 +90,7 @@ struct gi_ctx {
     // per tile
     uint2 *ranges = nullptr;
     float *loss_part = nullptr;
+    uint32_t *tile_order = nullptr;  // longest-first order of the raster workgroups
     // scalars
     DevState *state = nullptr;
     unsigned long long *pinned = nullptr;
@@ -99,6 +111,7 @@ struct gi_ctx {
     int64_t tmp_cap = 0;
     hipStream_t capture_stream = nullptr;
     std::string err;
+    std::string arch;  // the device's architecture name (autotune cache entries carry it)
     // stage timing (GI_OPT_TIMING)
     int timing = 0;
     struct Pending {
@@ -109,14 +122,20 @@ struct gi_ctx {
     std::vector<hipEvent_t> event_pool;
     double stage_ms[GI_STAGE_COUNT] = {0, 0, 0, 0, 0};
     int64_t stage_n[GI_STAGE_COUNT] = {0, 0, 0, 0, 0};
-    // autotuned settings per size class: (Gaussian class, pixel class) -> (pixels/lane, digit)
-    std::map<std::pair<int, int>, std::pair<int, int>> tuned;
+    // autotuned schedules per size class (covariance form, Gaussian class, pixel class)
+    std::map<std::tuple<int, int, int>, Schedule> tuned;
 };
 
+// A captured step, and the same step captured GRAPH_RUN times in a row: each graph launch
+// leaves the device idle for several microseconds at its boundary (8.7 us measured at 768x512,
+// about 7% of a step), so runs of steps are replayed GRAPH_RUN steps per launch.
+constexpr int GRAPH_RUN = 16;
 struct gi_graph {
     gi_ctx *ctx = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_run = nullptr;
+    hipGraphExec_t exec_run = nullptr;
 };
 
 namespace {
@@ -225,6 +244,7 @@ int ensure_tiles(gi_ctx *ctx, int64_t t) {
     CK(hipDeviceSynchronize());
     CK(grow(&ctx->ranges, c));
     CK(grow(&ctx->loss_part, c));
+    CK(grow(&ctx->tile_order, c));
     ctx->cap_t = c;
     return GI_OK;
 }
@@ -417,22 +437,39 @@ ImgTable single_table(int32_t H, int32_t W) {
     return t;
 }
 
-std::pair<int, int> size_class(int64_t n, int64_t n_pix) {
+std::tuple<int, int, int> size_class(const gi_ctx *ctx, int64_t n, int64_t n_pix) {
     auto cls = [](int64_t v) { return (int)std::lround(2.0 * std::log2((double)std::max<int64_t>(v, 1))); };
-    return {cls(n), cls(n_pix)};
+    return {ctx->cov, cls(n), cls(n_pix)};
+}
+
+const Schedule *tuned_for(const gi_ctx *ctx, int64_t n, int64_t n_pix) {
+    auto it = ctx->tuned.find(size_class(ctx, n, n_pix));
+    return it != ctx->tuned.end() ? &it->second : nullptr;
 }
 
 int pick_px(gi_ctx *ctx, int64_t n, int64_t n_pix) {
     if (ctx->fwd_px) return ctx->fwd_px;
-    auto it = ctx->tuned.find(size_class(n, n_pix));
-    return it != ctx->tuned.end() ? it->second.first : 4;
+    const Schedule *t = tuned_for(ctx, n, n_pix);
+    return t && t->px ? t->px : 4;
 }
 
 int pick_digit(gi_ctx *ctx, int64_t n, int64_t n_pix, int key_bits, int64_t keys) {
     if (ctx->sort_bits) return ctx->sort_bits;
-    auto it = ctx->tuned.find(size_class(n, n_pix));
-    if (it != ctx->tuned.end() && it->second.second) return it->second.second;
+    const Schedule *t = tuned_for(ctx, n, n_pix);
+    if (t && t->digit) return t->digit;
     return auto_digit_bits(key_bits, keys);
+}
+
+int pick_binning(gi_ctx *ctx, int64_t n, int64_t n_pix) {
+    if (ctx->binning) return ctx->binning;
+    const Schedule *t = tuned_for(ctx, n, n_pix);
+    return t ? t->binning : 0;
+}
+
+int pick_order(gi_ctx *ctx, int64_t n, int64_t n_pix) {
+    if (ctx->order) return ctx->order;
+    const Schedule *t = tuned_for(ctx, n, n_pix);
+    return t && t->order ? t->order : 1;
 }
 
 int64_t table_pixels(const ImgTable &tab, int64_t n_tiles) {
@@ -646,9 +683,10 @@ int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab
     // 3: rows.  Rows need every image at most ROW_MAX_TW tiles wide, else radix.
     const bool rows_ok = n > 0 && tab.max_tw >= 1 && tab.max_tw <= ROW_MAX_TW && tab.rows > 0 &&
                          (tab.B == 1 ? tab.rows : tab.row_win) <= ROW_WIN_MAX;
-    if ((ctx->binning == 0 || ctx->binning == 2) && n > 0 && n_tiles <= FUSED_MAX_TILES)
+    const int path = pick_binning(ctx, n, table_pixels(tab, n_tiles));
+    if ((path == 0 || path == 2) && n > 0 && n_tiles <= FUSED_MAX_TILES)
         return run_binning_fused(ctx, params, n, tab, n_tiles, s, bound, which);
-    if ((ctx->binning == 0 || ctx->binning == 3) && rows_ok)
+    if ((path == 0 || path == 3) && rows_ok)
         return run_binning_rows(ctx, params, n, tab, n_tiles, s, bound, which);
     ctx->off_cur = ctx->off;
     BinBuffers b = bin_buffers(ctx, params, n, n_tiles);
@@ -682,6 +720,16 @@ int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab
 }
 
 
+// The raster workgroups' tile order for this call: longest list first when chosen (one small
+// kernel after the binning), else tile index order (no table).
+hipError_t set_order(gi_ctx *ctx, RasterArgs &a, int64_t n, const ImgTable &tab, int64_t n_tiles,
+                     hipStream_t s) {
+    a.order = nullptr;
+    if (pick_order(ctx, n, table_pixels(tab, n_tiles)) != 2 || n_tiles <= 1) return hipSuccess;
+    a.order = ctx->tile_order;
+    return launch_tile_order(ctx->ranges, n_tiles, ctx->tile_order, s);
+}
+
 // Marks a render for the duration of its binning: the scatters then skip the key slots, which
 // only the adjoint reads.
 struct RenderScope {
@@ -702,6 +750,7 @@ int do_render(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab, 
     if (rc != GI_OK) return rc;
     RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FWD);
+    CK(set_order(ctx, a, n, tab, n_tiles, s));
     CK(launch_raster_fwd(a, image, pick_px(ctx, n, table_pixels(tab, n_tiles)), s));
     tm.stop();
     return GI_OK;
@@ -715,6 +764,7 @@ int do_grad(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab, in
     if (rc != GI_OK) return rc;
     RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
     StageTimer tm(ctx, s, GI_STAGE_RASTER_BWD);
+    CK(set_order(ctx, a, n, tab, n_tiles, s));
     CK(launch_raster_bwd(a, dl, ctx->part, s));
     tm.stop();
     UpdateArgs u{params, nullptr, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k,
@@ -734,6 +784,7 @@ int do_fit(gi_ctx *ctx, float *params, float *m, float *v, const float *target, 
     if (rc != GI_OK) return rc;
     RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
+    CK(set_order(ctx, a, n, tab, n_tiles, s));
     CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
                          pick_px(ctx, n, table_pixels(tab, n_tiles)), step, s));
     tm.stop();
@@ -774,6 +825,7 @@ int do_render_opacity(gi_ctx *ctx, const float *params, const float *opacity, in
     if (rc != GI_OK) return rc;
     RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FWD);
+    CK(set_order(ctx, a, n, tab, n_tiles, s));
     if (blend == BLEND_ALPHA)
         CK(launch_alpha_fwd(a, ctx->rec_o, image, s));
     else
@@ -793,6 +845,7 @@ int do_grad_opacity(gi_ctx *ctx, const float *params, const float *opacity, int6
     RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
     float *part = blend == BLEND_ALPHA ? ctx->part_a : ctx->part;
     StageTimer tm(ctx, s, GI_STAGE_RASTER_BWD);
+    CK(set_order(ctx, a, n, tab, n_tiles, s));
     if (blend == BLEND_ALPHA)
         CK(launch_alpha_bwd(a, ctx->rec_o, dl, part, s));
     else
@@ -818,6 +871,7 @@ int do_fit_opacity(gi_ctx *ctx, float *params, float *opacity, float *m, float *
     RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
     float *part = blend == BLEND_ALPHA ? ctx->part_a : ctx->part;
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
+    CK(set_order(ctx, a, n, tab, n_tiles, s));
     if (blend == BLEND_ALPHA)
         CK(launch_alpha_fit(a, ctx->rec_o, target, part, image_out, ctx->loss_part, step, s));
     else
@@ -848,6 +902,7 @@ int do_fit_recipe(gi_ctx *ctx, float *raw, float *state, const float *target, in
     if (rc != GI_OK) return rc;
     RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
+    CK(set_order(ctx, a, n, tab, n_tiles, s));
     CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
                          pick_px(ctx, n, table_pixels(tab, n_tiles)), step, s));
     tm.stop();
@@ -902,6 +957,7 @@ int do_fit_qat(gi_ctx *ctx, float *params, float *m, float *v, const float *targ
     if (rc != GI_OK) return rc;
     RasterArgs a{ctx->rec, ctx->slot, ctx->ranges, n_tiles, tab};
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
+    CK(set_order(ctx, a, n, tab, n_tiles, s));
     CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
                          pick_px(ctx, n, table_pixels(tab, n_tiles)), step, s));
     tm.stop();
@@ -966,6 +1022,7 @@ int gi_create(gi_ctx **out, int device) {
     DeviceGuard g(device);
     gi_ctx *ctx = new gi_ctx();
     ctx->device = device;
+    ctx->arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
     hipError_t e = hipMalloc((void **)&ctx->state, sizeof(DevState));
     if (e == hipSuccess) e = hipMemset(ctx->state, 0, sizeof(DevState));
     if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->pinned, sizeof(DevState));
@@ -989,7 +1046,7 @@ int gi_destroy(gi_ctx *ctx) {
                     ctx->tmp_v, ctx->fscan, ctx->fstatus, ctx->rec_o, ctx->part_a,
                     ctx->qpart, ctx->qscratch, ctx->rhist, ctx->bwin, ctx->rinfo,
                     ctx->chunk_row, ctx->rscan, ctx->row_base, ctx->row_tiles, ctx->row_seg,
-                    ctx->row_fb};
+                    ctx->row_fb, ctx->tile_order};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -1031,6 +1088,10 @@ int gi_set_option(gi_ctx *ctx, int option, int64_t value) {
                 return GI_ERR_INVALID_ARG;
             ctx->cov = (int)value;
             return GI_OK;
+        case GI_OPT_TILE_ORDER:
+            if (value < 0 || value > 2) return GI_ERR_INVALID_ARG;
+            ctx->order = (int)value;
+            return GI_OK;
         default:
             return GI_ERR_INVALID_ARG;
     }
@@ -1071,39 +1132,39 @@ int gi_get_option(gi_ctx *ctx, int option, int64_t *value) {
         case GI_OPT_BINNING: *value = ctx->binning; return GI_OK;
         case GI_OPT_TIMING: *value = ctx->timing; return GI_OK;
         case GI_OPT_COVARIANCE: *value = ctx->cov; return GI_OK;
+        case GI_OPT_TILE_ORDER: *value = ctx->order; return GI_OK;
         default: return GI_ERR_INVALID_ARG;
     }
 }
 
 int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n, int32_t H,
-                int32_t W, const gi_batch *batch, int32_t reps, void *stream,
-                int32_t *fwd_pixels, int32_t *sort_bits) {
+                int32_t W, const gi_batch *batch, int32_t reps, void *stream, gi_schedule *chosen) {
     if (!ctx || !target || reps < 1 || reps > 1000) return GI_ERR_INVALID_ARG;
     DeviceGuard g(ctx->device);
     hipStream_t s = (hipStream_t)stream;
     ImgTable tab;
-    int64_t T, n_pix;
+    int64_t T;
     if (batch) {
         if (check_batch(batch) != GI_OK) return GI_ERR_INVALID_ARG;
         n = batch->gauss_off_host[batch->count];
-        int64_t N;
+        int64_t N, n_pix;
         int rc = upload_batch(ctx, batch, &tab, &T, &N, &n_pix);
         if (rc != GI_OK) return rc;
     } else {
         if (check_single(n, H, W) != GI_OK) return GI_ERR_INVALID_ARG;
         tab = single_table(H, W);
         T = (int64_t)tab.TW * ((H + TILE - 1) / TILE);
-        n_pix = (int64_t)H * W;
     }
     if (n > 0 && (!params || !aligned16(params))) return GI_ERR_INVALID_ARG;
-    const std::pair<int, int> key = size_class(n, table_pixels(tab, T));
+    const auto key = size_class(ctx, n, table_pixels(tab, T));
     // scratch state: the caller's parameters are copied, never written
     float *p = nullptr, *m = nullptr, *v = nullptr;
     int32_t *step = nullptr;
     const size_t bytes = sizeof(float) * 8 * (size_t)std::max<int64_t>(n, 1);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = GI_OK;
-    struct Saved { int sync, px, bits, timing; } sv{ctx->sync, ctx->fwd_px, ctx->sort_bits, ctx->timing};
+    struct Saved { int sync, px, bits, binning, order, timing; } sv{
+        ctx->sync, ctx->fwd_px, ctx->sort_bits, ctx->binning, ctx->order, ctx->timing};
     auto cleanup = [&]() {
         if (p) (void)hipFree(p);
         if (m) (void)hipFree(m);
@@ -1111,7 +1172,8 @@ int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n
         if (step) (void)hipFree(step);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
-        ctx->sync = sv.sync; ctx->fwd_px = sv.px; ctx->sort_bits = sv.bits; ctx->timing = sv.timing;
+        ctx->sync = sv.sync; ctx->fwd_px = sv.px; ctx->sort_bits = sv.bits;
+        ctx->binning = sv.binning; ctx->order = sv.order; ctx->timing = sv.timing;
     };
     hipError_t e = hipMalloc((void **)&p, bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&m, bytes);
@@ -1124,46 +1186,108 @@ int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n
         return hip_fail(ctx, e, "gi_autotune scratch");
     }
     gi_adam hp{0.f, 0.f, 0.f, 0.9f, 0.999f, 1e-8f, 0.f};  // zero rates: the state stays fixed
-    const int pxs[3] = {1, 2, 4};
-    const int bits[5] = {0, 4, 6, 8, 11};
-    float best = 1e30f;
-    int best_px = 4, best_bits = 0;
     ctx->timing = 0;
-    // one synchronous pass sizes the workspace, then steps do not wait on the host
-    ctx->sync = 1;
-    int64_t bound;
-    int which;
-    rc = run_binning(ctx, params, n, tab, T, s, &bound, &which);
-    if (rc == GI_OK) rc = ensure_keys(ctx, bound + bound / 4 + 4096);
-    ctx->sync = 0;
-    for (int bi = 0; bi < 5 && rc == GI_OK; ++bi) {
-        for (int pi = 0; pi < 3 && rc == GI_OK; ++pi) {
-            ctx->fwd_px = pxs[pi];
-            ctx->sort_bits = bits[bi];
-            if (bits[bi] > key_bits_for(T) + 3) continue;
-            e = hipMemcpyAsync(p, params, bytes, hipMemcpyDeviceToDevice, s);
-            if (e == hipSuccess) e = hipMemsetAsync(m, 0, bytes, s);
-            if (e == hipSuccess) e = hipMemsetAsync(v, 0, bytes, s);
-            const int32_t one = 1;
-            if (e == hipSuccess) e = hipMemcpyAsync(step, &one, sizeof(one), hipMemcpyHostToDevice, s);
-            if (e != hipSuccess) { rc = hip_fail(ctx, e, "gi_autotune copy"); break; }
-            rc = do_fit(ctx, p, m, v, target, n, tab, T, &hp, step, nullptr, nullptr, s);
-            if (rc != GI_OK) break;
-            e = hipEventRecord(e0, s);
-            for (int r = 0; r < reps && rc == GI_OK && e == hipSuccess; ++r)
-                rc = do_fit(ctx, p, m, v, target, n, tab, T, &hp, step, nullptr, nullptr, s);
-            if (rc != GI_OK) break;
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) { rc = hip_fail(ctx, e, "gi_autotune timing"); break; }
-            if (ms < best) {
-                best = ms;
-                best_px = pxs[pi];
-                best_bits = bits[bi];
-            }
+    // Time `reps` fit steps (after one untimed step) under schedule sc, every knob explicit.
+    auto trial = [&](const Schedule &sc, float *ms) -> int {
+        ctx->binning = sc.binning;
+        ctx->fwd_px = sc.px;
+        ctx->sort_bits = sc.digit;
+        ctx->order = sc.order;
+        // one synchronous binning pass sizes this path's buffers; then no step waits
+        ctx->sync = 1;
+        int64_t bound;
+        int which;
+        int r = run_binning(ctx, params, n, tab, T, s, &bound, &which);
+        if (r == GI_OK) r = ensure_keys(ctx, bound + bound / 4 + 4096);
+        ctx->sync = 0;
+        if (r != GI_OK) return r;
+        hipError_t he = hipMemcpyAsync(p, params, bytes, hipMemcpyDeviceToDevice, s);
+        if (he == hipSuccess) he = hipMemsetAsync(m, 0, bytes, s);
+        if (he == hipSuccess) he = hipMemsetAsync(v, 0, bytes, s);
+        const int32_t one = 1;
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(step, &one, sizeof(one), hipMemcpyHostToDevice, s);
+        if (he != hipSuccess) return hip_fail(ctx, he, "gi_autotune copy");
+        r = do_fit(ctx, p, m, v, target, n, tab, T, &hp, step, nullptr, nullptr, s);
+        if (r != GI_OK) return r;
+        he = hipEventRecord(e0, s);
+        for (int k = 0; k < reps && r == GI_OK && he == hipSuccess; ++k)
+            r = do_fit(ctx, p, m, v, target, n, tab, T, &hp, step, nullptr, nullptr, s);
+        if (r != GI_OK) return r;
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+        if (he != hipSuccess) return hip_fail(ctx, he, "gi_autotune timing");
+        *ms = t / (float)reps;
+        return GI_OK;
+    };
+    // the binning paths this workload allows (the same tests as run_binning)
+    const bool fused_ok = n > 0 && T <= FUSED_MAX_TILES;
+    const bool rows_ok = n > 0 && tab.max_tw >= 1 && tab.max_tw <= ROW_MAX_TW && tab.rows > 0 &&
+                         (tab.B == 1 ? tab.rows : tab.row_win) <= ROW_WIN_MAX;
+    std::vector<int> paths;
+    if (fused_ok) paths.push_back(2);
+    if (rows_ok) paths.push_back(3);
+    paths.push_back(1);
+    // Warm the clocks and caches with the default schedule (three untimed trials), then try
+    // the knobs one at a time against the incumbent, the two timed in turn (candidate,
+    // incumbent, candidate, incumbent; the faster run of each counts) so that a drift of the
+    // clocks during the search affects both alike.  A candidate replaces the incumbent only
+    // when it is faster by more than TUNE_MARGIN: step times repeat to about a percent, so
+    // closer calls keep the incumbent (the default comes first).
+    constexpr float TUNE_MARGIN = 0.015f;
+    Schedule best;
+    best.binning = paths[0];
+    best.px = 4;
+    best.order = 1;
+    {
+        float junk = 0.f;
+        for (int k = 0; k < 3 && rc == GI_OK; ++k) rc = trial(best, &junk);
+    }
+    auto consider = [&](Schedule sc) -> int {
+        float c1 = 0.f, c2 = 0.f, i1 = 0.f, i2 = 0.f;
+        int r = trial(sc, &c1);
+        if (r == GI_OK) r = trial(best, &i1);
+        if (r == GI_OK) r = trial(sc, &c2);
+        if (r == GI_OK) r = trial(best, &i2);
+        if (r != GI_OK) return r;
+        const float c = std::min(c1, c2), inc = std::min(i1, i2);
+        if (c < inc * (1.f - TUNE_MARGIN)) {
+            best = sc;
+            best.ms = c;
+        } else {
+            best.ms = inc;
         }
+        return GI_OK;
+    };
+    for (size_t i = 1; i < paths.size() && rc == GI_OK; ++i) {
+        Schedule sc = best;
+        sc.binning = paths[i];
+        rc = consider(sc);
+    }
+    if (rc == GI_OK && best.binning == 1) {
+        const int digits[4] = {4, 6, 8, 11};
+        const Schedule base = best;
+        for (int i = 0; i < 4 && rc == GI_OK; ++i) {
+            if (digits[i] > key_bits_for(T) + 3) continue;
+            Schedule sc = base;
+            sc.digit = digits[i];
+            rc = consider(sc);
+        }
+    }
+    if (rc == GI_OK) {
+        const Schedule base = best;
+        for (int px : {1, 2}) {
+            Schedule sc = base;
+            sc.px = px;
+            if ((rc = consider(sc)) != GI_OK) break;
+        }
+    }
+    if (rc == GI_OK) {
+        Schedule sc = best;
+        sc.order = 2;
+        rc = consider(sc);
     }
     if (rc == GI_OK) {
         e = hipStreamSynchronize(s);
@@ -1171,10 +1295,75 @@ int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n
     }
     cleanup();
     if (rc != GI_OK) return rc;
-    ctx->tuned[key] = {best_px, best_bits};
-    if (fwd_pixels) *fwd_pixels = best_px;
-    if (sort_bits) *sort_bits = best_bits;
-    (void)n_pix;
+    ctx->tuned[key] = best;
+    if (chosen) *chosen = gi_schedule{best.binning, best.px, best.digit, best.order, best.ms};
+    return GI_OK;
+}
+
+int gi_autotune_save(gi_ctx *ctx, const char *path) {
+    if (!ctx || !path) return GI_ERR_INVALID_ARG;
+    FILE *f = fopen(path, "w");
+    if (!f) return GI_ERR_INVALID_ARG;
+    bool ok = true;
+    for (const auto &kv : ctx->tuned) {
+        const Schedule &sc = kv.second;
+        ok = ok && fprintf(f,
+                           "{\"arch\": \"%s\", \"cov\": %d, \"n_class\": %d, \"pix_class\": %d, "
+                           "\"binning\": %d, \"fwd_pixels\": %d, \"sort_bits\": %d, "
+                           "\"tile_order\": %d, \"ms_per_step\": %.6f}\n",
+                           ctx->arch.c_str(), std::get<0>(kv.first), std::get<1>(kv.first),
+                           std::get<2>(kv.first), sc.binning, sc.px, sc.digit, sc.order,
+                           (double)sc.ms) > 0;
+    }
+    ok = (fclose(f) == 0) && ok;
+    return ok ? GI_OK : GI_ERR_INVALID_ARG;
+}
+
+int gi_autotune_load(gi_ctx *ctx, const char *path, int32_t *loaded) {
+    if (loaded) *loaded = 0;
+    if (!ctx || !path) return GI_ERR_INVALID_ARG;
+    FILE *f = fopen(path, "r");
+    if (!f) return GI_ERR_INVALID_ARG;
+    char line[512];
+    int rc = GI_OK, count = 0;
+    std::vector<std::pair<std::tuple<int, int, int>, Schedule>> got;
+    while (fgets(line, sizeof(line), f)) {
+        char arch[64];
+        if (sscanf(line, " {\"arch\": \"%63[^\"]\"", arch) != 1) {
+            bool blank = true;
+            for (const char *c = line; *c; ++c) blank = blank && (*c == ' ' || *c == '\n' || *c == '\t' || *c == '\r');
+            if (!blank) rc = GI_ERR_INVALID_ARG;
+            continue;
+        }
+        if (ctx->arch != arch) continue;
+        int cov, nc, pc, bin, px, bits, order;
+        float ms;
+        const int k = sscanf(line,
+                             " {\"arch\": \"%*[^\"]\", \"cov\": %d, \"n_class\": %d, \"pix_class\": "
+                             "%d, \"binning\": %d, \"fwd_pixels\": %d, \"sort_bits\": %d, "
+                             "\"tile_order\": %d, \"ms_per_step\": %f}",
+                             &cov, &nc, &pc, &bin, &px, &bits, &order, &ms);
+        if (k != 8 || (cov != GI_COV_CHOLESKY && cov != GI_COV_ROTATION_SCALE) || bin < 0 ||
+            bin > 3 || (px != 0 && px != 1 && px != 2 && px != 4) || bits < 0 || bits > 11 ||
+            order < 0 || order > 2) {
+            rc = GI_ERR_INVALID_ARG;
+            continue;
+        }
+        Schedule sc;
+        sc.binning = bin;
+        sc.px = px;
+        sc.digit = bits;
+        sc.order = order;
+        sc.ms = ms;
+        got.push_back({std::make_tuple(cov, nc, pc), sc});
+    }
+    fclose(f);
+    if (rc != GI_OK) return rc;
+    for (const auto &kv : got) {
+        ctx->tuned[kv.first] = kv.second;
+        ++count;
+    }
+    if (loaded) *loaded = count;
     return GI_OK;
 }
 
@@ -1466,6 +1655,7 @@ int capture_step(gi_ctx *user, const float *params, int64_t n, int32_t H, int32_
     ctx->sort_bits = user->sort_bits;
     ctx->fwd_px = user->fwd_px;
     ctx->binning = user->binning;
+    ctx->order = user->order;
     ctx->cov = user->cov;
     ctx->tuned = user->tuned;
     gi_graph *gr = new gi_graph();
@@ -1473,6 +1663,8 @@ int capture_step(gi_ctx *user, const float *params, int64_t n, int32_t H, int32_
     auto fail = [&](int code) {
         if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
         if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        if (gr->exec_run) (void)hipGraphExecDestroy(gr->exec_run);
+        if (gr->graph_run) (void)hipGraphDestroy(gr->graph_run);
         delete gr;
         user->err = ctx->err;
         gi_destroy(ctx);
@@ -1502,18 +1694,23 @@ int capture_step(gi_ctx *user, const float *params, int64_t n, int32_t H, int32_
     if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamSynchronize"));
     ctx->sync = 0;
     hipStream_t cs = ctx->capture_stream;
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamBeginCapture"));
-    rc = step(ctx, tab, T, cs);
-    e = hipStreamEndCapture(cs, &gr->graph);
-    if (rc != GI_OK) return fail(rc);
-    if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamEndCapture"));
-    e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipGraphInstantiate"));
-    // move the executable graph to the device now, not at its first launch (no work runs)
-    e = hipGraphUpload(gr->exec, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipGraphUpload"));
+    // one step, then GRAPH_RUN steps in a row
+    for (int run = 0; run < 2; ++run) {
+        hipGraph_t *gp = run ? &gr->graph_run : &gr->graph;
+        hipGraphExec_t *xp = run ? &gr->exec_run : &gr->exec;
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamBeginCapture"));
+        for (int k = 0; k < (run ? GRAPH_RUN : 1) && rc == GI_OK; ++k) rc = step(ctx, tab, T, cs);
+        e = hipStreamEndCapture(cs, gp);
+        if (rc != GI_OK) return fail(rc);
+        if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamEndCapture"));
+        e = hipGraphInstantiate(xp, *gp, nullptr, nullptr, 0);
+        if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipGraphInstantiate"));
+        // move the executable graph to the device now, not at its first launch (no work runs)
+        e = hipGraphUpload(*xp, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipGraphUpload"));
+    }
     *out = gr;
     return GI_OK;
 }
@@ -1606,7 +1803,10 @@ int gi_fit_graph_launch(gi_graph *gr, int32_t steps, void *stream) {
     if (!gr || steps < 0) return GI_ERR_INVALID_ARG;
     gi_ctx *ctx = gr->ctx;
     DeviceGuard g(ctx->device);
-    for (int32_t i = 0; i < steps; ++i) CK(hipGraphLaunch(gr->exec, (hipStream_t)stream));
+    int32_t left = steps;
+    for (; left >= GRAPH_RUN; left -= GRAPH_RUN)
+        CK(hipGraphLaunch(gr->exec_run, (hipStream_t)stream));
+    for (; left > 0; --left) CK(hipGraphLaunch(gr->exec, (hipStream_t)stream));
     return GI_OK;
 }
 
@@ -1622,6 +1822,8 @@ int gi_fit_graph_destroy(gi_graph *gr) {
         (void)hipDeviceSynchronize();
         if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
         if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        if (gr->exec_run) (void)hipGraphExecDestroy(gr->exec_run);
+        if (gr->graph_run) (void)hipGraphDestroy(gr->graph_run);
     }
     gi_destroy(gr->ctx);
     delete gr;

@@ -99,9 +99,13 @@ __device__ __forceinline__ void fwd_tile(const float4 *__restrict__ rec, uint2 r
 #pragma unroll
         for (int k = 0; k < 8; ++k) ga[k] = rec[2 * (int64_t)i + k];
     }
-    for (uint32_t g = 0; g < ng;) {
+    // up to two groups per trip and one fold at its end: the loop has a single exit, so the
+    // totals stay in the same registers from trip to trip (an exit between the two halves had
+    // made the compiler copy all of them every trip)
+    for (uint32_t g = 0; g < ng; g += 2) {
         __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): group g is in ga
-        if (g + 1 < ng) {
+        const bool two = g + 1 < ng;
+        if (two) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) gb[k] = rec[2 * (int64_t)(i + 4) + k];
         }
@@ -109,19 +113,16 @@ __device__ __forceinline__ void fwd_tile(const float4 *__restrict__ rec, uint2 r
 #pragma unroll
         for (int k = 1; k < 4; ++k) fwd_eval<PX>(ga[2 * k], ga[2 * k + 1], px, py0, of, part);
         i += 4;
-        if (++g >= ng) {
-            fold();
-            break;
-        }
-        __builtin_amdgcn_s_waitcnt(0xc07f);  // group g is in gb
-        if (g + 1 < ng) {
+        if (two) {
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // group g + 1 is in gb
+            if (g + 2 < ng) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) ga[k] = rec[2 * (int64_t)(i + 4) + k];
-        }
+                for (int k = 0; k < 8; ++k) ga[k] = rec[2 * (int64_t)(i + 4) + k];
+            }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) fwd_eval<PX>(gb[2 * k], gb[2 * k + 1], px, py0, of, part);
-        i += 4;
-        ++g;
+            for (int k = 0; k < 4; ++k) fwd_eval<PX>(gb[2 * k], gb[2 * k + 1], px, py0, of, part);
+            i += 4;
+        }
         fold();
     }
     if (i < r.y) {
@@ -137,6 +138,10 @@ __device__ __forceinline__ void fwd_tile(const float4 *__restrict__ rec, uint2 r
 // Gaussian (neighbouring LDS words, so the two broadcast reads hit different banks) and add
 // their sums with one DPP step at the end.  Splitting each Gaussian in two halves the idle
 // lanes of a tile's last round (lists are a few hundred long, rounds are NT lanes wide).
+// Per pixel, with w = exp(-sigma) <dL/dC, c'>: the colour sums D += e g, then w, sum w u2 and
+// sum w u2^2, each product formed per pixel (no difference of larger sums, which would lose
+// the relative accuracy of a single term).  The column's sum of w is <D, c'> (the colour sums
+// are needed anyway), not a per-pixel sum.
 template <int NT>
 __device__ inline void bwd_tile(const float4 *__restrict__ rec, const uint32_t *__restrict__ slot,
                                 uint2 r, const TileInfo &ti, const float4 *sg,
@@ -157,9 +162,9 @@ __device__ inline void bwd_tile(const float4 *__restrict__ rec, const uint32_t *
 #pragma unroll
         for (int rr = 0; rr < TILE; ++rr) dy[rr] = (y0 + (float)rr) - A.y;
         float C0 = 0.f, C1 = 0.f, C2 = 0.f, P1 = 0.f, P2 = 0.f, Q11 = 0.f, Q12 = 0.f, Q22 = 0.f;
+        float dx = x0 - A.x;  // this lane's column 2k + par: dx advances by 2 per column
         for (int k = 0; k < TILE / 2; ++k) {
             const int cc = 2 * k + par;
-            const float dx = (x0 + (float)(2 * k)) - A.x;
             const float u1 = A.z * dx;
             const float u1s = u1 * u1;
             const float t = B.x * dx;
@@ -177,7 +182,7 @@ __device__ inline void bwd_tile(const float4 *__restrict__ rec, const uint32_t *
                 WU2 += wu2;
                 WU22 = fmaf(wu2, u2, WU22);
             }
-            // the column's sum of -dL/dsigma from its colour sums: sum_r e <g, c'> = <sum_r e g, c'>
+            // the column's sum of w from its colour sums: sum_r e <g, c'> = <sum_r e g, c'>
             const float Wc = fmaf(B.w, D2, fmaf(B.z, D1, B.y * D0));
             C0 += D0;
             C1 += D1;
@@ -187,6 +192,7 @@ __device__ inline void bwd_tile(const float4 *__restrict__ rec, const uint32_t *
             Q12 = fmaf(u1, WU2, Q12);
             P2 += WU2;
             Q22 += WU22;
+            dx += 2.0f;
         }
         // even lane + odd lane (quad_perm [1, 0, 3, 2])
         C0 = pair_add(C0);
@@ -259,9 +265,10 @@ __device__ inline float3 fwd_colour(const float *qs, int p) {
 template <int PX>
 __global__ __launch_bounds__(256) void k_raster_fwd(const float4 *__restrict__ rec,
                                                          const uint2 *__restrict__ ranges,
-                                                         ImgTable tab, float *__restrict__ image) {
+                                                         ImgTable tab, float *__restrict__ image,
+    const uint32_t *__restrict__ order) {
     __shared__ float qs[PARTS * 3 * TILE_PX];
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     fwd_parts<PX>(rec, ranges[tile], ti, qs);
     __syncthreads();
@@ -280,9 +287,10 @@ __global__ __launch_bounds__(BWD_T) void k_raster_bwd(const float4 *__restrict__
                                                       const uint32_t *__restrict__ slot,
                                                       const uint2 *__restrict__ ranges,
                                                       ImgTable tab, const float *__restrict__ G,
-                                                      float4 *__restrict__ part) {
+                                                      float4 *__restrict__ part,
+    const uint32_t *__restrict__ order) {
     __shared__ float4 sg[TILE_PX];
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     for (int p = threadIdx.x; p < TILE_PX; p += BWD_T) {
         const int x = ti.tx * TILE + (p & 15), y = ti.ty * TILE + (p >> 4);
@@ -299,10 +307,12 @@ __global__ __launch_bounds__(BWD_T) void k_raster_bwd(const float4 *__restrict__
 
 // Fit step for one tile: forward, residual and dL/dC = 2 (C - T) / (3 H W) into LDS, per-tile
 // sum of squared residuals, then the adjoint.
-// At most 96 VGPRs (five workgroups per CU): measured faster than the unconstrained 113 (four
-// per CU) and than 66 (six per CU).
+// Register budget for at least four workgroups per CU: the compiler then takes 102 VGPRs (five
+// workgroups per CU), measured faster than the 67 it takes under a five-workgroup bound
+// (107.5 -> 102.4 us at 768x512 / 70k, the same work: the extra registers buy scheduling, not
+// occupancy, which alone was measured slower at four, three and two workgroups).
 template <int PX>
-__global__ __launch_bounds__(256, 5) void k_raster_fit(const float4 *__restrict__ rec,
+__global__ __launch_bounds__(256, 4) void k_raster_fit(const float4 *__restrict__ rec,
                                                          const uint32_t *__restrict__ slot,
                                                          const uint2 *__restrict__ ranges,
                                                          ImgTable tab,
@@ -310,12 +320,13 @@ __global__ __launch_bounds__(256, 5) void k_raster_fit(const float4 *__restrict_
                                                          float4 *__restrict__ part,
                                                          float *__restrict__ image_out,
                                                          float *__restrict__ loss_part,
-                                                         int32_t *__restrict__ step_inc) {
+                                                         int32_t *__restrict__ step_inc,
+    const uint32_t *__restrict__ order) {
     constexpr int NT = 256;
     __shared__ float qs[PARTS * 3 * TILE_PX];
     __shared__ float4 sg[TILE_PX];
     __shared__ float red[NT / 64];
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     const uint2 r = ranges[tile];
     fwd_parts<PX>(rec, r, ti, qs);
@@ -436,10 +447,11 @@ __device__ inline void alpha_compose(const float4 *xs, int q, int pix, float &Tb
 __global__ __launch_bounds__(256) void k_alpha_fwd(const float4 *__restrict__ rec,
                                                    const float *__restrict__ rec_o,
                                                    const uint2 *__restrict__ ranges, ImgTable tab,
-                                                   float *__restrict__ image) {
+                                                   float *__restrict__ image,
+    const uint32_t *__restrict__ order) {
     constexpr int PX = 4;
     __shared__ float4 xs[ALPHA_PARTS * TILE_PX];
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int col = lane & 15, row = lane >> 4;
@@ -591,12 +603,13 @@ __global__ __launch_bounds__(256) void k_alpha_bwd(const float4 *__restrict__ re
                                                    const uint32_t *__restrict__ slot,
                                                    const uint2 *__restrict__ ranges, ImgTable tab,
                                                    const float *__restrict__ G,
-                                                   float4 *__restrict__ part) {
+                                                   float4 *__restrict__ part,
+    const uint32_t *__restrict__ order) {
     constexpr int PX = 4;
     __shared__ __align__(16) float red[ALPHA_PARTS * ALPHA_RED];
     static_assert(ALPHA_PARTS * ALPHA_RED >= 4 * ALPHA_PARTS * TILE_PX, "the part sums fit");
     float4 *xs = reinterpret_cast<float4 *>(red);
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     const uint2 r = ranges[tile];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
@@ -646,12 +659,13 @@ __global__ __launch_bounds__(256) void k_alpha_fit(const float4 *__restrict__ re
                                                    float4 *__restrict__ part,
                                                    float *__restrict__ image_out,
                                                    float *__restrict__ loss_part,
-                                                   int32_t *__restrict__ step_inc) {
+                                                   int32_t *__restrict__ step_inc,
+    const uint32_t *__restrict__ order) {
     constexpr int PX = 4;
     __shared__ __align__(16) float red[ALPHA_PARTS * ALPHA_RED];
     static_assert(ALPHA_PARTS * ALPHA_RED >= 4 * ALPHA_PARTS * TILE_PX, "the part sums fit");
     float4 *xs = reinterpret_cast<float4 *>(red);
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     const uint2 r = ranges[tile];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
@@ -1297,13 +1311,68 @@ __global__ __launch_bounds__(256) void k_finish(const float *__restrict__ loss_p
 
 }  // namespace
 
+// Longest list first: each tile goes to the bin of its list length (descending), the bins'
+// starts come from one exclusive scan in LDS, and each tile takes the next place of its bin
+// (an LDS atomic: within a bin the order is arbitrary, which only changes the dispatch order).
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2 *__restrict__ ranges,
+                                                     int64_t T, uint32_t *__restrict__ order) {
+    __shared__ uint32_t bin[TILE_ORDER_BINS];
+    __shared__ uint32_t wsum[1024 / 64];
+    for (int b = threadIdx.x; b < TILE_ORDER_BINS; b += 1024) bin[b] = 0u;
+    __syncthreads();
+    auto key = [&](int64_t t) {
+        const uint2 r = ranges[t];
+        const uint32_t len = r.y - r.x;
+        return (uint32_t)(TILE_ORDER_BINS - 1) - (len < (uint32_t)(TILE_ORDER_BINS - 1)
+                                                      ? len : (uint32_t)(TILE_ORDER_BINS - 1));
+    };
+    for (int64_t t = threadIdx.x; t < T; t += 1024) atomicAdd(&bin[key(t)], 1u);
+    __syncthreads();
+    // exclusive scan of the bins: each thread owns 4 consecutive bins
+    constexpr int PER = TILE_ORDER_BINS / 1024;
+    uint32_t v[PER], run = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        v[j] = bin[threadIdx.x * PER + j];
+        run += v[j];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    uint32_t at = base + inc - run;
+    __syncthreads();  // every bin has been read
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        bin[threadIdx.x * PER + j] = at;
+        at += v[j];
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < T; t += 1024)
+        order[atomicAdd(&bin[key(t)], 1u)] = (uint32_t)t;
+}
+
+hipError_t launch_tile_order(const uint2 *ranges, int64_t n_tiles, uint32_t *order,
+                             hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, n_tiles, order);
+    return hipGetLastError();
+}
+
 hipError_t launch_raster_fwd(const RasterArgs &a, float *image, int px, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
     const float4 *rec = reinterpret_cast<const float4 *>(a.rec);
     switch (px) {
-        case 1: hipLaunchKernelGGL(k_raster_fwd<1>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image); break;
-        case 4: hipLaunchKernelGGL(k_raster_fwd<4>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image); break;
-        default: hipLaunchKernelGGL(k_raster_fwd<2>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image); break;
+        case 1: hipLaunchKernelGGL(k_raster_fwd<1>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image, a.order); break;
+        case 4: hipLaunchKernelGGL(k_raster_fwd<4>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image, a.order); break;
+        default: hipLaunchKernelGGL(k_raster_fwd<2>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image, a.order); break;
     }
     return hipGetLastError();
 }
@@ -1312,7 +1381,7 @@ hipError_t launch_raster_bwd(const RasterArgs &a, const float *dl, float *part, 
     if (a.n_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_raster_bwd, dim3((unsigned)a.n_tiles), dim3(BWD_T), 0, s,
                        reinterpret_cast<const float4 *>(a.rec), a.slot, a.ranges, a.tab, dl,
-                       reinterpret_cast<float4 *>(part));
+                       reinterpret_cast<float4 *>(part), a.order);
     return hipGetLastError();
 }
 
@@ -1323,9 +1392,9 @@ hipError_t launch_raster_fit(const RasterArgs &a, const float *target, float *pa
     const float4 *rec = reinterpret_cast<const float4 *>(a.rec);
     float4 *p4 = reinterpret_cast<float4 *>(part);
     switch (px) {
-        case 1: hipLaunchKernelGGL(k_raster_fit<1>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc); break;
-        case 4: hipLaunchKernelGGL(k_raster_fit<4>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc); break;
-        default: hipLaunchKernelGGL(k_raster_fit<2>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc); break;
+        case 1: hipLaunchKernelGGL(k_raster_fit<1>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc, a.order); break;
+        case 4: hipLaunchKernelGGL(k_raster_fit<4>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc, a.order); break;
+        default: hipLaunchKernelGGL(k_raster_fit<2>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc, a.order); break;
     }
     return hipGetLastError();
 }
@@ -1333,7 +1402,7 @@ hipError_t launch_raster_fit(const RasterArgs &a, const float *target, float *pa
 hipError_t launch_alpha_fwd(const RasterArgs &a, const float *rec_o, float *image, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_alpha_fwd, dim3((unsigned)a.n_tiles), dim3(256), 0, s,
-                       reinterpret_cast<const float4 *>(a.rec), rec_o, a.ranges, a.tab, image);
+                       reinterpret_cast<const float4 *>(a.rec), rec_o, a.ranges, a.tab, image, a.order);
     return hipGetLastError();
 }
 
@@ -1342,7 +1411,7 @@ hipError_t launch_alpha_bwd(const RasterArgs &a, const float *rec_o, const float
     if (a.n_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_alpha_bwd, dim3((unsigned)a.n_tiles), dim3(256), 0, s,
                        reinterpret_cast<const float4 *>(a.rec), rec_o, a.slot, a.ranges, a.tab,
-                       dl, reinterpret_cast<float4 *>(part12));
+                       dl, reinterpret_cast<float4 *>(part12), a.order);
     return hipGetLastError();
 }
 
@@ -1412,7 +1481,7 @@ hipError_t launch_alpha_fit(const RasterArgs &a, const float *rec_o, const float
     hipLaunchKernelGGL(k_alpha_fit, dim3((unsigned)a.n_tiles), dim3(256), 0, s,
                        reinterpret_cast<const float4 *>(a.rec), rec_o, a.slot, a.ranges, a.tab,
                        target, reinterpret_cast<float4 *>(part12), image_out, loss_part,
-                       step_inc);
+                       step_inc, a.order);
     return hipGetLastError();
 }
 

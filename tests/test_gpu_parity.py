@@ -461,6 +461,39 @@ def test_graph_replay_matches_eager_steps(gi, binning):
     assert int(host(sb)[0]) == 5
 
 
+def test_graph_runs_of_sixteen_steps_match_eager_steps(gi):
+    # 37 steps in launches of 37 and 3: runs of 16 go out as one launch of the 16-step graph,
+    # the rest one step per launch; the result equals 40 eager steps bit for bit
+    w = synth.plain_256()
+    p0, T = w.params(), dev(w.target())
+    pa, pb = dev(p0), dev(p0)
+    ma, va, mb, vb = (torch.zeros_like(pa) for _ in range(4))
+    sa = torch.ones(1, dtype=torch.int32, device="cuda")
+    sb = torch.ones(1, dtype=torch.int32, device="cuda")
+    loss_a = torch.empty(1, device="cuda")
+    loss_b = torch.empty(1, device="cuda")
+    for _ in range(40):
+        gi.fit_step(pa, ma, va, T, sa, loss_out=loss_a)
+    import paper_2403_08551_amd as P
+    g = P.Context(0)
+    graph = g.fit_graph(pb, mb, vb, T, sb, loss_out=loss_b)
+    try:
+        graph.launch(37)
+        torch.cuda.synchronize()
+        _ = torch.zeros(10, device="cuda").sum().item()
+        graph.launch(3)
+        torch.cuda.synchronize()
+        assert graph.query()[1] == 0
+    finally:
+        graph.close()
+        g.close()
+    np.testing.assert_array_equal(host(pb), host(pa))
+    np.testing.assert_array_equal(host(mb), host(ma))
+    np.testing.assert_array_equal(host(vb), host(va))
+    np.testing.assert_array_equal(host(loss_b), host(loss_a))
+    assert int(host(sb)[0]) == 41
+
+
 def test_graph_launch_starts_from_the_parameters_as_they_are(gi):
     # every launch of a captured step bins the parameters as they are then, so parameters
     # changed between launches are the ones fitted
@@ -665,11 +698,119 @@ def test_autotune_reads_but_never_writes_and_keeps_results_exact(gi):
     T = dev(w.target())
     before = host(p).copy()
     ref_img = host(gi.render(p, w.height, w.width))
-    px, bits = gi.autotune(p, T, reps=2)
-    assert px in (1, 2, 4) and bits in (0, 4, 6, 8, 11)
+    sc = gi.autotune(p, T, reps=2)
+    assert sc["binning"] in (1, 2, 3) and sc["fwd_pixels"] in (1, 2, 4)
+    assert sc["sort_bits"] in (0, 4, 6, 8, 11) and sc["tile_order"] in (1, 2)
+    assert sc["ms_per_step"] > 0
     np.testing.assert_array_equal(host(p), before)
-    assert gi.get_option(P._lib.GI_OPT_FWD_PIXELS) == 0  # explicit options untouched
+    for opt in (P._lib.GI_OPT_FWD_PIXELS, P._lib.GI_OPT_BINNING, P._lib.GI_OPT_TILE_ORDER):
+        assert gi.get_option(opt) == 0  # explicit options untouched
     np.testing.assert_array_equal(host(gi.render(p, w.height, w.width)), ref_img)
+
+
+def _schedules(tiles, rows_ok=True):
+    """Every schedule the autotuner can choose for a workload with this many tiles."""
+    out = []
+    paths = ([2] if tiles <= 2048 else []) + ([3] if rows_ok else []) + [1]
+    for b in paths:
+        for px in (1, 2, 4):
+            for order in (1, 2):
+                out.append((b, px, 0, order))
+        if b == 1:
+            out += [(1, 4, d, 2) for d in (4, 6, 8, 11)]
+    return out
+
+
+def _run_schedule(P, sched, p0, T, h, w, G, batch=None):
+    ctx = P.Context(0)
+    try:
+        b, px, digit, order = sched
+        ctx.set_option(P._lib.GI_OPT_BINNING, b)
+        ctx.set_option(P._lib.GI_OPT_FWD_PIXELS, px)
+        ctx.set_option(P._lib.GI_OPT_SORT_BITS, digit)
+        ctx.set_option(P._lib.GI_OPT_TILE_ORDER, order)
+        pd = dev(p0)
+        if batch is None:
+            img = host(ctx.render(pd, h, w))
+            g = host(ctx.grad(pd, h, w, dev(G)))
+        else:
+            img = host(ctx.render_batched(pd, batch))
+            g = host(ctx.grad_batched(pd, batch, dev(G)))
+        m, v = torch.zeros_like(pd), torch.zeros_like(pd)
+        st = torch.ones(1, dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            if batch is None:
+                ctx.fit_step(pd, m, v, T, st)
+            else:
+                ctx.fit_step_batched(pd, m, v, T, batch, st)
+        assert ctx.query()[1] == 0
+        return img, g, host(pd), host(m), host(v)
+    finally:
+        ctx.close()
+
+
+def test_every_schedule_gives_the_same_bits_single_image():
+    # each knob the autotuner sets (binning path, radix digit, pixels per lane, tile order)
+    # leaves the render, the gradient and two fit steps bit for bit as the default schedule
+    import paper_2403_08551_amd as P
+    w = synth.plain_256()
+    p0, T = w.params(), dev(w.target())
+    G = synth.upstream_gradient(w.height, w.width, 3)
+    want = _run_schedule(P, (0, 0, 0, 0), p0, T, w.height, w.width, G)
+    for sched in _schedules(256):
+        got = _run_schedule(P, sched, p0, T, w.height, w.width, G)
+        for a, b, what in zip(got, want, ("image", "gradient", "params", "m", "v")):
+            np.testing.assert_array_equal(a, b, err_msg=f"{what} under schedule {sched}")
+
+
+def test_every_schedule_gives_the_same_bits_batch():
+    import paper_2403_08551_amd as P
+    dims = [(96, 160), (200, 72), (33, 257)]
+    ps = [synth.gaussians(300 + 100 * i, h, w, seed=40 + i) for i, (h, w) in enumerate(dims)]
+    off = np.concatenate([[0], np.cumsum([p.shape[0] for p in ps])])
+    batch = P.Batch([h for h, _ in dims], [w for _, w in dims], off)
+    p0 = np.concatenate(ps)
+    T = dev(np.full((sum(h * w for h, w in dims), 3), 0.5, np.float32))
+    G = np.concatenate([synth.upstream_gradient(h, w, 60 + i).reshape(-1, 3)
+                        for i, (h, w) in enumerate(dims)])
+    tiles = sum(((h + 15) // 16) * ((w + 15) // 16) for h, w in dims)
+    want = _run_schedule(P, (0, 0, 0, 0), p0, T, 0, 0, G, batch=batch)
+    for sched in _schedules(tiles):
+        got = _run_schedule(P, sched, p0, T, 0, 0, G, batch=batch)
+        for a, b, what in zip(got, want, ("images", "gradient", "params", "m", "v")):
+            np.testing.assert_array_equal(a, b, err_msg=f"{what} under schedule {sched}")
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    import paper_2403_08551_amd as P
+    w = synth.plain_256()
+    p, T = dev(w.params()), dev(w.target())
+    a = P.Context(0)
+    b = P.Context(0)
+    try:
+        sc = a.autotune(p, T, reps=1)
+        path = str(tmp_path / "tune.jsonl")
+        a.autotune_save(path)
+        lines = open(path).read().splitlines()
+        assert len(lines) == 1 and '"arch": "gfx950"' in lines[0]
+        assert f'"binning": {sc["binning"]}' in lines[0]
+        # an entry of another architecture is skipped; the file's own entry is taken
+        with open(path, "a") as f:
+            f.write(lines[0].replace('"arch": "gfx950"', '"arch": "gfx000"') + "\n")
+        assert b.autotune_load(path) == 1
+        # b now renders with the loaded schedule: same bits as a's tuned render
+        np.testing.assert_array_equal(host(b.render(p, w.height, w.width)),
+                                      host(a.render(p, w.height, w.width)))
+        bad = str(tmp_path / "bad.jsonl")
+        with open(bad, "w") as f:
+            f.write(lines[0].replace('"fwd_pixels": ', '"fwd_pixels": 3') + "\n")
+        with pytest.raises(P.GiError):
+            b.autotune_load(bad)
+        with pytest.raises(P.GiError):
+            b.autotune_load(str(tmp_path / "missing.jsonl"))
+    finally:
+        a.close()
+        b.close()
 
 
 def test_graphs_survive_later_growth_of_the_context(gi):
