@@ -13,7 +13,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cpu_ref.c")
-SO = os.path.join(HERE, "liboracle_cpu.so")
+# GI_ORACLE_SO: load another build of the same source (the sanitizer test's instrumented one)
+SO = os.environ.get("GI_ORACLE_SO") or os.path.join(HERE, "liboracle_cpu.so")
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -33,7 +34,8 @@ def build() -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(SO) or os.path.getmtime(SO) < os.path.getmtime(SRC):
+        if not os.environ.get("GI_ORACLE_SO") and (not os.path.exists(SO) or
+                                                   os.path.getmtime(SO) < os.path.getmtime(SRC)):
             build()
         L = ctypes.CDLL(SO)
         L.or_tile_rects.argtypes = [_P, _I64, _I32, _I32, _P, _P]

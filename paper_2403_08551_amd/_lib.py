@@ -8,7 +8,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgi.so")
+# GI_LIB: load another build of the library (for example one with host-side sanitizers)
+LIB_PATH = os.environ.get("GI_LIB") or os.path.join(HERE, "libgi.so")
 
 GI_OK = 0
 GI_ERR_INVALID_ARG = -1
