@@ -165,8 +165,13 @@ __device__ inline uint32_t project_one(const RecordSrc &src, int64_t i,
     int32_t TW, TH, IH, IW;
     uint32_t tb, rb = 0;
     if (tab.B == 1) {
-        TW = tab.TW; TH = (tab.H + TILE - 1) / TILE; tb = 0;
-        IH = tab.H; IW = tab.W;
+        // taken through readfirstlane so that they are values, not loads: the compiler had
+        // merged this branch and the table read below into one flat load through a pointer
+        // select (the kernel argument copied to private memory)
+        TW = __builtin_amdgcn_readfirstlane(tab.TW);
+        IH = __builtin_amdgcn_readfirstlane(tab.H);
+        IW = __builtin_amdgcn_readfirstlane(tab.W);
+        TH = (IH + TILE - 1) / TILE; tb = 0;
     } else {
         int32_t b = upper_index(tab.gauss_off, tab.B, (uint32_t)i);
         if (img_out) *img_out = b;

@@ -160,21 +160,32 @@ __device__ __forceinline__ void fwd_tile_lds(const float4 *__restrict__ rec, uin
         }
     };
     const uint32_t L = r.y - r.x;
-    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 stage = (uint32_t)lane < 2 * (L < CH ? L : CH) ? rec[2 * (int64_t)r.x + lane] : zero;
+    if (L == 0) return;
+    // The 16-byte words of records [first, first + cnt), cnt >= 1: lane l reads word l and lanes
+    // past the end read the last word again (in bounds; their LDS words are never read).  The
+    // load is unconditional on purpose: a load under a lane condition had been compiled into a
+    // flat load through a pointer select (a zero kept in private memory), and a flat load counts
+    // against the LDS wait counter too, so every LDS wait of a chunk waited for the prefetch.
+    auto chunk_word = [&](uint32_t first, uint32_t cnt) {
+        const uint32_t last = 2 * cnt - 1;
+        return rec[2 * (int64_t)first + ((uint32_t)lane < last ? (uint32_t)lane : last)];
+    };
+    float4 stage = chunk_word(r.x, L < CH ? L : CH);
     for (uint32_t c0 = 0; c0 < L; c0 += CH) {
         const uint32_t n = L - c0 < CH ? L - c0 : CH;
         lbuf[lane] = stage;
-        if (c0 + CH < L) {
-            const uint32_t nn = L - c0 - CH < CH ? L - c0 - CH : CH;
-            stage = (uint32_t)lane < 2 * nn ? rec[2 * (int64_t)(r.x + c0 + CH) + lane] : zero;
-        }
+        if (c0 + CH < L) stage = chunk_word(r.x + c0 + CH, L - c0 - CH < CH ? L - c0 - CH : CH);
         uint32_t k = 0;
         for (; k + 8 <= n; k += 8) {
             fwd_eval<PX, true>(lbuf[2 * k], lbuf[2 * k + 1], px, py0, of, part);
 #pragma unroll
-            for (uint32_t e = 1; e < 8; ++e)
+            for (uint32_t e = 1; e < 8; ++e) {
+                // scheduling fence between the two halves of the group (same arithmetic): left
+                // free, the compiler issues all 16 LDS reads first and clusters the exp2s, which
+                // measured 1.5% slower in the fit kernel
+                if (e == 4) __builtin_amdgcn_sched_barrier(0);
                 fwd_eval<PX>(lbuf[2 * (k + e)], lbuf[2 * (k + e) + 1], px, py0, of, part);
+            }
             fold();
         }
         if (k + 4 <= n) {
@@ -369,10 +380,10 @@ __global__ __launch_bounds__(BWD_T) void k_raster_bwd(const float4 *__restrict__
 
 // Fit step for one tile: forward, residual and dL/dC = 2 (C - T) / (3 H W) into LDS, per-tile
 // sum of squared residuals, then the adjoint.
-// Register budget for at least four workgroups per CU: the compiler then takes 102 VGPRs (five
-// workgroups per CU), measured faster than the 67 it takes under a five-workgroup bound
-// (107.5 -> 102.4 us at 768x512 / 70k, the same work: the extra registers buy scheduling, not
-// occupancy, which alone was measured slower at four, three and two workgroups).
+// The second bound is waves per SIMD: at least four (four workgroups per CU), so the compiler
+// may take up to 128 VGPRs.  Bounded at five waves it took 94 and measured 7% slower at
+// 768x512 / 70k (111.5 against 104 us): registers buy scheduling here more than a fifth
+// workgroup buys latency hiding.
 template <int PX>
 __global__ __launch_bounds__(256, 4) void k_raster_fit(const float4 *__restrict__ rec,
                                                          const uint32_t *__restrict__ slot,
