@@ -169,6 +169,19 @@ def valu_roofline(pairs, seconds, valu_per_pair, exp_per_pair, flops_per_pair, p
             "tflops": tflops, "frac_of_published_fp32": tflops / PUBLISHED_FP32_TFLOPS}
 
 
+def issued_fraction(executed, pairs, seconds, pk):
+    """The executed instructions (SQ counters) priced at the measured rates, over the launch
+    time: how close the kernel issues what it runs to the measured peak rates (frac above prices
+    the algorithmic count instead, so frac / frac_issued is the share of executed work that is
+    algorithmic)."""
+    if executed is None:
+        return {"frac_issued": None}
+    valu, exp2 = executed
+    t = pairs * (valu / pk["fp32_fma_per_s"] + exp2 / pk["exp2_marginal_per_s"])
+    return {"frac_issued": t / seconds, "executed_valu_per_pair": valu,
+            "executed_exp2_per_pair": exp2}
+
+
 def render_graph_leg(P, torch, params, H, W, renders):
     """Render FPS from a captured graph: 16 no-allocation renders (gi_render_noalloc) recorded
     into one HIP graph on a side stream (a graph launch leaves the device idle for a few
@@ -370,6 +383,21 @@ def _traffic_if_current(rec):
     if rec.get("kernel_source_sha256") != raster_fit_digest():
         return None
     return rec.get("bytes_per_launch")
+
+
+def executed_per_pair(kernel, workload):
+    """(FP32 VALU lane instructions, exp2) per pair that the kernel executed by the SQ counters
+    of the committed record (exp2 not among the first), if taken on the current source and the
+    same workload (else None)."""
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError):
+        return None
+    if (rec.get("kernel") != kernel or rec.get("workload") != workload
+            or rec.get("kernel_source_sha256") != raster_fit_digest()
+            or "executed_valu_per_pair" not in rec):
+        return None
+    return rec["executed_valu_per_pair"], rec["executed_exp2_per_pair"]
 
 
 def copy_calibration():
@@ -789,6 +817,8 @@ def main():
                      "raster_fwd": fwd_ms / max(fwd_n, 1)},
         "loss": {"after_warmup": loss_start, "after_timed": loss_end},
         "roofline": dict(roof, traffic=measured_traffic(f"k_raster_fit<{px_used}>", w.name),
+                         **issued_fraction(executed_per_pair(f"k_raster_fit<{px_used}>", w.name),
+                                           P_prof, fit_ms / fit_n / 1e3, pk),
                          kernel=f"k_raster_fit<{px_used}>", pairs_per_launch=P_prof,
                          avg_launch_ms=fit_ms / fit_n),
         "render_roofline": dict(fwd_roof, kernel=f"k_raster_fwd<{px_used}>",
