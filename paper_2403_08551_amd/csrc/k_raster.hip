@@ -808,8 +808,20 @@ __device__ inline void block_image_losses(const float *__restrict__ loss_part, c
             t1 = tab.tile_base[b + 1];
             npx = (double)tab.dims[b].x * tab.dims[b].y;
         }
+        // eight reads issued before any is added (the additions keep the order of a plain
+        // strided loop; lanes past the end read the last entry and drop it)
         double s = 0.0;
-        for (uint32_t t = t0 + threadIdx.x; t < t1; t += 256) s += (double)loss_part[t];
+        for (uint32_t t = t0 + threadIdx.x; t < t1; t += 256 * 8) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t u = t + 256u * k;
+                v[k] = loss_part[u < t1 ? u : t1 - 1];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (t + 256u * k < t1) s += (double)v[k];
+        }
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
         __syncthreads();  // red is free
