@@ -11,9 +11,10 @@
 //
 // Work mapping.  Forward: one workgroup of 256 threads per 16x16 tile.  The tile's list is cut
 // into four equal parts; each part is summed by one group of 256 / PX threads, each lane owning
-// PX pixels of one column (so per-column terms are shared by PX pixels), the part's records read
-// in sorted order through the scalar unit (every lane uses the same Gaussian at once), colour
-// accumulated in float32 registers with a two-level sum (partial sums of 8 Gaussians).  The
+// PX pixels of one column (so per-column terms are shared by PX pixels), the part's records
+// streamed in sorted order through the wave's own LDS and read as broadcasts (every lane uses the
+// same Gaussian at once), colour accumulated in float32 registers with a two-level sum (partial
+// sums of 8 Gaussians).  The
 // four part sums meet in LDS and are added in part order, so every PX gives the same bits.
 // Adjoint: one Gaussian per lane, the tile's 256 dL/dC values staged in LDS and read as
 // broadcasts, so each lane reduces its own
@@ -69,79 +70,17 @@ __device__ inline void fwd_eval(const float4 A, const float4 B, float px, float 
     }
 }
 
-// Forward accumulation for the PX pixels (one column) of this thread over the list range r.
-// Records are read in groups of four through the scalar unit into two register sets used in
-// turn: the next group is requested before the current one is evaluated, so its latency
-// overlaps the arithmetic.  Scalar loads complete out of order and can only be awaited
-// together, so each half-step first waits for everything (only the group about to be used is
-// outstanding then) and only then issues the next request.  Two-level sum: each loop step's
-// eight records form a partial sum (set by its first record), added to the totals at the end
-// of the step; records after the last whole group form one more partial sum.
-template <int PX>
-__device__ __forceinline__ void fwd_tile(const float4 *__restrict__ rec, uint2 r, float px,
-                                         float py0, const float (&of)[PX],
-                                         float (&acc)[PX][3]) {
-    float part[PX][3];
-#pragma unroll
-    for (int j = 0; j < PX; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.f;
-    auto fold = [&]() {
-#pragma unroll
-        for (int j = 0; j < PX; ++j) {
-            acc[j][0] += part[j][0];
-            acc[j][1] += part[j][1];
-            acc[j][2] += part[j][2];
-        }
-    };
-    const uint32_t ng = (r.y - r.x) / 4;
-    uint32_t i = r.x;
-    float4 ga[8], gb[8];
-    if (ng) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) ga[k] = rec[2 * (int64_t)i + k];
-    }
-    // up to two groups per trip and one fold at its end: the loop has a single exit, so the
-    // totals stay in the same registers from trip to trip (an exit between the two halves had
-    // made the compiler copy all of them every trip)
-    for (uint32_t g = 0; g < ng; g += 2) {
-        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): group g is in ga
-        const bool two = g + 1 < ng;
-        if (two) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) gb[k] = rec[2 * (int64_t)(i + 4) + k];
-        }
-        fwd_eval<PX, true>(ga[0], ga[1], px, py0, of, part);
-#pragma unroll
-        for (int k = 1; k < 4; ++k) fwd_eval<PX>(ga[2 * k], ga[2 * k + 1], px, py0, of, part);
-        i += 4;
-        if (two) {
-            __builtin_amdgcn_s_waitcnt(0xc07f);  // group g + 1 is in gb
-            if (g + 2 < ng) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) ga[k] = rec[2 * (int64_t)(i + 4) + k];
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) fwd_eval<PX>(gb[2 * k], gb[2 * k + 1], px, py0, of, part);
-            i += 4;
-        }
-        fold();
-    }
-    if (i < r.y) {
-        fwd_eval<PX, true>(rec[2 * (int64_t)i], rec[2 * (int64_t)i + 1], px, py0, of, part);
-        for (++i; i < r.y; ++i)
-            fwd_eval<PX>(rec[2 * (int64_t)i], rec[2 * (int64_t)i + 1], px, py0, of, part);
-        fold();
-    }
-}
-
-// Forward accumulation as fwd_tile, with the records reaching the VALU through LDS instead of
-// the scalar unit: a VALU instruction that reads a scalar register issues at half the rate of
-// one that reads only vector registers (measured on gfx950: 38 against 60-72 T lane-op/s), and
-// the per-record arithmetic reads the record in every instruction.  The wave streams its list
-// range in chunks of 32 records: one 16-byte load per lane (coalesced), written to the wave's own
-// 1 KB of LDS, then each record read back as two broadcast 16-byte LDS reads; the next chunk's
-// load is in flight while the current one is evaluated.  LDS operations of one wave complete in
-// order, so the wave needs no barrier.  The partial sums are grouped as in fwd_tile (8 records,
-// then 4, then the rest), so the result is the same bits.
+// Forward accumulation for the PX pixels (one column) of this thread over the list range r, the
+// records reaching the VALU through LDS rather than the scalar unit: a VALU instruction that
+// reads a scalar register issues at half the rate of one that reads only vector registers
+// (measured on gfx950: 38 against 60-72 T lane-op/s), and the per-record arithmetic reads the
+// record in every instruction.  The wave streams its list range in chunks of 32 records: one
+// 16-byte load per lane (coalesced), written to the wave's own 1 KB of LDS, then each record
+// read back as two broadcast 16-byte LDS reads; the next chunk's load is in flight while the
+// current one is evaluated.  LDS operations of one wave complete in order, so the wave needs no
+// barrier.  Two-level sum: each group of 8 records forms a partial sum (set by its first record),
+// added to the totals after the group; then one group of 4 and one of the rest, so the grouping
+// depends on the list alone, not on PX.
 template <int PX>
 __device__ __forceinline__ void fwd_tile_lds(const float4 *__restrict__ rec, uint2 r, float px,
                                              float py0, const float (&of)[PX],
