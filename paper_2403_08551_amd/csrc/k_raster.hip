@@ -339,6 +339,11 @@ __global__ __launch_bounds__(256, 4) void k_raster_fit(const float4 *__restrict_
     __shared__ float4 sg[TILE_PX];
     __shared__ float red[NT / 64];
     __shared__ float4 lrec[4 * 64];
+    // Wave priority: the forward at the highest level, the adjoint at the lowest.  The arbiter
+    // otherwise issues from the oldest waves first, so a workgroup that starts when another
+    // finishes waited behind the older ones and then ran alone at the end of the kernel; this
+    // way its forward takes the issue slots from the adjoints around it.  Same arithmetic.
+    __builtin_amdgcn_s_setprio(3);
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     const uint2 r = ranges[tile];
@@ -378,6 +383,7 @@ __global__ __launch_bounds__(256, 4) void k_raster_fit(const float4 *__restrict_
         // the step counter advances here; the update kernel that follows uses *step - 1
         if (step_inc && tile == 0) *step_inc += 1;
     }
+    __builtin_amdgcn_s_setprio(0);
     bwd_tile<NT>(rec, slot, r, ti, sg, part);
 }
 
