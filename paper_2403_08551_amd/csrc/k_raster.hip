@@ -80,8 +80,11 @@ __device__ inline void fwd_eval(const float4 A, const float4 B, float px, float 
 // current one is evaluated.  LDS operations of one wave complete in order, so the wave needs no
 // barrier.  Two-level sum: each group of 8 records forms a partial sum (set by its first record),
 // added to the totals after the group; then one group of 4 and one of the rest, so the grouping
-// depends on the list alone, not on PX.
-template <int PX>
+// depends on the list alone, not on PX.  With PRIO the wave lowers its issue priority from 3 to
+// 0 as it passes a quarter, a half and three quarters of its records, so the waves sharing a
+// SIMD progress together instead of oldest first (which leaves each CU's last workgroup running
+// alone, without a second wave to pair VALU instructions with).
+template <int PX, bool PRIO = false>
 __device__ __forceinline__ void fwd_tile_lds(const float4 *__restrict__ rec, uint2 r, float px,
                                              float py0, const float (&of)[PX],
                                              float (&acc)[PX][3], float4 *lbuf) {
@@ -110,8 +113,15 @@ __device__ __forceinline__ void fwd_tile_lds(const float4 *__restrict__ rec, uin
         return rec[2 * (int64_t)first + ((uint32_t)lane < last ? (uint32_t)lane : last)];
     };
     float4 stage = chunk_word(r.x, L < CH ? L : CH);
+    const uint32_t q1 = L >> 2, q2 = L >> 1, q3 = (L >> 2) + (L >> 1);
+    if (PRIO) __builtin_amdgcn_s_setprio(3);
     for (uint32_t c0 = 0; c0 < L; c0 += CH) {
         const uint32_t n = L - c0 < CH ? L - c0 : CH;
+        if (PRIO) {  // the chunk that crosses a quarter mark lowers the priority
+            if (c0 >= q1 && c0 < q1 + CH) __builtin_amdgcn_s_setprio(2);
+            if (c0 >= q2 && c0 < q2 + CH) __builtin_amdgcn_s_setprio(1);
+            if (c0 >= q3 && c0 < q3 + CH) __builtin_amdgcn_s_setprio(0);
+        }
         lbuf[lane] = stage;
         if (c0 + CH < L) stage = chunk_word(r.x + c0 + CH, L - c0 - CH < CH ? L - c0 - CH : CH);
         uint32_t k = 0;
@@ -231,7 +241,7 @@ __device__ inline uint2 list_part(uint2 r, int q) {
 // Part sums of the tile's pixels into qs[PARTS][3][TILE_PX].  PX groups of 256 / PX threads
 // (whole waves) each take PARTS / PX parts in turn; lane l of a group owns the PX consecutive
 // rows from (l >> 4) PX on of column l & 15.
-template <int PX>
+template <int PX, bool PRIO = false>
 __device__ __forceinline__ void fwd_parts(const float4 *__restrict__ rec, uint2 r,
                                           const TileInfo &ti, float *qs, float4 *lrec) {
     constexpr int GROUP = 256 / PX, PER = PARTS / PX;
@@ -248,7 +258,7 @@ __device__ __forceinline__ void fwd_parts(const float4 *__restrict__ rec, uint2 
     for (int k = 0; k < PER; ++k) {
         const int q = grp * PER + k;
         float acc[PX][3];
-        fwd_tile_lds<PX>(rec, list_part(r, q), px, py0, of, acc,
+        fwd_tile_lds<PX, PRIO>(rec, list_part(r, q), px, py0, of, acc,
                          lrec + 64 * (threadIdx.x >> 6));
 #pragma unroll
         for (int j = 0; j < PX; ++j) {
@@ -282,7 +292,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(const float4 *__restrict__ r
     __shared__ float4 lrec[4 * 64];
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
-    fwd_parts<PX>(rec, ranges[tile], ti, qs, lrec);
+    fwd_parts<PX, true>(rec, ranges[tile], ti, qs, lrec);
     __syncthreads();
     const int p = threadIdx.x;
     const int x = ti.tx * TILE + (p & 15), y = ti.ty * TILE + (p >> 4);
