@@ -107,9 +107,14 @@ enum {
                                  (default) or GI_COV_ROTATION_SCALE; read by every later call,
                                  and fixed into a captured step when it is created */
     GI_OPT_TILE_ORDER = 7     /* order in which the raster workgroups take the tiles: 0 = auto
-                                 (tuned, else 1), 1 = tile index, 2 = longest list first (one
-                                 small sorting kernel after the binning).  Never changes a
-                                 result: each tile's arithmetic is the same in any order */
+                                 (tuned, else 3 up to 16384 tiles and 1 above), 1 = tile index,
+                                 2 = longest list first (one small sorting kernel after the
+                                 binning), 3 = longest list first by the previous fit step's
+                                 lists (written by that step's update kernel at no extra launch,
+                                 up to 16384 tiles; a call whose tile count differs from the
+                                 previous one's sorts once as with 2, and above 16384 tiles that
+                                 first order stays).  Never changes a result: each tile's
+                                 arithmetic is the same in any order */
 };
 
 /* Values of GI_OPT_COVARIANCE. */
@@ -148,7 +153,7 @@ int gi_get_option(gi_ctx *ctx, int option, int64_t *value);
 
 /* A schedule of the tunable knobs (0 = the knob's automatic rule): binning path (GI_OPT_BINNING
  * values 1..3), forward pixels per lane (1, 2, 4), radix digit width (radix path only), tile
- * order (GI_OPT_TILE_ORDER values 1, 2); ms_per_step is the fit step time it was chosen with. */
+ * order (GI_OPT_TILE_ORDER values 1, 2, 3); ms_per_step is the fit step time it was chosen with. */
 typedef struct gi_schedule {
     int32_t binning;
     int32_t fwd_pixels;

@@ -397,10 +397,12 @@ struct AdamArgs {
     float lr_mu, lr_l, lr_c, beta1, beta2, eps, l_min;
 };
 // Adam update with step number *step - 1 (the fit kernel advanced the counter); also writes the
-// per-image losses when loss_out != nullptr.
+// per-image losses when loss_out != nullptr, and with order_out the longest-first order of the
+// n_tiles lists in `ranges` (a permutation of the tiles, in one extra block of the same launch).
 hipError_t launch_adam(const UpdateArgs &u, float *params, float *m, float *v,
                        int32_t *step, const AdamArgs &hp, const float *loss_part,
-                       const ImgTable &tab, int64_t n_tiles, float *loss_out, hipStream_t s);
+                       const ImgTable &tab, int64_t n_tiles, float *loss_out, hipStream_t s,
+                       const uint2 *ranges = nullptr, uint32_t *order_out = nullptr);
 // Adam over params and opacities of an opacity rendering (opacity uses the colour rate), as
 // launch_adam.
 hipError_t launch_adam_opacity(const UpdateArgs &u, float *params, float *opacity, float *m,

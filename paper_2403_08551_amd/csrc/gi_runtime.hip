@@ -33,7 +33,8 @@ struct gi_ctx {
     int sort_bits = 0;
     int fwd_px = 0;
     int binning = 0;
-    int order = 0;           // GI_OPT_TILE_ORDER: 0 auto, 1 tile index, 2 longest list first
+    int order = 0;           // GI_OPT_TILE_ORDER: 0 auto, 1 tile index, 2 longest list first,
+                             // 3 longest first by the previous fit step's lists
     int cov = COV_CHOLESKY;  // GI_OPT_COVARIANCE
     const CodecArgs *codec = nullptr;  // set for the duration of a codec render
     const float *opac_cur = nullptr;   // set for the duration of an opacity render / grad
@@ -91,6 +92,7 @@ struct gi_ctx {
     uint2 *ranges = nullptr;
     float *loss_part = nullptr;
     uint32_t *tile_order = nullptr;  // longest-first order of the raster workgroups
+    int64_t order_tiles = 0;         // tiles that tile_order holds a permutation of (0: none)
     // scalars
     DevState *state = nullptr;
     unsigned long long *pinned = nullptr;
@@ -245,6 +247,7 @@ int ensure_tiles(gi_ctx *ctx, int64_t t) {
     CK(grow(&ctx->ranges, c));
     CK(grow(&ctx->loss_part, c));
     CK(grow(&ctx->tile_order, c));
+    ctx->order_tiles = 0;
     ctx->cap_t = c;
     return GI_OK;
 }
@@ -466,10 +469,15 @@ int pick_binning(gi_ctx *ctx, int64_t n, int64_t n_pix) {
     return t ? t->binning : 0;
 }
 
+// Tile counts up to which the update kernel's one extra block writes the next step's order
+// (beyond, one block would take longer than the update itself).
+constexpr int64_t ORDER_BLOCK_MAX_TILES = 16384;
+
 int pick_order(gi_ctx *ctx, int64_t n, int64_t n_pix) {
     if (ctx->order) return ctx->order;
     const Schedule *t = tuned_for(ctx, n, n_pix);
-    return t && t->order ? t->order : 1;
+    if (t && t->order) return t->order;
+    return n_pix <= ORDER_BLOCK_MAX_TILES * TILE_PX ? 3 : 1;
 }
 
 int64_t table_pixels(const ImgTable &tab, int64_t n_tiles) {
@@ -720,14 +728,29 @@ int run_binning(gi_ctx *ctx, const float *params, int64_t n, const ImgTable &tab
 }
 
 
-// The raster workgroups' tile order for this call: longest list first when chosen (one small
-// kernel after the binning), else tile index order (no table).
+// The raster workgroups' tile order for this call: tile index order (no table); longest list
+// first (2: one small kernel after the binning); or (3) the longest-first order of the previous
+// fit step's lists, which that step's update kernel wrote at no cost (any permutation of the
+// tiles gives the same results; the first call for a tile count sorts once instead).
 hipError_t set_order(gi_ctx *ctx, RasterArgs &a, int64_t n, const ImgTable &tab, int64_t n_tiles,
                      hipStream_t s) {
     a.order = nullptr;
-    if (pick_order(ctx, n, table_pixels(tab, n_tiles)) != 2 || n_tiles <= 1) return hipSuccess;
+    const int o = pick_order(ctx, n, table_pixels(tab, n_tiles));
+    if ((o != 2 && o != 3) || n_tiles <= 1) return hipSuccess;
     a.order = ctx->tile_order;
+    if (o == 3 && ctx->order_tiles == n_tiles) return hipSuccess;
+    ctx->order_tiles = n_tiles;
     return launch_tile_order(ctx->ranges, n_tiles, ctx->tile_order, s);
+}
+
+// Where the update kernel writes the next step's tile order (mode 3, up to
+// ORDER_BLOCK_MAX_TILES tiles; above, the order sorted at the first call stays), else nullptr.
+uint32_t *order_for_next(gi_ctx *ctx, int64_t n, const ImgTable &tab, int64_t n_tiles) {
+    if (n_tiles <= 1 || n_tiles > ORDER_BLOCK_MAX_TILES ||
+        pick_order(ctx, n, table_pixels(tab, n_tiles)) != 3)
+        return nullptr;
+    ctx->order_tiles = n_tiles;
+    return ctx->tile_order;
 }
 
 // Marks a render for the duration of its binning: the scatters then skip the key slots, which
@@ -792,7 +815,8 @@ int do_fit(gi_ctx *ctx, float *params, float *m, float *v, const float *target, 
                  ctx->cov};
     AdamArgs h{hp->lr_mu, hp->lr_l, hp->lr_c, hp->beta1, hp->beta2, hp->eps, hp->l_min};
     StageTimer tu(ctx, s, GI_STAGE_UPDATE);
-    CK(launch_adam(u, params, m, v, step, h, ctx->loss_part, tab, n_tiles, loss_out, s));
+    CK(launch_adam(u, params, m, v, step, h, ctx->loss_part, tab, n_tiles, loss_out, s,
+                   ctx->ranges, order_for_next(ctx, n, tab, n_tiles)));
     tu.stop();
     return GI_OK;
 }
@@ -1089,7 +1113,7 @@ int gi_set_option(gi_ctx *ctx, int option, int64_t value) {
             ctx->cov = (int)value;
             return GI_OK;
         case GI_OPT_TILE_ORDER:
-            if (value < 0 || value > 2) return GI_ERR_INVALID_ARG;
+            if (value < 0 || value > 3) return GI_ERR_INVALID_ARG;
             ctx->order = (int)value;
             return GI_OK;
         default:
@@ -1240,7 +1264,7 @@ int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n
     Schedule best;
     best.binning = paths[0];
     best.px = 4;
-    best.order = 1;
+    best.order = 3;
     {
         float junk = 0.f;
         for (int k = 0; k < 3 && rc == GI_OK; ++k) rc = trial(best, &junk);
@@ -1285,9 +1309,12 @@ int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n
         }
     }
     if (rc == GI_OK) {
-        Schedule sc = best;
-        sc.order = 2;
-        rc = consider(sc);
+        const Schedule base = best;
+        for (int o : {1, 2}) {
+            Schedule sc = base;
+            sc.order = o;
+            if ((rc = consider(sc)) != GI_OK) break;
+        }
     }
     if (rc == GI_OK) {
         e = hipStreamSynchronize(s);
@@ -1345,7 +1372,7 @@ int gi_autotune_load(gi_ctx *ctx, const char *path, int32_t *loaded) {
                              &cov, &nc, &pc, &bin, &px, &bits, &order, &ms);
         if (k != 8 || (cov != GI_COV_CHOLESKY && cov != GI_COV_ROTATION_SCALE) || bin < 0 ||
             bin > 3 || (px != 0 && px != 1 && px != 2 && px != 4) || bits < 0 || bits > 11 ||
-            order < 0 || order > 2) {
+            order < 0 || order > 3) {
             rc = GI_ERR_INVALID_ARG;
             continue;
         }
@@ -1690,6 +1717,13 @@ int capture_step(gi_ctx *user, const float *params, int64_t n, int32_t H, int32_
     (void)prepare(ctx, false);
     if (rc == GI_OK) rc = ensure_keys(ctx, bound + bound / 4 + 4096);
     if (rc != GI_OK) return fail(rc);
+    // tile order 3: a first order now, outside the capture; each replay's update then writes
+    // the next one into the same table
+    if (T > 1 && pick_order(ctx, n, table_pixels(tab, T)) == 3) {
+        hipError_t oe = launch_tile_order(ctx->ranges, T, ctx->tile_order, s);
+        if (oe != hipSuccess) return fail(hip_fail(ctx, oe, "launch_tile_order"));
+        ctx->order_tiles = T;
+    }
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(hip_fail(ctx, e, "hipStreamSynchronize"));
     ctx->sync = 0;

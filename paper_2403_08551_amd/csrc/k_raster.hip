@@ -752,8 +752,10 @@ __global__ __launch_bounds__(256) void k_alpha_fit(const float4 *__restrict__ re
 // take images blockIdx.x, blockIdx.x + gridDim.x, ...  256 threads; call from all of them.
 __device__ inline void block_image_losses(const float *__restrict__ loss_part, const ImgTable &tab,
                                           int64_t n_tiles, float *__restrict__ loss_out,
-                                          double *red) {
-    for (int b = blockIdx.x; b < tab.B; b += gridDim.x) {
+                                          double *red, int first = -1, int stride = -1) {
+    if (first < 0) first = blockIdx.x;
+    if (stride < 0) stride = gridDim.x;
+    for (int b = first; b < tab.B; b += stride) {
         uint32_t t0 = 0, t1 = (uint32_t)n_tiles;
         double npx;
         if (tab.B == 1) {
@@ -959,7 +961,59 @@ __global__ __launch_bounds__(UPD_T) void k_grad_opacity(const float4 *__restrict
 // With an opacity rendering (BLEND != BLEND_NONE) lane 0 of each quad also updates the
 // Gaussian's opacity (moments m_op, v_op; colour learning rate), with the gradients of
 // k_grad_opacity.
-template <int COV, int BLEND = BLEND_NONE>
+// Longest list first: each tile goes to the bin of its list length (descending), the bins'
+// starts come from one exclusive scan in LDS, and each tile takes the next place of its bin
+// (an LDS atomic: within a bin the order is arbitrary, which only changes the dispatch order).
+template <int NTH>
+__device__ inline void tile_order_block(const uint2 *__restrict__ ranges, int64_t T,
+                                        uint32_t *__restrict__ order, uint32_t *bin,
+                                        uint32_t *wsum) {
+    for (int b = threadIdx.x; b < TILE_ORDER_BINS; b += NTH) bin[b] = 0u;
+    __syncthreads();
+    auto key = [&](int64_t t) {
+        const uint2 r = ranges[t];
+        const uint32_t len = r.y - r.x;
+        return (uint32_t)(TILE_ORDER_BINS - 1) - (len < (uint32_t)(TILE_ORDER_BINS - 1)
+                                                      ? len : (uint32_t)(TILE_ORDER_BINS - 1));
+    };
+    for (int64_t t = threadIdx.x; t < T; t += NTH) atomicAdd(&bin[key(t)], 1u);
+    __syncthreads();
+    // exclusive scan of the bins: each thread owns TILE_ORDER_BINS / NTH consecutive bins
+    constexpr int PER = TILE_ORDER_BINS / NTH;
+    uint32_t v[PER], run = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        v[j] = bin[threadIdx.x * PER + j];
+        run += v[j];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    uint32_t at = base + inc - run;
+    __syncthreads();  // every bin has been read
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        bin[threadIdx.x * PER + j] = at;
+        at += v[j];
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < T; t += NTH)
+        order[atomicAdd(&bin[key(t)], 1u)] = (uint32_t)t;
+}
+
+// With ORDER, block 0 writes the longest-first tile order of this step's lists into `order`
+// (for the next step's raster kernels, which any permutation of the tiles serves equally) and
+// the update runs in blocks 1, 2, ...; the order block starts with the first and ends long
+// before the last, so the order costs no launch and no time on the critical path.
+template <int COV, int BLEND = BLEND_NONE, bool ORDER = false>
 __global__ __launch_bounds__(UPD_T) void k_adam(float4 *__restrict__ params, int64_t n,
                                                 const uint32_t *__restrict__ count,
                                                 const uint32_t *__restrict__ off,
@@ -971,10 +1025,21 @@ __global__ __launch_bounds__(UPD_T) void k_adam(float4 *__restrict__ params, int
                                                 float *__restrict__ v_op,
                                                 const float *__restrict__ loss_part,
                                                 ImgTable tab, int64_t n_tiles,
-                                                float *__restrict__ loss_out) {
+                                                float *__restrict__ loss_out,
+                                                const uint2 *__restrict__ ranges = nullptr,
+                                                uint32_t *__restrict__ order = nullptr) {
     __shared__ float s_bc[2];
     __shared__ double red[4];
-    if (loss_out) block_image_losses(loss_part, tab, n_tiles, loss_out, red);
+    if constexpr (ORDER) {
+        __shared__ uint32_t obin[TILE_ORDER_BINS];
+        __shared__ uint32_t owsum[UPD_T / 64];
+        if (blockIdx.x == 0) {
+            tile_order_block<UPD_T>(ranges, n_tiles, order, obin, owsum);
+            return;
+        }
+    }
+    const int bx = (int)blockIdx.x - (ORDER ? 1 : 0), nbx = (int)gridDim.x - (ORDER ? 1 : 0);
+    if (loss_out) block_image_losses(loss_part, tab, n_tiles, loss_out, red, bx, nbx);
     if (threadIdx.x == 0) {
         const double t = (double)(*step - 1);  // the fit kernel has advanced the counter
         s_bc[0] = (float)(1.0 - pow((double)hp.beta1, t));
@@ -982,7 +1047,7 @@ __global__ __launch_bounds__(UPD_T) void k_adam(float4 *__restrict__ params, int
     }
     // The sums do not need the bias corrections: they are read while thread 0 forms them, and
     // the barrier comes only before the update.
-    const int64_t i = (int64_t)blockIdx.x * UPD_G + (threadIdx.x >> 2);
+    const int64_t i = (int64_t)bx * UPD_G + (threadIdx.x >> 2);
     const int q = threadIdx.x & 3;
     // the moments and the overflow flag are read along with the sums (the reads stay within
     // the key buffers either way); gradients incomplete on key overflow: the state is left alone
@@ -1352,52 +1417,11 @@ __global__ __launch_bounds__(256) void k_finish(const float *__restrict__ loss_p
 
 }  // namespace
 
-// Longest list first: each tile goes to the bin of its list length (descending), the bins'
-// starts come from one exclusive scan in LDS, and each tile takes the next place of its bin
-// (an LDS atomic: within a bin the order is arbitrary, which only changes the dispatch order).
 __global__ __launch_bounds__(1024) void k_tile_order(const uint2 *__restrict__ ranges,
                                                      int64_t T, uint32_t *__restrict__ order) {
     __shared__ uint32_t bin[TILE_ORDER_BINS];
     __shared__ uint32_t wsum[1024 / 64];
-    for (int b = threadIdx.x; b < TILE_ORDER_BINS; b += 1024) bin[b] = 0u;
-    __syncthreads();
-    auto key = [&](int64_t t) {
-        const uint2 r = ranges[t];
-        const uint32_t len = r.y - r.x;
-        return (uint32_t)(TILE_ORDER_BINS - 1) - (len < (uint32_t)(TILE_ORDER_BINS - 1)
-                                                      ? len : (uint32_t)(TILE_ORDER_BINS - 1));
-    };
-    for (int64_t t = threadIdx.x; t < T; t += 1024) atomicAdd(&bin[key(t)], 1u);
-    __syncthreads();
-    // exclusive scan of the bins: each thread owns 4 consecutive bins
-    constexpr int PER = TILE_ORDER_BINS / 1024;
-    uint32_t v[PER], run = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        v[j] = bin[threadIdx.x * PER + j];
-        run += v[j];
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t inc = run;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += o;
-    }
-    if (lane == 63) wsum[wave] = inc;
-    __syncthreads();
-    uint32_t base = 0;
-    for (int w = 0; w < wave; ++w) base += wsum[w];
-    uint32_t at = base + inc - run;
-    __syncthreads();  // every bin has been read
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        bin[threadIdx.x * PER + j] = at;
-        at += v[j];
-    }
-    __syncthreads();
-    for (int64_t t = threadIdx.x; t < T; t += 1024)
-        order[atomicAdd(&bin[key(t)], 1u)] = (uint32_t)t;
+    tile_order_block<1024>(ranges, T, order, bin, wsum);
 }
 
 hipError_t launch_tile_order(const uint2 *ranges, int64_t n_tiles, uint32_t *order,
@@ -1495,22 +1519,32 @@ hipError_t launch_grad_out(const UpdateArgs &u, float *dparams, hipStream_t s) {
 
 hipError_t launch_adam(const UpdateArgs &u, float *params, float *m, float *v, int32_t *step,
                        const AdamArgs &hp, const float *loss_part, const ImgTable &tab,
-                       int64_t n_tiles, float *loss_out, hipStream_t s) {
+                       int64_t n_tiles, float *loss_out, hipStream_t s, const uint2 *ranges,
+                       uint32_t *order_out) {
     if (u.n > 0) {
-        const dim3 grid((unsigned)((u.n + UPD_G - 1) / UPD_G));
+        const bool ord = order_out && ranges && n_tiles > 0;
+        const dim3 grid((unsigned)((u.n + UPD_G - 1) / UPD_G + (ord ? 1 : 0)));
         float4 *p4 = reinterpret_cast<float4 *>(params);
         const float4 *part = reinterpret_cast<const float4 *>(u.part);
         float2 *m2 = reinterpret_cast<float2 *>(m), *v2 = reinterpret_cast<float2 *>(v);
         float *nf = nullptr;
-        if (u.cov == COV_ROTATION_SCALE)
-            hipLaunchKernelGGL((k_adam<COV_ROTATION_SCALE, BLEND_NONE>), grid, dim3(UPD_T), 0, s,
-                               p4, u.n, u.count, u.off, part, u.state, u.cap, m2, v2, step, hp,
-                               nf, nf, nf, loss_part, tab, n_tiles, loss_out);
-        else
-            hipLaunchKernelGGL((k_adam<COV_CHOLESKY, BLEND_NONE>), grid, dim3(UPD_T), 0, s, p4,
-                               u.n, u.count, u.off, part, u.state, u.cap, m2, v2, step, hp, nf,
-                               nf, nf, loss_part, tab, n_tiles, loss_out);
+#define GI_LAUNCH_ADAM(C, O)                                                                    \
+    hipLaunchKernelGGL((k_adam<C, BLEND_NONE, O>), grid, dim3(UPD_T), 0, s, p4, u.n, u.count,  \
+                       u.off, part, u.state, u.cap, m2, v2, step, hp, nf, nf, nf, loss_part,   \
+                       tab, n_tiles, loss_out, ranges, order_out)
+        if (u.cov == COV_ROTATION_SCALE) {
+            if (ord) GI_LAUNCH_ADAM(COV_ROTATION_SCALE, true);
+            else GI_LAUNCH_ADAM(COV_ROTATION_SCALE, false);
+        } else {
+            if (ord) GI_LAUNCH_ADAM(COV_CHOLESKY, true);
+            else GI_LAUNCH_ADAM(COV_CHOLESKY, false);
+        }
+#undef GI_LAUNCH_ADAM
         return hipGetLastError();
+    }
+    if (order_out && ranges && n_tiles > 0) {
+        const hipError_t e = launch_tile_order(ranges, n_tiles, order_out, s);
+        if (e != hipSuccess) return e;
     }
     return launch_finish(loss_part, tab, n_tiles, loss_out, s);
 }

@@ -461,6 +461,77 @@ def test_graph_replay_matches_eager_steps(gi, binning):
     assert int(host(sb)[0]) == 5
 
 
+def test_tile_order_from_the_previous_step(gi):
+    # tile order 3: each fit step's update writes the next step's longest-first order; eager
+    # steps, a run of 16 captured steps and a change of image size on the same context all give
+    # the bits of the index order
+    import paper_2403_08551_amd as P
+    w = synth.plain_256()
+    p0, T = w.params(), dev(w.target())
+    small = synth.gaussians(400, 40, 72, seed=7)
+    Ts = dev(synth.target_noise_rects(40, 72, seed=8))
+
+    def run(order, captured):
+        ctx = P.Context(0)
+        ctx.set_option(P._lib.GI_OPT_TILE_ORDER, order)
+        try:
+            p = dev(p0)
+            m, v = torch.zeros_like(p), torch.zeros_like(p)
+            st = torch.ones(1, dtype=torch.int32, device="cuda")
+            if captured:
+                g = ctx.fit_graph(p, m, v, T, st)
+                g.launch(3)
+                g.launch(17)
+                torch.cuda.synchronize()
+                g.close()
+            else:
+                for _ in range(20):
+                    ctx.fit_step(p, m, v, T, st)
+            # another size on the same context, then the first size again
+            q = dev(small)
+            mq, vq = torch.zeros_like(q), torch.zeros_like(q)
+            sq = torch.ones(1, dtype=torch.int32, device="cuda")
+            for _ in range(3):
+                ctx.fit_step(q, mq, vq, Ts, sq)
+            img = host(ctx.render(p, w.height, w.width))
+            ctx.fit_step(p, m, v, T, st)
+            assert ctx.query(clear=True)[1] == 0
+            return host(p), host(m), host(q), img
+        finally:
+            ctx.close()
+
+    want = run(1, False)
+    for order, captured in ((3, False), (3, True), (2, True)):
+        got = run(order, captured)
+        for a, b in zip(got, want):
+            np.testing.assert_array_equal(a, b, err_msg=f"order {order}, captured {captured}")
+
+
+def test_tile_order_above_the_update_kernels_limit(gi):
+    # more than 16384 tiles: order 3 sorts once per tile count and keeps that order (the update
+    # kernel writes none); fit steps give the bits of the index order
+    import paper_2403_08551_amd as P
+    h, w = 2080, 2064  # 130 x 129 = 16770 tiles
+    p0 = synth.gaussians(3000, h, w, seed=31)
+    T = dev(synth.target_noise_rects(h, w, seed=32))
+    out = []
+    for order in (1, 3):
+        ctx = P.Context(0)
+        ctx.set_option(P._lib.GI_OPT_TILE_ORDER, order)
+        try:
+            p = dev(p0)
+            m, v = torch.zeros_like(p), torch.zeros_like(p)
+            st = torch.ones(1, dtype=torch.int32, device="cuda")
+            for _ in range(3):
+                ctx.fit_step(p, m, v, T, st)
+            assert ctx.query(clear=True)[1] == 0
+            out.append((host(p), host(m), host(v)))
+        finally:
+            ctx.close()
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_graph_runs_of_sixteen_steps_match_eager_steps(gi):
     # 37 steps in launches of 37 and 3: runs of 16 go out as one launch of the 16-step graph,
     # the rest one step per launch; the result equals 40 eager steps bit for bit
@@ -700,7 +771,7 @@ def test_autotune_reads_but_never_writes_and_keeps_results_exact(gi):
     ref_img = host(gi.render(p, w.height, w.width))
     sc = gi.autotune(p, T, reps=2)
     assert sc["binning"] in (1, 2, 3) and sc["fwd_pixels"] in (1, 2, 4)
-    assert sc["sort_bits"] in (0, 4, 6, 8, 11) and sc["tile_order"] in (1, 2)
+    assert sc["sort_bits"] in (0, 4, 6, 8, 11) and sc["tile_order"] in (1, 2, 3)
     assert sc["ms_per_step"] > 0
     np.testing.assert_array_equal(host(p), before)
     for opt in (P._lib.GI_OPT_FWD_PIXELS, P._lib.GI_OPT_BINNING, P._lib.GI_OPT_TILE_ORDER):
@@ -714,7 +785,7 @@ def _schedules(tiles, rows_ok=True):
     paths = ([2] if tiles <= 2048 else []) + ([3] if rows_ok else []) + [1]
     for b in paths:
         for px in (1, 2, 4):
-            for order in (1, 2):
+            for order in (1, 2, 3):
                 out.append((b, px, 0, order))
         if b == 1:
             out += [(1, 4, d, 2) for d in (4, 6, 8, 11)]
