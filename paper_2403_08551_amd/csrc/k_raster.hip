@@ -638,6 +638,8 @@ __global__ __launch_bounds__(256) void k_alpha_bwd(const float4 *__restrict__ re
     __shared__ __align__(16) float red[ALPHA_PARTS * ALPHA_RED];
     static_assert(ALPHA_PARTS * ALPHA_RED >= 4 * ALPHA_PARTS * TILE_PX, "the part sums fit");
     float4 *xs = reinterpret_cast<float4 *>(red);
+    // forward at wave priority 3, adjoint at 0 (as in k_raster_fit)
+    __builtin_amdgcn_s_setprio(3);
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     const uint2 r = ranges[tile];
@@ -673,6 +675,7 @@ __global__ __launch_bounds__(256) void k_alpha_bwd(const float4 *__restrict__ re
         for (int c = 0; c < 3; ++c) D[j][c] = C[c] - Cb[c];  // colour behind the part's start
     }
     __syncthreads();  // xs is read before the reduction rows overwrite it
+    __builtin_amdgcn_s_setprio(0);
     alpha_adjoint(rec, rec_o, slot, rq, (r.y - r.x + ALPHA_PARTS - 1) / ALPHA_PARTS, px, py, Tb,
                   D, g, part, red + q * ALPHA_RED);
 }
@@ -694,6 +697,8 @@ __global__ __launch_bounds__(256) void k_alpha_fit(const float4 *__restrict__ re
     __shared__ __align__(16) float red[ALPHA_PARTS * ALPHA_RED];
     static_assert(ALPHA_PARTS * ALPHA_RED >= 4 * ALPHA_PARTS * TILE_PX, "the part sums fit");
     float4 *xs = reinterpret_cast<float4 *>(red);
+    // forward at wave priority 3, adjoint at 0 (as in k_raster_fit)
+    __builtin_amdgcn_s_setprio(3);
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     const uint2 r = ranges[tile];
@@ -744,6 +749,7 @@ __global__ __launch_bounds__(256) void k_alpha_fit(const float4 *__restrict__ re
         }
     }
     __syncthreads();  // xs is read before the reduction rows overwrite it
+    __builtin_amdgcn_s_setprio(0);
     alpha_adjoint(rec, rec_o, slot, rq, (r.y - r.x + ALPHA_PARTS - 1) / ALPHA_PARTS, px, py, Tb,
                   D, g, part, red + q * ALPHA_RED);
 }
