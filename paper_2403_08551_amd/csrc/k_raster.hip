@@ -329,8 +329,9 @@ __global__ __launch_bounds__(BWD_T) void k_raster_bwd(const float4 *__restrict__
 
 // Fit step for one tile: forward, residual and dL/dC = 2 (C - T) / (3 H W) into LDS, per-tile
 // sum of squared residuals, then the adjoint.
-// The second bound is waves per SIMD: at least four (four workgroups per CU), so the compiler
-// may take up to 128 VGPRs.  Bounded at five waves it took 94 and measured 7% slower at
+// The second bound is waves per SIMD: at least four (four workgroups per CU; a timeline of the
+// launch shows five resident at the 117 VGPRs the compiler takes), so the compiler may take up
+// to 128 VGPRs.  Bounded at five waves it took 94 and measured 7% slower at
 // 768x512 / 70k (111.5 against 104 us): registers buy scheduling here more than a fifth
 // workgroup buys latency hiding.
 template <int PX>
@@ -974,6 +975,7 @@ template <int NTH>
 __device__ inline void tile_order_block(const uint2 *__restrict__ ranges, int64_t T,
                                         uint32_t *__restrict__ order, uint32_t *bin,
                                         uint32_t *wsum) {
+    static_assert(TILE_ORDER_BINS % NTH == 0 && NTH % 64 == 0, "bins split evenly over waves");
     for (int b = threadIdx.x; b < TILE_ORDER_BINS; b += NTH) bin[b] = 0u;
     __syncthreads();
     auto key = [&](int64_t t) {
