@@ -856,39 +856,59 @@ __global__ __launch_bounds__(CS_T) void k_chained_scan(uint32_t *__restrict__ da
         if (w == 0) s_prefix = 0;
     }
     if (w > 0 && threadIdx.x < 64) {
+        // Each lane polls two predecessors (j - lane and j - 64 - lane), both reads issued before
+        // either is awaited, so a launch of up to 129 blocks finds block 0's inclusive prefix in
+        // its first window: one round trip to the status words instead of two.
         const int lane = threadIdx.x;
         unsigned long long excl = 0;
         int64_t j = (int64_t)w - 1;
         bool stalled = false;
+        const unsigned long long before0 = tag | CS_PRE;  // before block 0: prefix 0
+        auto published = [&](unsigned long long st) {
+            return (st & CS_TAG_MASK) == tag && (st & CS_FLAG_MASK) != 0;
+        };
         while (true) {
-            const int64_t q = j - lane;
-            unsigned long long fl = 2, val = 0;  // before block 0: prefix 0
-            if (q >= 0) {
-                long spins = 0;
-                unsigned long long st = load_status(&status[q]);
-                // published in this launch: the tag matches and a flag is set
-                while (((st & CS_TAG_MASK) != tag || (st & CS_FLAG_MASK) == 0) &&
-                       spins < SPIN_LIMIT) {
-                    st = load_status(&status[q]);
-                    ++spins;
-                }
-                if ((st & CS_TAG_MASK) != tag || (st & CS_FLAG_MASK) == 0) {
-                    stalled = true;
-                    fl = 2;
-                    val = 0;
-                } else {
-                    fl = (st >> CS_FLAG_SHIFT) & 3ull;
-                    val = st & CS_VAL;
-                }
+            const int64_t qa = j - lane, qb = j - 64 - lane;
+            unsigned long long sa = load_status(&status[qa >= 0 ? qa : 0]);
+            unsigned long long sb = load_status(&status[qb >= 0 ? qb : 0]);
+            if (qa < 0) sa = before0;
+            if (qb < 0) sb = before0;
+            long spins = 0;
+            while (!published(sa) && spins < SPIN_LIMIT) {
+                sa = load_status(&status[qa]);
+                ++spins;
             }
-            const unsigned long long pre_mask = __ballot(fl == 2);
-            const int first = pre_mask ? __ffsll((long long)pre_mask) - 1 : 64;
-            unsigned long long contrib = lane <= first ? val : 0ull;
+            spins = 0;
+            while (!published(sb) && spins < SPIN_LIMIT) {
+                sb = load_status(&status[qb]);
+                ++spins;
+            }
+            if (!published(sa)) {
+                stalled = true;
+                sa = before0;
+            }
+            if (!published(sb)) {
+                stalled = true;
+                sb = before0;
+            }
+            const unsigned long long fa = (sa >> CS_FLAG_SHIFT) & 3ull, va = sa & CS_VAL;
+            const unsigned long long fb = (sb >> CS_FLAG_SHIFT) & 3ull, vb = sb & CS_VAL;
+            const unsigned long long ma = __ballot(fa == 2), mb = __ballot(fb == 2);
+            unsigned long long contrib;
+            if (ma) {  // the nearest inclusive prefix lies in the first half of the window
+                const int first = __ffsll((long long)ma) - 1;
+                contrib = lane <= first ? va : 0ull;
+            } else if (mb) {
+                const int first = __ffsll((long long)mb) - 1;
+                contrib = va + (lane <= first ? vb : 0ull);
+            } else {
+                contrib = va + vb;
+            }
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) contrib += __shfl_xor(contrib, d, 64);
             excl += contrib;
-            if (pre_mask) break;
-            j -= 64;
+            if (ma | mb) break;
+            j -= 128;
         }
         if (__ballot(stalled) && lane == 0) atomicOr(&state->flags, FLAG_SCAN_STALL);
         if (lane == 0) {
@@ -967,6 +987,11 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
     const uint2 inf_in = tinfo[ir];
     const uint32_t off_in = scan[ir];
     const float4 pa_in = proj[2 * ir], pb_in = proj[2 * ir + 1];  // one-pass: 32-byte stride
+    // the first tile whose range this thread writes (tiles chunk, chunk + nchunk, ...): both
+    // ends' scanned positions, read with the rest (indices clamped, values dropped if unused)
+    const int64_t tr = chunk + (int64_t)threadIdx.x * nchunk;
+    const int64_t tra = tr < T ? tr : T - 1, trb = tr + 1 < T ? tr + 1 : T - 1;
+    const uint32_t ra_in = scan[n + tra * nchunk], rb_in = scan[n + trb * nchunk];
     constexpr int TB_MAX = (int)((FUSED_MAX_TILES + NT - 1) / NT);
     uint32_t tb_in[TB_MAX];
 #pragma unroll
@@ -997,10 +1022,11 @@ __global__ __launch_bounds__(64 * FUSED_WAVES) void k_fused_scatter(
         const int t = (int)threadIdx.x + k * NT;
         if (t < T) tbase[t] = tb_in[k] - K;
     }
-    // tile ranges: this chunk writes tiles chunk, chunk + nchunk, ...
-    for (int64_t t = chunk + (int64_t)threadIdx.x * nchunk; t < T; t += (int64_t)NT * nchunk) {
-        uint32_t a = scan[n + t * nchunk] - K;
-        uint32_t b = t + 1 < T ? scan[n + (t + 1) * nchunk] - K : K;
+    // tile ranges: this chunk writes tiles chunk, chunk + nchunk, ... (the first one per
+    // thread from the values read above)
+    for (int64_t t = tr; t < T; t += (int64_t)NT * nchunk) {
+        uint32_t a = (t == tr ? ra_in : scan[n + t * nchunk]) - K;
+        uint32_t b = t + 1 < T ? (t == tr ? rb_in : scan[n + (t + 1) * nchunk]) - K : K;
         if (a > cap) a = (uint32_t)cap;
         if (b > cap) b = (uint32_t)cap;
         ranges[t] = make_uint2(a, b);
