@@ -329,11 +329,11 @@ __global__ __launch_bounds__(BWD_T) void k_raster_bwd(const float4 *__restrict__
 
 // Fit step for one tile: forward, residual and dL/dC = 2 (C - T) / (3 H W) into LDS, per-tile
 // sum of squared residuals, then the adjoint.
-// The second bound is waves per SIMD: at least four (four workgroups per CU; a timeline of the
-// launch shows five resident at the 117 VGPRs the compiler takes), so the compiler may take up
-// to 128 VGPRs.  Bounded at five waves it took 94 and measured 7% slower at
-// 768x512 / 70k (111.5 against 104 us): registers buy scheduling here more than a fifth
-// workgroup buys latency hiding.
+// The second bound is waves per SIMD: at least four (four workgroups per CU, which is what a
+// timeline of the launch shows resident at the 117 VGPRs the compiler takes: 1024 of the 1536
+// tiles of 768x512 start at once), so the compiler may take up to 128 VGPRs.  Bounded at five
+// waves it took 94 and measured 7% slower at 768x512 / 70k (111.5 against 104 us): registers
+// buy scheduling here more than a fifth workgroup buys latency hiding.
 template <int PX>
 __global__ __launch_bounds__(256, 4) void k_raster_fit(const float4 *__restrict__ rec,
                                                          const uint32_t *__restrict__ slot,
