@@ -33,12 +33,6 @@ constexpr int BWD_T = 256;
 // ---- begin: the fused fit kernel and the device functions it calls ----
 __device__ inline float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// v of this lane plus v of the other lane of its pair (lanes 2j, 2j + 1), one DPP add.
-__device__ inline float pair_add(float v) {
-    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-                                             0, __builtin_bit_cast(int, v), 0xb1, 0xf, 0xf, false));
-}
-
 // One Gaussian's contribution to the PX pixels of this lane (A = mu_x, mu_y, a, b;
 // B = k, c0, c1, c2).  The lane's pixels lie in one column and in one group of four rows
 // starting at row centre py0; pixel j sits of[j] rows below it.  Every pixel's u2 is taken from
@@ -153,82 +147,132 @@ __device__ __forceinline__ void fwd_tile_lds(const float4 *__restrict__ rec, uin
     }
 }
 
-// Adjoint of one tile: one (Gaussian, column parity) task per lane over the tile's list, dL/dC
-// of the tile in LDS.  Lanes 2j and 2j + 1 take the even and the odd columns of the same
-// Gaussian (neighbouring LDS words, so the two broadcast reads hit different banks) and add
-// their sums with one DPP step at the end.  Splitting each Gaussian in two halves the idle
-// lanes of a tile's last round (lists are a few hundred long, rounds are NT lanes wide).
+// The LPG lanes sharing a Gaussian in the adjoint add their values: DPP quad_perm [1, 0, 3, 2]
+// then [2, 3, 0, 1] (every lane of a quad then holds the quad's sum), row_half_mirror (every lane
+// of a group of 8 then holds its sum), row_mirror (every lane of a row of 16 then holds its
+// sum).  The order of the additions is fixed: ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7)),
+// and so on.
+template <int CTRL>
+__device__ inline float dpp_mov(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                         0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, false));
+}
+
+template <int LPG>
+__device__ inline float group_add(float v) {
+    v += dpp_mov<0xb1>(v);                 // quad_perm [1, 0, 3, 2]
+    if (LPG >= 4) v += dpp_mov<0x4e>(v);   // quad_perm [2, 3, 0, 1]
+    if (LPG >= 8) v += dpp_mov<0x141>(v);  // row_half_mirror
+    if (LPG >= 16) v += dpp_mov<0x140>(v); // row_mirror
+    return v;
+}
+
+// One round of the adjoint for this lane: Gaussian i (if act) over the tile's columns
+// LPG k + par (k < 16 / LPG), all 16 rows, dL/dC of the tile in LDS.  The LPG lanes of a
+// Gaussian (lanes LPG j ... LPG j + LPG - 1, neighbouring LDS words, so the broadcast reads hit
+// different banks) add their sums at the end and the group's first lane stores them.
 // Per pixel, with w = exp(-sigma) <dL/dC, c'>: the colour sums D += e g, then w, sum w u2 and
 // sum w u2^2, each product formed per pixel (no difference of larger sums, which would lose
 // the relative accuracy of a single term).  The column's sum of w is <D, c'> (the colour sums
 // are needed anyway), not a per-pixel sum.
-template <int NT>
-__device__ inline void bwd_tile(const float4 *__restrict__ rec, const uint32_t *__restrict__ slot,
-                                uint2 r, const TileInfo &ti, const float4 *sg,
-                                float4 *__restrict__ part) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int par = lane & 1;
+template <int LPG>
+__device__ __forceinline__ void bwd_round(const float4 *__restrict__ rec,
+                                          const uint32_t *__restrict__ slot, uint32_t i, bool act,
+                                          int par, const TileInfo &ti, const float4 *sg,
+                                          float4 *__restrict__ part) {
     const float x0 = (float)(ti.tx * TILE + par) + 0.5f;
     const float y0 = (float)(ti.ty * TILE) + 0.5f;
-    for (uint32_t c = r.x + (uint32_t)wave * 32u; c < r.y; c += NT / 2) {
-        const uint32_t i = c + (uint32_t)(lane >> 1);
-        const bool act = i < r.y;
-        float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
-        if (act) {
-            A = rec[2 * i];
-            B = rec[2 * i + 1];
-        }
-        float dy[TILE];
-#pragma unroll
-        for (int rr = 0; rr < TILE; ++rr) dy[rr] = (y0 + (float)rr) - A.y;
-        float C0 = 0.f, C1 = 0.f, C2 = 0.f, P1 = 0.f, P2 = 0.f, Q11 = 0.f, Q12 = 0.f, Q22 = 0.f;
-        float dx = x0 - A.x;  // this lane's column 2k + par: dx advances by 2 per column
-        for (int k = 0; k < TILE / 2; ++k) {
-            const int cc = 2 * k + par;
-            const float u1 = A.z * dx;
-            const float u1s = u1 * u1;
-            const float t = B.x * dx;
-            float D0 = 0.f, D1 = 0.f, D2 = 0.f, WU2 = 0.f, WU22 = 0.f;
-#pragma unroll
-            for (int rr = 0; rr < TILE; ++rr) {
-                const float4 g = sg[rr * TILE + cc];
-                const float u2 = fmaf(dy[rr], A.w, -t);
-                const float e = ex2(-fmaf(u2, u2, u1s));
-                D0 = fmaf(g.x, e, D0);
-                D1 = fmaf(g.y, e, D1);
-                D2 = fmaf(g.z, e, D2);
-                const float gc = fmaf(g.z, B.w, fmaf(g.y, B.z, g.x * B.y));
-                const float wu2 = (e * gc) * u2;  // -dL/dsigma of this pixel times u2
-                WU2 += wu2;
-                WU22 = fmaf(wu2, u2, WU22);
-            }
-            // the column's sum of w from its colour sums: sum_r e <g, c'> = <sum_r e g, c'>
-            const float Wc = fmaf(B.w, D2, fmaf(B.z, D1, B.y * D0));
-            C0 += D0;
-            C1 += D1;
-            C2 += D2;
-            P1 = fmaf(u1, Wc, P1);
-            Q11 = fmaf(u1s, Wc, Q11);
-            Q12 = fmaf(u1, WU2, Q12);
-            P2 += WU2;
-            Q22 += WU22;
-            dx += 2.0f;
-        }
-        // even lane + odd lane (quad_perm [1, 0, 3, 2])
-        C0 = pair_add(C0);
-        C1 = pair_add(C1);
-        C2 = pair_add(C2);
-        P1 = pair_add(P1);
-        P2 = pair_add(P2);
-        Q11 = pair_add(Q11);
-        Q12 = pair_add(Q12);
-        Q22 = pair_add(Q22);
-        if (act && par == 0) {
-            const int64_t sl = slot[i];
-            part[2 * sl] = make_float4(C0, C1, C2, P1);
-            part[2 * sl + 1] = make_float4(P2, Q11, Q12, Q22);
-        }
+    float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
+    if (act) {
+        A = rec[2 * i];
+        B = rec[2 * i + 1];
     }
+    float dy[TILE];
+#pragma unroll
+    for (int rr = 0; rr < TILE; ++rr) dy[rr] = (y0 + (float)rr) - A.y;
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, P1 = 0.f, P2 = 0.f, Q11 = 0.f, Q12 = 0.f, Q22 = 0.f;
+    float dx = x0 - A.x;  // this lane's column LPG k + par: dx advances by LPG per column
+    for (int k = 0; k < TILE / LPG; ++k) {
+        const int cc = LPG * k + par;
+        const float u1 = A.z * dx;
+        const float u1s = u1 * u1;
+        const float t = B.x * dx;
+        float D0 = 0.f, D1 = 0.f, D2 = 0.f, WU2 = 0.f, WU22 = 0.f;
+#pragma unroll
+        for (int rr = 0; rr < TILE; ++rr) {
+            const float4 g = sg[rr * TILE + cc];
+            const float u2 = fmaf(dy[rr], A.w, -t);
+            const float e = ex2(-fmaf(u2, u2, u1s));
+            D0 = fmaf(g.x, e, D0);
+            D1 = fmaf(g.y, e, D1);
+            D2 = fmaf(g.z, e, D2);
+            const float gc = fmaf(g.z, B.w, fmaf(g.y, B.z, g.x * B.y));
+            const float wu2 = (e * gc) * u2;  // -dL/dsigma of this pixel times u2
+            WU2 += wu2;
+            WU22 = fmaf(wu2, u2, WU22);
+        }
+        // the column's sum of w from its colour sums: sum_r e <g, c'> = <sum_r e g, c'>
+        const float Wc = fmaf(B.w, D2, fmaf(B.z, D1, B.y * D0));
+        C0 += D0;
+        C1 += D1;
+        C2 += D2;
+        P1 = fmaf(u1, Wc, P1);
+        Q11 = fmaf(u1s, Wc, Q11);
+        Q12 = fmaf(u1, WU2, Q12);
+        P2 += WU2;
+        Q22 += WU22;
+        dx += (float)LPG;
+    }
+    C0 = group_add<LPG>(C0);
+    C1 = group_add<LPG>(C1);
+    C2 = group_add<LPG>(C2);
+    P1 = group_add<LPG>(P1);
+    P2 = group_add<LPG>(P2);
+    Q11 = group_add<LPG>(Q11);
+    Q12 = group_add<LPG>(Q12);
+    Q22 = group_add<LPG>(Q22);
+    if (act && par == 0) {
+        const int64_t sl = slot[i];
+        part[2 * sl] = make_float4(C0, C1, C2, P1);
+        part[2 * sl + 1] = make_float4(P2, Q11, Q12, Q22);
+    }
+}
+
+// Adjoint of one tile by NT threads.  Rounds of NT / 2 Gaussians, two lanes per Gaussian (even
+// and odd columns), wave w taking Gaussians w 32 ... w 32 + 31 of each round.  A remainder of at
+// most NT / 4 Gaussians after the whole rounds takes one round with 4, 8 or 16 lanes per
+// Gaussian (the fewest that keep every Gaussian in it: 4 up to NT / 4 Gaussians, 8 up to NT / 8,
+// 16 up to NT / 16), each lane then covering 4, 2 or 1 columns: that round costs a half, a
+// quarter or an eighth of a full one, where a full round mostly of idle lanes would cost it all
+// (a list of L Gaussians otherwise pays ceil(L / (NT / 2)) full rounds).
+template <int NT>
+__device__ __forceinline__ void bwd_tile(const float4 *__restrict__ rec, const uint32_t *__restrict__ slot,
+                                uint2 r, const TileInfo &ti, const float4 *sg,
+                                float4 *__restrict__ part) {
+    constexpr uint32_t FULL = NT / 2, WAVES = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t L = r.y - r.x;
+    const uint32_t rem = L % FULL;
+    // rounds of two lanes per Gaussian: the whole ones, and the remainder when it is large
+    const uint32_t end2 = r.x + (L - rem) + (rem > FULL / 2 ? rem : 0u);
+    for (uint32_t c = r.x + (uint32_t)wave * 32u; c < end2; c += FULL) {
+        const uint32_t i = c + (uint32_t)(lane >> 1);
+        bwd_round<2>(rec, slot, i, i < end2, lane & 1, ti, sg, part);
+    }
+    const uint32_t left = r.y - end2;  // 0, or the remainder of at most FULL / 2
+    if (left == 0) return;
+    if (left > FULL / 4) {
+        const uint32_t i = end2 + (uint32_t)wave * (64u / 4u) + (uint32_t)(lane >> 2);
+        bwd_round<4>(rec, slot, i, i < r.y, lane & 3, ti, sg, part);
+    } else if (left > FULL / 8) {
+        const uint32_t i = end2 + (uint32_t)wave * (64u / 8u) + (uint32_t)(lane >> 3);
+        bwd_round<8>(rec, slot, i, i < r.y, lane & 7, ti, sg, part);
+    } else {
+        const uint32_t i = end2 + (uint32_t)wave * (64u / 16u) + (uint32_t)(lane >> 4);
+        bwd_round<16>(rec, slot, i, i < r.y, lane & 15, ti, sg, part);
+    }
+    static_assert(WAVES * (64 / 4) == FULL / 2 && WAVES * (64 / 16) == FULL / 8,
+                  "a tail round holds the remainder it is chosen for");
 }
 
 // Part q of a tile's list: [r.x + floor(q L / PARTS), r.x + floor((q + 1) L / PARTS)).
