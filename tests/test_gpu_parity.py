@@ -312,6 +312,35 @@ def test_fit_step_gradients_element_by_element(gi, which):
     assert gi.query(clear=True)[1] == 0
 
 
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 31, 33, 63, 64, 65, 127, 128, 129, 161, 193, 255,
+                               257, 320])
+def test_adjoint_round_tails(gi, n):
+    # one 16x16 tile whose list holds every Gaussian: n covers whole rounds of 128 Gaussians
+    # and remainders taken by rounds of 2, 4, 8 and 16 lanes per Gaussian; the standalone
+    # gradient (gi_grad) and the fused fit kernel's (first moment at beta1 = 0) against the oracle
+    import paper_2403_08551_amd as P
+    h = wd = 16
+    p0 = synth.gaussians(n, h, wd, seed=500 + n)
+    T = synth.target_noise_rects(h, wd, seed=600 + n)
+    G = synth.upstream_gradient(h, wd, 700 + n)
+    b = gi.binning(dev(p0), h, wd)
+    assert host(b["ranges"]).tolist() == [[0, n]]
+    d = host(gi.grad(dev(p0), h, wd, dev(G)))
+    og, Ag = ref.grads(p0, h, wd, G, with_abs=True)
+    assert_grads(d, og, Ag, f"one tile, {n} Gaussians")
+    o, A = ref.render_culled(p0, h, wd, with_abs=True)
+    g, bound = pu.grad_bound(ref.grads, p0, h, wd, ref.mse_grad(o, T), A)
+    hp = pu.linear_hp(pu.lr_for(p0, bound, [0, 1]), pu.lr_for(p0, bound, [2, 3, 4]),
+                      pu.lr_for(p0, bound, [5, 6, 7]))
+    pd = dev(p0)
+    md, vd = torch.zeros_like(pd), torch.zeros_like(pd)
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    gi.query(clear=True)
+    gi.fit_step(pd, md, vd, dev(T), step, P.AdamConfig(**hp))
+    pu.assert_gradient(host(md), g, bound, f"one tile, {n} Gaussians, fused gradient")
+    assert gi.query(clear=True)[1] == 0
+
+
 # ------------------------------------------------------------------ batched == plain
 
 def small_batch():
