@@ -307,6 +307,8 @@ def batched_vs_plain(ctx, inputs, steps, P, torch, np):
     m, v = torch.zeros_like(allp), torch.zeros_like(allp)
     step = torch.ones(1, dtype=torch.int32, device=dev)
     loss_b = torch.empty(images, device=dev)
+    # the batch's own schedule (its size class); the plain fits keep the default schedule
+    tuned = ctx.autotune(allp, allt, batch=batch, reps=3)
     g = ctx.fit_graph(allp, m, v, allt, step, batch=batch, loss_out=loss_b)
     g.launch(1)
     torch.cuda.synchronize()
@@ -349,7 +351,7 @@ def batched_vs_plain(ctx, inputs, steps, P, torch, np):
             "pixels": int(batch.n_pix), "batched_s": t_batched, "plain_s": t_plain,
             "speedup": t_plain / t_batched,
             "batched_image_steps_per_s": images * steps / t_batched,
-            "final_mse_max_rel_diff": float(rel.max()),
+            "final_mse_max_rel_diff": float(rel.max()), "batch_schedule": tuned,
             "images_within_1e-3": int((rel <= 1e-3).sum()),
             "params_bit_identical": bool(same_params)}
 
@@ -419,6 +421,7 @@ def apply_schedule(P, ctx, sched):
     ctx.set_option(P._lib.GI_OPT_FWD_PIXELS, sched["fwd_pixels"])
     ctx.set_option(P._lib.GI_OPT_SORT_BITS, sched["sort_bits"])
     ctx.set_option(P._lib.GI_OPT_TILE_ORDER, sched["tile_order"])
+    ctx.set_option(P._lib.GI_OPT_FIT_WAVES, sched["fit_waves"])
 
 
 def rotation_scale_leg(P, torch, w, steps, tuned):
@@ -694,6 +697,8 @@ def main():
     # ---- tune the kernel settings for this size class, then capture and replay fit steps
     tuned = ctx.autotune(params0, target, reps=5) if not args.no_tune else None
     px_used = (tuned or {}).get("fwd_pixels") or 4
+    waves_used = (tuned or {}).get("fit_waves") or 4
+    fit_kernel = f"k_raster_fit<{px_used}, {waves_used}>"
     params = params0.clone()
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
@@ -816,10 +821,10 @@ def main():
                      "render_binning": rbin_ms / max(rbin_n, 1),
                      "raster_fwd": fwd_ms / max(fwd_n, 1)},
         "loss": {"after_warmup": loss_start, "after_timed": loss_end},
-        "roofline": dict(roof, traffic=measured_traffic(f"k_raster_fit<{px_used}>", w.name),
-                         **issued_fraction(executed_per_pair(f"k_raster_fit<{px_used}>", w.name),
+        "roofline": dict(roof, traffic=measured_traffic(fit_kernel, w.name),
+                         **issued_fraction(executed_per_pair(fit_kernel, w.name),
                                            P_prof, fit_ms / fit_n / 1e3, pk),
-                         kernel=f"k_raster_fit<{px_used}>", pairs_per_launch=P_prof,
+                         kernel=fit_kernel, pairs_per_launch=P_prof,
                          avg_launch_ms=fit_ms / fit_n),
         "render_roofline": dict(fwd_roof, kernel=f"k_raster_fwd<{px_used}>",
                                 pairs_per_launch=P_pairs,

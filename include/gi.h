@@ -106,7 +106,7 @@ enum {
     GI_OPT_COVARIANCE = 6,    /* how params[2..4] describe Sigma (Sec. 3.1): GI_COV_CHOLESKY
                                  (default) or GI_COV_ROTATION_SCALE; read by every later call,
                                  and fixed into a captured step when it is created */
-    GI_OPT_TILE_ORDER = 7     /* order in which the raster workgroups take the tiles: 0 = auto
+    GI_OPT_TILE_ORDER = 7,    /* order in which the raster workgroups take the tiles: 0 = auto
                                  (tuned, else 3 up to 16384 tiles and 1 above), 1 = tile index,
                                  2 = longest list first (one small sorting kernel after the
                                  binning), 3 = longest list first by the previous fit step's
@@ -115,6 +115,11 @@ enum {
                                  previous one's sorts once as with 2, and above 16384 tiles that
                                  first order stays).  Never changes a result: each tile's
                                  arithmetic is the same in any order */
+    GI_OPT_FIT_WAVES = 8      /* resident waves per SIMD the fused fit kernel is compiled for:
+                                 0 = auto (tuned, else 4), 4 (up to 128 VGPRs: the most
+                                 registers for scheduling) or 6 (up to 80 VGPRs: more tiles in
+                                 flight, which pays when tile lists are short).  Never changes a
+                                 result: the two builds execute the same arithmetic */
 };
 
 /* Values of GI_OPT_COVARIANCE. */
@@ -153,12 +158,14 @@ int gi_get_option(gi_ctx *ctx, int option, int64_t *value);
 
 /* A schedule of the tunable knobs (0 = the knob's automatic rule): binning path (GI_OPT_BINNING
  * values 1..3), forward pixels per lane (1, 2, 4), radix digit width (radix path only), tile
- * order (GI_OPT_TILE_ORDER values 1, 2, 3); ms_per_step is the fit step time it was chosen with. */
+ * order (GI_OPT_TILE_ORDER values 1, 2, 3), fit kernel waves per SIMD (GI_OPT_FIT_WAVES values
+ * 4, 6); ms_per_step is the fit step time it was chosen with. */
 typedef struct gi_schedule {
     int32_t binning;
     int32_t fwd_pixels;
     int32_t sort_bits;
     int32_t tile_order;
+    int32_t fit_waves;
     float ms_per_step;
 } gi_schedule;
 
@@ -166,8 +173,8 @@ typedef struct gi_schedule {
  * width; else the batch) under the tunable knobs, one knob at a time in this order, each
  * starting from the best of the knobs before it: the binning path (one pass when the tiles
  * number at most 2048, row binning when the images allow it, radix always), the radix digit
- * width (automatic, 4, 6, 8, 11; radix path only), forward pixels per lane (1, 2, 4) and the
- * tile order (index, longest list first).  Runs on scratch copies of the parameters (the
+ * width (automatic, 4, 6, 8, 11; radix path only), forward pixels per lane (1, 2, 4), the
+ * tile order (index, longest list first) and the fit kernel's waves per SIMD (4, 6).  Runs on scratch copies of the parameters (the
  * caller's buffers are read, never written) with zero learning rates, so every timed step does
  * the same work: one untimed step, then `reps` timed steps per trial.  After three untimed
  * trials of the default schedule (clocks and caches warm up), each candidate is timed in turn

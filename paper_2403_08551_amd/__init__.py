@@ -270,7 +270,7 @@ class Context:
     def autotune(self, params, target, batch: Batch | None = None, reps: int = 5) -> dict:
         """Time the tunable knobs on fit steps of this workload (scratch copies, see
         gi_autotune) and keep the fastest schedule for its size class; returns it as a dict
-        (binning, fwd_pixels, sort_bits, tile_order, ms_per_step)."""
+        (binning, fwd_pixels, sort_bits, tile_order, fit_waves, ms_per_step)."""
         if batch is None:
             h, w = target.shape[0], target.shape[1]
             n = params.shape[0]

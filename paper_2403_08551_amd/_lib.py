@@ -30,6 +30,7 @@ GI_OPT_FWD_PIXELS = 3
 GI_OPT_BINNING = 4
 GI_OPT_TIMING = 5
 GI_OPT_TILE_ORDER = 7
+GI_OPT_FIT_WAVES = 8
 GI_OPT_COVARIANCE = 6
 
 GI_BLEND_SUM = 1
@@ -72,7 +73,7 @@ class gi_adam(ctypes.Structure):
 class gi_schedule(ctypes.Structure):
     _fields_ = [("binning", ctypes.c_int32), ("fwd_pixels", ctypes.c_int32),
                 ("sort_bits", ctypes.c_int32), ("tile_order", ctypes.c_int32),
-                ("ms_per_step", ctypes.c_float)]
+                ("fit_waves", ctypes.c_int32), ("ms_per_step", ctypes.c_float)]
 
 
 class gi_batch(ctypes.Structure):

@@ -366,7 +366,7 @@ hipError_t launch_raster_bwd(const RasterArgs &a, const float *dl_dimage, float 
 // the step number as *step - 1.
 hipError_t launch_raster_fit(const RasterArgs &a, const float *target, float *part,
                              float *image_out, float *loss_part, int px_per_lane,
-                             int32_t *step_inc, hipStream_t s);
+                             int waves_per_simd, int32_t *step_inc, hipStream_t s);
 // Alpha blending (BLEND_ALPHA): rec_o [cap] holds the opacities in tile order; part12 has
 // three float4 per key (colour sums, P1; P2, Q11, Q12, Q22; opacity sum).
 hipError_t launch_alpha_fwd(const RasterArgs &a, const float *rec_o, float *image, hipStream_t s);

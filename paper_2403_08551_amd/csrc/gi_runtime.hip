@@ -24,6 +24,7 @@ struct Schedule {
     int px = 0;       // forward pixels per lane
     int digit = 0;    // radix digit width
     int order = 0;    // 1 tile index, 2 longest list first
+    int waves = 0;    // fit kernel waves per SIMD: 4 or 6
     float ms = 0.f;   // measured time per fit step
 };
 
@@ -35,6 +36,7 @@ struct gi_ctx {
     int binning = 0;
     int order = 0;           // GI_OPT_TILE_ORDER: 0 auto, 1 tile index, 2 longest list first,
                              // 3 longest first by the previous fit step's lists
+    int fit_waves = 0;       // GI_OPT_FIT_WAVES: 0 auto, 4 or 6
     int cov = COV_CHOLESKY;  // GI_OPT_COVARIANCE
     const CodecArgs *codec = nullptr;  // set for the duration of a codec render
     const float *opac_cur = nullptr;   // set for the duration of an opacity render / grad
@@ -456,6 +458,12 @@ int pick_px(gi_ctx *ctx, int64_t n, int64_t n_pix) {
     return t && t->px ? t->px : 4;
 }
 
+int pick_fit_waves(gi_ctx *ctx, int64_t n, int64_t n_pix) {
+    if (ctx->fit_waves) return ctx->fit_waves;
+    const Schedule *t = tuned_for(ctx, n, n_pix);
+    return t && t->waves ? t->waves : 4;
+}
+
 int pick_digit(gi_ctx *ctx, int64_t n, int64_t n_pix, int key_bits, int64_t keys) {
     if (ctx->sort_bits) return ctx->sort_bits;
     const Schedule *t = tuned_for(ctx, n, n_pix);
@@ -809,7 +817,8 @@ int do_fit(gi_ctx *ctx, float *params, float *m, float *v, const float *target, 
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
     CK(set_order(ctx, a, n, tab, n_tiles, s));
     CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
-                         pick_px(ctx, n, table_pixels(tab, n_tiles)), step, s));
+                         pick_px(ctx, n, table_pixels(tab, n_tiles)),
+                         pick_fit_waves(ctx, n, table_pixels(tab, n_tiles)), step, s));
     tm.stop();
     UpdateArgs u{params, params, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k,
                  ctx->cov};
@@ -900,7 +909,8 @@ int do_fit_opacity(gi_ctx *ctx, float *params, float *opacity, float *m, float *
         CK(launch_alpha_fit(a, ctx->rec_o, target, part, image_out, ctx->loss_part, step, s));
     else
         CK(launch_raster_fit(a, target, part, image_out, ctx->loss_part,
-                             pick_px(ctx, n, table_pixels(tab, n_tiles)), step, s));
+                             pick_px(ctx, n, table_pixels(tab, n_tiles)),
+                         pick_fit_waves(ctx, n, table_pixels(tab, n_tiles)), step, s));
     tm.stop();
     UpdateArgs u{params, params, n, ctx->count, ctx->off_cur, part, ctx->state, ctx->cap_k,
                  ctx->cov};
@@ -928,7 +938,8 @@ int do_fit_recipe(gi_ctx *ctx, float *raw, float *state, const float *target, in
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
     CK(set_order(ctx, a, n, tab, n_tiles, s));
     CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
-                         pick_px(ctx, n, table_pixels(tab, n_tiles)), step, s));
+                         pick_px(ctx, n, table_pixels(tab, n_tiles)),
+                         pick_fit_waves(ctx, n, table_pixels(tab, n_tiles)), step, s));
     tm.stop();
     UpdateArgs u{raw, raw, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k,
                  ctx->cov};
@@ -983,7 +994,8 @@ int do_fit_qat(gi_ctx *ctx, float *params, float *m, float *v, const float *targ
     StageTimer tm(ctx, s, GI_STAGE_RASTER_FIT);
     CK(set_order(ctx, a, n, tab, n_tiles, s));
     CK(launch_raster_fit(a, target, ctx->part, image_out, ctx->loss_part,
-                         pick_px(ctx, n, table_pixels(tab, n_tiles)), step, s));
+                         pick_px(ctx, n, table_pixels(tab, n_tiles)),
+                         pick_fit_waves(ctx, n, table_pixels(tab, n_tiles)), step, s));
     tm.stop();
     UpdateArgs u{params, params, n, ctx->count, ctx->off_cur, ctx->part, ctx->state, ctx->cap_k,
                  ctx->cov};
@@ -1116,6 +1128,10 @@ int gi_set_option(gi_ctx *ctx, int option, int64_t value) {
             if (value < 0 || value > 3) return GI_ERR_INVALID_ARG;
             ctx->order = (int)value;
             return GI_OK;
+        case GI_OPT_FIT_WAVES:
+            if (value != 0 && value != 4 && value != 6) return GI_ERR_INVALID_ARG;
+            ctx->fit_waves = (int)value;
+            return GI_OK;
         default:
             return GI_ERR_INVALID_ARG;
     }
@@ -1157,6 +1173,7 @@ int gi_get_option(gi_ctx *ctx, int option, int64_t *value) {
         case GI_OPT_TIMING: *value = ctx->timing; return GI_OK;
         case GI_OPT_COVARIANCE: *value = ctx->cov; return GI_OK;
         case GI_OPT_TILE_ORDER: *value = ctx->order; return GI_OK;
+        case GI_OPT_FIT_WAVES: *value = ctx->fit_waves; return GI_OK;
         default: return GI_ERR_INVALID_ARG;
     }
 }
@@ -1187,8 +1204,9 @@ int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n
     const size_t bytes = sizeof(float) * 8 * (size_t)std::max<int64_t>(n, 1);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = GI_OK;
-    struct Saved { int sync, px, bits, binning, order, timing; } sv{
-        ctx->sync, ctx->fwd_px, ctx->sort_bits, ctx->binning, ctx->order, ctx->timing};
+    struct Saved { int sync, px, bits, binning, order, waves, timing; } sv{
+        ctx->sync, ctx->fwd_px, ctx->sort_bits, ctx->binning, ctx->order, ctx->fit_waves,
+        ctx->timing};
     auto cleanup = [&]() {
         if (p) (void)hipFree(p);
         if (m) (void)hipFree(m);
@@ -1197,7 +1215,8 @@ int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         ctx->sync = sv.sync; ctx->fwd_px = sv.px; ctx->sort_bits = sv.bits;
-        ctx->binning = sv.binning; ctx->order = sv.order; ctx->timing = sv.timing;
+        ctx->binning = sv.binning; ctx->order = sv.order; ctx->fit_waves = sv.waves;
+        ctx->timing = sv.timing;
     };
     hipError_t e = hipMalloc((void **)&p, bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&m, bytes);
@@ -1217,6 +1236,7 @@ int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n
         ctx->fwd_px = sc.px;
         ctx->sort_bits = sc.digit;
         ctx->order = sc.order;
+        ctx->fit_waves = sc.waves;
         // one synchronous binning pass sizes this path's buffers; then no step waits
         ctx->sync = 1;
         int64_t bound;
@@ -1265,6 +1285,7 @@ int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n
     best.binning = paths[0];
     best.px = 4;
     best.order = 3;
+    best.waves = 4;
     {
         float junk = 0.f;
         for (int k = 0; k < 3 && rc == GI_OK; ++k) rc = trial(best, &junk);
@@ -1317,13 +1338,19 @@ int gi_autotune(gi_ctx *ctx, const float *params, const float *target, int64_t n
         }
     }
     if (rc == GI_OK) {
+        Schedule sc = best;
+        sc.waves = 6;
+        rc = consider(sc);
+    }
+    if (rc == GI_OK) {
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) rc = hip_fail(ctx, e, "gi_autotune sync");
     }
     cleanup();
     if (rc != GI_OK) return rc;
     ctx->tuned[key] = best;
-    if (chosen) *chosen = gi_schedule{best.binning, best.px, best.digit, best.order, best.ms};
+    if (chosen)
+        *chosen = gi_schedule{best.binning, best.px, best.digit, best.order, best.waves, best.ms};
     return GI_OK;
 }
 
@@ -1337,10 +1364,10 @@ int gi_autotune_save(gi_ctx *ctx, const char *path) {
         ok = ok && fprintf(f,
                            "{\"arch\": \"%s\", \"cov\": %d, \"n_class\": %d, \"pix_class\": %d, "
                            "\"binning\": %d, \"fwd_pixels\": %d, \"sort_bits\": %d, "
-                           "\"tile_order\": %d, \"ms_per_step\": %.6f}\n",
+                           "\"tile_order\": %d, \"fit_waves\": %d, \"ms_per_step\": %.6f}\n",
                            ctx->arch.c_str(), std::get<0>(kv.first), std::get<1>(kv.first),
                            std::get<2>(kv.first), sc.binning, sc.px, sc.digit, sc.order,
-                           (double)sc.ms) > 0;
+                           sc.waves, (double)sc.ms) > 0;
     }
     ok = (fclose(f) == 0) && ok;
     return ok ? GI_OK : GI_ERR_INVALID_ARG;
@@ -1363,16 +1390,16 @@ int gi_autotune_load(gi_ctx *ctx, const char *path, int32_t *loaded) {
             continue;
         }
         if (ctx->arch != arch) continue;
-        int cov, nc, pc, bin, px, bits, order;
+        int cov, nc, pc, bin, px, bits, order, waves;
         float ms;
         const int k = sscanf(line,
                              " {\"arch\": \"%*[^\"]\", \"cov\": %d, \"n_class\": %d, \"pix_class\": "
                              "%d, \"binning\": %d, \"fwd_pixels\": %d, \"sort_bits\": %d, "
-                             "\"tile_order\": %d, \"ms_per_step\": %f}",
-                             &cov, &nc, &pc, &bin, &px, &bits, &order, &ms);
-        if (k != 8 || (cov != GI_COV_CHOLESKY && cov != GI_COV_ROTATION_SCALE) || bin < 0 ||
+                             "\"tile_order\": %d, \"fit_waves\": %d, \"ms_per_step\": %f}",
+                             &cov, &nc, &pc, &bin, &px, &bits, &order, &waves, &ms);
+        if (k != 9 || (cov != GI_COV_CHOLESKY && cov != GI_COV_ROTATION_SCALE) || bin < 0 ||
             bin > 3 || (px != 0 && px != 1 && px != 2 && px != 4) || bits < 0 || bits > 11 ||
-            order < 0 || order > 3) {
+            order < 0 || order > 3 || (waves != 0 && waves != 4 && waves != 6)) {
             rc = GI_ERR_INVALID_ARG;
             continue;
         }
@@ -1381,6 +1408,7 @@ int gi_autotune_load(gi_ctx *ctx, const char *path, int32_t *loaded) {
         sc.px = px;
         sc.digit = bits;
         sc.order = order;
+        sc.waves = waves;
         sc.ms = ms;
         got.push_back({std::make_tuple(cov, nc, pc), sc});
     }
@@ -1683,6 +1711,7 @@ int capture_step(gi_ctx *user, const float *params, int64_t n, int32_t H, int32_
     ctx->fwd_px = user->fwd_px;
     ctx->binning = user->binning;
     ctx->order = user->order;
+    ctx->fit_waves = user->fit_waves;
     ctx->cov = user->cov;
     ctx->tuned = user->tuned;
     gi_graph *gr = new gi_graph();

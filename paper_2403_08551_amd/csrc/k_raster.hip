@@ -373,13 +373,15 @@ __global__ __launch_bounds__(BWD_T) void k_raster_bwd(const float4 *__restrict__
 
 // Fit step for one tile: forward, residual and dL/dC = 2 (C - T) / (3 H W) into LDS, per-tile
 // sum of squared residuals, then the adjoint.
-// The second bound is waves per SIMD: at least four (four workgroups per CU, which is what a
-// timeline of the launch shows resident at the 117 VGPRs the compiler takes: 1024 of the 1536
-// tiles of 768x512 start at once), so the compiler may take up to 128 VGPRs.  Bounded at five
-// waves it took 94 and measured 7% slower at 768x512 / 70k (111.5 against 104 us): registers
-// buy scheduling here more than a fifth workgroup buys latency hiding.
-template <int PX>
-__global__ __launch_bounds__(256, 4) void k_raster_fit(const float4 *__restrict__ rec,
+// The second bound is waves per SIMD, WAVES of them.  With four (four workgroups per CU, which
+// is what a timeline of the launch shows resident at the 124 VGPRs the compiler takes: 1024 of
+// the 1536 tiles of 768x512 start at once) the compiler may take up to 128 VGPRs; bounded at
+// five it took 94 and measured 7% slower at 768x512 / 70k (111.5 against 104 us): there the
+// registers buy scheduling more than a fifth workgroup buys latency hiding.  With six (80 VGPRs)
+// more tiles are in flight, which pays when the lists are short (a batch of small images), so
+// both builds exist and the autotuner picks one per size class.
+template <int PX, int WAVES>
+__global__ __launch_bounds__(256, WAVES) void k_raster_fit(const float4 *__restrict__ rec,
                                                          const uint32_t *__restrict__ slot,
                                                          const uint2 *__restrict__ ranges,
                                                          ImgTable tab,
@@ -1503,16 +1505,29 @@ hipError_t launch_raster_bwd(const RasterArgs &a, const float *dl, float *part, 
 }
 
 hipError_t launch_raster_fit(const RasterArgs &a, const float *target, float *part,
-                             float *image_out, float *loss_part, int px, int32_t *step_inc,
-                             hipStream_t s) {
+                             float *image_out, float *loss_part, int px, int waves,
+                             int32_t *step_inc, hipStream_t s) {
     if (a.n_tiles <= 0) return hipSuccess;
     const float4 *rec = reinterpret_cast<const float4 *>(a.rec);
     float4 *p4 = reinterpret_cast<float4 *>(part);
-    switch (px) {
-        case 1: hipLaunchKernelGGL(k_raster_fit<1>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc, a.order); break;
-        case 4: hipLaunchKernelGGL(k_raster_fit<4>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc, a.order); break;
-        default: hipLaunchKernelGGL(k_raster_fit<2>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc, a.order); break;
+#define GI_LAUNCH_FIT(PX, WV)                                                                   \
+    hipLaunchKernelGGL((k_raster_fit<PX, WV>), dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, \
+                       a.slot, a.ranges, a.tab, target, p4, image_out, loss_part, step_inc,     \
+                       a.order)
+    if (waves == 6) {
+        switch (px) {
+            case 1: GI_LAUNCH_FIT(1, 6); break;
+            case 4: GI_LAUNCH_FIT(4, 6); break;
+            default: GI_LAUNCH_FIT(2, 6); break;
+        }
+    } else {
+        switch (px) {
+            case 1: GI_LAUNCH_FIT(1, 4); break;
+            case 4: GI_LAUNCH_FIT(4, 4); break;
+            default: GI_LAUNCH_FIT(2, 4); break;
+        }
     }
+#undef GI_LAUNCH_FIT
     return hipGetLastError();
 }
 

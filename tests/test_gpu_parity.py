@@ -801,9 +801,10 @@ def test_autotune_reads_but_never_writes_and_keeps_results_exact(gi):
     sc = gi.autotune(p, T, reps=2)
     assert sc["binning"] in (1, 2, 3) and sc["fwd_pixels"] in (1, 2, 4)
     assert sc["sort_bits"] in (0, 4, 6, 8, 11) and sc["tile_order"] in (1, 2, 3)
-    assert sc["ms_per_step"] > 0
+    assert sc["fit_waves"] in (4, 6) and sc["ms_per_step"] > 0
     np.testing.assert_array_equal(host(p), before)
-    for opt in (P._lib.GI_OPT_FWD_PIXELS, P._lib.GI_OPT_BINNING, P._lib.GI_OPT_TILE_ORDER):
+    for opt in (P._lib.GI_OPT_FWD_PIXELS, P._lib.GI_OPT_BINNING, P._lib.GI_OPT_TILE_ORDER,
+                P._lib.GI_OPT_FIT_WAVES):
         assert gi.get_option(opt) == 0  # explicit options untouched
     np.testing.assert_array_equal(host(gi.render(p, w.height, w.width)), ref_img)
 
@@ -815,17 +816,19 @@ def _schedules(tiles, rows_ok=True):
     for b in paths:
         for px in (1, 2, 4):
             for order in (1, 2, 3):
-                out.append((b, px, 0, order))
+                for waves in (4, 6):
+                    out.append((b, px, 0, order, waves))
         if b == 1:
-            out += [(1, 4, d, 2) for d in (4, 6, 8, 11)]
+            out += [(1, 4, d, 2, 4) for d in (4, 6, 8, 11)]
     return out
 
 
 def _run_schedule(P, sched, p0, T, h, w, G, batch=None):
     ctx = P.Context(0)
     try:
-        b, px, digit, order = sched
+        b, px, digit, order, waves = sched
         ctx.set_option(P._lib.GI_OPT_BINNING, b)
+        ctx.set_option(P._lib.GI_OPT_FIT_WAVES, waves)
         ctx.set_option(P._lib.GI_OPT_FWD_PIXELS, px)
         ctx.set_option(P._lib.GI_OPT_SORT_BITS, digit)
         ctx.set_option(P._lib.GI_OPT_TILE_ORDER, order)
@@ -850,13 +853,14 @@ def _run_schedule(P, sched, p0, T, h, w, G, batch=None):
 
 
 def test_every_schedule_gives_the_same_bits_single_image():
-    # each knob the autotuner sets (binning path, radix digit, pixels per lane, tile order)
-    # leaves the render, the gradient and two fit steps bit for bit as the default schedule
+    # each knob the autotuner sets (binning path, radix digit, pixels per lane, tile order, fit
+    # kernel waves per SIMD) leaves the render, the gradient and two fit steps bit for bit as
+    # the default schedule
     import paper_2403_08551_amd as P
     w = synth.plain_256()
     p0, T = w.params(), dev(w.target())
     G = synth.upstream_gradient(w.height, w.width, 3)
-    want = _run_schedule(P, (0, 0, 0, 0), p0, T, w.height, w.width, G)
+    want = _run_schedule(P, (0, 0, 0, 0, 0), p0, T, w.height, w.width, G)
     for sched in _schedules(256):
         got = _run_schedule(P, sched, p0, T, w.height, w.width, G)
         for a, b, what in zip(got, want, ("image", "gradient", "params", "m", "v")):
@@ -874,7 +878,7 @@ def test_every_schedule_gives_the_same_bits_batch():
     G = np.concatenate([synth.upstream_gradient(h, w, 60 + i).reshape(-1, 3)
                         for i, (h, w) in enumerate(dims)])
     tiles = sum(((h + 15) // 16) * ((w + 15) // 16) for h, w in dims)
-    want = _run_schedule(P, (0, 0, 0, 0), p0, T, 0, 0, G, batch=batch)
+    want = _run_schedule(P, (0, 0, 0, 0, 0), p0, T, 0, 0, G, batch=batch)
     for sched in _schedules(tiles):
         got = _run_schedule(P, sched, p0, T, 0, 0, G, batch=batch)
         for a, b, what in zip(got, want, ("images", "gradient", "params", "m", "v")):
