@@ -14,13 +14,14 @@
 // PX pixels of one column (so per-column terms are shared by PX pixels), the part's records
 // streamed in sorted order through the wave's own LDS and read as broadcasts (every lane uses the
 // same Gaussian at once), colour accumulated in float32 registers with a two-level sum (partial
-// sums of 8 Gaussians).  The
-// four part sums meet in LDS and are added in part order, so every PX gives the same bits.
-// Adjoint: one Gaussian per lane, the tile's 256 dL/dC values staged in LDS and read as
-// broadcasts, so each lane reduces its own
-// Gaussian over the tile's pixels in registers: no cross-lane reduction and no atomics.  The
-// eight partial sums of each (tile, Gaussian) pair are stored at that pair's key position and
-// the per-Gaussian kernel adds them in a fixed order, which keeps gradients deterministic.
+// sums of 8 Gaussians).  The four part sums meet in LDS and are added in part order, so every PX
+// gives the same bits.
+// Adjoint: each Gaussian of the tile's list is taken by a group of 2 lanes (4, 8 or 16 in a
+// short last round), each lane covering every second (fourth, ...) column; the tile's 256 dL/dC
+// values are staged in LDS and read as broadcasts, each lane reduces its share of the pixels in
+// registers and the group adds its lanes' sums with DPP steps: no atomics.  The eight partial
+// sums of each (tile, Gaussian) pair are stored at that pair's key position and the
+// per-Gaussian kernel adds them in a fixed order, which keeps gradients deterministic.
 #include "gi_common.h"
 
 namespace gi {
