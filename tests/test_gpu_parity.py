@@ -283,13 +283,15 @@ def test_fit_steps_match_oracle(gi):
         assert int(host(step)[0]) == t + 1
 
 
-@pytest.mark.parametrize("which", ["plain-256x256-2k", "kodak-768x512-70k"])
+@pytest.mark.parametrize("which", ["plain-256x256-2k", "kodak-768x512-10k", "kodak-768x512-30k",
+                                   "kodak-768x512-70k"])
 def test_fit_step_gradients_element_by_element(gi, which):
     # Adam with beta1 = beta2 = 0 and eps = 1: the first moment the fused fit kernel's update
     # writes is its gradient (L2 loss scale 2 / (3 H W) included), compared element by element
     # with the oracle's at the gradient bar; the step is then lr g / (|g| + 1), checked too
     import paper_2403_08551_amd as P
-    w = synth.plain_256() if which.startswith("plain") else synth.kodak_like(70_000)
+    w = synth.plain_256() if which.startswith("plain") else synth.kodak_like(
+        int(which.rsplit("-", 1)[1][:-1]) * 1000)
     orc = ref if which.startswith("plain") else cref
     h, wd = w.height, w.width
     p0, T = w.params(), w.target()
