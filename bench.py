@@ -292,9 +292,11 @@ def batch_inputs(images, which):
     return ws, ps, ts
 
 
-def batched_vs_plain(ctx, inputs, steps, P, torch, np):
+def batched_vs_plain(ctx, inputs, steps, P, torch, np, tune_plain=True):
     """Fit uneven images for `steps` steps as one batch (one launch per stage) and as sequential
-    single-image fits; both graph-replayed after one untimed replay each.  The batched fit is
+    single-image fits, each side with the schedule the autotuner picks for it (the batch's, and
+    every image's own, unless tune_plain is off: then the default schedule); both
+    graph-replayed after one untimed replay each.  The batched fit is
     bit-identical to the plain one, so every image's final loss is equal."""
     ws, ps, ts = inputs
     images = len(ws)
@@ -320,14 +322,19 @@ def batched_vs_plain(ctx, inputs, steps, P, torch, np):
     g.close()
     if flags & bad:
         raise RuntimeError(f"flags {flags} raised during the batched fit")
-    # plain: one graph per image, replayed in turn
+    # plain: one graph per image, replayed in turn, each image with its own tuned schedule
     singles = []
+    plain_tuned = {}
     for w, p, t in zip(ws, ps, ts):
         pd = torch.tensor(p, device=dev)
         td = torch.tensor(t, device=dev)
         md, vd = torch.zeros_like(pd), torch.zeros_like(pd)
         sd = torch.ones(1, dtype=torch.int32, device=dev)
         ld = torch.empty(1, device=dev)
+        if tune_plain:
+            sc = ctx.autotune(pd, td, reps=2)
+            key = f"waves {sc['fit_waves']}, binning {sc['binning']}"
+            plain_tuned[key] = plain_tuned.get(key, 0) + 1
         gr = ctx.fit_graph(pd, md, vd, td, sd, loss_out=ld)
         gr.launch(1)
         singles.append((gr, pd, ld))
@@ -352,6 +359,7 @@ def batched_vs_plain(ctx, inputs, steps, P, torch, np):
             "speedup": t_plain / t_batched,
             "batched_image_steps_per_s": images * steps / t_batched,
             "final_mse_max_rel_diff": float(rel.max()), "batch_schedule": tuned,
+            "plain_schedules": plain_tuned,
             "images_within_1e-3": int((rel <= 1e-3).sum()),
             "params_bit_identical": bool(same_params)}
 
@@ -793,7 +801,10 @@ def main():
     lng = long_fit_leg(P, torch, w, args.long_steps) if args.long_steps > 1 else None
     bvp = None
     if args.batch_images > 0:
-        bvp = batched_vs_plain(ctx, binputs, args.batch_steps, P, torch, np)
+        # every plain image tuned for the 64-image set; the 256 large images keep the default
+        # schedule (tuning each would take minutes)
+        bvp = batched_vs_plain(ctx, binputs, args.batch_steps, P, torch, np,
+                               tune_plain=args.batch_set == "small")
     ctx.close()
 
     out = {
