@@ -190,7 +190,10 @@ __device__ inline void qat_fake_quant(float (&q)[8], const QatArgs &a, QuantFact
     const float *books = a.quant + 6;
     double r0 = q[5], r1 = q[6], r2 = q[7];
     double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-    for (int m = 0; m < a.stages; ++m) {
+    // stages unrolled to the maximum so that idx[m] stays in registers
+#pragma unroll
+    for (int m = 0; m < QAT_MAX_STAGES; ++m) {
+        if (m >= a.stages) break;
         const float *bk = books + (int64_t)m * a.size * 3;
         int best = 0;
         double bd = 0.0;

@@ -1274,7 +1274,13 @@ __global__ __launch_bounds__(UPD_T) void k_qat_adam(float4 *__restrict__ params,
     __shared__ float rows[UPD_G][QAT_FSUMS];
     __shared__ double res[UPD_G][QAT_MAX_STAGES][3];
     __shared__ int32_t sidx[UPD_G][QAT_MAX_STAGES];
+    __shared__ float s_quant[6 + 3 * QAT_MAX_ENTRIES];  // gamma, beta and the codebooks
     if (loss_out) block_image_losses(loss_part, tab, n_tiles, loss_out, red);
+    // the quantiser is read from LDS by every Gaussian's search (one global read each here)
+    const int nq = 6 + 3 * qa.stages * qa.size;
+    for (int t = threadIdx.x; t < nq; t += UPD_T) s_quant[t] = qa.quant[t];
+    QatArgs ql = qa;
+    ql.quant = s_quant;
     if (threadIdx.x == 0) {
         const double t = (double)(*step - 1);  // the fit kernel has advanced the counter
         s_bc[0] = (float)(1.0 - pow((double)hp.beta1, t));
@@ -1295,7 +1301,7 @@ __global__ __launch_bounds__(UPD_T) void k_qat_adam(float4 *__restrict__ params,
         const float4 a = params[2 * i], b = params[2 * i + 1];
         float rq[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
         QuantFacts f;
-        qat_fake_quant(rq, qa, &f);
+        qat_fake_quant(rq, ql, &f);
         float g[8];
         float4 q0, q1;
         quad_grad<COV>(params, i, q, count, off, part, keys, g, q0, q1, nullptr, rq + 2);
@@ -1313,8 +1319,10 @@ __global__ __launch_bounds__(UPD_T) void k_qat_adam(float4 *__restrict__ params,
             // the residual before each stage and the chosen entry
             double r0 = b.y, r1 = b.z, r2 = b.w;  // the float colour
             double lc = 0.0;
-            const float *books = qa.quant + 6;
-            for (int m = 0; m < qa.stages; ++m) {
+            const float *books = ql.quant + 6;
+#pragma unroll
+            for (int m = 0; m < QAT_MAX_STAGES; ++m) {
+                if (m >= qa.stages) break;
                 const float *e = books + ((int64_t)m * qa.size + f.idx[m]) * 3;
                 res[gl][m][0] = r0;
                 res[gl][m][1] = r1;
@@ -1367,10 +1375,15 @@ __global__ __launch_bounds__(UPD_T) void k_qat_adam(float4 *__restrict__ params,
             qpart[(int64_t)t * blocks + blockIdx.x] = acc;
         } else {
             const int e = (t - QAT_FSUMS) >> 2, ch = (t - QAT_FSUMS) & 3;
-            const int m = e / qa.size, k = e % qa.size;
+            const int m = e / qa.size, k = e % qa.size, chr = ch < 3 ? ch : 0;
+            // every term is read (no load waits on a comparison) and a Gaussian that chose
+            // another entry adds -0.0, which leaves any sum unchanged
             double acc = 0.0;
-            for (int j = 0; j < UPD_G; ++j)
-                if (sidx[j][m] == k) acc += ch < 3 ? res[j][m][ch] : 1.0;
+#pragma unroll 16
+            for (int j = 0; j < UPD_G; ++j) {
+                const double r = ch < 3 ? res[j][m][chr] : 1.0;
+                acc += sidx[j][m] == k ? r : -0.0;
+            }
             dpart[(int64_t)(t - QAT_FSUMS) * blocks + blockIdx.x] = acc;
         }
     }

@@ -7,8 +7,8 @@ own flags, and every kernel in it is checked for
 - no flat memory instructions: a flat access counts against both the vector-memory and the LDS
   wait counters, so an LDS wait after it also waits for memory (the raster forward's chunk
   prefetch had turned into one and every LDS wait of the chunk waited for it);
-- no private (scratch) memory, except the fine-tuning update, which keeps the per-stage codebook
-  indices of a Gaussian in a small array indexed by the runtime stage count;
+- no private (scratch) memory (the fine-tuning's per-stage codebook indices, indexed by the
+  runtime stage count, are kept in registers by unrolling the stages to their maximum);
 - no calls: every device function of a kernel is inlined (a call spills the caller's registers).
 """
 import os
@@ -26,7 +26,6 @@ CSRC = os.path.join(ROOT, "paper_2403_08551_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # kernels allowed private memory, with the reason in the module docstring
-SCRATCH_OK = ("k_qat_adam",)
 # the kernels of the hot path, which must exist under these names
 HOT = ("k_raster_fit", "k_raster_fwd", "k_raster_bwd", "k_project_hist", "k_chained_scan",
        "k_fused_scatter", "k_adam")
@@ -97,9 +96,8 @@ def test_no_flat_memory_instructions(kernels):
     assert not bad, bad
 
 
-def test_no_private_memory_outside_the_fine_tuning_update(kernels):
-    bad = sorted({_short(k) for k, (_, _, scratch) in kernels.items()
-                  if scratch and _short(k) not in SCRATCH_OK})
+def test_no_private_memory(kernels):
+    bad = sorted({_short(k) for k, (_, _, scratch) in kernels.items() if scratch})
     assert not bad, bad
 
 
