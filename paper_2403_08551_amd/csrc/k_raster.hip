@@ -1412,19 +1412,28 @@ __global__ __launch_bounds__(256) void k_qat_quant_update(float *__restrict__ qu
     const double *dpart = reinterpret_cast<const double *>(qpart + qat_dsum_offset(blocks));
     __shared__ double red[4][4];
     const int nv = (t >= 6 && t < 6 + entries) ? 4 : 1;
-    for (int c = 0; c < nv; ++c) {
-        double s = 0.0;
-        if (nv == 4) {
-            const double *src = dpart + (int64_t)(4 * (t - 6) + c) * blocks;
-            for (int64_t b = threadIdx.x; b < blocks; b += 256) s += src[b];
-        } else {
-            const int row = t < 6 ? t : 6;  // the commitment sum after the six LSQ terms
-            const float *src = qpart + (int64_t)row * blocks;
-            for (int64_t b = threadIdx.x; b < blocks; b += 256) s += (double)src[b];
-        }
+    // each value's strided thread sums and shuffle tree; an entry's four values side by side,
+    // so that their reads are in flight together
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (nv == 4) {
+        const double *src = dpart + (int64_t)(4 * (t - 6)) * blocks;
+        for (int64_t b = threadIdx.x; b < blocks; b += 256) {
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-        if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = s;
+            for (int c = 0; c < 4; ++c) s[c] += src[c * blocks + b];
+        }
+    } else {
+        const int row = t < 6 ? t : 6;  // the commitment sum after the six LSQ terms
+        const float *src = qpart + (int64_t)row * blocks;
+        for (int64_t b = threadIdx.x; b < blocks; b += 256) s[0] += (double)src[b];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[c] += __shfl_xor(s[c], d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) red[c][threadIdx.x >> 6] = s[c];
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
