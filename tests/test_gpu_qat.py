@@ -129,6 +129,40 @@ def test_fine_tuning_steps_match_oracle(gi):
     assert int(host(step)[0]) == 4
 
 
+@pytest.mark.parametrize("stages,size", [(1, 64), (8, 8), (4, 4)])
+def test_fine_tuning_codebook_shapes(gi, stages, size):
+    """Codebook shapes away from the paper's 2 x 8: the most entries (64, one stage), the most
+    stages (8), and a small square case.  Two steps: the fake-quantised image within the
+    forward bar, and the moving average of every entry against the oracle's from the same
+    state (the search, the per-entry sums and the quantiser update at these sizes)."""
+    import paper_2403_08551_amd as P
+    h, w = 96, 112
+    p0 = clustered(900, h, w, 83 + stages)
+    T = synth.target_noise_rects(h, w, seed=84)
+    qz = P.Quantiser.zeros("cuda", stages=stages, size=size, lam=1.0, lr_q=1e-3, decay=0.9)
+    pd = dev(p0)
+    gi.qat_init(pd, qz, 5)
+    hp = dict(ref.DEFAULT_ADAM)
+    md, vd = torch.zeros_like(pd), torch.zeros_like(pd)
+    step = torch.ones(1, dtype=torch.int32, device="cuda")
+    img = torch.empty(h, w, 3, device="cuda")
+    for t in range(1, 3):
+        pin = host(pd).copy()
+        quant = host(qz.quant).copy()
+        ema_in = host(qz.ema).copy()
+        gi.fit_step_qat(pd, md, vd, dev(T), step, qz, P.AdamConfig(**hp), image_out=img)
+        g, b, books = quant[0:3], quant[3:6], quant[6:].reshape(stages, size, 3)
+        _, _, _, _, want_img, idx, resids = qat.qat_grads(pin, g, b, books, 6, h, w, T)
+        q, *_ = qat.fake_quant(pin, g, b, books, 6)
+        _, A = ref.render_culled(q.astype(np.float32), h, w, with_abs=True)
+        assert np.all(np.abs(host(img) - want_img) <= pu.FWD_RTOL * A + 1e-30), t
+        assert idx.shape[1] == stages and idx.max() < size
+        _check_codebooks(qz, books, ema_in, idx, resids, float(np.float32(0.9)),
+                         f"{stages} x {size}, step {t}")
+    _, flags = gi.query(clear=True)
+    assert flags == 0
+
+
 def test_fine_tuning_gradients_element_by_element(gi):
     # beta1 = beta2 = 0, eps = 1: the first moments are the gradients of the records (through
     # the straight-through estimates) and of gamma and beta (LSQ+), compared with the oracle at
