@@ -362,7 +362,9 @@ constexpr int TILE_ORDER_BINS = 4096;
 hipError_t launch_tile_order(const uint2 *ranges, int64_t n_tiles, uint32_t *order,
                              hipStream_t s);
 
-hipError_t launch_raster_fwd(const RasterArgs &a, float *image, int px_per_lane, hipStream_t s);
+// flag_state (optional): block 0 hands that state's flags to flags_out (if given) and clears them
+hipError_t launch_raster_fwd(const RasterArgs &a, float *image, int px_per_lane, hipStream_t s,
+                             DevState *flag_state = nullptr, uint32_t *flags_out = nullptr);
 hipError_t launch_raster_bwd(const RasterArgs &a, const float *dl_dimage, float *part,
                              hipStream_t s);
 // step_inc (may be null): advanced by one by the kernel; the update kernel that follows reads

@@ -2109,9 +2109,9 @@ int gi_render_noalloc(const float *params, int64_t n, int32_t H, int32_t W, floa
     if (launch_fused_a(f, tb, s) != hipSuccess) return GI_ERR_HIP;
     if (launch_fused_c(f, nullptr, s) != hipSuccess) return GI_ERR_HIP;
     RasterArgs a{b.rec, nullptr, b.ranges, T, tb};
-    if (launch_raster_fwd(a, image, 4, s) != hipSuccess) return GI_ERR_HIP;
-    hipLaunchKernelGGL(k_noalloc_flags, dim3(1), dim3(1), 0, s, state, flags_out);
-    return hipGetLastError() == hipSuccess ? GI_OK : GI_ERR_HIP;
+    // the render kernel hands the call's flags over and clears them (no launch of its own)
+    if (launch_raster_fwd(a, image, 4, s, state, flags_out) != hipSuccess) return GI_ERR_HIP;
+    return GI_OK;
 }
 
 }  // extern "C"

@@ -332,9 +332,16 @@ template <int PX>
 __global__ __launch_bounds__(256) void k_raster_fwd(const float4 *__restrict__ rec,
                                                          const uint2 *__restrict__ ranges,
                                                          ImgTable tab, float *__restrict__ image,
-    const uint32_t *__restrict__ order) {
+    const uint32_t *__restrict__ order, DevState *flag_state, uint32_t *flags_out) {
     __shared__ float qs[PARTS * 3 * TILE_PX];
     __shared__ float4 lrec[4 * 64];
+    // the render's flags are final once the binning has run (this kernel raises none): one
+    // thread hands them to the caller and clears them, where the caller asks for that
+    if (flag_state && blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t f = flag_state->flags;
+        if (flags_out) *flags_out = f;
+        flag_state->flags = 0u;
+    }
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     const TileInfo ti = tile_info(tab, tile);
     fwd_parts<PX, true>(rec, ranges[tile], ti, qs, lrec);
@@ -1508,13 +1515,14 @@ hipError_t launch_tile_order(const uint2 *ranges, int64_t n_tiles, uint32_t *ord
     return hipGetLastError();
 }
 
-hipError_t launch_raster_fwd(const RasterArgs &a, float *image, int px, hipStream_t s) {
+hipError_t launch_raster_fwd(const RasterArgs &a, float *image, int px, hipStream_t s,
+                             DevState *flag_state, uint32_t *flags_out) {
     if (a.n_tiles <= 0) return hipSuccess;
     const float4 *rec = reinterpret_cast<const float4 *>(a.rec);
     switch (px) {
-        case 1: hipLaunchKernelGGL(k_raster_fwd<1>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image, a.order); break;
-        case 4: hipLaunchKernelGGL(k_raster_fwd<4>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image, a.order); break;
-        default: hipLaunchKernelGGL(k_raster_fwd<2>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image, a.order); break;
+        case 1: hipLaunchKernelGGL(k_raster_fwd<1>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image, a.order, flag_state, flags_out); break;
+        case 4: hipLaunchKernelGGL(k_raster_fwd<4>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image, a.order, flag_state, flags_out); break;
+        default: hipLaunchKernelGGL(k_raster_fwd<2>, dim3((unsigned)a.n_tiles), dim3(256), 0, s, rec, a.ranges, a.tab, image, a.order, flag_state, flags_out); break;
     }
     return hipGetLastError();
 }
